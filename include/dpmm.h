@@ -1,0 +1,232 @@
+/*
+ * dpmm.h -- C ABI of libdpmm, an MI355X (gfx950) sampler for a
+ * Dirichlet-process mixture of multinomials over single-cell UMI counts with
+ * sub-cluster split/merge moves (Duan, Pinto & Xie, "Parallel Clustering of
+ * Single Cell Transcriptomic Data with Split-Merge Sampling on Dirichlet
+ * Process Mixtures", arXiv:1812.10048).
+ *
+ * Conventions for every entry point
+ *   - Pointers are plain host or device addresses, as stated per argument.
+ *     Device pointers must come from the GPU the context was created on.
+ *   - Every call returns a dpmm_status.  The library never aborts or exits.
+ *     On failure, dpmm_last_error() returns a message for the calling thread
+ *     (valid until that thread's next call into the library).
+ *   - A context is used by one host thread at a time.  Work is issued on the
+ *     HIP stream given at init (a hipStream_t passed as void*, NULL meaning
+ *     the default stream).  Calls marked "async" only enqueue work; calls
+ *     marked "sync" wait for the stream before returning.
+ *   - Paper notation: x_i^u is the UMI count of gene u in cell i, c_i the
+ *     cluster of cell i and cbar_i in {0,1} its sub-cluster, theta_k and
+ *     thetabar_{k,r} the multinomial parameters of clusters and sub-clusters,
+ *     pi the mixing proportions, alpha the CRP parameter and lambda the
+ *     Dirichlet hyper-parameter (here beta_u, one per gene, with
+ *     lambdabar = lambda).
+ */
+#ifndef DPMM_H
+#define DPMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum dpmm_status {
+    DPMM_OK = 0,
+    DPMM_ERR_ARG = -1,          /* invalid argument (null pointer, size, range)    */
+    DPMM_ERR_HIP = -2,          /* a HIP runtime call failed; message has its text  */
+    DPMM_ERR_NOMEM = -3,        /* the workspace is smaller than required           */
+    DPMM_ERR_STATE = -4,        /* context not usable for this call                 */
+    DPMM_ERR_UNSUPPORTED = -5,  /* valid input outside what this build supports     */
+    DPMM_ERR_DATA = -6          /* the CSR content failed validation on the device  */
+} dpmm_status;
+
+/* Arithmetic of the per-cell log-likelihood contraction (steps of Section 2.1
+ * eq. 4 third line and Section 2.3 eq. 8).  Parameters are always redrawn in
+ * FP64 and the split/merge ratios are always FP64. */
+typedef enum dpmm_precision {
+    DPMM_FP64 = 0,        /* FP64 log theta, FP64 accumulation                     */
+    DPMM_FP32 = 1,        /* FP32 log theta, FP32 accumulation (vector ALU)        */
+    DPMM_SPLIT_BF16 = 2   /* log theta = hi + lo in BF16, counts in BF16 (exact up
+                             to 256, larger counts corrected in FP32), MFMA with
+                             FP32 accumulation                                     */
+} dpmm_precision;
+
+/* UMI count matrix (Section 2.1: the V x N matrix x_i^u), given cell-major
+ * as CSR.  All three arrays are DEVICE pointers, read only during dpmm_init
+ * (the library keeps its own packed copy in the workspace), never written.
+ * Columns must be strictly increasing within a row and < n_genes; values
+ * must be in [1, 65535].  Violations make dpmm_init return DPMM_ERR_DATA. */
+typedef struct dpmm_csr {
+    int64_t n_cells;          /* N, >= 1                                           */
+    int32_t n_genes;          /* G (the paper's V), 1 <= G <= 65535                */
+    int32_t reserved;         /* must be 0                                         */
+    int64_t nnz;              /* row_ptr[N]                                        */
+    const int64_t* row_ptr;   /* device, N + 1 entries, row_ptr[0] = 0             */
+    const int32_t* col;       /* device, nnz gene indices                          */
+    const int32_t* val;       /* device, nnz counts                                */
+} dpmm_csr;
+
+/* Hyper-parameters and sampler settings, copied at dpmm_init. */
+typedef struct dpmm_params {
+    double alpha;                  /* CRP parameter alpha (Section 2.1), > 0      */
+    double beta;                   /* Dirichlet lambda for every gene, > 0, used
+                                      when beta_per_gene is NULL                  */
+    const double* beta_per_gene;   /* DEVICE, G entries > 0, or NULL; copied     */
+    uint64_t seed;                 /* key of every Philox4x32-10 draw            */
+    int32_t k_init;                /* initial clusters, 1..k_max (cells spread
+                                      uniformly when > 1)                         */
+    int32_t k_max;                 /* cluster capacity, 1..1024                   */
+    int32_t precision;             /* dpmm_precision                               */
+    uint32_t flags;                /* reserved, must be 0                          */
+    double refine_tol;             /* decisions whose relative Gumbel-max margin
+                                      is below this are re-scored in FP64;
+                                      < 0 selects the precision's default         */
+} dpmm_params;
+
+typedef struct dpmm_ctx dpmm_ctx;
+
+/* Counters of a context (cumulative since init or the last dpmm_set_state). */
+typedef struct dpmm_stats_out {
+    int64_t step;               /* Philox step: sweeps + split/merge calls so far */
+    int32_t K;                  /* current number of clusters                     */
+    int32_t last_pass;          /* -1 none yet, 0 split pass, 1 merge pass         */
+    int64_t sweeps;
+    int64_t sm_calls;
+    int64_t splits_proposed;
+    int64_t splits_accepted;
+    int64_t merges_proposed;
+    int64_t merges_accepted;
+    int64_t kmax_skips;         /* accepted splits dropped for lack of capacity   */
+    int64_t refined;            /* decisions re-scored in FP64                    */
+    int64_t gamma_caps;         /* Gamma draws that hit the rejection cap (64)    */
+} dpmm_stats_out;
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* dpmm_last_error(void);
+
+/* Bytes of device workspace dpmm_init needs for this matrix and these
+ * settings.  Pure host computation: reads only the sizes in csr and params. */
+dpmm_status dpmm_workspace_size(const dpmm_csr* csr, const dpmm_params* params, size_t* bytes);
+
+/* Create a sampler.  `workspace` is a DEVICE buffer of at least
+ * dpmm_workspace_size() bytes, 256-byte aligned, owned by the caller, which
+ * must keep it alive and untouched until dpmm_destroy.  Validates and packs
+ * the CSR, draws the initial labels (all cells in one cluster, or spread over
+ * k_init clusters), computes the sufficient statistics and flags every
+ * cluster for a random sub-cluster start.  Sync.  On success *out owns a
+ * small host object released by dpmm_destroy. */
+dpmm_status dpmm_init(const dpmm_csr* csr, const dpmm_params* params, void* workspace,
+                      size_t workspace_bytes, void* stream, dpmm_ctx** out);
+
+/* Release the host object.  The workspace is the caller's to free afterwards
+ * (after the stream has drained).  Sync. */
+dpmm_status dpmm_destroy(dpmm_ctx* ctx);
+
+/* n_sweeps sweeps of the instantiated sampler.  Each sweep:
+ *   (a1) redraws pi ~ Dir(n_1..n_K, alpha), theta_k ~ Dir(lambda + s_k) and
+ *        thetabar_{k,r} ~ Dir(lambda + s_{k,r})  (Section 2.1 eq. 4, first two
+ *        lines; Section 2.3 eq. 19), in FP64;
+ *   (a2-a3) draws every c_i by Gumbel-max over log pi_k + x_i . log theta_k
+ *        (eq. 4 third line with eq. 26), then cbar_i within the chosen cluster
+ *        with weights nbar_{k,r} less the cell's own old membership times
+ *        prod_u thetabar^x (eq. 8); cells are independent given the parameters
+ *        (Section 2.2);
+ *   (a4) recomputes the integer statistics n_{k,r} and s_{k,r,u};
+ *   then drops empty clusters and flags clusters with an empty sub-cluster
+ *   for a random sub-cluster restart.  Async. */
+dpmm_status dpmm_sweep(dpmm_ctx* ctx, int32_t n_sweeps);
+
+/* One split/merge move (Sections 2.3-2.4, eq. 7).  A fair Philox coin picks
+ * the split chain or the random-split/merge chain (Section 2.4, last
+ * paragraph).  Split pass: every cluster whose sub-clusters are both
+ * non-empty proposes the split into its sub-clusters with the collapsed
+ * ratio log R = log alpha + lgamma(n_0) + lgamma(n_1) - lgamma(n)
+ * + logDM(s_0) + logDM(s_1) - logDM(s) (eq. 10 with eq. 12 integrated over
+ * theta).  Merge pass: every pair proposes the merge with the inverse ratio
+ * times (1/2)^(n_1 + n_2 - 2) (eq. 23); accepted pairs are applied in random
+ * order, each cluster at most once.  All ratios are FP64 lgamma sums.  Async. */
+dpmm_status dpmm_split_merge(dpmm_ctx* ctx);
+
+/* One empirical-Bayes fixed-point step for the per-gene lambda (beta_u), not
+ * in the paper: beta_u <- beta_u * sum_k [psi(s_ku + beta_u) - psi(beta_u)]
+ * / sum_k [psi(S_k + B) - psi(B)] over the current clusters (Minka 2000),
+ * clamped to [1e-6, 1e6].  Async. */
+dpmm_status dpmm_eb_update(dpmm_ctx* ctx);
+
+/* Counters into *out (HOST).  If nsub_host is not NULL it receives 2K int64
+ * entries n_{k,r} at 2k + r (HOST, capacity 2 k_max).  If ssub_dev is not
+ * NULL it receives the 2K x G int64 statistics s_{k,r,u} at (2k + r) G + u
+ * (DEVICE, capacity 2 k_max G).  Sync. */
+dpmm_status dpmm_stats(dpmm_ctx* ctx, dpmm_stats_out* out, int64_t* nsub_host, int64_t* ssub_dev);
+
+/* Copy the labels c (int32) and cbar (uint8), N entries each, into DEVICE
+ * buffers.  Sync. */
+dpmm_status dpmm_get_labels(dpmm_ctx* ctx, int32_t* c_dev, uint8_t* cs_dev);
+
+/* Replace the chain state: step counter, K, labels (DEVICE, N entries, c in
+ * [0, K), cbar in {0,1}) and the K reset flags (HOST).  Statistics are
+ * recomputed from the labels, counters are cleared.  Resuming from a saved
+ * (step, K, c, cbar, reset, beta) reproduces the chain exactly.  Sync. */
+dpmm_status dpmm_set_state(dpmm_ctx* ctx, int64_t step, int32_t K, const int32_t* c_dev,
+                           const uint8_t* cs_dev, const uint8_t* reset_host);
+
+/* Parameters drawn by the last sweep, FP64 DEVICE buffers: log pi (k_max
+ * entries, first K valid) and log theta (3 k_max x G: row k for cluster k,
+ * row k_max + 2k + r for sub-cluster r of cluster k).  Sync. */
+dpmm_status dpmm_get_params(dpmm_ctx* ctx, double* logpi_dev, double* logtheta_dev);
+
+/* Per-gene lambda (beta_u), G FP64 entries, DEVICE buffers.  Sync. */
+dpmm_status dpmm_get_beta(dpmm_ctx* ctx, double* beta_dev);
+dpmm_status dpmm_set_beta(dpmm_ctx* ctx, const double* beta_dev);
+
+/* Split/merge ratios of the last dpmm_split_merge: *pass (0 split, 1 merge,
+ * -1 none), *n candidates, and, when not NULL, their FP64 log R (HOST, NaN
+ * for clusters not eligible to split) and accept flags (HOST).  Split
+ * candidate k is cluster k; merge candidate k2 (k2 - 1) / 2 + k1 is the pair
+ * k1 < k2.  Capacity k_max + k_max (k_max - 1) / 2.  Sync. */
+dpmm_status dpmm_get_hastings(dpmm_ctx* ctx, int32_t* pass, int32_t* n, double* logr_host,
+                              uint8_t* accept_host);
+
+/* Debug output of the sweep's own log-likelihood arithmetic: while set, every
+ * sweep writes, per cell i, x_i . log theta_k for k < K followed by the two
+ * sub-clusters of the cell's new cluster, as FP32 into a DEVICE buffer of
+ * N x (k_cap + 2) entries (row stride k_cap + 2; requires K <= k_cap).  The
+ * values are the ones the decisions were taken on (before any FP64
+ * re-scoring).  NULL disables.  Sync. */
+dpmm_status dpmm_set_debug_scores(dpmm_ctx* ctx, float* scores_dev, int32_t k_cap);
+
+/* Split-BF16 tables of the last sweep (precision DPMM_SPLIT_BF16 only): the
+ * bit patterns of hi = bf16(log theta) and lo = bf16(log theta - hi) for the
+ * K clusters, K x G uint16 each, DEVICE.  Sync. */
+dpmm_status dpmm_get_split_tables(dpmm_ctx* ctx, uint16_t* hi_dev, uint16_t* lo_dev);
+
+/* Kernel timing with HIP events on the context's stream.  While enabled,
+ * every sweep records an event pair around its log-likelihood/assignment
+ * kernel; dpmm_timing_read returns the summed milliseconds and the number of
+ * launches since the last reset (sync) and resets the accumulator. */
+dpmm_status dpmm_timing_enable(dpmm_ctx* ctx, int32_t enable);
+dpmm_status dpmm_timing_read(dpmm_ctx* ctx, double* total_ms, int64_t* launches);
+
+/* Log Dirichlet-multinomial marginal of J count vectors (the per-cluster
+ * factor of eq. 12 with theta integrated against eq. 28, without the
+ * multinomial coefficient that eq. 26 drops):
+ *   out[j] = lgamma(B) - lgamma(B + S_j) + sum_u [lgamma(beta_u + s_ju) - lgamma(beta_u)],
+ * B = sum_u beta_u, S_j = sum_u s_ju.  s: J x G int64 (row-major, >= 0),
+ * beta: G FP64 (> 0), out: J FP64; all DEVICE.  Stateless.  Async on stream. */
+dpmm_status dpmm_dm_logmarginal(const int64_t* s, int32_t J, int32_t G, const double* beta,
+                                double* out, void* stream);
+
+/* Gradient of sum_j g_j out[j] with respect to beta:
+ *   grad_beta[u] = sum_j g_j [psi(B) - psi(B + S_j) + psi(beta_u + s_ju) - psi(beta_u)].
+ * s: J x G int64, beta: G, g: J, grad_beta: G FP64; all DEVICE.  Stateless.
+ * Async on stream. */
+dpmm_status dpmm_dm_grad(const int64_t* s, int32_t J, int32_t G, const double* beta,
+                         const double* g, double* grad_beta, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DPMM_H */

@@ -1,0 +1,338 @@
+"""Test infrastructure: ctypes loader for the double-precision CPU oracle.
+
+Only the tests, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  The product (``paper_1812_10048_amd``)
+never does; it shares no code with the oracle.
+
+The oracle follows Duan, Pinto & Xie (arXiv:1812.10048): the instantiated
+Gibbs cycle of Section 2.1 (eq. 4), the local sub-cluster Gibbs step of
+Section 2.3 (eq. 8, eq. 19), the split/merge Hastings ratios of Sections 2.3
+and 2.4 (eq. 7, eq. 10, eq. 12, eq. 23) and, beyond the paper, an
+empirical-Bayes step for a per-gene Dirichlet concentration.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "dpmm_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle_dpmm.so")
+
+# Philox stream identifiers (the counter's top byte); see dpmm_oracle.c.
+ST_INIT, ST_GAMMA, ST_PI, ST_GUMBEL_C, ST_GUMBEL_S, ST_RESUB, ST_CHAIN, ST_SPLIT, ST_MERGE = range(1, 10)
+SUB_ROW_BASE = 0x10000
+
+COUNTER_NAMES = [
+    "gamma_caps", "gamma_near_ties", "splits_proposed", "splits_accepted",
+    "merges_proposed", "merges_accepted", "kmax_skips", "sweeps", "sm_calls",
+]
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (C11, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        _lib = ctypes.CDLL(_LIB)
+        _declare(_lib)
+    return _lib
+
+
+_P = ctypes.c_void_p
+_D = ctypes.c_double
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+_U32 = ctypes.c_uint32
+_U64 = ctypes.c_uint64
+
+
+class _State(ctypes.Structure):
+    _fields_ = [
+        ("n_cells", _I64), ("n_genes", _I32), ("k_max", _I32),
+        ("row_ptr", _P), ("col", _P), ("val", _P),
+        ("alpha", _D), ("beta", _P), ("seed", _U64),
+        ("step", _I64), ("K", _I32), ("pad_", _I32),
+        ("c", _P), ("cs", _P), ("reset", _P), ("nsub", _P), ("ssub", _P),
+        ("logpi", _P), ("logtheta", _P),
+        ("margin_c", _P), ("margin_s", _P),
+        ("sm_logr", _P), ("sm_scale", _P), ("sm_accept", _P),
+        ("sm_pass", _I32), ("sm_n", _I32),
+        ("counters", _I64 * 16),
+    ]
+
+
+def _declare(L: ctypes.CDLL) -> None:
+    S = ctypes.POINTER(_State)
+    L.oracle_philox4x32_10.argtypes = [_U32, _U32, _P, _P]
+    L.oracle_philox4x32_10.restype = None
+    L.oracle_u23.argtypes = [_U32]
+    L.oracle_u23.restype = _D
+    L.oracle_u52.argtypes = [_U32, _U32]
+    L.oracle_u52.restype = _D
+    L.oracle_lgamma.argtypes = [_D]
+    L.oracle_lgamma.restype = _D
+    L.oracle_digamma.argtypes = [_D]
+    L.oracle_digamma.restype = _D
+    L.oracle_log_gamma_variate.argtypes = [_D, _U64, _U32, _U32, _I64, _U32]
+    L.oracle_log_gamma_variate.restype = _D
+    L.oracle_logdm.argtypes = [_P, _P, _I32]
+    L.oracle_logdm.restype = _D
+    L.oracle_log_partition_prior.argtypes = [_P, _I32, _D]
+    L.oracle_log_partition_prior.restype = _D
+    L.oracle_dm_grad.argtypes = [_P, _I32, _I32, _P, _P, _P]
+    L.oracle_dm_grad.restype = None
+    L.oracle_dm_logmarginal.argtypes = [_P, _I32, _I32, _P, _P]
+    L.oracle_dm_logmarginal.restype = None
+    L.oracle_split_logr.argtypes = [_P, _P, _I64, _I64, _P, _I32, _D, _P]
+    L.oracle_split_logr.restype = _D
+    L.oracle_merge_logr.argtypes = [_P, _P, _I64, _I64, _P, _I32, _D, _P]
+    L.oracle_merge_logr.restype = _D
+    for name in ("oracle_stats", "oracle_redraw", "oracle_assign", "oracle_assign_only",
+                 "oracle_sweep", "oracle_split_merge", "oracle_eb_update"):
+        getattr(L, name).argtypes = [S]
+        getattr(L, name).restype = None
+    L.oracle_init.argtypes = [S, _I32]
+    L.oracle_init.restype = None
+    L.oracle_set_state.argtypes = [S, _I64, _I32]
+    L.oracle_set_state.restype = None
+    L.oracle_log_joint.argtypes = [S]
+    L.oracle_log_joint.restype = _D
+    L.oracle_cell_logliks.argtypes = [S, _P, _I64, _P]
+    L.oracle_cell_logliks.restype = None
+    L.oracle_num_threads.argtypes = []
+    L.oracle_num_threads.restype = ctypes.c_int
+
+
+def _ptr(a: np.ndarray) -> int:
+    return a.ctypes.data
+
+
+# ----------------------------------------------------------------------------
+# Scalar helpers
+# ----------------------------------------------------------------------------
+
+def philox4x32_10(key: int, ctr) -> np.ndarray:
+    c = np.ascontiguousarray(np.asarray(ctr, dtype=np.uint32))
+    out = np.zeros(4, dtype=np.uint32)
+    lib().oracle_philox4x32_10(key & 0xFFFFFFFF, (key >> 32) & 0xFFFFFFFF, _ptr(c), _ptr(out))
+    return out
+
+
+def u23(w: int) -> float:
+    return lib().oracle_u23(w)
+
+
+def u52(hi: int, lo: int) -> float:
+    return lib().oracle_u52(hi, lo)
+
+
+def lgamma(x: float) -> float:
+    return lib().oracle_lgamma(x)
+
+
+def digamma(x: float) -> float:
+    return lib().oracle_digamma(x)
+
+
+def log_gamma_variate(a: float, seed: int, element: int, sub: int, step: int, stream: int) -> float:
+    return lib().oracle_log_gamma_variate(a, seed, element, sub, step, stream)
+
+
+def logdm(s, beta) -> float:
+    s = np.ascontiguousarray(s, dtype=np.int64)
+    beta = np.ascontiguousarray(beta, dtype=np.float64)
+    return lib().oracle_logdm(_ptr(s), _ptr(beta), s.shape[-1])
+
+
+def log_partition_prior(n, alpha: float) -> float:
+    n = np.ascontiguousarray(n, dtype=np.int64)
+    return lib().oracle_log_partition_prior(_ptr(n), n.size, alpha)
+
+
+def dm_logmarginal(s, beta) -> np.ndarray:
+    s = np.ascontiguousarray(s, dtype=np.int64)
+    beta = np.ascontiguousarray(beta, dtype=np.float64)
+    J, G = s.shape
+    out = np.zeros(J)
+    lib().oracle_dm_logmarginal(_ptr(s), J, G, _ptr(beta), _ptr(out))
+    return out
+
+
+def dm_grad(s, beta, g) -> np.ndarray:
+    s = np.ascontiguousarray(s, dtype=np.int64)
+    beta = np.ascontiguousarray(beta, dtype=np.float64)
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    J, G = s.shape
+    out = np.zeros(G)
+    lib().oracle_dm_grad(_ptr(s), J, G, _ptr(beta), _ptr(g), _ptr(out))
+    return out
+
+
+def split_logr(s0, s1, n0, n1, beta, alpha):
+    s0 = np.ascontiguousarray(s0, dtype=np.int64)
+    s1 = np.ascontiguousarray(s1, dtype=np.int64)
+    beta = np.ascontiguousarray(beta, dtype=np.float64)
+    sc = np.zeros(1)
+    v = lib().oracle_split_logr(_ptr(s0), _ptr(s1), int(n0), int(n1), _ptr(beta), s0.size, alpha, _ptr(sc))
+    return v, float(sc[0])
+
+
+def merge_logr(s1, s2, n1, n2, beta, alpha):
+    s1 = np.ascontiguousarray(s1, dtype=np.int64)
+    s2 = np.ascontiguousarray(s2, dtype=np.int64)
+    beta = np.ascontiguousarray(beta, dtype=np.float64)
+    sc = np.zeros(1)
+    v = lib().oracle_merge_logr(_ptr(s1), _ptr(s2), int(n1), int(n2), _ptr(beta), s1.size, alpha, _ptr(sc))
+    return v, float(sc[0])
+
+
+def num_threads() -> int:
+    return lib().oracle_num_threads()
+
+
+# ----------------------------------------------------------------------------
+# Sampler state
+# ----------------------------------------------------------------------------
+
+class Oracle:
+    """Host-side sampler state over a cell-major CSR matrix of UMI counts.
+
+    ``row_ptr`` (int64, N+1), ``col`` (int32, sorted within each row) and
+    ``val`` (int32, >= 1) are kept alive by this object.  Every array of the
+    chain state is a numpy array that the tests may read or overwrite.
+    """
+
+    def __init__(self, row_ptr, col, val, n_genes: int, alpha: float = 1.0, beta=1.0,
+                 seed: int = 0, k_max: int = 64, k_init: int = 1, init: bool = True):
+        self.row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        self.col = np.ascontiguousarray(col, dtype=np.int32)
+        self.val = np.ascontiguousarray(val, dtype=np.int32)
+        N = self.row_ptr.size - 1
+        G = int(n_genes)
+        self.N, self.G, self.k_max = N, G, int(k_max)
+        b = np.broadcast_to(np.asarray(beta, dtype=np.float64), (G,))
+        self.beta = np.ascontiguousarray(b.copy())
+        self.c = np.zeros(N, dtype=np.int32)
+        self.cs = np.zeros(N, dtype=np.uint8)
+        self.reset = np.zeros(self.k_max, dtype=np.uint8)
+        self.nsub = np.zeros(2 * self.k_max, dtype=np.int64)
+        self.ssub = np.zeros((2 * self.k_max, G), dtype=np.int64)
+        self.logpi = np.zeros(self.k_max, dtype=np.float64)
+        self.logtheta = np.zeros((3 * self.k_max, G), dtype=np.float64)
+        self.margin_c = np.zeros(N, dtype=np.float64)
+        self.margin_s = np.zeros(N, dtype=np.float64)
+        ncand = self.k_max + self.k_max * (self.k_max - 1) // 2
+        self.sm_logr = np.zeros(ncand, dtype=np.float64)
+        self.sm_scale = np.zeros(ncand, dtype=np.float64)
+        self.sm_accept = np.zeros(ncand, dtype=np.uint8)
+        st = _State()
+        st.n_cells, st.n_genes, st.k_max = N, G, self.k_max
+        st.row_ptr, st.col, st.val = _ptr(self.row_ptr), _ptr(self.col), _ptr(self.val)
+        st.alpha, st.beta, st.seed = float(alpha), _ptr(self.beta), int(seed) & 0xFFFFFFFFFFFFFFFF
+        st.step, st.K = 0, 0
+        for name in ("c", "cs", "reset", "nsub", "ssub", "logpi", "logtheta", "margin_c",
+                     "margin_s", "sm_logr", "sm_scale", "sm_accept"):
+            setattr(st, name, _ptr(getattr(self, name)))
+        self._st = st
+        if init:
+            lib().oracle_init(ctypes.byref(st), int(k_init))
+
+    # -- state access -------------------------------------------------------
+    @property
+    def K(self) -> int:
+        return self._st.K
+
+    @property
+    def step(self) -> int:
+        return self._st.step
+
+    @step.setter
+    def step(self, v: int) -> None:
+        self._st.step = int(v)
+
+    @property
+    def alpha(self) -> float:
+        return self._st.alpha
+
+    @property
+    def sm_pass(self) -> int:
+        return self._st.sm_pass
+
+    @property
+    def sm_n(self) -> int:
+        return self._st.sm_n
+
+    def counters(self) -> dict:
+        return {n: int(self._st.counters[i]) for i, n in enumerate(COUNTER_NAMES)}
+
+    def logtheta_clusters(self) -> np.ndarray:
+        return self.logtheta[: self.K]
+
+    def logtheta_sub(self) -> np.ndarray:
+        """[K, 2, G] sub-cluster log-parameters."""
+        return self.logtheta[self.k_max: self.k_max + 2 * self.K].reshape(self.K, 2, self.G)
+
+    # -- steps ---------------------------------------------------------------
+    def set_state(self, step: int, K: int, c, cs, reset) -> None:
+        self.c[:] = np.asarray(c, dtype=np.int32)
+        self.cs[:] = np.asarray(cs, dtype=np.uint8)
+        self.reset[:] = 0
+        self.reset[: len(reset)] = np.asarray(reset, dtype=np.uint8)
+        lib().oracle_set_state(ctypes.byref(self._st), int(step), int(K))
+
+    def stats(self) -> None:
+        lib().oracle_stats(ctypes.byref(self._st))
+
+    def redraw(self) -> None:
+        lib().oracle_redraw(ctypes.byref(self._st))
+
+    def assign(self) -> None:
+        lib().oracle_assign_only(ctypes.byref(self._st))
+
+    def sweep(self, n: int = 1) -> None:
+        for _ in range(n):
+            lib().oracle_sweep(ctypes.byref(self._st))
+
+    def split_merge(self) -> None:
+        lib().oracle_split_merge(ctypes.byref(self._st))
+
+    def iterate(self, n: int = 1) -> None:
+        """n iterations of (sweep, split/merge)."""
+        for _ in range(n):
+            self.sweep()
+            self.split_merge()
+
+    def eb_update(self) -> None:
+        lib().oracle_eb_update(ctypes.byref(self._st))
+
+    def log_joint(self) -> float:
+        return lib().oracle_log_joint(ctypes.byref(self._st))
+
+    def cell_logliks(self, cells) -> np.ndarray:
+        cells = np.ascontiguousarray(cells, dtype=np.int64)
+        out = np.zeros((cells.size, self.K + 2))
+        lib().oracle_cell_logliks(ctypes.byref(self._st), _ptr(cells), cells.size, _ptr(out))
+        return out
+
+    def snapshot(self) -> dict:
+        K = self.K
+        return dict(step=self.step, K=K, c=self.c.copy(), cs=self.cs.copy(),
+                    reset=self.reset[:K].copy(), nsub=self.nsub[: 2 * K].copy(),
+                    ssub=self.ssub[: 2 * K].copy(), beta=self.beta.copy())

@@ -1,0 +1,323 @@
+"""Pins for the oracle's sampler steps (test infrastructure).
+
+* Redraw (eq. 4, eq. 19): empirical means of exp(log theta) and exp(log pi)
+  over many steps equal the Dirichlet posterior means, row by row; this fixes
+  which statistics feed which row.
+* Assignment (eq. 4 third line, eq. 8): empirical label frequencies over many
+  steps equal the exact categorical probabilities computed here with numpy,
+  for the cluster choice, the sub-cluster choice with its n_{r,-i} weights,
+  the equal-weight case and the reset coin.
+* Statistics and compaction: conservation and consistency invariants.
+* Split and merge application: acceptance frequency equals min(1, R); moved
+  statistics equal statistics recomputed from the moved labels.
+* The whole chain: the small four-cluster recipe is recovered; a resumed chain
+  is identical to an uninterrupted one.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import stats
+from sklearn.metrics import adjusted_rand_score
+
+import oracle
+from paper_1812_10048_amd import synth
+
+
+def _dense_oracle(X, k_max=8, beta=1.0, alpha=1.0, seed=0):
+    d = synth.from_dense(X)
+    rp, col, val = d.host_arrays()
+    return oracle.Oracle(rp, col, val, X.shape[1], alpha=alpha, beta=beta, seed=seed, k_max=k_max, init=False)
+
+
+def _chi2_ok(counts, probs, min_p=1e-4):
+    counts = np.asarray(counts, dtype=float)
+    probs = np.asarray(probs, dtype=float)
+    exp = probs * counts.sum()
+    keep = exp > 5
+    chi = ((counts[keep] - exp[keep]) ** 2 / exp[keep]).sum()
+    dof = max(1, keep.sum() - 1)
+    return stats.chi2.sf(chi, dof) > min_p, (counts, exp)
+
+
+# --------------------------------------------------------------------------
+# statistics
+# --------------------------------------------------------------------------
+
+def test_stats_invariants():
+    d = synth.generate("c1", seed=3, n_cells=600)
+    rp, col, val = d.host_arrays()
+    o = oracle.Oracle(rp, col, val, d.n_genes, seed=1, k_max=16, init=False)
+    rng = np.random.default_rng(0)
+    K = 5
+    c = rng.integers(0, K, size=d.n_cells)
+    cs = rng.integers(0, 2, size=d.n_cells)
+    o.set_state(0, K, c, cs, np.zeros(K))
+    colsum = np.bincount(col, weights=val, minlength=d.n_genes)
+    assert np.array_equal(o.ssub[: 2 * K].sum(0), colsum)
+    assert o.nsub[: 2 * K].sum() == d.n_cells
+    lib = np.add.reduceat(val, rp[:-1]) if val.size else np.zeros(d.n_cells)
+    grp = 2 * c + cs
+    assert np.array_equal(o.ssub[: 2 * K].sum(1), np.bincount(grp, weights=lib, minlength=2 * K))
+    assert np.array_equal(o.nsub[: 2 * K], np.bincount(grp, minlength=2 * K))
+    assert not o.ssub[2 * K:].any() and not o.nsub[2 * K:].any()
+
+
+# --------------------------------------------------------------------------
+# redraw
+# --------------------------------------------------------------------------
+
+def test_redraw_matches_dirichlet_posterior_means():
+    rng = np.random.default_rng(4)
+    G = 4
+    X = rng.integers(0, 9, size=(7, G))
+    X[:, 0] += 3
+    beta = np.array([0.5, 1.0, 2.0, 0.3])
+    o = _dense_oracle(X, k_max=4, beta=beta, alpha=1.7)
+    c = np.array([0, 0, 0, 1, 1, 1, 1])
+    cs = np.array([0, 1, 1, 0, 0, 1, 0])
+    o.set_state(0, 2, c, cs, np.zeros(2))
+    T = 6000
+    acc_t = np.zeros((3 * 2, G))
+    acc_p = np.zeros(2)
+    for t in range(T):
+        o.step = t
+        o.redraw()
+        acc_t[:2] += np.exp(o.logtheta[:2])
+        acc_t[2:] += np.exp(o.logtheta[4:8])
+        acc_p += np.exp(o.logpi[:2])
+        np.testing.assert_allclose(np.exp(o.logtheta[:2]).sum(1), 1.0, rtol=1e-12)
+    s = np.zeros((4, G))
+    for i in range(7):
+        s[2 * c[i] + cs[i]] += X[i]
+    rows = [s[0] + s[1], s[2] + s[3], s[0], s[1], s[2], s[3]]
+    for r, sr in enumerate(rows):
+        a = beta + sr
+        mean = a / a.sum()
+        var = mean * (1 - mean) / (a.sum() + 1)
+        np.testing.assert_array_less(np.abs(acc_t[r] / T - mean), 5 * np.sqrt(var / T) + 1e-12)
+    n = np.array([3.0, 4.0])
+    a = np.concatenate([n, [1.7]])
+    mean = (a / a.sum())[:2]
+    var = mean * (1 - mean) / (a.sum() + 1)
+    np.testing.assert_array_less(np.abs(acc_p / T - mean), 5 * np.sqrt(var / T))
+
+
+# --------------------------------------------------------------------------
+# assignment
+# --------------------------------------------------------------------------
+
+def test_cluster_choice_frequencies_are_softmax():
+    rng = np.random.default_rng(9)
+    N, G, K = 5, 4, 3
+    X = rng.integers(0, 4, size=(N, G))
+    o = _dense_oracle(X, k_max=4)
+    o.set_state(0, K, np.zeros(N), np.zeros(N), np.ones(K))
+    logth = np.log(rng.dirichlet(np.ones(G), size=K))
+    # scale so that the choices are genuinely random
+    logth = logth * 0.3 + np.log(1.0 / G) * 0.7
+    logpi = np.log(np.array([0.5, 0.3, 0.2]))
+    T = 20000
+    counts = np.zeros((N, K))
+    for t in range(T):
+        o.logtheta[:K] = logth
+        o.logpi[:K] = logpi
+        o.c[:] = 0
+        o.cs[:] = 0
+        o.step = t
+        o.assign()
+        counts[np.arange(N), o.c] += 1
+    score = logpi[None, :] + X @ logth.T
+    p = np.exp(score - score.max(1, keepdims=True))
+    p /= p.sum(1, keepdims=True)
+    for i in range(N):
+        ok, info = _chi2_ok(counts[i], p[i])
+        assert ok, (i, info)
+
+
+def test_subcluster_choice_uses_counts_without_the_cell():
+    rng = np.random.default_rng(12)
+    N, G = 5, 3
+    X = rng.integers(0, 3, size=(N, G))
+    o = _dense_oracle(X, k_max=4)
+    c = np.zeros(N, dtype=np.int32)
+    cs = np.array([0, 0, 1, 1, 1], dtype=np.uint8)       # nbar = (2, 3)
+    o.set_state(0, 2, c, cs, np.zeros(2))
+    # cluster 1 is never chosen
+    logpi = np.array([0.0, -1e6])
+    lsub = np.log(rng.dirichlet(np.ones(G) * 3, size=2))
+    T = 20000
+    ones = np.zeros(N)
+    for t in range(T):
+        o.logpi[:2] = logpi
+        o.logtheta[:2] = np.log(1.0 / G)
+        o.logtheta[4:6] = lsub
+        o.c[:] = c
+        o.cs[:] = cs
+        o.step = t
+        o.assign()
+        assert np.all(o.c == 0)
+        ones += o.cs
+    for i in range(N):
+        w = np.array([2.0, 3.0])
+        w[cs[i]] -= 1.0
+        sc = np.log(w) + lsub @ X[i]
+        p1 = 1.0 / (1.0 + np.exp(sc[0] - sc[1]))
+        ok, info = _chi2_ok([T - ones[i], ones[i]], [1 - p1, p1])
+        assert ok, (i, info)
+
+
+def test_subcluster_equal_weights_and_reset_coin():
+    X = np.array([[3, 1, 0], [0, 2, 2]])
+    o = _dense_oracle(X, k_max=4)
+    # cell 0 alone in cluster 0 (weights (0,0) -> equal), cell 1 in a reset cluster 1
+    c = np.array([0, 1], dtype=np.int32)
+    cs = np.array([0, 0], dtype=np.uint8)
+    o.set_state(0, 2, c, cs, np.array([0, 1]))
+    lsub = np.log(np.array([[0.5, 0.3, 0.2], [0.2, 0.3, 0.5]]))
+    T = 20000
+    ones = np.zeros(2)
+    for t in range(T):
+        o.logpi[:2] = [0.0, 0.0]
+        o.logtheta[0] = np.log([0.998, 0.001, 0.001])
+        o.logtheta[1] = np.log([0.001, 0.499, 0.5])
+        o.logtheta[4:6] = lsub
+        o.c[:] = c
+        o.cs[:] = cs
+        o.step = t
+        o.assign()
+        assert list(o.c) == [0, 1]
+        ones += o.cs
+    sc = lsub @ X[0]
+    p1 = 1.0 / (1.0 + np.exp(sc[0] - sc[1]))
+    assert _chi2_ok([T - ones[0], ones[0]], [1 - p1, p1])[0]
+    assert _chi2_ok([T - ones[1], ones[1]], [0.5, 0.5])[0]
+
+
+# --------------------------------------------------------------------------
+# sweep bookkeeping
+# --------------------------------------------------------------------------
+
+def _recomputed_stats(o):
+    K = o.K
+    s = np.zeros((2 * K, o.G), dtype=np.int64)
+    n = np.zeros(2 * K, dtype=np.int64)
+    for i in range(o.N):
+        g = 2 * o.c[i] + o.cs[i]
+        n[g] += 1
+        s[g, o.col[o.row_ptr[i]:o.row_ptr[i + 1]]] += o.val[o.row_ptr[i]:o.row_ptr[i + 1]]
+    return n, s
+
+
+def test_sweeps_keep_statistics_and_flags_consistent():
+    d = synth.generate("c1", seed=5, n_cells=400)
+    rp, col, val = d.host_arrays()
+    o = oracle.Oracle(rp, col, val, d.n_genes, seed=2, k_max=32, k_init=6)
+    total = np.bincount(col, weights=val, minlength=d.n_genes)
+    for it in range(12):
+        o.sweep()
+        K = o.K
+        n, s = _recomputed_stats(o)
+        assert np.array_equal(n, o.nsub[: 2 * K]) and np.array_equal(s, o.ssub[: 2 * K])
+        nk = n[0::2] + n[1::2]
+        assert np.all(nk > 0)
+        flag = (nk >= 2) & ((n[0::2] == 0) | (n[1::2] == 0))
+        assert np.array_equal(o.reset[:K].astype(bool), flag)
+        assert np.array_equal(o.ssub[: 2 * K].sum(0), total)
+        o.split_merge()
+        K = o.K
+        n, s = _recomputed_stats(o)
+        assert np.array_equal(n, o.nsub[: 2 * K]) and np.array_equal(s, o.ssub[: 2 * K])
+        assert np.all(n[0::2] + n[1::2] > 0)
+        assert o.c.max() < K
+
+
+def test_split_acceptance_frequency_is_min_one_r():
+    rng = np.random.default_rng(21)
+    G = 3
+    X = rng.integers(0, 3, size=(6, G))
+    c = np.zeros(6, dtype=np.int32)
+    cs = np.array([0, 1, 0, 1, 0, 1], dtype=np.uint8)
+    o = _dense_oracle(X, k_max=4, alpha=1.0)
+    o.set_state(0, 1, c, cs, np.zeros(1))
+    # choose alpha so that log R = -1 (log R is linear in log alpha)
+    logr1, _ = oracle.split_logr(o.ssub[0], o.ssub[1], 3, 3, o.beta, 1.0)
+    alpha = math.exp(-1.0 - logr1)
+    o = _dense_oracle(X, k_max=4, alpha=alpha)
+    o.set_state(0, 1, c, cs, np.zeros(1))
+    logr, _ = oracle.split_logr(o.ssub[0], o.ssub[1], 3, 3, o.beta, alpha)
+    assert abs(logr + 1.0) < 1e-9
+    splits = accepted = 0
+    for t in range(6000):
+        o.set_state(t, 1, c, cs, np.zeros(1))
+        o.split_merge()
+        if o.sm_pass == 0:
+            splits += 1
+            assert abs(o.sm_logr[0] - logr) < 1e-12
+            if o.K == 2:
+                accepted += 1
+                # sub-cluster 1 became cluster 1, both flagged for reset
+                assert np.array_equal(o.c, cs.astype(np.int32)) and not o.cs.any()
+                assert list(o.reset[:2]) == [1, 1]
+        else:
+            assert o.K == 1
+    p = math.exp(logr)
+    assert abs(splits / 6000 - 0.5) < 5 * math.sqrt(0.25 / 6000)
+    assert abs(accepted / splits - p) < 5 * math.sqrt(p * (1 - p) / splits)
+
+
+def test_merge_pass_merges_disjoint_pairs():
+    rng = np.random.default_rng(5)
+    G = 4
+    X = rng.integers(1, 4, size=(12, G))
+    # a tiny alpha makes every merge attractive
+    o = _dense_oracle(X, k_max=8, alpha=1e-30)
+    c = np.repeat(np.arange(4), 3).astype(np.int32)
+    cs = np.tile([0, 1, 0], 4).astype(np.uint8)
+    seen_merge = False
+    for t in range(40):
+        o.set_state(t, 4, c, cs, np.zeros(4))
+        o.split_merge()
+        if o.sm_pass != 1:
+            continue
+        seen_merge = True
+        assert o.K == 2
+        # each new cluster is the union of two old clusters, with the old
+        # clusters as its sub-clusters
+        for k in range(2):
+            members = np.nonzero(o.c == k)[0]
+            old = sorted(set(c[members]))
+            assert len(old) == 2
+            assert np.array_equal(o.cs[members], (c[members] == old[1]).astype(np.uint8))
+        n, s = _recomputed_stats(o)
+        assert np.array_equal(n, o.nsub[:4]) and np.array_equal(s, o.ssub[:4])
+        assert np.sum(o.sm_accept[:6]) == 2
+    assert seen_merge
+
+
+# --------------------------------------------------------------------------
+# whole chain
+# --------------------------------------------------------------------------
+
+def test_small_recipe_recovers_its_clusters():
+    d = synth.generate("c1", seed=0)
+    rp, col, val = d.host_arrays()
+    o = oracle.Oracle(rp, col, val, d.n_genes, alpha=1.0, beta=1.0, seed=0, k_max=64)
+    o.iterate(100)
+    assert o.K == d.n_true
+    assert adjusted_rand_score(d.z, o.c) > 0.95
+
+
+def test_resumed_chain_is_identical():
+    d = synth.generate("c1", seed=1, n_cells=500)
+    rp, col, val = d.host_arrays()
+    a = oracle.Oracle(rp, col, val, d.n_genes, seed=4, k_max=32, beta=0.7)
+    a.iterate(6)
+    b = oracle.Oracle(rp, col, val, d.n_genes, seed=4, k_max=32, beta=0.7)
+    b.iterate(3)
+    snap = b.snapshot()
+    r = oracle.Oracle(rp, col, val, d.n_genes, seed=4, k_max=32, beta=snap["beta"], init=False)
+    r.set_state(snap["step"], snap["K"], snap["c"], snap["cs"], snap["reset"])
+    r.iterate(3)
+    assert r.K == a.K and r.step == a.step
+    assert np.array_equal(r.c, a.c) and np.array_equal(r.cs, a.cs)

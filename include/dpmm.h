@@ -101,6 +101,8 @@ typedef struct dpmm_stats_out {
     int64_t kmax_skips;         /* accepted splits dropped for lack of capacity   */
     int64_t refined;            /* decisions re-scored in FP64                    */
     int64_t gamma_caps;         /* Gamma draws that hit the rejection cap (64)    */
+    int64_t evals;              /* cell x cluster log-likelihood evaluations:
+                                   the sum over sweeps of N (K + 2)              */
 } dpmm_stats_out;
 
 /* Message of the last failed call on this thread ("" if none). */
@@ -171,6 +173,10 @@ dpmm_status dpmm_get_labels(dpmm_ctx* ctx, int32_t* c_dev, uint8_t* cs_dev);
  * (step, K, c, cbar, reset, beta) reproduces the chain exactly.  Sync. */
 dpmm_status dpmm_set_state(dpmm_ctx* ctx, int64_t step, int32_t K, const int32_t* c_dev,
                            const uint8_t* cs_dev, const uint8_t* reset_host);
+
+/* The K reset flags (1 = the cluster re-draws its sub-labels at random on
+ * the next sweep) into a HOST buffer of capacity k_max.  Sync. */
+dpmm_status dpmm_get_reset_flags(dpmm_ctx* ctx, uint8_t* reset_host);
 
 /* Parameters drawn by the last sweep, FP64 DEVICE buffers: log pi (k_max
  * entries, first K valid) and log theta (3 k_max x G: row k for cluster k,

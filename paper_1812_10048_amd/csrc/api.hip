@@ -1,0 +1,575 @@
+// api.hip -- host side of the libdpmm C ABI (include/dpmm.h): argument
+// checks, workspace carving, and the order in which the kernels of a sweep,
+// a split/merge move and the empirical-Bayes step are enqueued.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "../../include/dpmm.h"
+#include "dpmm_common.hpp"
+#include "kernels.hpp"
+
+using namespace dpmm;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+dpmm_status fail(dpmm_status st, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                           \
+    do {                                                                                        \
+        hipError_t e_ = (expr);                                                                 \
+        if (e_ != hipSuccess) return fail(DPMM_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+constexpr int kMaxTimed = 4096;
+constexpr int kMfmaGeneTile = 32;
+constexpr bool kHaveSplitBf16 = false;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+
+struct Layout {
+    size_t ent, roff, tiles, c0, c1, cs0, cs1, st, reset, nsub, ssub, beta, logpi, lt64, lc32, ls32, lhi, llo,
+        refine, relab_c, relab_s, sm_logr, sm_acc, mkey, mlist, dm_k, eb_tmp, total;
+};
+
+Layout plan(int64_t N, int32_t G, int64_t nnz, int32_t k_max)
+{
+    Layout L{};
+    const int64_t nnz_pad = nnz + 3 * N;
+    const int64_t kpad = (k_max + 15) / 16 * 16;
+    const int64_t Gpad = (G + kMfmaGeneTile - 1) / kMfmaGeneTile * kMfmaGeneTile;
+    const int64_t ncand = (int64_t)k_max + (int64_t)k_max * (k_max - 1) / 2;
+    const int64_t ntiles = (N + 4095) / 4096 + 1;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o += align_up(bytes); return at; };
+    L.ent = take(4 * (size_t)nnz_pad);
+    L.roff = take(8 * (size_t)(N + 1));
+    L.tiles = take(8 * (size_t)(ntiles + 1));
+    L.c0 = take(4 * (size_t)N);
+    L.c1 = take(4 * (size_t)N);
+    L.cs0 = take((size_t)N);
+    L.cs1 = take((size_t)N);
+    L.st = take(sizeof(DevState));
+    L.reset = take((size_t)k_max);
+    L.nsub = take(16 * (size_t)k_max);
+    L.ssub = take(16 * (size_t)k_max * (size_t)G);
+    L.beta = take(8 * (size_t)G);
+    L.logpi = take(8 * (size_t)k_max);
+    L.lt64 = take(24 * (size_t)k_max * (size_t)G);
+    L.lc32 = take(4 * (size_t)G * (size_t)kpad);
+    L.ls32 = take(8 * (size_t)G * (size_t)k_max);
+    L.lhi = take(2 * (size_t)Gpad * (size_t)kpad);
+    L.llo = take(2 * (size_t)Gpad * (size_t)kpad);
+    L.refine = take(4 * (size_t)N);
+    L.relab_c = take(8 * (size_t)k_max);
+    L.relab_s = take(2 * (size_t)k_max);
+    L.sm_logr = take(8 * (size_t)ncand);
+    L.sm_acc = take((size_t)ncand);
+    L.mkey = take(8 * (size_t)ncand);
+    L.mlist = take(4 * (size_t)ncand);
+    L.dm_k = take(8 * (size_t)k_max);
+    L.eb_tmp = take(8 * ((size_t)k_max + (size_t)G));
+    L.total = o;
+    return L;
+}
+
+dpmm_status check_args(const dpmm_csr* csr, const dpmm_params* p)
+{
+    if (!csr || !p) return fail(DPMM_ERR_ARG, "null csr or params");
+    if (csr->n_cells < 1 || csr->n_cells >= (1ll << 30)) return fail(DPMM_ERR_ARG, "n_cells must be in [1, 2^30)");
+    if (csr->n_genes < 1 || csr->n_genes > 65535) return fail(DPMM_ERR_ARG, "n_genes must be in [1, 65535]");
+    if (csr->nnz < 0) return fail(DPMM_ERR_ARG, "nnz must be >= 0");
+    if (csr->reserved != 0) return fail(DPMM_ERR_ARG, "reserved field must be 0");
+    if (!(p->alpha > 0.0)) return fail(DPMM_ERR_ARG, "alpha must be > 0");
+    if (!p->beta_per_gene && !(p->beta > 0.0)) return fail(DPMM_ERR_ARG, "beta must be > 0");
+    if (p->k_max < 1 || p->k_max > 1024) return fail(DPMM_ERR_ARG, "k_max must be in [1, 1024]");
+    if (p->k_init < 1 || p->k_init > p->k_max) return fail(DPMM_ERR_ARG, "k_init must be in [1, k_max]");
+    if (p->precision < DPMM_FP64 || p->precision > DPMM_SPLIT_BF16) return fail(DPMM_ERR_ARG, "unknown precision");
+    if (p->flags != 0) return fail(DPMM_ERR_ARG, "flags must be 0");
+    if (p->precision == DPMM_SPLIT_BF16 && !kHaveSplitBf16) return fail(DPMM_ERR_UNSUPPORTED, "split-BF16 path not built");
+    return DPMM_OK;
+}
+
+}  // namespace
+
+struct dpmm_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int64_t N = 0, nnz = 0;
+    int32_t G = 0, k_max = 0, precision = 0;
+    double refine_tol = 0.0;
+    int64_t step = 0;
+    int cur = 0;                       // which label buffer holds the current labels
+    int64_t sweeps = 0, sm_calls = 0;
+    int last_pass = -1;
+    int tables_valid = 0;              // a sweep has drawn parameters since init/set_state
+    Ws ws{};
+    int32_t* c[2] = {nullptr, nullptr};
+    uint8_t* cs[2] = {nullptr, nullptr};
+    int64_t* tiles = nullptr;
+    float* dbg = nullptr;
+    int32_t dbg_cap = 0;
+    bool timing = false;
+    std::vector<hipEvent_t> ev;        // pairs (start, stop)
+    int n_timed = 0;
+};
+
+namespace {
+
+dpmm_status set_device(dpmm_ctx* ctx)
+{
+    HIP_TRY(hipSetDevice(ctx->device));
+    return DPMM_OK;
+}
+
+dpmm_status read_state(dpmm_ctx* ctx, DevState* out)
+{
+    HIP_TRY(hipMemcpyAsync(out, ctx->ws.st, sizeof(DevState), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return DPMM_OK;
+}
+
+// statistics from the current labels, then compaction without touching flags
+dpmm_status recompute_stats(dpmm_ctx* ctx)
+{
+    launch_stats(ctx->ws, ctx->c[ctx->cur], ctx->cs[ctx->cur], ctx->stream);
+    launch_compact(ctx->ws, 0, ctx->stream);
+    launch_relabel(ctx->ws, ctx->c[ctx->cur], ctx->cs[ctx->cur], ctx->stream);
+    HIP_TRY(hipGetLastError());
+    return DPMM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dpmm_last_error(void) { return g_err; }
+
+dpmm_status dpmm_workspace_size(const dpmm_csr* csr, const dpmm_params* params, size_t* bytes)
+{
+    dpmm_status s = check_args(csr, params);
+    if (s != DPMM_OK) return s;
+    if (!bytes) return fail(DPMM_ERR_ARG, "null bytes");
+    *bytes = plan(csr->n_cells, csr->n_genes, csr->nnz, params->k_max).total;
+    return DPMM_OK;
+}
+
+dpmm_status dpmm_init(const dpmm_csr* csr, const dpmm_params* params, void* workspace, size_t workspace_bytes,
+                      void* stream, dpmm_ctx** out)
+{
+    g_err[0] = 0;
+    dpmm_status s = check_args(csr, params);
+    if (s != DPMM_OK) return s;
+    if (!out) return fail(DPMM_ERR_ARG, "null out");
+    *out = nullptr;
+    if (!workspace || ((uintptr_t)workspace & (kAlign - 1))) return fail(DPMM_ERR_ARG, "workspace must be 256-byte aligned");
+    if (!csr->row_ptr || (csr->nnz > 0 && (!csr->col || !csr->val))) return fail(DPMM_ERR_ARG, "null CSR array");
+    const Layout L = plan(csr->n_cells, csr->n_genes, csr->nnz, params->k_max);
+    if (workspace_bytes < L.total)
+        return fail(DPMM_ERR_NOMEM, "workspace of %zu bytes, %zu needed", workspace_bytes, L.total);
+
+    dpmm_ctx* ctx = new (std::nothrow) dpmm_ctx();
+    if (!ctx) return fail(DPMM_ERR_NOMEM, "host allocation failed");
+    hipError_t he = hipGetDevice(&ctx->device);
+    if (he != hipSuccess) { delete ctx; return fail(DPMM_ERR_HIP, "hipGetDevice: %s", hipGetErrorString(he)); }
+    ctx->stream = (hipStream_t)stream;
+    ctx->N = csr->n_cells;
+    ctx->nnz = csr->nnz;
+    ctx->G = csr->n_genes;
+    ctx->k_max = params->k_max;
+    ctx->precision = params->precision;
+    ctx->refine_tol = params->refine_tol < 0.0 ? 0.0 : params->refine_tol;
+
+    char* base = (char*)workspace;
+    Ws& ws = ctx->ws;
+    ws.N = csr->n_cells;
+    ws.G = csr->n_genes;
+    ws.k_max = params->k_max;
+    ws.kpad = (params->k_max + 15) / 16 * 16;
+    ws.Gpad = (csr->n_genes + kMfmaGeneTile - 1) / kMfmaGeneTile * kMfmaGeneTile;
+    ws.alpha = params->alpha;
+    ws.seed = params->seed;
+    ws.ent = (const uint32_t*)(base + L.ent);
+    ws.roff = (const int64_t*)(base + L.roff);
+    ws.st = (DevState*)(base + L.st);
+    ws.reset = (uint8_t*)(base + L.reset);
+    ws.nsub = (unsigned long long*)(base + L.nsub);
+    ws.ssub = (unsigned long long*)(base + L.ssub);
+    ws.beta = (double*)(base + L.beta);
+    ws.logpi = (double*)(base + L.logpi);
+    ws.lt64 = (double*)(base + L.lt64);
+    ws.lc32 = (float*)(base + L.lc32);
+    ws.ls32 = (float2*)(base + L.ls32);
+    ws.lhi = (uint16_t*)(base + L.lhi);
+    ws.llo = (uint16_t*)(base + L.llo);
+    ws.refine = (uint32_t*)(base + L.refine);
+    ws.relab_c = (int32_t*)(base + L.relab_c);
+    ws.relab_s = (uint8_t*)(base + L.relab_s);
+    ws.sm_logr = (double*)(base + L.sm_logr);
+    ws.sm_acc = (uint8_t*)(base + L.sm_acc);
+    ws.mkey = (unsigned long long*)(base + L.mkey);
+    ws.mlist = (int32_t*)(base + L.mlist);
+    ws.dm_k = (double*)(base + L.dm_k);
+    ws.eb_tmp = (double*)(base + L.eb_tmp);
+    ctx->c[0] = (int32_t*)(base + L.c0);
+    ctx->c[1] = (int32_t*)(base + L.c1);
+    ctx->cs[0] = (uint8_t*)(base + L.cs0);
+    ctx->cs[1] = (uint8_t*)(base + L.cs1);
+    ctx->tiles = (int64_t*)(base + L.tiles);
+
+    auto cleanup = [&](dpmm_status st) { delete ctx; return st; };
+    he = hipMemsetAsync(ws.st, 0, sizeof(DevState), ctx->stream);
+    if (he == hipSuccess) he = hipMemsetAsync(ws.lc32, 0, L.ls32 - L.lc32, ctx->stream);
+    if (he == hipSuccess) he = hipMemsetAsync(ws.lhi, 0, L.refine - L.lhi, ctx->stream);
+    if (he != hipSuccess) return cleanup(fail(DPMM_ERR_HIP, "hipMemsetAsync: %s", hipGetErrorString(he)));
+    launch_pack(csr->row_ptr, csr->col, csr->val, csr->n_cells, csr->n_genes, csr->nnz, (int64_t*)ws.roff,
+                ctx->tiles, (uint32_t*)ws.ent, ws.st, ctx->stream);
+    if (params->beta_per_gene)
+        he = hipMemcpyAsync(ws.beta, params->beta_per_gene, 8 * (size_t)ws.G, hipMemcpyDeviceToDevice, ctx->stream);
+    else
+        launch_fill(ws.beta, ws.G, params->beta, ctx->stream);
+    if (he != hipSuccess) return cleanup(fail(DPMM_ERR_HIP, "beta copy: %s", hipGetErrorString(he)));
+    launch_init_labels(ws, params->k_init, ctx->c[0], ctx->cs[0], ctx->stream);
+    he = hipGetLastError();
+    if (he != hipSuccess) return cleanup(fail(DPMM_ERR_HIP, "init launch: %s", hipGetErrorString(he)));
+    DevState dst;
+    he = hipMemcpyAsync(&dst, ws.st, sizeof(DevState), hipMemcpyDeviceToHost, ctx->stream);
+    if (he == hipSuccess) he = hipStreamSynchronize(ctx->stream);
+    if (he != hipSuccess) return cleanup(fail(DPMM_ERR_HIP, "init sync: %s", hipGetErrorString(he)));
+    if (dst.data_error) return cleanup(fail(DPMM_ERR_DATA, "CSR validation failed on %d rows", dst.data_error));
+    // the input's row_ptr[N] must equal nnz
+    int64_t last = 0;
+    he = hipMemcpy(&last, csr->row_ptr + csr->n_cells, sizeof(int64_t), hipMemcpyDeviceToHost);
+    if (he != hipSuccess) return cleanup(fail(DPMM_ERR_HIP, "row_ptr read: %s", hipGetErrorString(he)));
+    if (last != csr->nnz) return cleanup(fail(DPMM_ERR_DATA, "row_ptr[N] = %lld differs from nnz = %lld",
+                                              (long long)last, (long long)csr->nnz));
+    s = recompute_stats(ctx);
+    if (s != DPMM_OK) return cleanup(s);
+    he = hipStreamSynchronize(ctx->stream);
+    if (he != hipSuccess) return cleanup(fail(DPMM_ERR_HIP, "init stats: %s", hipGetErrorString(he)));
+    *out = ctx;
+    return DPMM_OK;
+}
+
+dpmm_status dpmm_destroy(dpmm_ctx* ctx)
+{
+    if (!ctx) return fail(DPMM_ERR_ARG, "null ctx");
+    hipSetDevice(ctx->device);
+    hipStreamSynchronize(ctx->stream);
+    for (hipEvent_t e : ctx->ev) hipEventDestroy(e);
+    delete ctx;
+    return DPMM_OK;
+}
+
+dpmm_status dpmm_sweep(dpmm_ctx* ctx, int32_t n_sweeps)
+{
+    if (!ctx) return fail(DPMM_ERR_ARG, "null ctx");
+    if (n_sweeps < 0) return fail(DPMM_ERR_ARG, "n_sweeps must be >= 0");
+    dpmm_status s = set_device(ctx);
+    if (s != DPMM_OK) return s;
+    const Ws& ws = ctx->ws;
+    for (int32_t n = 0; n < n_sweeps; ++n) {
+        const int nxt = 1 - ctx->cur;
+        const uint32_t step = (uint32_t)ctx->step;
+        launch_redraw(ws, step, ctx->precision == DPMM_SPLIT_BF16, ctx->stream);
+        HIP_TRY(hipMemsetAsync(&ws.st->n_refine, 0, sizeof(int32_t), ctx->stream));
+        AssignArgs a{};
+        a.c_old = ctx->c[ctx->cur];
+        a.cs_old = ctx->cs[ctx->cur];
+        a.c_new = ctx->c[nxt];
+        a.cs_new = ctx->cs[nxt];
+        a.step = step;
+        a.dbg = ctx->dbg;
+        a.dbg_stride = ctx->dbg_cap + 2;
+        a.refine = ctx->precision != DPMM_FP64;
+        a.refine_tol = (float)ctx->refine_tol;
+        const bool timed = ctx->timing && ctx->n_timed < kMaxTimed;
+        if (timed) HIP_TRY(hipEventRecord(ctx->ev[2 * ctx->n_timed], ctx->stream));
+        if (ctx->precision == DPMM_FP64) launch_assign_fp64(ws, a, ctx->stream);
+        else if (ctx->precision == DPMM_FP32) launch_assign_fp32(ws, a, ctx->stream);
+        else launch_assign_bf16(ws, a, ctx->stream);
+        if (timed) {
+            HIP_TRY(hipEventRecord(ctx->ev[2 * ctx->n_timed + 1], ctx->stream));
+            ctx->n_timed++;
+        }
+        if (a.refine) launch_refine(ws, a, ctx->stream);
+        launch_stats(ws, ctx->c[nxt], ctx->cs[nxt], ctx->stream);
+        launch_compact(ws, 1, ctx->stream);
+        launch_relabel(ws, ctx->c[nxt], ctx->cs[nxt], ctx->stream);
+        HIP_TRY(hipGetLastError());
+        ctx->cur = nxt;
+        ctx->step += 1;
+        ctx->sweeps += 1;
+        ctx->tables_valid = 1;
+    }
+    return DPMM_OK;
+}
+
+dpmm_status dpmm_split_merge(dpmm_ctx* ctx)
+{
+    if (!ctx) return fail(DPMM_ERR_ARG, "null ctx");
+    dpmm_status s = set_device(ctx);
+    if (s != DPMM_OK) return s;
+    const uint32_t step = (uint32_t)ctx->step;
+    // the chain coin depends only on (seed, step): drawn here, without a sync
+    const Words w = philox(ctx->ws.seed, 0u, 0u, step, kChain, 0u);
+    const int merge_pass = unit52(w.w[0], w.w[1]) < 0.5 ? 0 : 1;
+    if (merge_pass) launch_merge_ratios(ctx->ws, ctx->stream);
+    else launch_split_ratios(ctx->ws, ctx->stream);
+    launch_sm_decide(ctx->ws, merge_pass, step, ctx->stream);
+    launch_relabel(ctx->ws, ctx->c[ctx->cur], ctx->cs[ctx->cur], ctx->stream);
+    HIP_TRY(hipGetLastError());
+    ctx->last_pass = merge_pass;
+    ctx->step += 1;
+    ctx->sm_calls += 1;
+    return DPMM_OK;
+}
+
+dpmm_status dpmm_eb_update(dpmm_ctx* ctx)
+{
+    if (!ctx) return fail(DPMM_ERR_ARG, "null ctx");
+    dpmm_status s = set_device(ctx);
+    if (s != DPMM_OK) return s;
+    launch_eb_update(ctx->ws, ctx->stream);
+    HIP_TRY(hipGetLastError());
+    return DPMM_OK;
+}
+
+dpmm_status dpmm_stats(dpmm_ctx* ctx, dpmm_stats_out* out, int64_t* nsub_host, int64_t* ssub_dev)
+{
+    if (!ctx || !out) return fail(DPMM_ERR_ARG, "null argument");
+    dpmm_status s = set_device(ctx);
+    if (s != DPMM_OK) return s;
+    DevState d;
+    s = read_state(ctx, &d);
+    if (s != DPMM_OK) return s;
+    memset(out, 0, sizeof(*out));
+    out->step = ctx->step;
+    out->K = d.K;
+    out->last_pass = ctx->last_pass;
+    out->sweeps = ctx->sweeps;
+    out->sm_calls = ctx->sm_calls;
+    out->splits_proposed = (int64_t)d.counters[kCntSplitsProposed];
+    out->splits_accepted = (int64_t)d.counters[kCntSplitsAccepted];
+    out->merges_proposed = (int64_t)d.counters[kCntMergesProposed];
+    out->merges_accepted = (int64_t)d.counters[kCntMergesAccepted];
+    out->kmax_skips = (int64_t)d.counters[kCntKmaxSkips];
+    out->refined = (int64_t)d.counters[kCntRefined];
+    out->gamma_caps = (int64_t)d.counters[kCntGammaCaps];
+    out->evals = (int64_t)d.counters[kCntEvals];
+    if (nsub_host)
+        HIP_TRY(hipMemcpy(nsub_host, ctx->ws.nsub, 16 * (size_t)d.K, hipMemcpyDeviceToHost));
+    if (ssub_dev)
+        HIP_TRY(hipMemcpyAsync(ssub_dev, ctx->ws.ssub, 16 * (size_t)d.K * (size_t)ctx->G, hipMemcpyDeviceToDevice,
+                               ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return DPMM_OK;
+}
+
+dpmm_status dpmm_get_labels(dpmm_ctx* ctx, int32_t* c_dev, uint8_t* cs_dev)
+{
+    if (!ctx || !c_dev || !cs_dev) return fail(DPMM_ERR_ARG, "null argument");
+    dpmm_status s = set_device(ctx);
+    if (s != DPMM_OK) return s;
+    HIP_TRY(hipMemcpyAsync(c_dev, ctx->c[ctx->cur], 4 * (size_t)ctx->N, hipMemcpyDeviceToDevice, ctx->stream));
+    HIP_TRY(hipMemcpyAsync(cs_dev, ctx->cs[ctx->cur], (size_t)ctx->N, hipMemcpyDeviceToDevice, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return DPMM_OK;
+}
+
+dpmm_status dpmm_set_state(dpmm_ctx* ctx, int64_t step, int32_t K, const int32_t* c_dev, const uint8_t* cs_dev,
+                           const uint8_t* reset_host)
+{
+    if (!ctx || !c_dev || !cs_dev || !reset_host) return fail(DPMM_ERR_ARG, "null argument");
+    if (K < 1 || K > ctx->k_max) return fail(DPMM_ERR_ARG, "K must be in [1, k_max]");
+    if (step < 0 || step > 0xFFFFFFFFll) return fail(DPMM_ERR_ARG, "step must be in [0, 2^32)");
+    dpmm_status s = set_device(ctx);
+    if (s != DPMM_OK) return s;
+    const Ws& ws = ctx->ws;
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    HIP_TRY(hipMemcpyAsync(ctx->c[0], c_dev, 4 * (size_t)ctx->N, hipMemcpyDeviceToDevice, ctx->stream));
+    HIP_TRY(hipMemcpyAsync(ctx->cs[0], cs_dev, (size_t)ctx->N, hipMemcpyDeviceToDevice, ctx->stream));
+    std::vector<uint8_t> flags((size_t)ctx->k_max, 0);
+    for (int k = 0; k < K; ++k) flags[k] = reset_host[k] ? 1 : 0;
+    HIP_TRY(hipMemcpyAsync(ws.reset, flags.data(), (size_t)ctx->k_max, hipMemcpyHostToDevice, ctx->stream));
+    DevState d;
+    memset(&d, 0, sizeof(d));
+    d.K = K;
+    HIP_TRY(hipMemcpyAsync(ws.st, &d, sizeof(d), hipMemcpyHostToDevice, ctx->stream));
+    ctx->cur = 0;
+    launch_check_labels(ws, ctx->c[0], ctx->cs[0], K, ctx->stream);
+    DevState chk;
+    s = read_state(ctx, &chk);
+    if (s != DPMM_OK) return s;
+    if (chk.data_error) {
+        HIP_TRY(hipMemsetAsync(&ws.st->data_error, 0, sizeof(int32_t), ctx->stream));
+        return fail(DPMM_ERR_ARG, "%d labels out of range", chk.data_error);
+    }
+    s = recompute_stats(ctx);
+    if (s != DPMM_OK) return s;
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    ctx->step = step;
+    ctx->sweeps = ctx->sm_calls = 0;
+    ctx->last_pass = -1;
+    return DPMM_OK;
+}
+
+dpmm_status dpmm_get_reset_flags(dpmm_ctx* ctx, uint8_t* reset_host)
+{
+    if (!ctx || !reset_host) return fail(DPMM_ERR_ARG, "null argument");
+    dpmm_status s = set_device(ctx);
+    if (s != DPMM_OK) return s;
+    DevState d;
+    s = read_state(ctx, &d);
+    if (s != DPMM_OK) return s;
+    HIP_TRY(hipMemcpy(reset_host, ctx->ws.reset, (size_t)d.K, hipMemcpyDeviceToHost));
+    return DPMM_OK;
+}
+
+dpmm_status dpmm_get_params(dpmm_ctx* ctx, double* logpi_dev, double* logtheta_dev)
+{
+    if (!ctx) return fail(DPMM_ERR_ARG, "null ctx");
+    dpmm_status s = set_device(ctx);
+    if (s != DPMM_OK) return s;
+    if (logpi_dev)
+        HIP_TRY(hipMemcpyAsync(logpi_dev, ctx->ws.logpi, 8 * (size_t)ctx->k_max, hipMemcpyDeviceToDevice, ctx->stream));
+    if (logtheta_dev)
+        HIP_TRY(hipMemcpyAsync(logtheta_dev, ctx->ws.lt64, 24 * (size_t)ctx->k_max * (size_t)ctx->G,
+                               hipMemcpyDeviceToDevice, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return DPMM_OK;
+}
+
+dpmm_status dpmm_get_beta(dpmm_ctx* ctx, double* beta_dev)
+{
+    if (!ctx || !beta_dev) return fail(DPMM_ERR_ARG, "null argument");
+    dpmm_status s = set_device(ctx);
+    if (s != DPMM_OK) return s;
+    HIP_TRY(hipMemcpyAsync(beta_dev, ctx->ws.beta, 8 * (size_t)ctx->G, hipMemcpyDeviceToDevice, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return DPMM_OK;
+}
+
+dpmm_status dpmm_set_beta(dpmm_ctx* ctx, const double* beta_dev)
+{
+    if (!ctx || !beta_dev) return fail(DPMM_ERR_ARG, "null argument");
+    dpmm_status s = set_device(ctx);
+    if (s != DPMM_OK) return s;
+    HIP_TRY(hipMemcpyAsync(ctx->ws.beta, beta_dev, 8 * (size_t)ctx->G, hipMemcpyDeviceToDevice, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return DPMM_OK;
+}
+
+dpmm_status dpmm_get_hastings(dpmm_ctx* ctx, int32_t* pass, int32_t* n, double* logr_host, uint8_t* accept_host)
+{
+    if (!ctx || !pass || !n) return fail(DPMM_ERR_ARG, "null argument");
+    dpmm_status s = set_device(ctx);
+    if (s != DPMM_OK) return s;
+    DevState d;
+    s = read_state(ctx, &d);
+    if (s != DPMM_OK) return s;
+    *pass = ctx->last_pass;
+    *n = ctx->last_pass < 0 ? 0 : d.sm_n;
+    if (*n > 0 && logr_host) HIP_TRY(hipMemcpy(logr_host, ctx->ws.sm_logr, 8 * (size_t)*n, hipMemcpyDeviceToHost));
+    if (*n > 0 && accept_host) HIP_TRY(hipMemcpy(accept_host, ctx->ws.sm_acc, (size_t)*n, hipMemcpyDeviceToHost));
+    return DPMM_OK;
+}
+
+dpmm_status dpmm_set_debug_scores(dpmm_ctx* ctx, float* scores_dev, int32_t k_cap)
+{
+    if (!ctx) return fail(DPMM_ERR_ARG, "null ctx");
+    if (scores_dev && (k_cap < 1 || k_cap > ctx->k_max)) return fail(DPMM_ERR_ARG, "k_cap must be in [1, k_max]");
+    dpmm_status s = set_device(ctx);
+    if (s != DPMM_OK) return s;
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    ctx->dbg = scores_dev;
+    ctx->dbg_cap = scores_dev ? k_cap : 0;
+    return DPMM_OK;
+}
+
+dpmm_status dpmm_get_split_tables(dpmm_ctx* ctx, uint16_t* hi_dev, uint16_t* lo_dev)
+{
+    if (!ctx || !hi_dev || !lo_dev) return fail(DPMM_ERR_ARG, "null argument");
+    if (ctx->precision != DPMM_SPLIT_BF16) return fail(DPMM_ERR_STATE, "context is not split-BF16");
+    dpmm_status s = set_device(ctx);
+    if (s != DPMM_OK) return s;
+    DevState d;
+    s = read_state(ctx, &d);
+    if (s != DPMM_OK) return s;
+    // gene-major [Gpad][kpad] -> cluster-major K x G
+    const size_t pitch = 2 * (size_t)ctx->ws.kpad;
+    for (int k = 0; k < d.K; ++k) {
+        HIP_TRY(hipMemcpy2DAsync(hi_dev + (size_t)k * ctx->G, 2, ctx->ws.lhi + k, pitch, 2, (size_t)ctx->G,
+                                 hipMemcpyDeviceToDevice, ctx->stream));
+        HIP_TRY(hipMemcpy2DAsync(lo_dev + (size_t)k * ctx->G, 2, ctx->ws.llo + k, pitch, 2, (size_t)ctx->G,
+                                 hipMemcpyDeviceToDevice, ctx->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return DPMM_OK;
+}
+
+dpmm_status dpmm_timing_enable(dpmm_ctx* ctx, int32_t enable)
+{
+    if (!ctx) return fail(DPMM_ERR_ARG, "null ctx");
+    dpmm_status s = set_device(ctx);
+    if (s != DPMM_OK) return s;
+    if (enable && ctx->ev.empty()) {
+        ctx->ev.resize(2 * kMaxTimed);
+        for (auto& e : ctx->ev) HIP_TRY(hipEventCreate(&e));
+    }
+    ctx->timing = enable != 0;
+    return DPMM_OK;
+}
+
+dpmm_status dpmm_timing_read(dpmm_ctx* ctx, double* total_ms, int64_t* launches)
+{
+    if (!ctx || !total_ms || !launches) return fail(DPMM_ERR_ARG, "null argument");
+    dpmm_status s = set_device(ctx);
+    if (s != DPMM_OK) return s;
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    double tot = 0.0;
+    for (int q = 0; q < ctx->n_timed; ++q) {
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, ctx->ev[2 * q], ctx->ev[2 * q + 1]));
+        tot += ms;
+    }
+    *total_ms = tot;
+    *launches = ctx->n_timed;
+    ctx->n_timed = 0;
+    return DPMM_OK;
+}
+
+dpmm_status dpmm_dm_logmarginal(const int64_t* sv, int32_t J, int32_t G, const double* beta, double* out, void* stream)
+{
+    if (J < 0 || G < 1) return fail(DPMM_ERR_ARG, "J must be >= 0 and G >= 1");
+    if (J == 0) return DPMM_OK;
+    if (!sv || !beta || !out) return fail(DPMM_ERR_ARG, "null argument");
+    launch_dm_logmarginal(sv, J, G, beta, out, (hipStream_t)stream);
+    HIP_TRY(hipGetLastError());
+    return DPMM_OK;
+}
+
+dpmm_status dpmm_dm_grad(const int64_t* sv, int32_t J, int32_t G, const double* beta, const double* g,
+                         double* grad_beta, void* stream)
+{
+    if (J < 0 || G < 1) return fail(DPMM_ERR_ARG, "J must be >= 0 and G >= 1");
+    if (!beta || !grad_beta || (J > 0 && (!sv || !g))) return fail(DPMM_ERR_ARG, "null argument");
+    launch_dm_grad(sv, J, G, beta, g, grad_beta, (hipStream_t)stream);
+    HIP_TRY(hipGetLastError());
+    return DPMM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,301 @@
+// bookkeeping.hip -- packing of the count matrix, initial labels, the integer
+// sufficient statistics (step a4), compaction of empty clusters and label
+// relabelling.
+#include "dpmm_common.hpp"
+#include "kernels.hpp"
+
+namespace dpmm {
+
+// ---------------------------------------------------------------------------
+// Packing.  Each CSR row becomes a run of 32-bit entries (gene | count << 16)
+// padded to a multiple of four entries so that rows start 16-byte aligned.
+// ---------------------------------------------------------------------------
+
+__global__ void k_padded_lengths(const int64_t* __restrict__ row_ptr, int64_t N, int64_t* __restrict__ out,
+                                 DevState* st)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int64_t len = row_ptr[i + 1] - row_ptr[i];
+    if (len < 0 || (i == 0 && row_ptr[0] != 0)) atomicAdd(&st->data_error, 1);
+    out[i] = len < 0 ? 0 : ((len + 3) & ~(int64_t)3);
+}
+
+// Exclusive scan of v[0..n) in place, v[n] = total.  Three phases over
+// tiles of kScanTile elements.
+constexpr int kScanThreads = 256;
+constexpr int kScanPerThread = 16;
+constexpr int kScanTile = kScanThreads * kScanPerThread;
+
+__device__ inline int64_t block_exclusive_scan(int64_t v, int64_t* lds, int64_t* total)
+{
+    const int t = threadIdx.x;
+    lds[t] = v;
+    __syncthreads();
+    for (int off = 1; off < kScanThreads; off <<= 1) {
+        const int64_t add = t >= off ? lds[t - off] : 0;
+        __syncthreads();
+        lds[t] += add;
+        __syncthreads();
+    }
+    const int64_t incl = lds[t];
+    *total = lds[kScanThreads - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ void k_scan_tiles(int64_t* __restrict__ v, int64_t n, int64_t* __restrict__ tile_sums)
+{
+    __shared__ int64_t lds[kScanThreads];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPerThread;
+    int64_t loc[kScanPerThread];
+    int64_t s = 0;
+#pragma unroll
+    for (int j = 0; j < kScanPerThread; ++j) {
+        const int64_t idx = base + j;
+        loc[j] = idx < n ? v[idx] : 0;
+        s += loc[j];
+    }
+    int64_t total;
+    int64_t run = block_exclusive_scan(s, lds, &total);
+#pragma unroll
+    for (int j = 0; j < kScanPerThread; ++j) {
+        const int64_t idx = base + j;
+        if (idx < n) v[idx] = run;
+        run += loc[j];
+    }
+    if (threadIdx.x == 0) tile_sums[blockIdx.x] = total;
+}
+
+__global__ void k_scan_tile_sums(int64_t* __restrict__ tile_sums, int64_t ntiles)
+{
+    __shared__ int64_t lds[kScanThreads];
+    int64_t carry = 0;
+    for (int64_t b = 0; b < ntiles; b += kScanThreads) {
+        const int64_t idx = b + threadIdx.x;
+        const int64_t v = idx < ntiles ? tile_sums[idx] : 0;
+        int64_t total;
+        const int64_t ex = block_exclusive_scan(v, lds, &total);
+        if (idx < ntiles) tile_sums[idx] = carry + ex;
+        carry += total;
+    }
+    if (threadIdx.x == 0) tile_sums[ntiles] = carry;
+}
+
+__global__ void k_scan_add(int64_t* __restrict__ v, int64_t n, const int64_t* __restrict__ tile_sums,
+                           int64_t ntiles)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) v[i] += tile_sums[i / kScanTile];
+    if (i == 0) v[n] = tile_sums[ntiles];
+}
+
+void launch_exclusive_scan(int64_t* v, int64_t n, int64_t* tile_sums, hipStream_t s)
+{
+    const int64_t ntiles = (n + kScanTile - 1) / kScanTile;
+    if (ntiles > 0) hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)ntiles), dim3(kScanThreads), 0, s, v, n, tile_sums);
+    hipLaunchKernelGGL(k_scan_tile_sums, dim3(1), dim3(kScanThreads), 0, s, tile_sums, ntiles);
+    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)((n + 256) / 256)), dim3(256), 0, s, v, n, tile_sums, ntiles);
+}
+
+// One wavefront per row: validate (columns strictly increasing and < G,
+// counts in [1, 65535]) and write the packed, padded row.
+__global__ void k_pack_rows(const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                            const int32_t* __restrict__ val, int64_t N, int32_t G, int64_t nnz,
+                            const int64_t* __restrict__ roff, uint32_t* __restrict__ ent, DevState* st)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (row >= N) return;
+    const int64_t b = row_ptr[row], e = row_ptr[row + 1];
+    const int64_t o = roff[row], pe = roff[row + 1];
+    int bad = 0;
+    if (b < 0 || e > nnz || e < b) bad = 1;
+    for (int64_t j = lane; j < pe - o; j += 64) {
+        uint32_t packed = kPadEntry;
+        if (!bad && j < e - b) {
+            const int32_t g = col[b + j];
+            const int32_t x = val[b + j];
+            if (g < 0 || g >= G || x < 1 || x > 65535) bad = 1;
+            if (j > 0 && col[b + j - 1] >= g) bad = 1;
+            packed = (uint32_t)(g & 0xFFFF) | ((uint32_t)(x & 0xFFFF) << 16);
+        }
+        ent[o + j] = packed;
+    }
+    if (bad) atomicAdd(&st->data_error, 1);
+}
+
+void launch_pack(const int64_t* row_ptr, const int32_t* col, const int32_t* val, int64_t N, int32_t G, int64_t nnz,
+                 int64_t* roff, int64_t* tile_sums, uint32_t* ent, DevState* st, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_padded_lengths, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, row_ptr, N, roff, st);
+    launch_exclusive_scan(roff, N, tile_sums, s);
+    hipLaunchKernelGGL(k_pack_rows, dim3((unsigned)((N + 3) / 4)), dim3(256), 0, s, row_ptr, col, val, N, G, nnz,
+                       roff, ent, st);
+}
+
+// ---------------------------------------------------------------------------
+// Initial labels: one cluster, or k_init clusters drawn uniformly.
+// ---------------------------------------------------------------------------
+__global__ void k_init_labels(Ws ws, int32_t k_init, int32_t* __restrict__ c, uint8_t* __restrict__ cs)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < ws.N) {
+        int32_t k = 0;
+        if (k_init > 1) {
+            const Words w = philox(ws.seed, (uint32_t)i, 0u, 0u, kInit, 0u);
+            k = (int32_t)(((uint64_t)w.w[0] * (uint64_t)k_init) >> 32);
+        }
+        c[i] = k;
+        cs[i] = 0;
+    }
+    if (i < ws.k_max) ws.reset[i] = i < (k_init < 1 ? 1 : k_init) ? 1 : 0;
+    if (i == 0) ws.st->K = k_init < 1 ? 1 : k_init;
+}
+
+void launch_init_labels(const Ws& ws, int32_t k_init, int32_t* c, uint8_t* cs, hipStream_t s)
+{
+    const int64_t n = ws.N > ws.k_max ? ws.N : ws.k_max;
+    hipLaunchKernelGGL(k_init_labels, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, ws, k_init, c, cs);
+}
+
+// ---------------------------------------------------------------------------
+// Step a4: integer statistics n_{k,r} and s_{k,r,u}.  One wavefront per cell,
+// 64-bit atomics into the (zeroed) tables; integer sums are exact, so the
+// result does not depend on the order of the additions.
+// ---------------------------------------------------------------------------
+__global__ void k_stats(Ws ws, const int32_t* __restrict__ c, const uint8_t* __restrict__ cs)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    const int K = ws.st->K;
+    for (int64_t i = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); i < ws.N; i += waves) {
+        const int32_t k = c[i];
+        if (k < 0 || k >= K) continue;   // labels are always in range; guards the tables
+        const int64_t grp = 2 * (int64_t)k + (cs[i] & 1);
+        if (lane == 0) atomicAdd(&ws.nsub[grp], 1ull);
+        unsigned long long* row = ws.ssub + grp * ws.G;
+        const int64_t b = ws.roff[i], e = ws.roff[i + 1];
+        for (int64_t j = b + lane; j < e; j += 64) {
+            const uint32_t en = ws.ent[j];
+            const uint32_t x = en >> 16;
+            if (x) atomicAdd(&row[en & 0xFFFF], (unsigned long long)x);
+        }
+    }
+}
+
+void launch_stats(const Ws& ws, const int32_t* c, const uint8_t* cs, hipStream_t s)
+{
+    hipMemsetAsync(ws.nsub, 0, sizeof(unsigned long long) * 2 * (size_t)ws.k_max, s);
+    hipMemsetAsync(ws.ssub, 0, sizeof(unsigned long long) * 2 * (size_t)ws.k_max * (size_t)ws.G, s);
+    int64_t blocks = (ws.N + 3) / 4;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_stats, dim3((unsigned)blocks), dim3(256), 0, s, ws, c, cs);
+}
+
+// ---------------------------------------------------------------------------
+// Compaction: drop clusters with no cells, keep the order of the others, and
+// move statistics and reset flags with them (one workgroup).  After a sweep
+// the consumed reset flags are cleared and a cluster of >= 2 cells with an
+// empty sub-cluster is flagged; after a split/merge the flags move along.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(1024) k_compact(Ws ws, int after_sweep)
+{
+    extern __shared__ int32_t lds_map[];      // [k_max]
+    __shared__ int32_t s_nk, s_changed;
+    const int K = ws.st->K;
+    const int t = threadIdx.x;
+    if (t == 0) {
+        int nk = 0, changed = 0;
+        for (int k = 0; k < K; ++k) {
+            const unsigned long long n = ws.nsub[2 * k] + ws.nsub[2 * k + 1];
+            lds_map[k] = n > 0 ? nk++ : -1;
+            if (lds_map[k] != k) changed = 1;
+        }
+        s_nk = nk;
+        s_changed = changed;
+    }
+    __syncthreads();
+    const int nk = s_nk;
+    const int G = ws.G;
+    if (s_changed) {
+        for (int k = 0; k < K; ++k) {
+            const int j = lds_map[k];
+            if (j >= 0 && j != k) {
+                for (int u = t; u < 2 * G; u += blockDim.x)
+                    ws.ssub[(int64_t)2 * j * G + u] = ws.ssub[(int64_t)2 * k * G + u];
+                if (t < 2) ws.nsub[2 * j + t] = ws.nsub[2 * k + t];
+                if (t == 0) ws.reset[j] = ws.reset[k];
+            }
+            __syncthreads();
+        }
+        for (int k = nk; k < K; ++k) {
+            for (int u = t; u < 2 * G; u += blockDim.x) ws.ssub[(int64_t)2 * k * G + u] = 0;
+            if (t < 2) ws.nsub[2 * k + t] = 0;
+            if (t == 0) ws.reset[k] = 0;
+        }
+        __syncthreads();
+    }
+    for (int k = t; k < K; k += blockDim.x) {
+        ws.relab_c[2 * k] = lds_map[k];
+        ws.relab_c[2 * k + 1] = lds_map[k];
+        ws.relab_s[2 * k] = 0xFF;
+        ws.relab_s[2 * k + 1] = 0xFF;
+    }
+    if (after_sweep) {
+        for (int k = t; k < ws.k_max; k += blockDim.x) {
+            uint8_t flag = 0;
+            if (k < nk) {
+                const unsigned long long n0 = ws.nsub[2 * k], n1 = ws.nsub[2 * k + 1];
+                flag = (n0 + n1 >= 2 && (n0 == 0 || n1 == 0)) ? 1 : 0;
+            }
+            ws.reset[k] = flag;
+        }
+    }
+    if (t == 0) {
+        ws.st->K = nk;
+        ws.st->relabel = s_changed;
+    }
+}
+
+void launch_compact(const Ws& ws, int after_sweep, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), sizeof(int32_t) * (size_t)ws.k_max, s, ws, after_sweep);
+}
+
+// Apply relab_c / relab_s to every label when the relabel flag is set.
+__global__ void k_relabel(Ws ws, int32_t* __restrict__ c, uint8_t* __restrict__ cs)
+{
+    if (!ws.st->relabel) return;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ws.N; i += stride) {
+        const int32_t k = c[i];
+        if (k < 0 || k >= ws.k_max) continue;
+        const int q = 2 * k + (cs[i] & 1);
+        c[i] = ws.relab_c[q];
+        const uint8_t r = ws.relab_s[q];
+        if (r != 0xFF) cs[i] = r;
+    }
+}
+
+void launch_relabel(const Ws& ws, int32_t* c, uint8_t* cs, hipStream_t s)
+{
+    int64_t blocks = (ws.N + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_relabel, dim3((unsigned)blocks), dim3(256), 0, s, ws, c, cs);
+}
+
+// Labels written by the caller: count out-of-range values.
+__global__ void k_check_labels(Ws ws, const int32_t* __restrict__ c, const uint8_t* __restrict__ cs, int32_t K)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ws.N) return;
+    if (c[i] < 0 || c[i] >= K || cs[i] > 1) atomicAdd(&ws.st->data_error, 1);
+}
+
+void launch_check_labels(const Ws& ws, const int32_t* c, const uint8_t* cs, int32_t K, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_check_labels, dim3((unsigned)((ws.N + 255) / 256)), dim3(256), 0, s, ws, c, cs, K);
+}
+
+}  // namespace dpmm

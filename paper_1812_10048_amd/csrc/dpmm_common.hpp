@@ -1,0 +1,143 @@
+// dpmm_common.hpp -- definitions shared by the HIP kernels and the host side
+// of libdpmm (gfx950).  Nothing here is shared with the CPU oracle.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dpmm {
+
+// ---------------------------------------------------------------------------
+// Random numbers.  Philox4x32-10 (Salmon et al., SC'11) addressed by
+// (element, sub-index, step, stream, call): every draw of the sampler has a
+// fixed counter, so a chain does not depend on thread scheduling.
+// ---------------------------------------------------------------------------
+enum Stream : uint32_t {
+    kInit = 1,      // initial labels
+    kGamma = 2,     // Gamma variates of theta and thetabar
+    kPi = 3,        // Gamma variates of the mixing proportions
+    kGumbelC = 4,   // Gumbel noise of the cluster choice
+    kGumbelS = 5,   // Gumbel noise of the sub-cluster choice
+    kResub = 6,     // fair coins of a reset cluster's sub-labels
+    kChain = 7,     // split chain or merge chain
+    kSplit = 8,     // split acceptance
+    kMerge = 9      // merge acceptance and visiting order
+};
+
+constexpr uint32_t kSubRowBase = 0x10000u;   // Philox row id of thetabar_{k,r} = base + 2k + r
+constexpr uint32_t kAlphaElement = 0xFFFFFFFFu;
+constexpr int kGammaTries = 64;
+
+struct Words { uint32_t w[4]; };
+
+__host__ __device__ inline uint32_t mul_hi32(uint32_t a, uint32_t b)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __umulhi(a, b);
+#else
+    return (uint32_t)(((uint64_t)a * (uint64_t)b) >> 32);
+#endif
+}
+
+__host__ __device__ inline Words philox(uint64_t seed, uint32_t element, uint32_t sub, uint32_t step,
+                                        uint32_t stream, uint32_t call)
+{
+    uint32_t x0 = element, x1 = sub, x2 = step, x3 = (stream << 24) | (call & 0xFFFFFFu);
+    uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t hi0 = mul_hi32(0xD2511F53u, x0), lo0 = 0xD2511F53u * x0;
+        const uint32_t hi1 = mul_hi32(0xCD9E8D57u, x2), lo1 = 0xCD9E8D57u * x2;
+        x0 = hi1 ^ x1 ^ k0;
+        x1 = lo1;
+        x2 = hi0 ^ x3 ^ k1;
+        x3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    Words o;
+    o.w[0] = x0; o.w[1] = x1; o.w[2] = x2; o.w[3] = x3;
+    return o;
+}
+
+// (w >> 9 + 1/2) 2^-23: an odd multiple of 2^-24, exact in float and double.
+__host__ __device__ inline float unit23f(uint32_t w) { return ((float)(w >> 9) + 0.5f) * 0x1p-23f; }
+__host__ __device__ inline double unit23d(uint32_t w) { return ((double)(w >> 9) + 0.5) * 0x1p-23; }
+// 52 random bits from two words, an odd multiple of 2^-53, exact in double.
+__host__ __device__ inline double unit52(uint32_t hi, uint32_t lo)
+{
+    return ((double)((((uint64_t)hi << 32) | lo) >> 12) + 0.5) * 0x1p-52;
+}
+
+// ---------------------------------------------------------------------------
+// Device-resident scalars of a context (K changes on the device).
+// ---------------------------------------------------------------------------
+enum Counter {
+    kCntGammaCaps = 0,
+    kCntSplitsProposed = 1,
+    kCntSplitsAccepted = 2,
+    kCntMergesProposed = 3,
+    kCntMergesAccepted = 4,
+    kCntKmaxSkips = 5,
+    kCntRefined = 6,
+    kCntEvals = 7,        // sum over sweeps of N (K + 2)
+    kNumCounters = 8
+};
+
+struct DevState {
+    int32_t K;            // current number of clusters
+    int32_t relabel;      // nonzero if the relabel map must be applied to the labels
+    int32_t sm_pass;      // 0 split, 1 merge (last split/merge call)
+    int32_t sm_n;         // candidates of the last split/merge call
+    int32_t n_refine;     // cells queued for FP64 re-scoring in the current sweep
+    int32_t data_error;   // CSR validation failures
+    int32_t pad[2];
+    unsigned long long counters[kNumCounters];
+};
+
+// Packed count entry: gene in the low 16 bits, count in the high 16 bits.
+// Rows are padded to a multiple of 4 entries (16 bytes) with kPadEntry.
+constexpr uint32_t kPadEntry = 0x0000FFFFu;   // gene 0xFFFF, count 0
+
+// Refine-queue flags (high bits of a queued cell index).
+constexpr uint32_t kRefineCluster = 1u << 31;
+constexpr uint32_t kRefineSub = 1u << 30;
+constexpr uint32_t kRefineMask = (1u << 30) - 1;
+
+// ---------------------------------------------------------------------------
+// View of the workspace, passed by value to kernels.
+// ---------------------------------------------------------------------------
+struct Ws {
+    int64_t N;
+    int32_t G;
+    int32_t k_max;
+    int32_t Gpad;          // G rounded up to the split-BF16 gene tile
+    int32_t kpad;          // k_max rounded up to a multiple of 16
+    double alpha;
+    uint64_t seed;
+
+    const uint32_t* ent;   // [nnz_pad] packed entries
+    const int64_t* roff;   // [N + 1] padded row offsets (multiples of 4)
+    DevState* st;
+    uint8_t* reset;        // [k_max]
+    unsigned long long* nsub;   // [2 k_max]
+    unsigned long long* ssub;   // [2 k_max G]   (k, r, u) at (2k + r) G + u
+    double* beta;          // [G]
+    double* logpi;         // [k_max]
+    double* lt64;          // [3 k_max G]: rows k, then k_max + 2k + r
+    float* lc32;           // [G][kpad] cluster log theta, gene-major
+    float2* ls32;          // [G][k_max] sub-cluster log theta pairs, gene-major
+    uint16_t* lhi;         // split-BF16 tables, see assign_mfma.hip
+    uint16_t* llo;
+    uint32_t* refine;      // [N] queued cells with flags
+    int32_t* relab_c;      // [2 k_max] new cluster of an old (k, r)
+    uint8_t* relab_s;      // [2 k_max] new sub-label of an old (k, r); 0xFF keeps it
+    double* sm_logr;       // [k_max + k_max (k_max - 1) / 2]
+    uint8_t* sm_acc;       // same size
+    unsigned long long* mkey;   // same size: random keys of accepted merge pairs
+    int32_t* mlist;        // same size: their pair indices
+    double* dm_k;          // [k_max] logDM of each cluster's statistics
+    double* eb_tmp;        // [k_max + G] scratch of the empirical-Bayes step
+};
+
+}  // namespace dpmm

@@ -1,0 +1,51 @@
+// kernels.hpp -- host-side launchers of the libdpmm kernels (all enqueue on
+// the given stream and return immediately).
+#pragma once
+
+#include "dpmm_common.hpp"
+
+namespace dpmm {
+
+// bookkeeping.hip
+void launch_exclusive_scan(int64_t* v, int64_t n, int64_t* tile_sums, hipStream_t s);
+void launch_pack(const int64_t* row_ptr, const int32_t* col, const int32_t* val, int64_t N, int32_t G, int64_t nnz,
+                 int64_t* roff, int64_t* tile_sums, uint32_t* ent, DevState* st, hipStream_t s);
+void launch_init_labels(const Ws& ws, int32_t k_init, int32_t* c, uint8_t* cs, hipStream_t s);
+void launch_stats(const Ws& ws, const int32_t* c, const uint8_t* cs, hipStream_t s);
+void launch_compact(const Ws& ws, int after_sweep, hipStream_t s);
+void launch_relabel(const Ws& ws, int32_t* c, uint8_t* cs, hipStream_t s);
+void launch_check_labels(const Ws& ws, const int32_t* c, const uint8_t* cs, int32_t K, hipStream_t s);
+
+// redraw.hip
+void launch_redraw(const Ws& ws, uint32_t step, int write_split, hipStream_t s);
+
+// assign.hip
+struct AssignArgs {
+    const int32_t* c_old;
+    const uint8_t* cs_old;
+    int32_t* c_new;
+    uint8_t* cs_new;
+    uint32_t step;
+    float* dbg;           // optional score dump, row stride dbg_stride
+    int32_t dbg_stride;
+    int32_t refine;       // queue uncertain decisions for the FP64 re-score
+    float refine_tol;     // extra relative-margin threshold (0: bound only)
+};
+void launch_assign_fp32(const Ws& ws, const AssignArgs& a, hipStream_t s);
+void launch_assign_fp64(const Ws& ws, const AssignArgs& a, hipStream_t s);
+void launch_assign_bf16(const Ws& ws, const AssignArgs& a, hipStream_t s);
+void launch_refine(const Ws& ws, const AssignArgs& a, hipStream_t s);
+
+// splitmerge.hip
+void launch_split_ratios(const Ws& ws, hipStream_t s);
+void launch_merge_ratios(const Ws& ws, hipStream_t s);
+void launch_sm_decide(const Ws& ws, int merge_pass, uint32_t step, hipStream_t s);
+
+// dm.hip
+void launch_dm_logmarginal(const int64_t* sv, int32_t J, int32_t G, const double* beta, double* out, hipStream_t s);
+void launch_dm_grad(const int64_t* sv, int32_t J, int32_t G, const double* beta, const double* g, double* grad,
+                    hipStream_t s);
+void launch_eb_update(const Ws& ws, hipStream_t s);
+void launch_fill(double* p, int64_t n, double v, hipStream_t s);
+
+}  // namespace dpmm

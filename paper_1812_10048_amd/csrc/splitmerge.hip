@@ -1,0 +1,432 @@
+// splitmerge.hip -- step a5: split/merge Hastings ratios (Section 2.3 eq. 7)
+// in their collapsed form and the moves they accept.
+//
+// With logDM(s) = lgamma(B) - lgamma(B + S) + sum_u [lgamma(beta_u + s_u) -
+// lgamma(beta_u)] (eq. 12 integrated over theta against the Dirichlet
+// normaliser of eq. 28) and the partition prior of eq. 10 (with Gamma(alpha)),
+//   split of k into its sub-clusters:
+//     log R = log alpha + lgamma(n_0) + lgamma(n_1) - lgamma(n)
+//           + logDM(s_0) + logDM(s_1) - logDM(s_0 + s_1)
+//   merge of k1 < k2 (reverse of a random split, eq. 23):
+//     log R = -[log alpha + lgamma(n_1) + lgamma(n_2) - lgamma(n_1 + n_2)
+//             + logDM(s_1) + logDM(s_2) - logDM(s_1 + s_2)] + (n_1 + n_2 - 2) log 1/2.
+// Each candidate is one workgroup reducing over genes in FP64 with
+// compensated sums; the decisions are taken by a single workgroup.
+#include "dpmm_common.hpp"
+#include "kernels.hpp"
+
+namespace dpmm {
+
+constexpr int kSmThreads = 256;
+
+// Compensated accumulator (Neumaier): value = s + c.
+struct CSum {
+    double s = 0.0, c = 0.0;
+    __device__ inline void add(double v)
+    {
+        const double t = s + v;
+        c += fabs(s) >= fabs(v) ? (s - t) + v : (v - t) + s;
+        s = t;
+    }
+    __device__ inline void merge(const CSum& o)
+    {
+        add(o.s);
+        c += o.c;
+    }
+    __device__ inline double value() const { return s + c; }
+};
+
+// Workgroup reduction of a compensated sum, three int64 sums and a double.
+struct SmRed {
+    CSum cs;
+    long long a, b;
+    double beta;
+};
+
+__device__ inline SmRed block_reduce(SmRed v)
+{
+    __shared__ double ls[kSmThreads], lc[kSmThreads], lb[kSmThreads];
+    __shared__ long long la[kSmThreads], lbb[kSmThreads];
+    const int t = threadIdx.x;
+    ls[t] = v.cs.s; lc[t] = v.cs.c; la[t] = v.a; lbb[t] = v.b; lb[t] = v.beta;
+    __syncthreads();
+    for (int off = kSmThreads / 2; off > 0; off >>= 1) {
+        if (t < off) {
+            CSum x; x.s = ls[t]; x.c = lc[t];
+            CSum y; y.s = ls[t + off]; y.c = lc[t + off];
+            x.merge(y);
+            ls[t] = x.s; lc[t] = x.c;
+            la[t] += la[t + off];
+            lbb[t] += lbb[t + off];
+            lb[t] += lb[t + off];
+        }
+        __syncthreads();
+    }
+    SmRed r;
+    r.cs.s = ls[0]; r.cs.c = lc[0]; r.a = la[0]; r.b = lbb[0]; r.beta = lb[0];
+    __syncthreads();
+    return r;
+}
+
+// lgamma(beta + v) - lgamma(beta), zero for v = 0
+__device__ inline double rising(double beta, long long v)
+{
+    return v ? lgamma(beta + (double)v) - lgamma(beta) : 0.0;
+}
+
+__global__ void __launch_bounds__(kSmThreads) k_split_ratios(Ws ws)
+{
+    const int K = ws.st->K;
+    const int G = ws.G;
+    for (int k = blockIdx.x; k < K; k += gridDim.x) {
+        const unsigned long long n0 = ws.nsub[2 * k], n1 = ws.nsub[2 * k + 1];
+        if (ws.reset[k] || n0 < 1 || n1 < 1) {
+            if (threadIdx.x == 0) ws.sm_logr[k] = __builtin_nan("");
+            continue;
+        }
+        const unsigned long long* s0 = ws.ssub + (int64_t)(2 * k) * G;
+        const unsigned long long* s1 = s0 + G;
+        SmRed r;
+        r.a = r.b = 0;
+        r.beta = 0.0;
+        for (int u = threadIdx.x; u < G; u += kSmThreads) {
+            const double bu = ws.beta[u];
+            const long long a = (long long)s0[u], b = (long long)s1[u];
+            r.beta += bu;
+            r.a += a;
+            r.b += b;
+            if (a + b == 0) continue;
+            r.cs.add(rising(bu, a));
+            r.cs.add(rising(bu, b));
+            r.cs.add(-rising(bu, a + b));
+        }
+        r = block_reduce(r);
+        if (threadIdx.x == 0) {
+            const double B = r.beta;
+            CSum tot = r.cs;
+            const double lB = lgamma(B);
+            tot.add(lB - lgamma(B + (double)r.a));
+            tot.add(lB - lgamma(B + (double)r.b));
+            tot.add(-(lB - lgamma(B + (double)(r.a + r.b))));
+            tot.add(log(ws.alpha) + lgamma((double)n0) + lgamma((double)n1) - lgamma((double)(n0 + n1)));
+            ws.sm_logr[k] = tot.value();
+        }
+    }
+}
+
+// logDM of every cluster's statistics s_k = s_{k,0} + s_{k,1}
+__global__ void __launch_bounds__(kSmThreads) k_cluster_logdm(Ws ws)
+{
+    const int K = ws.st->K;
+    const int G = ws.G;
+    for (int k = blockIdx.x; k < K; k += gridDim.x) {
+        const unsigned long long* s0 = ws.ssub + (int64_t)(2 * k) * G;
+        const unsigned long long* s1 = s0 + G;
+        SmRed r;
+        r.a = r.b = 0;
+        r.beta = 0.0;
+        for (int u = threadIdx.x; u < G; u += kSmThreads) {
+            const double bu = ws.beta[u];
+            const long long v = (long long)(s0[u] + s1[u]);
+            r.beta += bu;
+            r.a += v;
+            r.cs.add(rising(bu, v));
+        }
+        r = block_reduce(r);
+        if (threadIdx.x == 0) {
+            CSum tot = r.cs;
+            tot.add(lgamma(r.beta) - lgamma(r.beta + (double)r.a));
+            ws.dm_k[k] = tot.value();
+        }
+    }
+}
+
+__device__ inline void pair_of(long long p, int* k1, int* k2)
+{
+    int b = (int)((1.0 + sqrt(1.0 + 8.0 * (double)p)) * 0.5);
+    while ((long long)b * (b - 1) / 2 > p) --b;
+    while ((long long)(b + 1) * b / 2 <= p) ++b;
+    *k2 = b;
+    *k1 = (int)(p - (long long)b * (b - 1) / 2);
+}
+
+__global__ void __launch_bounds__(kSmThreads) k_merge_ratios(Ws ws)
+{
+    const int K = ws.st->K;
+    const int G = ws.G;
+    const long long npairs = (long long)K * (K - 1) / 2;
+    for (long long p = blockIdx.x; p < npairs; p += gridDim.x) {
+        int k1, k2;
+        pair_of(p, &k1, &k2);
+        const unsigned long long* a0 = ws.ssub + (int64_t)(2 * k1) * G;
+        const unsigned long long* b0 = ws.ssub + (int64_t)(2 * k2) * G;
+        SmRed r;
+        r.a = r.b = 0;
+        r.beta = 0.0;
+        for (int u = threadIdx.x; u < G; u += kSmThreads) {
+            const double bu = ws.beta[u];
+            const long long v = (long long)(a0[u] + a0[u + G] + b0[u] + b0[u + G]);
+            r.beta += bu;
+            r.a += v;
+            r.cs.add(rising(bu, v));
+        }
+        r = block_reduce(r);
+        if (threadIdx.x == 0) {
+            const double n1 = (double)(ws.nsub[2 * k1] + ws.nsub[2 * k1 + 1]);
+            const double n2 = (double)(ws.nsub[2 * k2] + ws.nsub[2 * k2 + 1]);
+            CSum split;   // log R of splitting the union into k1 and k2
+            split.add(log(ws.alpha) + lgamma(n1) + lgamma(n2) - lgamma(n1 + n2));
+            split.add(ws.dm_k[k1]);
+            split.add(ws.dm_k[k2]);
+            CSum dm12 = r.cs;
+            dm12.add(lgamma(r.beta) - lgamma(r.beta + (double)r.a));
+            split.add(-dm12.s);
+            split.add(-dm12.c);
+            ws.sm_logr[p] = -split.value() + (n1 + n2 - 2.0) * log(0.5);
+        }
+    }
+}
+
+void launch_split_ratios(const Ws& ws, hipStream_t s)
+{
+    const int blocks = ws.k_max < 1024 ? ws.k_max : 1024;
+    hipLaunchKernelGGL(k_split_ratios, dim3(blocks), dim3(kSmThreads), 0, s, ws);
+}
+
+void launch_merge_ratios(const Ws& ws, hipStream_t s)
+{
+    const int blocks = ws.k_max < 1024 ? ws.k_max : 1024;
+    hipLaunchKernelGGL(k_cluster_logdm, dim3(blocks), dim3(kSmThreads), 0, s, ws);
+    const long long np = (long long)ws.k_max * (ws.k_max - 1) / 2;
+    const int mb = np < 4096 ? (int)(np > 0 ? np : 1) : 4096;
+    hipLaunchKernelGGL(k_merge_ratios, dim3(mb), dim3(kSmThreads), 0, s, ws);
+}
+
+// ---------------------------------------------------------------------------
+// Decisions (one workgroup of 1024 threads).
+// ---------------------------------------------------------------------------
+constexpr int kDecideThreads = 1024;
+
+__device__ void move_row_pair(Ws& ws, int from, int to)
+{
+    // statistics and counts of cluster `from` (both sub-clusters) to `to`
+    const int G = ws.G;
+    for (int u = threadIdx.x; u < 2 * G; u += kDecideThreads)
+        ws.ssub[(int64_t)2 * to * G + u] = ws.ssub[(int64_t)2 * from * G + u];
+    if (threadIdx.x < 2) ws.nsub[2 * to + threadIdx.x] = ws.nsub[2 * from + threadIdx.x];
+    if (threadIdx.x == 0) ws.reset[to] = ws.reset[from];
+}
+
+__global__ void __launch_bounds__(kDecideThreads) k_sm_decide(Ws ws, int merge_pass, uint32_t step)
+{
+    extern __shared__ int32_t lds[];          // 3 k_max ints
+    int32_t* newlab = lds;                     // split: new label of sub-cluster 1; merge: target cluster
+    int32_t* cmap = lds + ws.k_max;            // compaction map
+    int32_t* used = lds + 2 * ws.k_max;        // merge: cluster already merged
+    __shared__ unsigned long long rkey[kDecideThreads];
+    __shared__ long long ridx[kDecideThreads];
+    __shared__ int s_count, s_K, s_any;
+    const int t = threadIdx.x;
+    const int K = ws.st->K;
+    const int G = ws.G;
+    for (int k = t; k < ws.k_max; k += kDecideThreads) {
+        newlab[k] = -1;
+        used[k] = 0;
+    }
+    if (t == 0) { s_count = 0; s_any = 0; }
+    __syncthreads();
+
+    if (!merge_pass) {
+        // acceptance tests in parallel, new labels in cluster order
+        for (int k = t; k < K; k += kDecideThreads) {
+            ws.sm_acc[k] = 0;
+            const double lr = ws.sm_logr[k];
+            used[k] = 0;
+            if (isnan(lr)) continue;
+            const Words w = philox(ws.seed, (uint32_t)k, 0u, step, kSplit, 0u);
+            used[k] = log(unit52(w.w[0], w.w[1])) < lr ? 2 : 1;   // 1 proposed, 2 accepted
+        }
+        __syncthreads();
+        if (t == 0) {
+            int knew = K;
+            unsigned long long prop = 0, acc = 0, skip = 0;
+            for (int k = 0; k < K; ++k) {
+                if (used[k] == 0) continue;
+                ++prop;
+                if (used[k] == 2) {
+                    if (knew < ws.k_max) {
+                        newlab[k] = knew++;
+                        ws.sm_acc[k] = 1;
+                        ++acc;
+                    } else {
+                        ++skip;
+                    }
+                }
+            }
+            ws.st->counters[kCntSplitsProposed] += prop;
+            ws.st->counters[kCntSplitsAccepted] += acc;
+            ws.st->counters[kCntKmaxSkips] += skip;
+            s_K = knew;
+            s_any = acc > 0;
+        }
+        __syncthreads();
+        for (int k = 0; k < K; ++k) {
+            const int j = newlab[k];
+            if (j < 0) continue;
+            for (int u = t; u < G; u += kDecideThreads) {
+                ws.ssub[(int64_t)(2 * j) * G + u] = ws.ssub[(int64_t)(2 * k + 1) * G + u];
+                ws.ssub[(int64_t)(2 * j + 1) * G + u] = 0;
+                ws.ssub[(int64_t)(2 * k + 1) * G + u] = 0;
+            }
+            if (t == 0) {
+                ws.nsub[2 * j] = ws.nsub[2 * k + 1];
+                ws.nsub[2 * j + 1] = 0;
+                ws.nsub[2 * k + 1] = 0;
+                ws.reset[k] = 1;
+                ws.reset[j] = 1;
+            }
+            __syncthreads();
+        }
+        for (int k = t; k < K; k += kDecideThreads) {
+            const int j = newlab[k];
+            ws.relab_c[2 * k] = k;
+            ws.relab_c[2 * k + 1] = j >= 0 ? j : k;
+            ws.relab_s[2 * k] = j >= 0 ? 0 : 0xFF;
+            ws.relab_s[2 * k + 1] = j >= 0 ? 0 : 0xFF;
+        }
+        if (t == 0) {
+            ws.st->K = s_K;
+            ws.st->relabel = s_any;
+            ws.st->sm_pass = 0;
+            ws.st->sm_n = K;
+        }
+        return;
+    }
+
+    // merge pass: collect the accepted pairs with their random keys
+    const long long npairs = (long long)K * (K - 1) / 2;
+    for (long long p = t; p < npairs; p += kDecideThreads) {
+        ws.sm_acc[p] = 0;
+        const Words w = philox(ws.seed, (uint32_t)p, 0u, step, kMerge, 0u);
+        if (log(unit52(w.w[0], w.w[1])) < ws.sm_logr[p]) {
+            const int q = atomicAdd(&s_count, 1);
+            ws.mkey[q] = ((unsigned long long)w.w[2] << 32) | w.w[3];
+            ws.mlist[q] = (int32_t)p;
+        }
+    }
+    __syncthreads();
+    const int ncand = s_count;
+    // visit in ascending (key, pair index); a cluster merges at most once
+    unsigned long long merges = 0;
+    for (;;) {
+        unsigned long long bk = ~0ull;
+        long long bp = -1;
+        for (int q = t; q < ncand; q += kDecideThreads) {
+            const long long p = ws.mlist[q];
+            int k1, k2;
+            pair_of(p, &k1, &k2);
+            if (used[k1] || used[k2]) continue;
+            const unsigned long long key = ws.mkey[q];
+            if (bp < 0 || key < bk || (key == bk && p < bp)) { bk = key; bp = p; }
+        }
+        rkey[t] = bk;
+        ridx[t] = bp;
+        __syncthreads();
+        for (int off = kDecideThreads / 2; off > 0; off >>= 1) {
+            if (t < off) {
+                const long long p2 = ridx[t + off];
+                if (p2 >= 0 && (ridx[t] < 0 || rkey[t + off] < rkey[t] ||
+                                (rkey[t + off] == rkey[t] && p2 < ridx[t]))) {
+                    rkey[t] = rkey[t + off];
+                    ridx[t] = p2;
+                }
+            }
+            __syncthreads();
+        }
+        const long long win = ridx[0];
+        __syncthreads();
+        if (win < 0) break;
+        if (t == 0) {
+            int k1, k2;
+            pair_of(win, &k1, &k2);
+            used[k1] = used[k2] = 1;
+            newlab[k1] = k1;
+            newlab[k2] = k1;
+            ws.sm_acc[win] = 1;
+        }
+        ++merges;
+        __syncthreads();
+    }
+    // apply the merges: the union takes k1's label, its sub-clusters are the
+    // two old clusters
+    for (int k2 = 0; k2 < K; ++k2) {
+        const int k1 = newlab[k2];
+        if (k1 < 0 || k1 == k2) continue;
+        for (int u = t; u < G; u += kDecideThreads) {
+            const unsigned long long a = ws.ssub[(int64_t)(2 * k1) * G + u] + ws.ssub[(int64_t)(2 * k1 + 1) * G + u];
+            const unsigned long long b = ws.ssub[(int64_t)(2 * k2) * G + u] + ws.ssub[(int64_t)(2 * k2 + 1) * G + u];
+            ws.ssub[(int64_t)(2 * k1) * G + u] = a;
+            ws.ssub[(int64_t)(2 * k1 + 1) * G + u] = b;
+            ws.ssub[(int64_t)(2 * k2) * G + u] = 0;
+            ws.ssub[(int64_t)(2 * k2 + 1) * G + u] = 0;
+        }
+        if (t == 0) {
+            const unsigned long long na = ws.nsub[2 * k1] + ws.nsub[2 * k1 + 1];
+            const unsigned long long nb = ws.nsub[2 * k2] + ws.nsub[2 * k2 + 1];
+            ws.nsub[2 * k1] = na;
+            ws.nsub[2 * k1 + 1] = nb;
+            ws.nsub[2 * k2] = ws.nsub[2 * k2 + 1] = 0;
+            ws.reset[k1] = 0;
+            ws.reset[k2] = 0;
+        }
+        __syncthreads();
+    }
+    // compaction of the emptied clusters
+    if (t == 0) {
+        int nk = 0;
+        for (int k = 0; k < K; ++k) {
+            const bool gone = newlab[k] >= 0 && newlab[k] != k;
+            cmap[k] = gone ? -1 : nk++;
+        }
+        s_K = nk;
+        ws.st->counters[kCntMergesProposed] += (unsigned long long)npairs;
+        ws.st->counters[kCntMergesAccepted] += merges;
+    }
+    __syncthreads();
+    const int nk = s_K;
+    if (merges) {
+        for (int k = 0; k < K; ++k) {
+            const int j = cmap[k];
+            if (j >= 0 && j != k) move_row_pair(ws, k, j);
+            __syncthreads();
+        }
+        for (int k = nk; k < K; ++k) {
+            for (int u = t; u < 2 * G; u += kDecideThreads) ws.ssub[(int64_t)2 * k * G + u] = 0;
+            if (t < 2) ws.nsub[2 * k + t] = 0;
+            if (t == 0) ws.reset[k] = 0;
+        }
+    }
+    for (int k = t; k < K; k += kDecideThreads) {
+        const int target = newlab[k] >= 0 ? newlab[k] : k;
+        const int lab = cmap[target];
+        const uint8_t sub = newlab[k] >= 0 ? (uint8_t)(newlab[k] == k ? 0 : 1) : 0xFF;
+        ws.relab_c[2 * k] = lab;
+        ws.relab_c[2 * k + 1] = lab;
+        ws.relab_s[2 * k] = sub;
+        ws.relab_s[2 * k + 1] = sub;
+    }
+    if (t == 0) {
+        ws.st->K = nk;
+        ws.st->relabel = merges > 0;
+        ws.st->sm_pass = 1;
+        ws.st->sm_n = (int32_t)npairs;
+    }
+}
+
+void launch_sm_decide(const Ws& ws, int merge_pass, uint32_t step, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sm_decide, dim3(1), dim3(kDecideThreads), sizeof(int32_t) * 3 * (size_t)ws.k_max, s, ws,
+                       merge_pass, step);
+}
+
+}  // namespace dpmm

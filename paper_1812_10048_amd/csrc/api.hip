@@ -42,7 +42,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
 struct Layout {
     size_t ent, roff, tiles, c0, c1, cs0, cs1, st, reset, nsub, ssub, beta, logpi, lt64, lc32, ls32, lhi, llo,
-        refine, relab_c, relab_s, sm_logr, sm_acc, mkey, mlist, dm_k, eb_tmp, total;
+        refine, perm, grp_cnt, grp_off, grp_cur, relab_c, relab_s, sm_logr, sm_acc, mkey, mlist, dm_k, eb_tmp, total;
 };
 
 Layout plan(int64_t N, int32_t G, int64_t nnz, int32_t k_max)
@@ -74,6 +74,10 @@ Layout plan(int64_t N, int32_t G, int64_t nnz, int32_t k_max)
     L.lhi = take(2 * (size_t)Gpad * (size_t)kpad);
     L.llo = take(2 * (size_t)Gpad * (size_t)kpad);
     L.refine = take(4 * (size_t)N);
+    L.perm = take(4 * (size_t)N);
+    L.grp_cnt = take(8 * (size_t)k_max);
+    L.grp_off = take(8 * (size_t)k_max + 4);
+    L.grp_cur = take(8 * (size_t)k_max);
     L.relab_c = take(8 * (size_t)k_max);
     L.relab_s = take(2 * (size_t)k_max);
     L.sm_logr = take(8 * (size_t)ncand);
@@ -216,6 +220,10 @@ dpmm_status dpmm_init(const dpmm_csr* csr, const dpmm_params* params, void* work
     ws.lhi = (uint16_t*)(base + L.lhi);
     ws.llo = (uint16_t*)(base + L.llo);
     ws.refine = (uint32_t*)(base + L.refine);
+    ws.perm = (int32_t*)(base + L.perm);
+    ws.grp_cnt = (int32_t*)(base + L.grp_cnt);
+    ws.grp_off = (int32_t*)(base + L.grp_off);
+    ws.grp_cur = (int32_t*)(base + L.grp_cur);
     ws.relab_c = (int32_t*)(base + L.relab_c);
     ws.relab_s = (uint8_t*)(base + L.relab_s);
     ws.sm_logr = (double*)(base + L.sm_logr);

@@ -160,20 +160,161 @@ void launch_init_labels(const Ws& ws, int32_t k_init, int32_t* c, uint8_t* cs, h
 }
 
 // ---------------------------------------------------------------------------
-// Step a4: integer statistics n_{k,r} and s_{k,r,u}.  One wavefront per cell,
-// 64-bit atomics into the (zeroed) tables; integer sums are exact, so the
-// result does not depend on the order of the additions.
+// Step a4: integer statistics n_{k,r} and s_{k,r,u}.
+//
+// The cells are first counting-sorted by group q = 2k + r (labels c, cbar):
+// per-workgroup LDS histograms, one global reservation per (workgroup,
+// group), then a scatter of cell indices into `perm`.  The group sizes are
+// n_{k,r} themselves.  The statistics kernel then walks `perm` in ranges of
+// kStatCells cells: a range holds one or a few runs of equal group, each
+// accumulated in an LDS histogram over genes and flushed with one 64-bit
+// atomic per non-zero gene.  Integer sums are exact, so the order of the
+// additions (and the order of cells within a group) does not matter.
+// `perm` also serves as the processing order of the next sweep, which keeps
+// the cells of one cluster together.
 // ---------------------------------------------------------------------------
-__global__ void k_stats(Ws ws, const int32_t* __restrict__ c, const uint8_t* __restrict__ cs)
+constexpr int kSortThreads = 1024;
+constexpr int kSortCellsPerBlock = 16384;
+constexpr int kStatThreads = 256;
+constexpr int kStatCells = 2048;
+constexpr int kStatMaxGenes = 16384;
+
+__global__ void __launch_bounds__(kSortThreads) k_group_count(Ws ws, const int32_t* __restrict__ c,
+                                                              const uint8_t* __restrict__ cs)
+{
+    extern __shared__ uint32_t hist[];   // [2 k_max]
+    const int ng = 2 * ws.k_max;
+    for (int q = threadIdx.x; q < ng; q += kSortThreads) hist[q] = 0;
+    __syncthreads();
+    const int64_t b0 = (int64_t)blockIdx.x * kSortCellsPerBlock;
+    const int64_t b1 = min(ws.N, b0 + kSortCellsPerBlock);
+    for (int64_t i = b0 + threadIdx.x; i < b1; i += kSortThreads) {
+        const int32_t k = c[i];
+        if (k >= 0 && k < ws.k_max) atomicAdd(&hist[2 * k + (cs[i] & 1)], 1u);
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < ng; q += kSortThreads)
+        if (hist[q]) atomicAdd(&ws.grp_cnt[q], (int32_t)hist[q]);
+}
+
+// exclusive scan of the group sizes; n_{k,r} = group sizes
+__global__ void __launch_bounds__(kSortThreads) k_group_scan(Ws ws)
+{
+    __shared__ int32_t lds[kSortThreads];
+    const int ng = 2 * ws.k_max;
+    int32_t carry = 0;
+    for (int base = 0; base < ng; base += kSortThreads) {
+        const int q = base + threadIdx.x;
+        const int32_t v = q < ng ? ws.grp_cnt[q] : 0;
+        lds[threadIdx.x] = v;
+        __syncthreads();
+        for (int off = 1; off < kSortThreads; off <<= 1) {
+            const int32_t add = (int)threadIdx.x >= off ? lds[threadIdx.x - off] : 0;
+            __syncthreads();
+            lds[threadIdx.x] += add;
+            __syncthreads();
+        }
+        if (q < ng) {
+            ws.grp_off[q] = carry + lds[threadIdx.x] - v;
+            ws.grp_cur[q] = 0;
+            ws.nsub[q] = (unsigned long long)v;
+        }
+        carry += lds[kSortThreads - 1];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) ws.grp_off[ng] = carry;
+}
+
+__global__ void __launch_bounds__(kSortThreads) k_group_scatter(Ws ws, const int32_t* __restrict__ c,
+                                                                const uint8_t* __restrict__ cs)
+{
+    extern __shared__ uint32_t lds_u[];      // [2 k_max] counts, then [2 k_max] bases
+    const int ng = 2 * ws.k_max;
+    uint32_t* cnt = lds_u;
+    uint32_t* base = lds_u + ng;
+    for (int q = threadIdx.x; q < ng; q += kSortThreads) cnt[q] = 0;
+    __syncthreads();
+    const int64_t b0 = (int64_t)blockIdx.x * kSortCellsPerBlock;
+    const int64_t b1 = min(ws.N, b0 + kSortCellsPerBlock);
+    // pass 1: block-local counts; pass 2: one reservation per group; pass 3: ranks
+    for (int64_t i = b0 + threadIdx.x; i < b1; i += kSortThreads) {
+        const int32_t k = c[i];
+        if (k >= 0 && k < ws.k_max) atomicAdd(&cnt[2 * k + (cs[i] & 1)], 1u);
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < ng; q += kSortThreads) {
+        base[q] = cnt[q] ? (uint32_t)(ws.grp_off[q] + atomicAdd(&ws.grp_cur[q], (int32_t)cnt[q])) : 0u;
+        cnt[q] = 0;
+    }
+    __syncthreads();
+    for (int64_t i = b0 + threadIdx.x; i < b1; i += kSortThreads) {
+        const int32_t k = c[i];
+        if (k < 0 || k >= ws.k_max) continue;
+        const int q = 2 * k + (cs[i] & 1);
+        const uint32_t pos = base[q] + atomicAdd(&cnt[q], 1u);
+        if (pos < (uint32_t)ws.N) ws.perm[pos] = (int32_t)i;
+    }
+}
+
+// group of a sorted position (binary search over the group offsets)
+__device__ inline int group_of(const Ws& ws, int64_t pos, int ng)
+{
+    int lo = 0, hi = ng;   // grp_off[lo] <= pos < grp_off[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (ws.grp_off[mid] <= pos) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(kStatThreads) k_stats_sorted(Ws ws)
+{
+    extern __shared__ uint32_t hist[];       // [G]
+    const int G = ws.G;
+    const int ng = 2 * ws.st->K;
+    const int64_t p0 = (int64_t)blockIdx.x * kStatCells;
+    const int64_t p1 = min(ws.N, p0 + kStatCells);
+    if (p0 >= p1) return;
+    for (int u = threadIdx.x; u < G; u += kStatThreads) hist[u] = 0;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    for (int q = group_of(ws, p0, ng); q < ng && ws.grp_off[q] < p1; ++q) {
+        const int64_t r0 = max(p0, (int64_t)ws.grp_off[q]);
+        const int64_t r1 = min(p1, (int64_t)ws.grp_off[q + 1]);
+        if (r0 >= r1) continue;
+        __syncthreads();
+        for (int64_t p = r0 + wave; p < r1; p += kStatThreads / 64) {
+            const int32_t i = ws.perm[p];
+            const int64_t b = ws.roff[i], e = ws.roff[i + 1];
+            for (int64_t j = b + lane; j < e; j += 64) {
+                const uint32_t en = ws.ent[j];
+                const uint32_t x = en >> 16;
+                if (x) atomicAdd(&hist[en & 0xFFFFu], x);
+            }
+        }
+        __syncthreads();
+        unsigned long long* row = ws.ssub + (int64_t)q * G;
+        for (int u = threadIdx.x; u < G; u += kStatThreads) {
+            const uint32_t v = hist[u];
+            if (v) {
+                atomicAdd(&row[u], (unsigned long long)v);
+                hist[u] = 0;
+            }
+        }
+    }
+}
+
+// Fallback for very wide gene panels: one wavefront per cell, 64-bit atomics.
+__global__ void k_stats_atomic(Ws ws, const int32_t* __restrict__ c, const uint8_t* __restrict__ cs)
 {
     const int lane = threadIdx.x & 63;
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
     const int K = ws.st->K;
     for (int64_t i = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); i < ws.N; i += waves) {
         const int32_t k = c[i];
-        if (k < 0 || k >= K) continue;   // labels are always in range; guards the tables
+        if (k < 0 || k >= K) continue;
         const int64_t grp = 2 * (int64_t)k + (cs[i] & 1);
-        if (lane == 0) atomicAdd(&ws.nsub[grp], 1ull);
         unsigned long long* row = ws.ssub + grp * ws.G;
         const int64_t b = ws.roff[i], e = ws.roff[i + 1];
         for (int64_t j = b + lane; j < e; j += 64) {
@@ -186,11 +327,21 @@ __global__ void k_stats(Ws ws, const int32_t* __restrict__ c, const uint8_t* __r
 
 void launch_stats(const Ws& ws, const int32_t* c, const uint8_t* cs, hipStream_t s)
 {
-    hipMemsetAsync(ws.nsub, 0, sizeof(unsigned long long) * 2 * (size_t)ws.k_max, s);
-    hipMemsetAsync(ws.ssub, 0, sizeof(unsigned long long) * 2 * (size_t)ws.k_max * (size_t)ws.G, s);
-    int64_t blocks = (ws.N + 3) / 4;
-    if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(k_stats, dim3((unsigned)blocks), dim3(256), 0, s, ws, c, cs);
+    const int ng = 2 * ws.k_max;
+    hipMemsetAsync(ws.grp_cnt, 0, sizeof(int32_t) * (size_t)ng, s);
+    hipMemsetAsync(ws.ssub, 0, sizeof(unsigned long long) * (size_t)ng * (size_t)ws.G, s);
+    const unsigned sb = (unsigned)((ws.N + kSortCellsPerBlock - 1) / kSortCellsPerBlock);
+    hipLaunchKernelGGL(k_group_count, dim3(sb), dim3(kSortThreads), sizeof(uint32_t) * (size_t)ng, s, ws, c, cs);
+    hipLaunchKernelGGL(k_group_scan, dim3(1), dim3(kSortThreads), 0, s, ws);
+    hipLaunchKernelGGL(k_group_scatter, dim3(sb), dim3(kSortThreads), 2 * sizeof(uint32_t) * (size_t)ng, s, ws, c, cs);
+    if (ws.G <= kStatMaxGenes) {
+        const unsigned blocks = (unsigned)((ws.N + kStatCells - 1) / kStatCells);
+        hipLaunchKernelGGL(k_stats_sorted, dim3(blocks), dim3(kStatThreads), sizeof(uint32_t) * (size_t)ws.G, s, ws);
+    } else {
+        int64_t blocks = (ws.N + 3) / 4;
+        if (blocks > 65536) blocks = 65536;
+        hipLaunchKernelGGL(k_stats_atomic, dim3((unsigned)blocks), dim3(256), 0, s, ws, c, cs);
+    }
 }
 
 // ---------------------------------------------------------------------------

@@ -130,6 +130,10 @@ struct Ws {
     uint16_t* lhi;         // split-BF16 tables, see assign_mfma.hip
     uint16_t* llo;
     uint32_t* refine;      // [N] queued cells with flags
+    int32_t* perm;         // [N] cells sorted by group 2k + r (processing order of a sweep)
+    int32_t* grp_cnt;      // [2 k_max] group sizes
+    int32_t* grp_off;      // [2 k_max + 1] group offsets in perm
+    int32_t* grp_cur;      // [2 k_max] scatter cursors
     int32_t* relab_c;      // [2 k_max] new cluster of an old (k, r)
     uint8_t* relab_s;      // [2 k_max] new sub-label of an old (k, r); 0xFF keeps it
     double* sm_logr;       // [k_max + k_max (k_max - 1) / 2]

@@ -283,3 +283,27 @@ def test_resume_reproduces_the_chain():
         cx, csx = _labels(x)
         ca, csa = _labels(a)
         assert np.array_equal(cx, ca) and np.array_equal(csx, csa)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("k_init", [24, 40, 56, 70])
+def test_many_cluster_kernel_paths(precision, k_init):
+    """Cluster counts that select each register-tile width of the assignment
+    kernel, its cluster-group loop (K > 64) and the gathered sub-cluster pass."""
+    _say("paths", precision, k_init)
+    d = synth.generate("c1", seed=6, n_cells=3000)
+    kw = dict(alpha=1.0, beta=1.0, seed=13, k_max=96, k_init=k_init)
+    o = _oracle(d, **kw)
+    s = _sampler(d, precision, **kw)
+    assert o.K == s.K == k_init
+    for it in range(2):
+        o.sweep()
+        s.sweep(1)
+        _compare_params(o, s)
+        assert _compare_labels(o, s, f"paths sweep {it}") == 0
+        _compare_stats(o, s)
+        o.split_merge()
+        s.split_merge()
+        _compare_hastings(o, s)
+        assert _compare_labels(o, s, f"paths sm {it}") == 0
+        _compare_stats(o, s)

@@ -76,13 +76,14 @@ def cpu_baseline(d, K_true, budget_s: float, seed: int):
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="c5", choices=sorted(WORKLOADS))
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "split_bf16"])
+    ap.add_argument("--precision", default="split_bf16", choices=["fp32", "fp64", "split_bf16"])
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true", help="skip the plain FP32 reference run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is described "
@@ -102,45 +103,72 @@ def main() -> int:
     log(f"generated {recipe}: N={d.n_cells} G={d.n_genes} nnz={d.nnz} zeros={d.zero_fraction():.3f} "
         f"in {time.time() - t0:.1f}s")
     K_true = d.n_true
-    s = Sampler(d.row_ptr, d.col, d.val, d.n_genes, alpha=1.0, beta=1.0, seed=args.seed, k_init=1,
-                k_max=128, precision=args.precision)
     rng = np.random.default_rng(args.seed)
-    s.set_state(0, K_true, torch.from_numpy(d.z), torch.from_numpy(rng.integers(0, 2, size=d.n_cells)),
-                np.ones(K_true, dtype=np.uint8))
+    c0 = torch.from_numpy(d.z)
+    cs0 = torch.from_numpy(rng.integers(0, 2, size=d.n_cells))
 
-    def step(i):
-        s.sweep(1)
-        s.split_merge()
+    def make(precision):
+        smp = Sampler(d.row_ptr, d.col, d.val, d.n_genes, alpha=1.0, beta=1.0, seed=args.seed, k_init=1,
+                      k_max=128, precision=precision)
+        smp.set_state(0, K_true, c0, cs0, np.ones(K_true, dtype=np.uint8))
+        return smp
+
+    def step(smp, i):
+        smp.sweep(1)
+        smp.split_merge()
         if (i + 1) % 10 == 0:
-            s.eb_update()
+            smp.eb_update()
 
-    for i in range(args.warmup):
-        step(i)
-        log(f"warmup step {i} done")
-    torch.cuda.synchronize()
-    st0 = s.stats()
-    s.timing(True)
-    s.timing_read()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step(args.warmup + i)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    st1 = s.stats()
-    kms, launches = s.timing_read()
-    s.timing(False)
-    evals = st1["evals"] - st0["evals"]
+    def run(precision):
+        smp = make(precision)
+        for i in range(args.warmup):
+            step(smp, i)
+        torch.cuda.synchronize()
+        st0 = smp.stats()
+        smp.timing(True)
+        smp.timing_read()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            step(smp, args.warmup + i)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st1 = smp.stats()
+        kms, launches = smp.timing_read()
+        smp.timing(False)
+        c, cs = smp.labels()
+        res = dict(dt=dt, evals=st1["evals"] - st0["evals"], kms=kms, launches=launches, K0=st0["K"], K1=st1["K"],
+                   refined=st1["refined"] - st0["refined"], c=c, cs=cs)
+        log(f"{precision}: {args.steps} steps in {dt:.4f}s, K {res['K0']} -> {res['K1']}, assign kernel "
+            f"{kms / max(1, launches):.4f} ms x {launches}, refined {res['refined']}")
+        smp.close()
+        return res
+
+    main_run = run(args.precision)
+    cmp = None
+    if args.precision != "fp32" and not args.no_compare:
+        ref = run("fp32")
+        same = bool(torch.equal(ref["c"], main_run["c"]) and torch.equal(ref["cs"], main_run["cs"]))
+        cmp = {"fp32_value": ref["evals"] / ref["dt"], "fp32_ms_per_step": ref["dt"] / args.steps * 1e3,
+               "fp32_assign_kernel_ms": ref["kms"] / max(1, ref["launches"]),
+               "speedup_vs_fp32": (main_run["evals"] / main_run["dt"]) / (ref["evals"] / ref["dt"]),
+               "kernel_speedup_vs_fp32": (ref["kms"] / max(1, ref["launches"])) /
+                                         max(1e-12, main_run["kms"] / max(1, main_run["launches"])),
+               "labels_identical_to_fp32": same}
+    dt, kms, launches = main_run["dt"], main_run["kms"], main_run["launches"]
+    evals = main_run["evals"]
     value = evals / dt
-    log(f"timed {args.steps} steps in {dt:.3f}s, K {st0['K']} -> {st1['K']}, assign kernel "
-        f"{kms / max(1, launches):.3f} ms x {launches}, refined {st1['refined'] - st0['refined']}")
+    st0 = {"K": main_run["K0"]}
+    st1 = {"K": main_run["K1"]}
 
     kernel_s = kms / 1e3 / max(1, launches)
     nbytes = alg_bytes(d.n_cells, d.nnz)
     achieved = nbytes / kernel_s / 1e9
+    kname = {"split_bf16": "k_assign_bf16", "fp32": "k_assign_valu<float>", "fp64": "k_assign_valu<double>"}
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                "kernel": "k_assign", "alg_bytes_per_launch": nbytes, "avg_launch_ms": kms / max(1, launches)}
+                "kernel": kname[args.precision], "alg_bytes_per_launch": nbytes,
+                "avg_launch_ms": kms / max(1, launches)}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -157,6 +185,7 @@ def main() -> int:
                    "step": "sweep + split/merge (+ empirical-Bayes beta step every 10th)"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "comparison": cmp,
     }
     print(json.dumps(out), flush=True)
     return 0

@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libdpmm.so")
 BUILD_DIR = os.path.join(os.path.dirname(HERE), "_build")
-SOURCES = ["api.hip", "bookkeeping.hip", "redraw.hip", "assign.hip", "assign_mfma.hip", "splitmerge.hip", "dm.hip"]
+SOURCES = ["api.hip", "bookkeeping.hip", "layout.hip", "redraw.hip", "assign.hip", "assign_mfma.hip", "substats.hip",
+           "splitmerge.hip", "dm.hip"]
 ARCH = "gfx950"
 
 FLAGS = [

@@ -35,24 +35,29 @@ dpmm_status fail(dpmm_status st, const char* fmt, ...)
 
 constexpr size_t kAlign = 256;
 constexpr int kMaxTimed = 4096;
-constexpr int kMfmaGeneTile = 32;
-constexpr bool kHaveSplitBf16 = false;
+constexpr int kMfmaGeneTile = 64;      // gene chunk of the split-BF16 kernel
+constexpr int kTablePadRows = 64;      // spare cluster rows read by its last column group
 
 size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
 struct Layout {
     size_t ent, roff, tiles, c0, c1, cs0, cs1, st, reset, nsub, ssub, beta, logpi, lt64, lc32, ls32, lhi, llo,
-        refine, perm, grp_cnt, grp_off, grp_cur, relab_c, relab_s, sm_logr, sm_acc, mkey, mlist, dm_k, eb_tmp, total;
+        refine, perm, grp_cnt, grp_off, grp_cur, nsub_prev, blk_ent, blk_off, relab_c, relab_s, sm_logr, sm_acc, mkey, mlist, dm_k, eb_tmp, total;
 };
 
-Layout plan(int64_t N, int32_t G, int64_t nnz, int32_t k_max)
+int32_t num_blocks(int64_t N) { return (int32_t)((N + kBlkCells - 1) / kBlkCells); }
+int32_t num_chunks(int32_t G) { return (G + kBlkGenes - 1) / kBlkGenes; }
+
+Layout plan(int64_t N, int32_t G, int64_t nnz, int32_t k_max, int32_t precision)
 {
     Layout L{};
     const int64_t nnz_pad = nnz + 3 * N;
     const int64_t kpad = (k_max + 15) / 16 * 16;
     const int64_t Gpad = (G + kMfmaGeneTile - 1) / kMfmaGeneTile * kMfmaGeneTile;
     const int64_t ncand = (int64_t)k_max + (int64_t)k_max * (k_max - 1) / 2;
-    const int64_t ntiles = (N + 4095) / 4096 + 1;
+    const bool blocked = precision == DPMM_SPLIT_BF16;
+    const int64_t nseg = blocked ? (int64_t)num_blocks(N) * num_chunks(G) : 0;
+    const int64_t ntiles = ((N > nseg ? N : nseg) + 4095) / 4096 + 1;
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o += align_up(bytes); return at; };
     L.ent = take(4 * (size_t)nnz_pad);
@@ -69,15 +74,18 @@ Layout plan(int64_t N, int32_t G, int64_t nnz, int32_t k_max)
     L.beta = take(8 * (size_t)G);
     L.logpi = take(8 * (size_t)k_max);
     L.lt64 = take(24 * (size_t)k_max * (size_t)G);
-    L.lc32 = take(4 * (size_t)G * (size_t)kpad);
+    L.lc32 = take(4 * ((size_t)G * (size_t)kpad + kTablePadRows));
     L.ls32 = take(8 * (size_t)G * (size_t)k_max);
-    L.lhi = take(2 * (size_t)Gpad * (size_t)kpad);
-    L.llo = take(2 * (size_t)Gpad * (size_t)kpad);
+    L.lhi = take(2 * (size_t)Gpad * (size_t)(kpad + kTablePadRows));
+    L.llo = take(2 * (size_t)Gpad * (size_t)(kpad + kTablePadRows));
     L.refine = take(4 * (size_t)N);
     L.perm = take(4 * (size_t)N);
     L.grp_cnt = take(8 * (size_t)k_max);
     L.grp_off = take(8 * (size_t)k_max + 4);
     L.grp_cur = take(8 * (size_t)k_max);
+    L.nsub_prev = take(16 * (size_t)k_max);
+    L.blk_ent = take(blocked ? 4 * (size_t)(nnz + 3 * nseg) : 0);
+    L.blk_off = take(blocked ? 8 * (size_t)(nseg + 1) : 0);
     L.relab_c = take(8 * (size_t)k_max);
     L.relab_s = take(2 * (size_t)k_max);
     L.sm_logr = take(8 * (size_t)ncand);
@@ -103,7 +111,6 @@ dpmm_status check_args(const dpmm_csr* csr, const dpmm_params* p)
     if (p->k_init < 1 || p->k_init > p->k_max) return fail(DPMM_ERR_ARG, "k_init must be in [1, k_max]");
     if (p->precision < DPMM_FP64 || p->precision > DPMM_SPLIT_BF16) return fail(DPMM_ERR_ARG, "unknown precision");
     if (p->flags != 0) return fail(DPMM_ERR_ARG, "flags must be 0");
-    if (p->precision == DPMM_SPLIT_BF16 && !kHaveSplitBf16) return fail(DPMM_ERR_UNSUPPORTED, "split-BF16 path not built");
     return DPMM_OK;
 }
 
@@ -129,6 +136,7 @@ struct dpmm_ctx {
     bool timing = false;
     std::vector<hipEvent_t> ev;        // pairs (start, stop)
     int n_timed = 0;
+    int32_t* k_host = nullptr;         // pinned copy of K, refreshed after every call
 };
 
 namespace {
@@ -145,6 +153,15 @@ dpmm_status read_state(dpmm_ctx* ctx, DevState* out)
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     return DPMM_OK;
 }
+
+// queue a copy of the device K into the pinned hint (read by later launches)
+dpmm_status refresh_k_hint(dpmm_ctx* ctx)
+{
+    HIP_TRY(hipMemcpyAsync(ctx->k_host, &ctx->ws.st->K, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+    return DPMM_OK;
+}
+
+int32_t k_hint(const dpmm_ctx* ctx) { return *reinterpret_cast<volatile int32_t*>(ctx->k_host); }
 
 // statistics from the current labels, then compaction without touching flags
 dpmm_status recompute_stats(dpmm_ctx* ctx)
@@ -167,7 +184,7 @@ dpmm_status dpmm_workspace_size(const dpmm_csr* csr, const dpmm_params* params, 
     dpmm_status s = check_args(csr, params);
     if (s != DPMM_OK) return s;
     if (!bytes) return fail(DPMM_ERR_ARG, "null bytes");
-    *bytes = plan(csr->n_cells, csr->n_genes, csr->nnz, params->k_max).total;
+    *bytes = plan(csr->n_cells, csr->n_genes, csr->nnz, params->k_max, params->precision).total;
     return DPMM_OK;
 }
 
@@ -181,7 +198,7 @@ dpmm_status dpmm_init(const dpmm_csr* csr, const dpmm_params* params, void* work
     *out = nullptr;
     if (!workspace || ((uintptr_t)workspace & (kAlign - 1))) return fail(DPMM_ERR_ARG, "workspace must be 256-byte aligned");
     if (!csr->row_ptr || (csr->nnz > 0 && (!csr->col || !csr->val))) return fail(DPMM_ERR_ARG, "null CSR array");
-    const Layout L = plan(csr->n_cells, csr->n_genes, csr->nnz, params->k_max);
+    const Layout L = plan(csr->n_cells, csr->n_genes, csr->nnz, params->k_max, params->precision);
     if (workspace_bytes < L.total)
         return fail(DPMM_ERR_NOMEM, "workspace of %zu bytes, %zu needed", workspace_bytes, L.total);
 
@@ -224,6 +241,11 @@ dpmm_status dpmm_init(const dpmm_csr* csr, const dpmm_params* params, void* work
     ws.grp_cnt = (int32_t*)(base + L.grp_cnt);
     ws.grp_off = (int32_t*)(base + L.grp_off);
     ws.grp_cur = (int32_t*)(base + L.grp_cur);
+    ws.nsub_prev = (unsigned long long*)(base + L.nsub_prev);
+    ws.blk_ent = (const uint32_t*)(base + L.blk_ent);
+    ws.blk_off = (int64_t*)(base + L.blk_off);
+    ws.nblk = num_blocks(csr->n_cells);
+    ws.nch = num_chunks(csr->n_genes);
     ws.relab_c = (int32_t*)(base + L.relab_c);
     ws.relab_s = (uint8_t*)(base + L.relab_s);
     ws.sm_logr = (double*)(base + L.sm_logr);
@@ -238,13 +260,25 @@ dpmm_status dpmm_init(const dpmm_csr* csr, const dpmm_params* params, void* work
     ctx->cs[1] = (uint8_t*)(base + L.cs1);
     ctx->tiles = (int64_t*)(base + L.tiles);
 
-    auto cleanup = [&](dpmm_status st) { delete ctx; return st; };
+    auto cleanup = [&](dpmm_status st) {
+        if (ctx->k_host) hipHostFree(ctx->k_host);
+        delete ctx;
+        return st;
+    };
+    he = hipHostMalloc((void**)&ctx->k_host, sizeof(int32_t), hipHostMallocDefault);
+    if (he != hipSuccess) { ctx->k_host = nullptr; return cleanup(fail(DPMM_ERR_HIP, "hipHostMalloc: %s", hipGetErrorString(he))); }
+    *ctx->k_host = params->k_init;
+    if (params->precision == DPMM_SPLIT_BF16) {
+        he = configure_assign_bf16();
+        if (he != hipSuccess) return cleanup(fail(DPMM_ERR_HIP, "kernel attributes: %s", hipGetErrorString(he)));
+    }
     he = hipMemsetAsync(ws.st, 0, sizeof(DevState), ctx->stream);
     if (he == hipSuccess) he = hipMemsetAsync(ws.lc32, 0, L.ls32 - L.lc32, ctx->stream);
     if (he == hipSuccess) he = hipMemsetAsync(ws.lhi, 0, L.refine - L.lhi, ctx->stream);
     if (he != hipSuccess) return cleanup(fail(DPMM_ERR_HIP, "hipMemsetAsync: %s", hipGetErrorString(he)));
     launch_pack(csr->row_ptr, csr->col, csr->val, csr->n_cells, csr->n_genes, csr->nnz, (int64_t*)ws.roff,
                 ctx->tiles, (uint32_t*)ws.ent, ws.st, ctx->stream);
+    if (params->precision == DPMM_SPLIT_BF16) launch_build_blocked(ws, ctx->tiles, ctx->stream);
     if (params->beta_per_gene)
         he = hipMemcpyAsync(ws.beta, params->beta_per_gene, 8 * (size_t)ws.G, hipMemcpyDeviceToDevice, ctx->stream);
     else
@@ -265,6 +299,7 @@ dpmm_status dpmm_init(const dpmm_csr* csr, const dpmm_params* params, void* work
     if (last != csr->nnz) return cleanup(fail(DPMM_ERR_DATA, "row_ptr[N] = %lld differs from nnz = %lld",
                                               (long long)last, (long long)csr->nnz));
     s = recompute_stats(ctx);
+    if (s == DPMM_OK) s = refresh_k_hint(ctx);
     if (s != DPMM_OK) return cleanup(s);
     he = hipStreamSynchronize(ctx->stream);
     if (he != hipSuccess) return cleanup(fail(DPMM_ERR_HIP, "init stats: %s", hipGetErrorString(he)));
@@ -278,6 +313,7 @@ dpmm_status dpmm_destroy(dpmm_ctx* ctx)
     hipSetDevice(ctx->device);
     hipStreamSynchronize(ctx->stream);
     for (hipEvent_t e : ctx->ev) hipEventDestroy(e);
+    if (ctx->k_host) hipHostFree(ctx->k_host);
     delete ctx;
     return DPMM_OK;
 }
@@ -304,6 +340,7 @@ dpmm_status dpmm_sweep(dpmm_ctx* ctx, int32_t n_sweeps)
         a.dbg_stride = ctx->dbg_cap + 2;
         a.refine = ctx->precision != DPMM_FP64;
         a.refine_tol = (float)ctx->refine_tol;
+        a.k_hint = k_hint(ctx);
         const bool timed = ctx->timing && ctx->n_timed < kMaxTimed;
         if (timed) HIP_TRY(hipEventRecord(ctx->ev[2 * ctx->n_timed], ctx->stream));
         if (ctx->precision == DPMM_FP64) launch_assign_fp64(ws, a, ctx->stream);
@@ -314,10 +351,20 @@ dpmm_status dpmm_sweep(dpmm_ctx* ctx, int32_t n_sweeps)
             ctx->n_timed++;
         }
         if (a.refine) launch_refine(ws, a, ctx->stream);
-        launch_stats(ws, ctx->c[nxt], ctx->cs[nxt], ctx->stream);
+        SubArgs sa{};
+        sa.c_old = ctx->c[ctx->cur];
+        sa.cs_old = ctx->cs[ctx->cur];
+        sa.c_new = ctx->c[nxt];
+        sa.cs_new = ctx->cs[nxt];
+        sa.step = step;
+        sa.dbg = ctx->dbg;
+        sa.dbg_stride = ctx->dbg_cap + 2;
+        launch_sub_stats(ws, sa, ctx->stream);
         launch_compact(ws, 1, ctx->stream);
         launch_relabel(ws, ctx->c[nxt], ctx->cs[nxt], ctx->stream);
         HIP_TRY(hipGetLastError());
+        s = refresh_k_hint(ctx);
+        if (s != DPMM_OK) return s;
         ctx->cur = nxt;
         ctx->step += 1;
         ctx->sweeps += 1;
@@ -340,6 +387,8 @@ dpmm_status dpmm_split_merge(dpmm_ctx* ctx)
     launch_sm_decide(ctx->ws, merge_pass, step, ctx->stream);
     launch_relabel(ctx->ws, ctx->c[ctx->cur], ctx->cs[ctx->cur], ctx->stream);
     HIP_TRY(hipGetLastError());
+    s = refresh_k_hint(ctx);
+    if (s != DPMM_OK) return s;
     ctx->last_pass = merge_pass;
     ctx->step += 1;
     ctx->sm_calls += 1;
@@ -427,6 +476,7 @@ dpmm_status dpmm_set_state(dpmm_ctx* ctx, int64_t step, int32_t K, const int32_t
         return fail(DPMM_ERR_ARG, "%d labels out of range", chk.data_error);
     }
     s = recompute_stats(ctx);
+    if (s == DPMM_OK) s = refresh_k_hint(ctx);
     if (s != DPMM_OK) return s;
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     ctx->step = step;
@@ -517,13 +567,12 @@ dpmm_status dpmm_get_split_tables(dpmm_ctx* ctx, uint16_t* hi_dev, uint16_t* lo_
     DevState d;
     s = read_state(ctx, &d);
     if (s != DPMM_OK) return s;
-    // gene-major [Gpad][kpad] -> cluster-major K x G
-    const size_t pitch = 2 * (size_t)ctx->ws.kpad;
+    // cluster-major [k][Gpad] -> K x G
     for (int k = 0; k < d.K; ++k) {
-        HIP_TRY(hipMemcpy2DAsync(hi_dev + (size_t)k * ctx->G, 2, ctx->ws.lhi + k, pitch, 2, (size_t)ctx->G,
-                                 hipMemcpyDeviceToDevice, ctx->stream));
-        HIP_TRY(hipMemcpy2DAsync(lo_dev + (size_t)k * ctx->G, 2, ctx->ws.llo + k, pitch, 2, (size_t)ctx->G,
-                                 hipMemcpyDeviceToDevice, ctx->stream));
+        HIP_TRY(hipMemcpyAsync(hi_dev + (size_t)k * ctx->G, ctx->ws.lhi + (size_t)k * ctx->ws.Gpad, 2 * (size_t)ctx->G,
+                               hipMemcpyDeviceToDevice, ctx->stream));
+        HIP_TRY(hipMemcpyAsync(lo_dev + (size_t)k * ctx->G, ctx->ws.llo + (size_t)k * ctx->ws.Gpad, 2 * (size_t)ctx->G,
+                               hipMemcpyDeviceToDevice, ctx->stream));
     }
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     return DPMM_OK;

@@ -1,9 +1,262 @@
-// assign_mfma.hip -- split-BF16 MFMA log-likelihood kernel (not yet built).
+// assign_mfma.hip -- the cluster draw (eq. 4, third line) with the cluster
+// log-likelihoods on the matrix cores: S = X L^T for a block of cells, X their
+// UMI counts (eq. 26) and L = log theta split as hi + lo in BF16.
+//
+//   * counts <= 256 are exact in BF16; a larger count x is stored as xa (x
+//     with its low bits cleared to keep 8 significant bits, exact in BF16)
+//     and the rest (x - xa) log theta is added in FP32;
+//   * products of a count and a BF16 value are exact in FP32; the MFMA
+//     accumulates in FP32 (v_mfma_f32_16x16x32_bf16, gfx950);
+//   * S = X hi^T + X lo^T, |log theta - hi - lo| <= 2^-17 |log theta|.
+//
+// A workgroup of 4 wavefronts owns one block of kBlkCells cells of the
+// blocked layout; wavefront w owns cells 64w .. 64w + 63 (4 row tiles of 16).
+// For each chunk of 64 genes: the workgroup stages the hi/lo chunk of
+// log theta cluster-major, reads the chunk's segment with coalesced 16-byte
+// loads and writes each entry into the dense BF16 tile in LDS (entry-parallel,
+// balanced), then each wavefront issues 2 k-steps x 4 row tiles x Nt column
+// tiles x 2 (hi, lo) MFMAs, and the entries are cleared again.  Counts above
+// 256 go to a short LDS list whose FP32 corrections are added to the scores.
+// The cell's lane then takes the Gumbel-max over the K scores with a
+// certified rounding bound; close decisions are queued for the FP64 re-score.
 #include "dpmm_common.hpp"
 #include "kernels.hpp"
 
 namespace dpmm {
 
-void launch_assign_bf16(const Ws&, const AssignArgs&, hipStream_t) {}
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float floatx4_t;
+
+constexpr int kMfmaThreads = kBlkCells;       // 256: one thread per cell
+constexpr int kMfmaRow = kBlkGenes + 8;       // BF16 elements per LDS tile row (padded)
+constexpr int kOvfCap = 1024;                 // counts > 256 per block and column group
+
+__host__ __device__ constexpr size_t mfma_main_bytes(int nt)
+{
+    // A tile (256 cells) + hi/lo B tiles, or the FP32 score tile reusing them
+    return (size_t)(kBlkCells * kMfmaRow * 2 + 2 * 16 * nt * kMfmaRow * 2) >
+                   (size_t)kBlkCells * (16 * nt + 1) * 4
+               ? (size_t)(kBlkCells * kMfmaRow * 2 + 2 * 16 * nt * kMfmaRow * 2)
+               : (size_t)kBlkCells * (16 * nt + 1) * 4;
+}
+__host__ __device__ constexpr size_t mfma_lds_bytes(int nt) { return mfma_main_bytes(nt) + 8 * (size_t)kOvfCap; }
+
+__device__ inline uint16_t bf16_of_count(uint32_t x)
+{
+    // at most 8 significant bits: the float is exact and its top half is the BF16 value
+    return (uint16_t)(__float_as_uint((float)x) >> 16);
+}
+
+// x = xa + xb with xa keeping the top 8 significant bits of x
+__device__ inline uint32_t count_head(uint32_t x)
+{
+    if (x <= 256u) return x;
+    const int sh = (32 - __clz((int)x)) - 8;
+    return (x >> sh) << sh;
+}
+
+__device__ inline float gumbel32(uint32_t w) { return -logf(-logf(unit23f(w))); }
+
+// rounding bound of a split-BF16 score: representation 2^-17, FP32
+// accumulation over nsteps MFMA k-steps (with slack for the 32-term products
+// inside each), FP32 overflow corrections and the FP32 Gumbel noise
+__device__ inline float bf16_bound(float acc, float lp, int nsteps)
+{
+    return ((float)(nsteps + 40) * 0x1p-24f + 0x1p-17f) * (fabsf(acc) + fabsf(lp) + 20.0f) + 1e-5f;
+}
+
+template <int NT>
+__global__ void __launch_bounds__(kMfmaThreads) k_assign_bf16(Ws ws, AssignArgs a)
+{
+    extern __shared__ __attribute__((aligned(16))) char lds[];
+    __shared__ int s_novf;
+    __shared__ uint8_t s_force[kBlkCells];
+    uint16_t* atile = reinterpret_cast<uint16_t*>(lds);
+    uint16_t* bhi = atile + kBlkCells * kMfmaRow;
+    uint16_t* blo = bhi + 16 * NT * kMfmaRow;
+    float* sc = reinterpret_cast<float*>(lds);                         // epilogue alias
+    uint2* ovf = reinterpret_cast<uint2*>(lds + mfma_main_bytes(NT));  // (cell | gene << 8, extra count)
+    constexpr int SS = 16 * NT + 1;
+
+    const int K = ws.st->K;
+    const int t = threadIdx.x;
+    const int lane = t & 63;
+    const int wave = t >> 6;
+    const int blk = blockIdx.x;
+    const int64_t i = (int64_t)blk * kBlkCells + t;
+    const bool valid = i < ws.N;
+    const int64_t* soff = ws.blk_off + (int64_t)blk * ws.nch;
+    s_force[t] = 0;
+
+    float t1 = -INFINITY, t2 = -INFINITY, a1 = 0.f, a2 = 0.f, p1 = 0.f, p2 = 0.f;
+    int k1 = 0;
+    const int nsteps = 2 * ws.nch;
+
+    for (int kb = 0; kb < K; kb += 16 * NT) {
+        floatx4_t acc[4][NT];
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int n = 0; n < NT; ++n) acc[m][n] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+        __syncthreads();
+        // clear the tile once; afterwards only written entries are cleared
+        for (int g = 0; g < kMfmaRow; g += 8)
+            *reinterpret_cast<uint4*>(atile + t * kMfmaRow + g) = make_uint4(0, 0, 0, 0);
+        if (t == 0) s_novf = 0;
+
+        for (int j = 0; j < ws.nch; ++j) {
+            const int c0 = j * kBlkGenes;
+            __syncthreads();
+            // hi/lo rows kb .. kb + 16 NT, genes c0 .. c0 + 64, 16-byte copies
+            for (int idx = t; idx < 2 * 16 * NT * (kBlkGenes / 8); idx += kMfmaThreads) {
+                const int tbl = idx / (16 * NT * (kBlkGenes / 8));
+                const int rem = idx % (16 * NT * (kBlkGenes / 8));
+                const int row = rem / (kBlkGenes / 8);
+                const int seg = rem % (kBlkGenes / 8);
+                const uint16_t* src = (tbl ? ws.llo : ws.lhi) + (int64_t)(kb + row) * ws.Gpad + c0 + seg * 8;
+                uint16_t* dst = (tbl ? blo : bhi) + row * kMfmaRow + seg * 8;
+                *reinterpret_cast<uint4*>(dst) = *reinterpret_cast<const uint4*>(src);
+            }
+            // the segment's entries into the tile
+            const int64_t e0 = soff[j], e1 = soff[j + 1];
+            for (int64_t q = e0 + 4 * t; q < e1; q += 4 * kMfmaThreads) {
+                const uint4 v = *reinterpret_cast<const uint4*>(ws.blk_ent + q);
+                const uint32_t en[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const uint32_t x = en[r] >> 16;
+                    if (!x) continue;
+                    const uint32_t cell = en[r] & 0xFFu;
+                    const uint32_t g = (en[r] >> 8) & 0x3Fu;
+                    const uint32_t xa = count_head(x);
+                    atile[cell * kMfmaRow + g] = bf16_of_count(xa);
+                    if (xa != x) {
+                        const int o = atomicAdd(&s_novf, 1);
+                        if (o < kOvfCap) ovf[o] = make_uint2(cell | ((uint32_t)(c0 + g) << 8), x - xa);
+                        else s_force[cell] = 1;
+                    }
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                const int col = 32 * s + 8 * (lane >> 4);
+                bf16x8_t af[4];
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+                    af[m] = *reinterpret_cast<const bf16x8_t*>(atile + (64 * wave + 16 * m + (lane & 15)) * kMfmaRow + col);
+#pragma unroll
+                for (int n = 0; n < NT; ++n) {
+                    const bf16x8_t bh = *reinterpret_cast<const bf16x8_t*>(bhi + (16 * n + (lane & 15)) * kMfmaRow + col);
+                    const bf16x8_t bl = *reinterpret_cast<const bf16x8_t*>(blo + (16 * n + (lane & 15)) * kMfmaRow + col);
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) {
+                        acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[m], bh, acc[m][n], 0, 0, 0);
+                        acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[m], bl, acc[m][n], 0, 0, 0);
+                    }
+                }
+            }
+            __syncthreads();
+            // clear the written entries (same loads, now from cache)
+            for (int64_t q = e0 + 4 * t; q < e1; q += 4 * kMfmaThreads) {
+                const uint4 v = *reinterpret_cast<const uint4*>(ws.blk_ent + q);
+                const uint32_t en[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (en[r] >> 16) atile[(en[r] & 0xFFu) * kMfmaRow + ((en[r] >> 8) & 0x3Fu)] = 0;
+            }
+        }
+        __syncthreads();
+        // scores through LDS: lane l holds, for row tile m and column tile n,
+        // cells 64w + 16m + 4(l/16) + j (j < 4) against cluster 16n + l%16
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int n = 0; n < NT; ++n)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    sc[(64 * wave + 16 * m + 4 * (lane >> 4) + q) * SS + 16 * n + (lane & 15)] = acc[m][n][q];
+        __syncthreads();
+        // FP32 corrections of the counts above 256
+        const int novf = min(s_novf, kOvfCap);
+        for (int o = t; o < novf; o += kMfmaThreads) {
+            const uint2 ov = ovf[o];
+            const int cell = (int)(ov.x & 0xFFu);
+            const int g = (int)(ov.x >> 8);
+            const float xb = (float)ov.y;
+            const float* lrow = ws.lc32 + (int64_t)g * ws.kpad + kb;
+            for (int k = 0; k < 16 * NT && kb + k < K; ++k) atomicAdd(&sc[cell * SS + k], xb * lrow[k]);
+        }
+        __syncthreads();
+        if (valid) {
+            Words w{};
+#pragma unroll
+            for (int k = 0; k < 16 * NT; ++k) {
+                const int kk = kb + k;
+                if (kk >= K) break;
+                if ((k & 3) == 0) w = philox(ws.seed, (uint32_t)i, (uint32_t)(kk >> 2), a.step, kGumbelC, 0u);
+                const float s = sc[t * SS + k];
+                const float lp = (float)ws.logpi[kk];
+                const float v = lp + s + gumbel32(w.w[k & 3]);
+                if (a.dbg && K + 2 <= a.dbg_stride) a.dbg[i * a.dbg_stride + kk] = s;
+                if (v > t1) {
+                    t2 = t1; a2 = a1; p2 = p1;
+                    t1 = v; a1 = s; p1 = lp; k1 = kk;
+                } else if (v > t2) {
+                    t2 = v; a2 = s; p2 = lp;
+                }
+            }
+        }
+    }
+    if (!valid) return;
+    bool uncertain = s_force[t] != 0;
+    if (K >= 2) {
+        const float bnd = bf16_bound(a1, p1, nsteps) + bf16_bound(a2, p2, nsteps);
+        if (t1 - t2 <= bnd || (t1 - t2) / fmaxf(1.0f, fabsf(t1)) < a.refine_tol) uncertain = true;
+    }
+    a.c_new[i] = k1;
+    if (uncertain) {
+        const int q = atomicAdd(&ws.st->n_refine, 1);
+        if (q < ws.N) ws.refine[q] = (uint32_t)i | kRefineCluster;
+    }
+}
+
+template <int NT>
+static void launch_nt(const Ws& ws, const AssignArgs& a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_assign_bf16<NT>, dim3((unsigned)ws.nblk), dim3(kMfmaThreads), mfma_lds_bytes(NT), s, ws, a);
+}
+
+// Allow the dynamic LDS size of every variant on the current device.
+hipError_t configure_assign_bf16()
+{
+    hipError_t e = hipFuncSetAttribute((const void*)k_assign_bf16<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)mfma_lds_bytes(1));
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)k_assign_bf16<2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)mfma_lds_bytes(2));
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)k_assign_bf16<3>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)mfma_lds_bytes(3));
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)k_assign_bf16<4>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)mfma_lds_bytes(4));
+    return e;
+}
+
+// The column-tile count is fixed at launch while K lives on the device: the
+// host passes the last K it has seen (k_hint); if K has grown beyond it the
+// kernel loops over column groups.
+void launch_assign_bf16(const Ws& ws, const AssignArgs& a, hipStream_t s)
+{
+    const int k_hint = a.k_hint > 0 ? a.k_hint : ws.k_max;
+    const int nt = k_hint <= 16 ? 1 : k_hint <= 32 ? 2 : k_hint <= 48 ? 3 : 4;
+    switch (nt) {
+    case 1: launch_nt<1>(ws, a, s); break;
+    case 2: launch_nt<2>(ws, a, s); break;
+    case 3: launch_nt<3>(ws, a, s); break;
+    default: launch_nt<4>(ws, a, s); break;
+    }
+}
 
 }  // namespace dpmm

@@ -179,29 +179,31 @@ constexpr int kStatThreads = 256;
 constexpr int kStatCells = 2048;
 constexpr int kStatMaxGenes = 16384;
 
+__device__ inline int sort_group(int32_t k, uint8_t r, int by_cluster) { return by_cluster ? k : 2 * k + (r & 1); }
+
 __global__ void __launch_bounds__(kSortThreads) k_group_count(Ws ws, const int32_t* __restrict__ c,
-                                                              const uint8_t* __restrict__ cs)
+                                                              const uint8_t* __restrict__ cs, int by_cluster)
 {
-    extern __shared__ uint32_t hist[];   // [2 k_max]
-    const int ng = 2 * ws.k_max;
+    extern __shared__ uint32_t hist[];   // [groups]
+    const int ng = by_cluster ? ws.k_max : 2 * ws.k_max;
     for (int q = threadIdx.x; q < ng; q += kSortThreads) hist[q] = 0;
     __syncthreads();
     const int64_t b0 = (int64_t)blockIdx.x * kSortCellsPerBlock;
     const int64_t b1 = min(ws.N, b0 + kSortCellsPerBlock);
     for (int64_t i = b0 + threadIdx.x; i < b1; i += kSortThreads) {
         const int32_t k = c[i];
-        if (k >= 0 && k < ws.k_max) atomicAdd(&hist[2 * k + (cs[i] & 1)], 1u);
+        if (k >= 0 && k < ws.k_max) atomicAdd(&hist[sort_group(k, cs[i], by_cluster)], 1u);
     }
     __syncthreads();
     for (int q = threadIdx.x; q < ng; q += kSortThreads)
         if (hist[q]) atomicAdd(&ws.grp_cnt[q], (int32_t)hist[q]);
 }
 
-// exclusive scan of the group sizes; n_{k,r} = group sizes
-__global__ void __launch_bounds__(kSortThreads) k_group_scan(Ws ws)
+// exclusive scan of the group sizes; with groups (k, r) the sizes are n_{k,r}
+__global__ void __launch_bounds__(kSortThreads) k_group_scan(Ws ws, int by_cluster)
 {
     __shared__ int32_t lds[kSortThreads];
-    const int ng = 2 * ws.k_max;
+    const int ng = by_cluster ? ws.k_max : 2 * ws.k_max;
     int32_t carry = 0;
     for (int base = 0; base < ng; base += kSortThreads) {
         const int q = base + threadIdx.x;
@@ -217,7 +219,7 @@ __global__ void __launch_bounds__(kSortThreads) k_group_scan(Ws ws)
         if (q < ng) {
             ws.grp_off[q] = carry + lds[threadIdx.x] - v;
             ws.grp_cur[q] = 0;
-            ws.nsub[q] = (unsigned long long)v;
+            if (!by_cluster) ws.nsub[q] = (unsigned long long)v;
         }
         carry += lds[kSortThreads - 1];
         __syncthreads();
@@ -226,10 +228,10 @@ __global__ void __launch_bounds__(kSortThreads) k_group_scan(Ws ws)
 }
 
 __global__ void __launch_bounds__(kSortThreads) k_group_scatter(Ws ws, const int32_t* __restrict__ c,
-                                                                const uint8_t* __restrict__ cs)
+                                                                const uint8_t* __restrict__ cs, int by_cluster)
 {
-    extern __shared__ uint32_t lds_u[];      // [2 k_max] counts, then [2 k_max] bases
-    const int ng = 2 * ws.k_max;
+    extern __shared__ uint32_t lds_u[];      // [groups] counts, then [groups] bases
+    const int ng = by_cluster ? ws.k_max : 2 * ws.k_max;
     uint32_t* cnt = lds_u;
     uint32_t* base = lds_u + ng;
     for (int q = threadIdx.x; q < ng; q += kSortThreads) cnt[q] = 0;
@@ -239,7 +241,7 @@ __global__ void __launch_bounds__(kSortThreads) k_group_scatter(Ws ws, const int
     // pass 1: block-local counts; pass 2: one reservation per group; pass 3: ranks
     for (int64_t i = b0 + threadIdx.x; i < b1; i += kSortThreads) {
         const int32_t k = c[i];
-        if (k >= 0 && k < ws.k_max) atomicAdd(&cnt[2 * k + (cs[i] & 1)], 1u);
+        if (k >= 0 && k < ws.k_max) atomicAdd(&cnt[sort_group(k, cs[i], by_cluster)], 1u);
     }
     __syncthreads();
     for (int q = threadIdx.x; q < ng; q += kSortThreads) {
@@ -250,7 +252,7 @@ __global__ void __launch_bounds__(kSortThreads) k_group_scatter(Ws ws, const int
     for (int64_t i = b0 + threadIdx.x; i < b1; i += kSortThreads) {
         const int32_t k = c[i];
         if (k < 0 || k >= ws.k_max) continue;
-        const int q = 2 * k + (cs[i] & 1);
+        const int q = sort_group(k, cs[i], by_cluster);
         const uint32_t pos = base[q] + atomicAdd(&cnt[q], 1u);
         if (pos < (uint32_t)ws.N) ws.perm[pos] = (int32_t)i;
     }
@@ -325,15 +327,22 @@ __global__ void k_stats_atomic(Ws ws, const int32_t* __restrict__ c, const uint8
     }
 }
 
+void launch_sort(const Ws& ws, const int32_t* c, const uint8_t* cs, int by_cluster, hipStream_t s)
+{
+    const int ng = by_cluster ? ws.k_max : 2 * ws.k_max;
+    hipMemsetAsync(ws.grp_cnt, 0, sizeof(int32_t) * (size_t)ng, s);
+    const unsigned sb = (unsigned)((ws.N + kSortCellsPerBlock - 1) / kSortCellsPerBlock);
+    hipLaunchKernelGGL(k_group_count, dim3(sb), dim3(kSortThreads), sizeof(uint32_t) * (size_t)ng, s, ws, c, cs,
+                       by_cluster);
+    hipLaunchKernelGGL(k_group_scan, dim3(1), dim3(kSortThreads), 0, s, ws, by_cluster);
+    hipLaunchKernelGGL(k_group_scatter, dim3(sb), dim3(kSortThreads), 2 * sizeof(uint32_t) * (size_t)ng, s, ws, c,
+                       cs, by_cluster);
+}
+
 void launch_stats(const Ws& ws, const int32_t* c, const uint8_t* cs, hipStream_t s)
 {
-    const int ng = 2 * ws.k_max;
-    hipMemsetAsync(ws.grp_cnt, 0, sizeof(int32_t) * (size_t)ng, s);
-    hipMemsetAsync(ws.ssub, 0, sizeof(unsigned long long) * (size_t)ng * (size_t)ws.G, s);
-    const unsigned sb = (unsigned)((ws.N + kSortCellsPerBlock - 1) / kSortCellsPerBlock);
-    hipLaunchKernelGGL(k_group_count, dim3(sb), dim3(kSortThreads), sizeof(uint32_t) * (size_t)ng, s, ws, c, cs);
-    hipLaunchKernelGGL(k_group_scan, dim3(1), dim3(kSortThreads), 0, s, ws);
-    hipLaunchKernelGGL(k_group_scatter, dim3(sb), dim3(kSortThreads), 2 * sizeof(uint32_t) * (size_t)ng, s, ws, c, cs);
+    hipMemsetAsync(ws.ssub, 0, sizeof(unsigned long long) * 2 * (size_t)ws.k_max * (size_t)ws.G, s);
+    launch_sort(ws, c, cs, 0, s);
     if (ws.G <= kStatMaxGenes) {
         const unsigned blocks = (unsigned)((ws.N + kStatCells - 1) / kStatCells);
         hipLaunchKernelGGL(k_stats_sorted, dim3(blocks), dim3(kStatThreads), sizeof(uint32_t) * (size_t)ws.G, s, ws);

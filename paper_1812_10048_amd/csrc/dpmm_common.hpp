@@ -99,10 +99,44 @@ struct DevState {
 // Rows are padded to a multiple of 4 entries (16 bytes) with kPadEntry.
 constexpr uint32_t kPadEntry = 0x0000FFFFu;   // gene 0xFFFF, count 0
 
+constexpr int kBlkCells = 256;
+constexpr int kBlkGenes = 64;
+
 // Refine-queue flags (high bits of a queued cell index).
 constexpr uint32_t kRefineCluster = 1u << 31;
 constexpr uint32_t kRefineSub = 1u << 30;
 constexpr uint32_t kRefineMask = (1u << 30) - 1;
+
+// Row walker: entries are read 16 bytes at a time (rows start and end on
+// 16-byte boundaries) with the next block already in flight.
+#if defined(__HIPCC__)
+struct RowCursor {
+    int64_t pos, end;
+    uint4 cur, nxt;
+    __device__ inline void start(const uint32_t* ent, int64_t b, int64_t e)
+    {
+        pos = b;
+        end = e;
+        const uint4 pad = make_uint4(kPadEntry, kPadEntry, kPadEntry, kPadEntry);
+        cur = b < e ? *reinterpret_cast<const uint4*>(ent + b) : pad;
+        nxt = b + 4 < e ? *reinterpret_cast<const uint4*>(ent + b + 4) : pad;
+    }
+    __device__ inline uint32_t peek() const
+    {
+        const int sl = (int)(pos & 3);
+        return sl == 0 ? cur.x : sl == 1 ? cur.y : sl == 2 ? cur.z : cur.w;
+    }
+    __device__ inline void advance(const uint32_t* ent)
+    {
+        ++pos;
+        if ((pos & 3) == 0) {
+            cur = nxt;
+            nxt = pos + 4 < end ? *reinterpret_cast<const uint4*>(ent + pos + 4)
+                                : make_uint4(kPadEntry, kPadEntry, kPadEntry, kPadEntry);
+        }
+    }
+};
+#endif
 
 // ---------------------------------------------------------------------------
 // View of the workspace, passed by value to kernels.
@@ -134,6 +168,14 @@ struct Ws {
     int32_t* grp_cnt;      // [2 k_max] group sizes
     int32_t* grp_off;      // [2 k_max + 1] group offsets in perm
     int32_t* grp_cur;      // [2 k_max] scatter cursors
+    unsigned long long* nsub_prev;   // [2 k_max] n_{k,r} at the start of the sweep
+    // blocked copy of the counts for the matrix cores: cell blocks of
+    // kBlkCells cells x gene chunks of kBlkGenes genes, one segment per
+    // (block, chunk), entries (cell in block | gene in chunk << 8 | count << 16)
+    const uint32_t* blk_ent;
+    int64_t* blk_off;      // [nblk * nch + 1] segment offsets (multiples of 4)
+    int32_t nblk;
+    int32_t nch;
     int32_t* relab_c;      // [2 k_max] new cluster of an old (k, r)
     uint8_t* relab_s;      // [2 k_max] new sub-label of an old (k, r); 0xFF keeps it
     double* sm_logr;       // [k_max + k_max (k_max - 1) / 2]

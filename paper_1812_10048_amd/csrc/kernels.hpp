@@ -12,6 +12,22 @@ void launch_pack(const int64_t* row_ptr, const int32_t* col, const int32_t* val,
                  int64_t* roff, int64_t* tile_sums, uint32_t* ent, DevState* st, hipStream_t s);
 void launch_init_labels(const Ws& ws, int32_t k_init, int32_t* c, uint8_t* cs, hipStream_t s);
 void launch_stats(const Ws& ws, const int32_t* c, const uint8_t* cs, hipStream_t s);
+void launch_sort(const Ws& ws, const int32_t* c, const uint8_t* cs, int by_cluster, hipStream_t s);
+
+// layout.hip
+void launch_build_blocked(const Ws& ws, int64_t* tile_sums, hipStream_t s);
+
+// substats.hip
+struct SubArgs {
+    const int32_t* c_old;
+    const uint8_t* cs_old;
+    const int32_t* c_new;
+    uint8_t* cs_new;
+    uint32_t step;
+    float* dbg;
+    int32_t dbg_stride;
+};
+void launch_sub_stats(const Ws& ws, const SubArgs& a, hipStream_t s);
 void launch_compact(const Ws& ws, int after_sweep, hipStream_t s);
 void launch_relabel(const Ws& ws, int32_t* c, uint8_t* cs, hipStream_t s);
 void launch_check_labels(const Ws& ws, const int32_t* c, const uint8_t* cs, int32_t K, hipStream_t s);
@@ -30,10 +46,12 @@ struct AssignArgs {
     int32_t dbg_stride;
     int32_t refine;       // queue uncertain decisions for the FP64 re-score
     float refine_tol;     // extra relative-margin threshold (0: bound only)
+    int32_t k_hint;       // recent K known to the host (sizes the MFMA column tiles)
 };
 void launch_assign_fp32(const Ws& ws, const AssignArgs& a, hipStream_t s);
 void launch_assign_fp64(const Ws& ws, const AssignArgs& a, hipStream_t s);
 void launch_assign_bf16(const Ws& ws, const AssignArgs& a, hipStream_t s);
+hipError_t configure_assign_bf16();
 void launch_refine(const Ws& ws, const AssignArgs& a, hipStream_t s);
 
 // splitmerge.hip

@@ -150,13 +150,13 @@ __global__ void __launch_bounds__(kRedrawThreads) k_redraw(Ws ws, uint32_t step,
         if (r < 0) {
             ws.lc32[(int64_t)u * ws.kpad + k] = (float)v;
             if (write_split) {
-                // split-BF16: hi = bf16(v), lo = bf16(v - hi), in the
-                // gene-major layout [Gpad][kpad] of the MFMA kernel
+                // split-BF16: hi = bf16(v), lo = bf16(v - hi), cluster-major
+                // [k][Gpad] as the MFMA kernel stages them
                 const float f = (float)v;
                 const uint16_t hi = bf16_bits(f);
                 const uint16_t lo = bf16_bits((float)(v - (double)bf16_value(hi)));
-                ws.lhi[(int64_t)u * ws.kpad + k] = hi;
-                ws.llo[(int64_t)u * ws.kpad + k] = lo;
+                ws.lhi[(int64_t)k * ws.Gpad + u] = hi;
+                ws.llo[(int64_t)k * ws.Gpad + u] = lo;
             }
         } else {
             ls[((int64_t)u * ws.k_max + k) * 2 + r] = (float)v;

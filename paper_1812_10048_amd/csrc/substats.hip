@@ -1,0 +1,164 @@
+// substats.hip -- the sub-cluster draw (Section 2.3, eq. 8) fused with the
+// integer sufficient statistics (step a4).
+//
+// After the cluster draw, the cells are counting-sorted by their new cluster
+// (`perm`, offsets `grp_off`).  A workgroup takes kSubCells consecutive
+// sorted cells, i.e. one run (or a few) of a single cluster k.  For each run
+// it stages thetabar_{k,0} and thetabar_{k,1} (FP64) in LDS; each wavefront
+// then reads whole rows with 16-byte loads (256 entries per instruction),
+// forms the two FP64 sub-cluster log-likelihoods (fixed-order wavefront
+// reduction), draws cbar_i by Gumbel-max with weights nbar_{k,r} less the
+// cell's own old membership, and adds the row's counts to the LDS histogram
+// of (k, cbar_i).  The histograms are flushed with one 64-bit atomic per
+// non-zero gene.  The matrix is read once for both jobs.
+#include "dpmm_common.hpp"
+#include "kernels.hpp"
+
+namespace dpmm {
+
+constexpr int kSubThreads = 256;
+constexpr int kSubCells = 1024;          // sorted cells per workgroup
+constexpr int kSubStageGenes = 2048;     // thetabar rows staged in LDS up to this G
+constexpr int kSubHistGenes = 8192;      // LDS histograms up to this G
+
+__device__ inline double wave_sum(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__global__ void __launch_bounds__(kSubThreads) k_sub_stats(Ws ws, SubArgs a)
+{
+    extern __shared__ __attribute__((aligned(16))) char lds[];
+    const int G = ws.G;
+    const bool stage = G <= kSubStageGenes;
+    const bool lhist = G <= kSubHistGenes;
+    double* th = reinterpret_cast<double*>(lds);                        // [2][G] if staged
+    uint32_t* hist = reinterpret_cast<uint32_t*>(lds + (stage ? 16 * (size_t)G : 0));   // [2][G]
+    __shared__ uint32_t ncnt[2];
+    const int K = ws.st->K;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int64_t p0 = (int64_t)blockIdx.x * kSubCells;
+    const int64_t p1 = min(ws.N, p0 + kSubCells);
+    if (p0 >= p1) return;
+    // first cluster whose run reaches p0
+    int k = 0;
+    {
+        int lo = 0, hi = K;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (ws.grp_off[mid] <= p0) lo = mid;
+            else hi = mid;
+        }
+        k = lo;
+    }
+    for (; k < K && ws.grp_off[k] < p1; ++k) {
+        const int64_t r0 = max(p0, (int64_t)ws.grp_off[k]);
+        const int64_t r1 = min(p1, (int64_t)ws.grp_off[k + 1]);
+        if (r0 >= r1) continue;
+        const bool reset = ws.reset[k] != 0;
+        const double* g0 = ws.lt64 + (int64_t)(ws.k_max + 2 * k) * G;
+        const double* g1 = g0 + G;
+        __syncthreads();
+        if (stage && !reset)
+            for (int u = threadIdx.x; u < G; u += kSubThreads) {
+                th[u] = g0[u];
+                th[G + u] = g1[u];
+            }
+        if (lhist)
+            for (int u = threadIdx.x; u < 2 * G; u += kSubThreads) hist[u] = 0;
+        if (threadIdx.x < 2) ncnt[threadIdx.x] = 0;
+        __syncthreads();
+        const double* t0 = stage ? th : g0;
+        const double* t1 = stage ? th + G : g1;
+        for (int64_t p = r0 + wave; p < r1; p += kSubThreads / 64) {
+            const int64_t i = ws.perm[p];
+            const int64_t b = ws.roff[i], e = ws.roff[i + 1];
+            int sub;
+            double s0 = 0.0, s1 = 0.0;
+            if (reset) {
+                const Words w = philox(ws.seed, (uint32_t)i, 0u, a.step, kResub, 0u);
+                sub = (int)(w.w[0] >> 31);
+            } else {
+                for (int64_t q = b + 4 * lane; q < e; q += 256) {
+                    const uint4 v = *reinterpret_cast<const uint4*>(ws.ent + q);
+                    const uint32_t en[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const uint32_t x = en[j] >> 16;
+                        if (!x) continue;
+                        const int g = (int)(en[j] & 0xFFFFu);
+                        s0 = fma((double)x, t0[g], s0);
+                        s1 = fma((double)x, t1[g], s1);
+                    }
+                }
+                s0 = wave_sum(s0);
+                s1 = wave_sum(s1);
+                const int32_t c_old = a.c_old[i];
+                const int s_old = a.cs_old[i] & 1;
+                const long long w0 = (long long)ws.nsub_prev[2 * k] - ((c_old == k && s_old == 0) ? 1 : 0);
+                const long long w1 = (long long)ws.nsub_prev[2 * k + 1] - ((c_old == k && s_old == 1) ? 1 : 0);
+                double lw0, lw1;
+                if (w0 == 0 && w1 == 0) {
+                    lw0 = lw1 = 0.0;
+                } else {
+                    lw0 = w0 > 0 ? log((double)w0) : -INFINITY;
+                    lw1 = w1 > 0 ? log((double)w1) : -INFINITY;
+                }
+                const Words w = philox(ws.seed, (uint32_t)i, 0u, a.step, kGumbelS, 0u);
+                const double v0 = lw0 + s0 + (-log(-log(unit23d(w.w[0]))));
+                const double v1 = lw1 + s1 + (-log(-log(unit23d(w.w[1]))));
+                sub = v1 > v0 ? 1 : 0;
+            }
+            // statistics of (k, sub)
+            unsigned long long* grow = ws.ssub + (int64_t)(2 * k + sub) * G;
+            for (int64_t q = b + 4 * lane; q < e; q += 256) {
+                const uint4 v = *reinterpret_cast<const uint4*>(ws.ent + q);
+                const uint32_t en[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const uint32_t x = en[j] >> 16;
+                    if (!x) continue;
+                    const uint32_t g = en[j] & 0xFFFFu;
+                    if (lhist) atomicAdd(&hist[sub * G + g], x);
+                    else atomicAdd(&grow[g], (unsigned long long)x);
+                }
+            }
+            if (lane == 0) {
+                atomicAdd(&ncnt[sub], 1u);
+                a.cs_new[i] = (uint8_t)sub;
+                if (a.dbg && K + 2 <= a.dbg_stride) {
+                    a.dbg[i * a.dbg_stride + K] = reset ? __builtin_nanf("") : (float)s0;
+                    a.dbg[i * a.dbg_stride + K + 1] = reset ? __builtin_nanf("") : (float)s1;
+                }
+            }
+        }
+        __syncthreads();
+        if (lhist) {
+            unsigned long long* row = ws.ssub + (int64_t)(2 * k) * G;
+            for (int u = threadIdx.x; u < 2 * G; u += kSubThreads) {
+                const uint32_t v = hist[u];
+                if (v) atomicAdd(&row[u], (unsigned long long)v);
+            }
+        }
+        if (threadIdx.x < 2 && ncnt[threadIdx.x])
+            atomicAdd(&ws.nsub[2 * k + threadIdx.x], (unsigned long long)ncnt[threadIdx.x]);
+    }
+}
+
+void launch_sub_stats(const Ws& ws, const SubArgs& a, hipStream_t s)
+{
+    // counts at the start of the sweep feed eq. 8; the new ones accumulate from zero
+    hipMemcpyAsync(ws.nsub_prev, ws.nsub, sizeof(unsigned long long) * 2 * (size_t)ws.k_max, hipMemcpyDeviceToDevice, s);
+    hipMemsetAsync(ws.nsub, 0, sizeof(unsigned long long) * 2 * (size_t)ws.k_max, s);
+    hipMemsetAsync(ws.ssub, 0, sizeof(unsigned long long) * 2 * (size_t)ws.k_max * (size_t)ws.G, s);
+    launch_sort(ws, a.c_new, a.cs_old, 1, s);
+    size_t lds = 0;
+    if (ws.G <= kSubStageGenes) lds += 16 * (size_t)ws.G;
+    if (ws.G <= kSubHistGenes) lds += 8 * (size_t)ws.G;
+    hipLaunchKernelGGL(k_sub_stats, dim3((unsigned)((ws.N + kSubCells - 1) / kSubCells)), dim3(kSubThreads), lds, s,
+                       ws, a);
+}
+
+}  // namespace dpmm

@@ -110,7 +110,7 @@ def test_init_state_matches_oracle(k_init):
     _compare_stats(o, s)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "split_bf16"])
 def test_chain_lockstep_small_recipe(precision):
     """Two independent chains, one per implementation, from the same seed:
     identical at every sweep and split/merge while no near-tie occurs."""
@@ -140,16 +140,22 @@ def test_chain_lockstep_small_recipe(precision):
     _say("K", st["K"], "refined", st["refined"], "splits", st["splits_accepted"], "merges", st["merges_accepted"])
 
 
-def test_fp32_sweep_at_68k_cells_matches_oracle():
+SCORE_TOL = {"fp32": 1e-4, "split_bf16": 3e-5}
+
+
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
+def test_sweep_at_68k_cells_matches_oracle(precision):
     """The 68,000 x 1,000 recipe: one sweep and one split/merge from a state
-    reached by the oracle, with the FP32 log-likelihoods checked cell by cell."""
-    _say("c2 full size")
+    reached by the oracle, with the log-likelihoods checked cell by cell
+    (FP32: 1e-4 relative; split-BF16: 3e-5 relative, its certified bound is
+    about 1.5e-5)."""
+    _say("c2 full size", precision)
     d = synth.generate("c2", seed=0)
     kw = dict(alpha=1.0, beta=1.0, seed=5, k_max=64)
     o = _oracle(d, k_init=1, **kw)
     o.iterate(6)
     snap = o.snapshot()
-    s = _sampler(d, "fp32", k_init=1, **kw)
+    s = _sampler(d, precision, k_init=1, **kw)
     s.set_state(snap["step"], snap["K"], snap["c"], snap["cs"], snap["reset"])
     _compare_stats(o, s)
     K = o.K
@@ -169,9 +175,13 @@ def test_fp32_sweep_at_68k_cells_matches_oracle():
     assert K2 <= K
     gk = got[:, :K2]
     rk = ref[:, :K2]
-    assert np.all(np.abs(gk - rk) <= 1e-4 * np.abs(rk) + 1e-3)
+    tol = SCORE_TOL[precision]
+    rel = np.abs(gk - rk) / np.maximum(1.0, np.abs(rk))
+    _say("max relative log-likelihood error", float(rel.max()), "median", float(np.median(rel)))
+    assert np.all(np.abs(gk - rk) <= tol * np.abs(rk) + 1e-3)
     live = ~np.isnan(got[:, K2])   # cells of clusters not flagged for reset
-    assert np.all(np.abs(got[live, K2:K2 + 2] - ref[live, K2:K2 + 2]) <= 1e-4 * np.abs(ref[live, K2:K2 + 2]) + 1e-3)
+    # the two sub-cluster scores are FP64 in every precision
+    assert np.all(np.abs(got[live, K2:K2 + 2] - ref[live, K2:K2 + 2]) <= 1e-6 * np.abs(ref[live, K2:K2 + 2]) + 1e-3)
     s.debug_scores(None)
     o.split_merge()
     s.split_merge()
@@ -223,7 +233,7 @@ def test_edge_cases():
     # a cell with no counts, a single gene, a single cell
     X = np.array([[0, 3, 1], [0, 0, 0], [5, 0, 2], [1, 1, 1]])
     d = synth.from_dense(X)
-    for prec in ("fp64", "fp32"):
+    for prec in ("fp64", "fp32", "split_bf16"):
         o = _oracle(d, seed=1, k_max=4, k_init=2)
         s = _sampler(d, prec, seed=1, k_max=4, k_init=2)
         for _ in range(6):
@@ -285,8 +295,8 @@ def test_resume_reproduces_the_chain():
         assert np.array_equal(cx, ca) and np.array_equal(csx, csa)
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp64"])
-@pytest.mark.parametrize("k_init", [24, 40, 56, 70])
+@pytest.mark.parametrize("precision", ["fp32", "fp64", "split_bf16"])
+@pytest.mark.parametrize("k_init", [12, 24, 40, 56, 70])
 def test_many_cluster_kernel_paths(precision, k_init):
     """Cluster counts that select each register-tile width of the assignment
     kernel, its cluster-group loop (K > 64) and the gathered sub-cluster pass."""
@@ -307,3 +317,24 @@ def test_many_cluster_kernel_paths(precision, k_init):
         _compare_hastings(o, s)
         assert _compare_labels(o, s, f"paths sm {it}") == 0
         _compare_stats(o, s)
+
+
+def test_split_bf16_tables_are_hi_lo_of_log_theta():
+    """Row a8: hi = bf16(fp32(log theta)), lo = bf16(fp32(log theta - hi)),
+    round to nearest even, and |log theta - hi - lo| <= 2^-17 |log theta|."""
+    _say("split tables")
+    d = synth.generate("c1", seed=3, n_cells=1500)
+    s = _sampler(d, "split_bf16", seed=4, k_max=16, k_init=3, beta=0.3)
+    s.sweep(2)
+    K = s.K
+    _, lt = s.params()
+    lt = lt[:K]
+    hi, lo = s.split_tables()
+    hi_f = hi.view(torch.bfloat16).float().double()
+    lo_f = lo.view(torch.bfloat16).float().double()
+    exp_hi = lt.float().bfloat16()
+    assert torch.equal(hi.view(torch.bfloat16), exp_hi)
+    exp_lo = (lt - exp_hi.double()).float().bfloat16()
+    assert torch.equal(lo.view(torch.bfloat16), exp_lo)
+    resid = (lt - hi_f - lo_f).abs()
+    assert bool((resid <= 2.0 ** -17 * lt.abs() + 1e-300).all())

@@ -84,6 +84,8 @@ def main() -> int:
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the plain FP32 reference run")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="copy a buffer of this many MiB once before the run, to calibrate memory counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is described "
@@ -144,6 +146,13 @@ def main() -> int:
         smp.close()
         return res
 
+    if args.copy_probe_mb:
+        src = torch.empty(args.copy_probe_mb << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: {args.copy_probe_mb} MiB read + {args.copy_probe_mb} MiB written")
+        del src, dst
     main_run = run(args.precision)
     cmp = None
     if args.precision != "fp32" and not args.no_compare:

@@ -42,7 +42,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
 struct Layout {
     size_t ent, roff, tiles, c0, c1, cs0, cs1, st, reset, nsub, ssub, beta, logpi, lt64, lc32, ls32, lhi, llo,
-        refine, perm, grp_cnt, grp_off, grp_cur, nsub_prev, blk_ent, blk_off, relab_c, relab_s, sm_logr, sm_acc, mkey, mlist, dm_k, eb_tmp, total;
+        refine, perm, srow, grp_cnt, grp_off, grp_cur, nsub_prev, blk_ent, blk_off, ovf_off, ovf_ent, relab_c, relab_s, sm_logr, sm_acc, mkey, mlist, dm_k, eb_tmp, total;
 };
 
 int32_t num_blocks(int64_t N) { return (int32_t)((N + kBlkCells - 1) / kBlkCells); }
@@ -80,12 +80,15 @@ Layout plan(int64_t N, int32_t G, int64_t nnz, int32_t k_max, int32_t precision)
     L.llo = take(2 * (size_t)Gpad * (size_t)(kpad + kTablePadRows));
     L.refine = take(4 * (size_t)N);
     L.perm = take(4 * (size_t)N);
+    L.srow = take(16 * (size_t)N);
     L.grp_cnt = take(8 * (size_t)k_max);
     L.grp_off = take(8 * (size_t)k_max + 4);
     L.grp_cur = take(8 * (size_t)k_max);
     L.nsub_prev = take(16 * (size_t)k_max);
     L.blk_ent = take(blocked ? 4 * (size_t)(nnz + 3 * nseg) : 0);
     L.blk_off = take(blocked ? 8 * (size_t)(nseg + 1) : 0);
+    L.ovf_off = take(blocked ? 8 * (size_t)(num_blocks(N) + 1) : 0);
+    L.ovf_ent = take(blocked ? 8 * (size_t)(nnz > 0 ? nnz : 1) : 0);   // at most every entry
     L.relab_c = take(8 * (size_t)k_max);
     L.relab_s = take(2 * (size_t)k_max);
     L.sm_logr = take(8 * (size_t)ncand);
@@ -238,12 +241,15 @@ dpmm_status dpmm_init(const dpmm_csr* csr, const dpmm_params* params, void* work
     ws.llo = (uint16_t*)(base + L.llo);
     ws.refine = (uint32_t*)(base + L.refine);
     ws.perm = (int32_t*)(base + L.perm);
+    ws.srow = (uint4*)(base + L.srow);
     ws.grp_cnt = (int32_t*)(base + L.grp_cnt);
     ws.grp_off = (int32_t*)(base + L.grp_off);
     ws.grp_cur = (int32_t*)(base + L.grp_cur);
     ws.nsub_prev = (unsigned long long*)(base + L.nsub_prev);
     ws.blk_ent = (const uint32_t*)(base + L.blk_ent);
     ws.blk_off = (int64_t*)(base + L.blk_off);
+    ws.ovf_off = (int64_t*)(base + L.ovf_off);
+    ws.ovf_ent = (uint2*)(base + L.ovf_ent);
     ws.nblk = num_blocks(csr->n_cells);
     ws.nch = num_chunks(csr->n_genes);
     ws.relab_c = (int32_t*)(base + L.relab_c);

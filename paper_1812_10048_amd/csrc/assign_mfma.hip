@@ -13,10 +13,12 @@
 // blocked layout; wavefront w owns cells 64w .. 64w + 63 (4 row tiles of 16).
 // For each chunk of 64 genes: the workgroup stages the hi/lo chunk of
 // log theta cluster-major, reads the chunk's segment with coalesced 16-byte
-// loads and writes each entry into the dense BF16 tile in LDS (entry-parallel,
-// balanced), then each wavefront issues 2 k-steps x 4 row tiles x Nt column
-// tiles x 2 (hi, lo) MFMAs, and the entries are cleared again.  Counts above
-// 256 go to a short LDS list whose FP32 corrections are added to the scores.
+// loads and writes each pre-encoded entry (BF16 value at its LDS byte offset)
+// into the dense tile, then each wavefront issues 2 k-steps x 4 row tiles x
+// Nt column tiles x 2 (hi, lo) MFMAs, and the entries are cleared again.  The
+// next chunk's entries and log theta rows are loaded into registers while
+// this chunk computes.  Counts above 256 come from a static per-block list
+// whose FP32 corrections are added to the scores.
 // The cell's lane then takes the Gumbel-max over the K scores with a
 // certified rounding bound; close decisions are queued for the FP64 re-score.
 #include "dpmm_common.hpp"
@@ -28,8 +30,10 @@ typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float floatx4_t;
 
 constexpr int kMfmaThreads = kBlkCells;       // 256: one thread per cell
-constexpr int kMfmaRow = kBlkGenes + 8;       // BF16 elements per LDS tile row (padded)
-constexpr int kOvfCap = 1024;                 // counts > 256 per block and column group
+constexpr int kMfmaRow = kBlkRow;             // BF16 elements per LDS tile row (padded)
+constexpr int kPrefetch = 4;                  // segment entries held in registers: 4 x 4 per thread
+constexpr uint32_t kPadSlot = (uint32_t)(kBlkGenes * 2) << 16;   // writes into a padding column
+constexpr int kMaxChunks = (65535 + kBlkGenes - 1) / kBlkGenes;
 
 __host__ __device__ constexpr size_t mfma_main_bytes(int nt)
 {
@@ -39,21 +43,11 @@ __host__ __device__ constexpr size_t mfma_main_bytes(int nt)
                ? (size_t)(kBlkCells * kMfmaRow * 2 + 2 * 16 * nt * kMfmaRow * 2)
                : (size_t)kBlkCells * (16 * nt + 1) * 4;
 }
-__host__ __device__ constexpr size_t mfma_lds_bytes(int nt) { return mfma_main_bytes(nt) + 8 * (size_t)kOvfCap; }
+__host__ __device__ constexpr size_t mfma_lds_bytes(int nt) { return mfma_main_bytes(nt); }
 
-__device__ inline uint16_t bf16_of_count(uint32_t x)
-{
-    // at most 8 significant bits: the float is exact and its top half is the BF16 value
-    return (uint16_t)(__float_as_uint((float)x) >> 16);
-}
-
-// x = xa + xb with xa keeping the top 8 significant bits of x
-__device__ inline uint32_t count_head(uint32_t x)
-{
-    if (x <= 256u) return x;
-    const int sh = (32 - __clz((int)x)) - 8;
-    return (x >> sh) << sh;
-}
+// one pre-encoded entry into the tile: BF16 value at its byte offset
+__device__ inline void put(char* tile, uint32_t en) { *reinterpret_cast<uint16_t*>(tile + (en >> 16)) = (uint16_t)en; }
+__device__ inline void wipe(char* tile, uint32_t en) { *reinterpret_cast<uint16_t*>(tile + (en >> 16)) = 0; }
 
 __device__ inline float gumbel32(uint32_t w) { return -logf(-logf(unit23f(w))); }
 
@@ -69,13 +63,10 @@ template <int NT>
 __global__ void __launch_bounds__(kMfmaThreads) k_assign_bf16(Ws ws, AssignArgs a)
 {
     extern __shared__ __attribute__((aligned(16))) char lds[];
-    __shared__ int s_novf;
-    __shared__ uint8_t s_force[kBlkCells];
     uint16_t* atile = reinterpret_cast<uint16_t*>(lds);
     uint16_t* bhi = atile + kBlkCells * kMfmaRow;
     uint16_t* blo = bhi + 16 * NT * kMfmaRow;
     float* sc = reinterpret_cast<float*>(lds);                         // epilogue alias
-    uint2* ovf = reinterpret_cast<uint2*>(lds + mfma_main_bytes(NT));  // (cell | gene << 8, extra count)
     constexpr int SS = 16 * NT + 1;
 
     const int K = ws.st->K;
@@ -86,7 +77,11 @@ __global__ void __launch_bounds__(kMfmaThreads) k_assign_bf16(Ws ws, AssignArgs 
     const int64_t i = (int64_t)blk * kBlkCells + t;
     const bool valid = i < ws.N;
     const int64_t* soff = ws.blk_off + (int64_t)blk * ws.nch;
-    s_force[t] = 0;
+    const uint32_t* bent = ws.blk_ent + soff[0];       // this block's entries, 32-bit offsets below
+    // the block's segment offsets, relative to its first entry, once into LDS
+    __shared__ uint32_t s_off[kMaxChunks + 1];
+    for (int q = t; q <= ws.nch; q += kMfmaThreads) s_off[q] = (uint32_t)(soff[q] - soff[0]);
+    __syncthreads();
 
     float t1 = -INFINITY, t2 = -INFINITY, a1 = 0.f, a2 = 0.f, p1 = 0.f, p2 = 0.f;
     int k1 = 0;
@@ -102,42 +97,63 @@ __global__ void __launch_bounds__(kMfmaThreads) k_assign_bf16(Ws ws, AssignArgs 
         // clear the tile once; afterwards only written entries are cleared
         for (int g = 0; g < kMfmaRow; g += 8)
             *reinterpret_cast<uint4*>(atile + t * kMfmaRow + g) = make_uint4(0, 0, 0, 0);
-        if (t == 0) s_novf = 0;
+
+        // software pipeline: the next chunk's B rows and first kPrefetch x 4
+        // segment entries are loaded into registers while this chunk computes
+        uint4 nb[NT], cur[kPrefetch], nxt[kPrefetch];
+        const uint4 pad4 = make_uint4(kPadSlot, kPadSlot, kPadSlot, kPadSlot);
+        uint32_t ce0 = 0, ce1 = 0, ne0 = 0, ne1 = s_off[1];
+        auto load_chunk = [&](int jj, uint4* seg, uint32_t f0, uint32_t f1) {
+#pragma unroll
+            for (int r = 0; r < NT; ++r) {
+                const int idx = t + r * kMfmaThreads;           // < 2 * 16 NT * 8
+                const int tbl = idx / (16 * NT * (kBlkGenes / 8));
+                const int rem = idx % (16 * NT * (kBlkGenes / 8));
+                const int row = rem / (kBlkGenes / 8);
+                const int sg = rem % (kBlkGenes / 8);
+                nb[r] = *reinterpret_cast<const uint4*>((tbl ? ws.llo : ws.lhi) + (int64_t)(kb + row) * ws.Gpad +
+                                                        jj * kBlkGenes + sg * 8);
+            }
+#pragma unroll
+            for (int r = 0; r < kPrefetch; ++r) {
+                const uint32_t q = f0 + 4 * t + 4 * kMfmaThreads * r;
+                seg[r] = q < f1 ? *reinterpret_cast<const uint4*>(bent + q) : pad4;
+            }
+        };
+        load_chunk(0, nxt, ne0, ne1);
 
         for (int j = 0; j < ws.nch; ++j) {
             const int c0 = j * kBlkGenes;
             __syncthreads();
-            // hi/lo rows kb .. kb + 16 NT, genes c0 .. c0 + 64, 16-byte copies
-            for (int idx = t; idx < 2 * 16 * NT * (kBlkGenes / 8); idx += kMfmaThreads) {
+            // commit chunk j: B rows to LDS, entries into the tile
+#pragma unroll
+            for (int r = 0; r < NT; ++r) {
+                const int idx = t + r * kMfmaThreads;
                 const int tbl = idx / (16 * NT * (kBlkGenes / 8));
                 const int rem = idx % (16 * NT * (kBlkGenes / 8));
                 const int row = rem / (kBlkGenes / 8);
-                const int seg = rem % (kBlkGenes / 8);
-                const uint16_t* src = (tbl ? ws.llo : ws.lhi) + (int64_t)(kb + row) * ws.Gpad + c0 + seg * 8;
-                uint16_t* dst = (tbl ? blo : bhi) + row * kMfmaRow + seg * 8;
-                *reinterpret_cast<uint4*>(dst) = *reinterpret_cast<const uint4*>(src);
+                const int sg = rem % (kBlkGenes / 8);
+                *reinterpret_cast<uint4*>((tbl ? blo : bhi) + row * kMfmaRow + sg * 8) = nb[r];
             }
-            // the segment's entries into the tile
-            const int64_t e0 = soff[j], e1 = soff[j + 1];
-            for (int64_t q = e0 + 4 * t; q < e1; q += 4 * kMfmaThreads) {
-                const uint4 v = *reinterpret_cast<const uint4*>(ws.blk_ent + q);
-                const uint32_t en[4] = {v.x, v.y, v.z, v.w};
+            ce0 = ne0;
+            ce1 = ne1;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const uint32_t x = en[r] >> 16;
-                    if (!x) continue;
-                    const uint32_t cell = en[r] & 0xFFu;
-                    const uint32_t g = (en[r] >> 8) & 0x3Fu;
-                    const uint32_t xa = count_head(x);
-                    atile[cell * kMfmaRow + g] = bf16_of_count(xa);
-                    if (xa != x) {
-                        const int o = atomicAdd(&s_novf, 1);
-                        if (o < kOvfCap) ovf[o] = make_uint2(cell | ((uint32_t)(c0 + g) << 8), x - xa);
-                        else s_force[cell] = 1;
-                    }
-                }
+            for (int r = 0; r < kPrefetch; ++r) cur[r] = nxt[r];
+            char* tileb = reinterpret_cast<char*>(atile);
+#pragma unroll
+            for (int r = 0; r < kPrefetch; ++r) {
+                put(tileb, cur[r].x); put(tileb, cur[r].y); put(tileb, cur[r].z); put(tileb, cur[r].w);
+            }
+            for (uint32_t q = ce0 + 4 * t + 4 * kMfmaThreads * kPrefetch; q < ce1; q += 4 * kMfmaThreads) {
+                const uint4 v = *reinterpret_cast<const uint4*>(bent + q);
+                put(tileb, v.x); put(tileb, v.y); put(tileb, v.z); put(tileb, v.w);
             }
             __syncthreads();
+            if (j + 1 < ws.nch) {
+                ne0 = s_off[j + 1];
+                ne1 = s_off[j + 2];
+                load_chunk(j + 1, nxt, ne0, ne1);
+            }
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
                 const int col = 32 * s + 8 * (lane >> 4);
@@ -148,22 +164,27 @@ __global__ void __launch_bounds__(kMfmaThreads) k_assign_bf16(Ws ws, AssignArgs 
 #pragma unroll
                 for (int n = 0; n < NT; ++n) {
                     const bf16x8_t bh = *reinterpret_cast<const bf16x8_t*>(bhi + (16 * n + (lane & 15)) * kMfmaRow + col);
+#pragma unroll
+                    for (int m = 0; m < 4; ++m)
+                        acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[m], bh, acc[m][n], 0, 0, 0);
+                }
+#pragma unroll
+                for (int n = 0; n < NT; ++n) {
                     const bf16x8_t bl = *reinterpret_cast<const bf16x8_t*>(blo + (16 * n + (lane & 15)) * kMfmaRow + col);
 #pragma unroll
-                    for (int m = 0; m < 4; ++m) {
-                        acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[m], bh, acc[m][n], 0, 0, 0);
+                    for (int m = 0; m < 4; ++m)
                         acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[m], bl, acc[m][n], 0, 0, 0);
-                    }
                 }
             }
             __syncthreads();
-            // clear the written entries (same loads, now from cache)
-            for (int64_t q = e0 + 4 * t; q < e1; q += 4 * kMfmaThreads) {
-                const uint4 v = *reinterpret_cast<const uint4*>(ws.blk_ent + q);
-                const uint32_t en[4] = {v.x, v.y, v.z, v.w};
+            // clear the written entries: the first ones are still in registers
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    if (en[r] >> 16) atile[(en[r] & 0xFFu) * kMfmaRow + ((en[r] >> 8) & 0x3Fu)] = 0;
+            for (int r = 0; r < kPrefetch; ++r) {
+                wipe(tileb, cur[r].x); wipe(tileb, cur[r].y); wipe(tileb, cur[r].z); wipe(tileb, cur[r].w);
+            }
+            for (uint32_t q = ce0 + 4 * t + 4 * kMfmaThreads * kPrefetch; q < ce1; q += 4 * kMfmaThreads) {
+                const uint4 v = *reinterpret_cast<const uint4*>(bent + q);
+                wipe(tileb, v.x); wipe(tileb, v.y); wipe(tileb, v.z); wipe(tileb, v.w);
             }
         }
         __syncthreads();
@@ -177,10 +198,9 @@ __global__ void __launch_bounds__(kMfmaThreads) k_assign_bf16(Ws ws, AssignArgs 
                 for (int q = 0; q < 4; ++q)
                     sc[(64 * wave + 16 * m + 4 * (lane >> 4) + q) * SS + 16 * n + (lane & 15)] = acc[m][n][q];
         __syncthreads();
-        // FP32 corrections of the counts above 256
-        const int novf = min(s_novf, kOvfCap);
-        for (int o = t; o < novf; o += kMfmaThreads) {
-            const uint2 ov = ovf[o];
+        // FP32 corrections of the counts above 256 (static list of this block)
+        for (int64_t o = ws.ovf_off[blk] + t; o < ws.ovf_off[blk + 1]; o += kMfmaThreads) {
+            const uint2 ov = ws.ovf_ent[o];
             const int cell = (int)(ov.x & 0xFFu);
             const int g = (int)(ov.x >> 8);
             const float xb = (float)ov.y;
@@ -209,7 +229,7 @@ __global__ void __launch_bounds__(kMfmaThreads) k_assign_bf16(Ws ws, AssignArgs 
         }
     }
     if (!valid) return;
-    bool uncertain = s_force[t] != 0;
+    bool uncertain = false;
     if (K >= 2) {
         const float bnd = bf16_bound(a1, p1, nsteps) + bf16_bound(a2, p2, nsteps);
         if (t1 - t2 <= bnd || (t1 - t2) / fmaxf(1.0f, fabsf(t1)) < a.refine_tol) uncertain = true;

@@ -254,7 +254,13 @@ __global__ void __launch_bounds__(kSortThreads) k_group_scatter(Ws ws, const int
         if (k < 0 || k >= ws.k_max) continue;
         const int q = sort_group(k, cs[i], by_cluster);
         const uint32_t pos = base[q] + atomicAdd(&cnt[q], 1u);
-        if (pos < (uint32_t)ws.N) ws.perm[pos] = (int32_t)i;
+        if (pos < (uint32_t)ws.N) {
+            ws.perm[pos] = (int32_t)i;
+            // the row of the sorted cell, so that kernels walking the sorted
+            // order reach it with one load
+            const int64_t r0 = ws.roff[i];
+            ws.srow[pos] = make_uint4((uint32_t)i, (uint32_t)r0, (uint32_t)(r0 >> 32), (uint32_t)(ws.roff[i + 1] - r0));
+        }
     }
 }
 

@@ -101,6 +101,7 @@ constexpr uint32_t kPadEntry = 0x0000FFFFu;   // gene 0xFFFF, count 0
 
 constexpr int kBlkCells = 256;
 constexpr int kBlkGenes = 64;
+constexpr int kBlkRow = kBlkGenes + 8;   // BF16 elements per row of the dense LDS tile (padded)
 
 // Refine-queue flags (high bits of a queued cell index).
 constexpr uint32_t kRefineCluster = 1u << 31;
@@ -165,15 +166,18 @@ struct Ws {
     uint16_t* llo;
     uint32_t* refine;      // [N] queued cells with flags
     int32_t* perm;         // [N] cells sorted by group 2k + r (processing order of a sweep)
+    uint4* srow;           // [N] per sorted position: (cell, row offset lo, hi, row length)
     int32_t* grp_cnt;      // [2 k_max] group sizes
     int32_t* grp_off;      // [2 k_max + 1] group offsets in perm
     int32_t* grp_cur;      // [2 k_max] scatter cursors
     unsigned long long* nsub_prev;   // [2 k_max] n_{k,r} at the start of the sweep
     // blocked copy of the counts for the matrix cores: cell blocks of
     // kBlkCells cells x gene chunks of kBlkGenes genes, one segment per
-    // (block, chunk), entries (cell in block | gene in chunk << 8 | count << 16)
+    // (block, chunk), entries (BF16 count | LDS byte offset << 16)
     const uint32_t* blk_ent;
     int64_t* blk_off;      // [nblk * nch + 1] segment offsets (multiples of 4)
+    int64_t* ovf_off;      // [nblk + 1] offsets of each block's counts above 256
+    uint2* ovf_ent;        // (cell in block | gene << 8, count - its BF16 head)
     int32_t nblk;
     int32_t nch;
     int32_t* relab_c;      // [2 k_max] new cluster of an old (k, r)

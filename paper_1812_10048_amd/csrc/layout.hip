@@ -3,11 +3,16 @@
 //
 // Cells are taken in blocks of kBlkCells (in input order) and genes in chunks
 // of kBlkGenes.  Segment (b, j) holds every entry of block b's cells whose
-// gene is in chunk j, ordered by cell then gene, as
-//   cell-in-block (8 bits) | gene-in-chunk << 8 (6 bits) | count << 16,
-// and is padded with zero entries (count 0) to a multiple of four, so that a
-// workgroup reads a chunk's entries with coalesced 16-byte loads and scatters
-// them into its dense tile entry by entry, with no per-cell walk.
+// gene is in chunk j, ordered by cell then gene.  Since the counts never
+// change, each entry is stored ready for the kernel's scatter into its dense
+// BF16 tile in LDS:
+//   low 16 bits   BF16 value of the count (of its top 8 significant bits
+//                 when the count exceeds 256),
+//   high 16 bits  byte offset of (cell, gene) in the tile.
+// Segments are padded to a multiple of four with entries that write zero into
+// a padding column of the tile, so the scatter needs no test.  Counts above
+// 256 also go to a per-block list (cell, gene, count - head) whose FP32
+// corrections the kernel adds to the scores.
 #include "dpmm_common.hpp"
 #include "kernels.hpp"
 
@@ -15,23 +20,62 @@ namespace dpmm {
 
 constexpr int kLayThreads = kBlkCells;   // one thread per cell of the block
 
-// entries of each (block, chunk), padded to a multiple of 4
+__device__ inline uint32_t count_head(uint32_t x)
+{
+    if (x <= 256u) return x;
+    const int sh = (32 - __clz((int)x)) - 8;
+    return (x >> sh) << sh;
+}
+
+__device__ inline uint32_t encode_entry(int cell, int g_local, uint32_t x)
+{
+    // a count with at most 8 significant bits is exact in FP32 and BF16
+    const uint32_t bf = __float_as_uint((float)count_head(x)) >> 16;
+    const uint32_t off = (uint32_t)(cell * kBlkRow + g_local) * 2u;
+    return bf | (off << 16);
+}
+
+// entries of each (block, chunk), padded to a multiple of 4, and the number
+// of counts above 256 of each block
 __global__ void __launch_bounds__(kLayThreads) k_seg_count(Ws ws)
 {
     extern __shared__ uint32_t cnt[];    // [nch]
+    __shared__ uint32_t novf;
     const int b = blockIdx.x;
     for (int j = threadIdx.x; j < ws.nch; j += kLayThreads) cnt[j] = 0;
+    if (threadIdx.x == 0) novf = 0;
     __syncthreads();
     const int64_t i = (int64_t)b * kBlkCells + threadIdx.x;
     if (i < ws.N) {
         for (int64_t p = ws.roff[i]; p < ws.roff[i + 1]; ++p) {
             const uint32_t en = ws.ent[p];
-            if (en >> 16) atomicAdd(&cnt[(en & 0xFFFFu) / kBlkGenes], 1u);
+            const uint32_t x = en >> 16;
+            if (!x) continue;
+            atomicAdd(&cnt[(en & 0xFFFFu) / kBlkGenes], 1u);
+            if (count_head(x) != x) atomicAdd(&novf, 1u);
         }
     }
     __syncthreads();
     for (int j = threadIdx.x; j < ws.nch; j += kLayThreads)
         ws.blk_off[(int64_t)b * ws.nch + j] = (int64_t)((cnt[j] + 3u) & ~3u);
+    if (threadIdx.x == 0) ws.ovf_off[b] = (int64_t)novf;
+}
+
+__device__ inline uint32_t block_exclusive(uint32_t v, uint32_t* scan, uint32_t* total)
+{
+    const int t = threadIdx.x;
+    scan[t] = v;
+    __syncthreads();
+    for (int off = 1; off < kLayThreads; off <<= 1) {
+        const uint32_t add = t >= off ? scan[t - off] : 0u;
+        __syncthreads();
+        scan[t] += add;
+        __syncthreads();
+    }
+    const uint32_t incl = scan[t];
+    *total = scan[kLayThreads - 1];
+    __syncthreads();
+    return incl - v;
 }
 
 // write the entries: per chunk, a workgroup-wide exclusive scan of the cells'
@@ -42,9 +86,11 @@ __global__ void __launch_bounds__(kLayThreads) k_seg_fill(Ws ws)
     const int b = blockIdx.x;
     const int t = threadIdx.x;
     const int64_t i = (int64_t)b * kBlkCells + t;
-    int64_t pos = i < ws.N ? ws.roff[i] : 0;
+    const int64_t rb = i < ws.N ? ws.roff[i] : 0;
     const int64_t end = i < ws.N ? ws.roff[i + 1] : 0;
     uint32_t* out = const_cast<uint32_t*>(ws.blk_ent);
+    const uint32_t pad = (uint32_t)(kBlkGenes * 2) << 16;   // zero into cell 0's padding column
+    int64_t pos = rb;
     for (int j = 0; j < ws.nch; ++j) {
         const int hi = (j + 1) * kBlkGenes;
         uint32_t n = 0;
@@ -53,29 +99,33 @@ __global__ void __launch_bounds__(kLayThreads) k_seg_fill(Ws ws)
             if ((int)(en & 0xFFFFu) >= hi) break;
             if (en >> 16) ++n;
         }
-        scan[t] = n;
-        __syncthreads();
-        for (int off = 1; off < kLayThreads; off <<= 1) {
-            const uint32_t add = t >= off ? scan[t - off] : 0u;
-            __syncthreads();
-            scan[t] += add;
-            __syncthreads();
-        }
-        const uint32_t total = scan[kLayThreads - 1];
+        uint32_t total;
+        const uint32_t before = block_exclusive(n, scan, &total);
         const int64_t seg = ws.blk_off[(int64_t)b * ws.nch + j];
         const int64_t seg_end = ws.blk_off[(int64_t)b * ws.nch + j + 1];
-        int64_t w = seg + scan[t] - n;
+        int64_t w = seg + before;
         while (pos < end) {
             const uint32_t en = ws.ent[pos];
             const int g = (int)(en & 0xFFFFu);
             if (g >= hi) break;
-            if (en >> 16) {
-                out[w++] = (uint32_t)t | ((uint32_t)(g - j * kBlkGenes) << 8) | (en & 0xFFFF0000u);
-            }
+            if (en >> 16) out[w++] = encode_entry(t, g - j * kBlkGenes, en >> 16);
             ++pos;
         }
-        for (int64_t q = seg + total + t; q < seg_end; q += kLayThreads) out[q] = 0u;
-        __syncthreads();
+        for (int64_t q = seg + total + t; q < seg_end; q += kLayThreads) out[q] = pad;
+    }
+    // counts above 256: (cell | gene << 8, count - head)
+    uint32_t n = 0;
+    for (int64_t p = rb; p < end; ++p) {
+        const uint32_t x = ws.ent[p] >> 16;
+        if (x && count_head(x) != x) ++n;
+    }
+    uint32_t total;
+    int64_t w = ws.ovf_off[b] + block_exclusive(n, scan, &total);
+    for (int64_t p = rb; p < end; ++p) {
+        const uint32_t en = ws.ent[p];
+        const uint32_t x = en >> 16;
+        if (x && count_head(x) != x)
+            ws.ovf_ent[w++] = make_uint2((uint32_t)t | ((en & 0xFFFFu) << 8), x - count_head(x));
     }
 }
 
@@ -84,6 +134,7 @@ void launch_build_blocked(const Ws& ws, int64_t* tile_sums, hipStream_t s)
     const int64_t nseg = (int64_t)ws.nblk * ws.nch;
     hipLaunchKernelGGL(k_seg_count, dim3(ws.nblk), dim3(kLayThreads), sizeof(uint32_t) * (size_t)ws.nch, s, ws);
     launch_exclusive_scan(ws.blk_off, nseg, tile_sums, s);
+    launch_exclusive_scan(ws.ovf_off, ws.nblk, tile_sums, s);
     hipLaunchKernelGGL(k_seg_fill, dim3(ws.nblk), dim3(kLayThreads), 0, s, ws);
 }
 

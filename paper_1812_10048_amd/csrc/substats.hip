@@ -5,9 +5,9 @@
 // (`perm`, offsets `grp_off`).  A workgroup takes kSubCells consecutive
 // sorted cells, i.e. one run (or a few) of a single cluster k.  For each run
 // it stages thetabar_{k,0} and thetabar_{k,1} (FP64) in LDS; each wavefront
-// then reads whole rows with 16-byte loads (256 entries per instruction),
-// forms the two FP64 sub-cluster log-likelihoods (fixed-order wavefront
-// reduction), draws cbar_i by Gumbel-max with weights nbar_{k,r} less the
+// then works on four cells at a time, 16 lanes per cell reading the row with
+// 16-byte loads, forms the two FP64 sub-cluster log-likelihoods (fixed-order
+// reduction over the 16 lanes), draws cbar_i by Gumbel-max with weights nbar_{k,r} less the
 // cell's own old membership, and adds the row's counts to the LDS histogram
 // of (k, cbar_i).  The histograms are flushed with one 64-bit atomic per
 // non-zero gene.  The matrix is read once for both jobs.
@@ -21,9 +21,10 @@ constexpr int kSubCells = 1024;          // sorted cells per workgroup
 constexpr int kSubStageGenes = 2048;     // thetabar rows staged in LDS up to this G
 constexpr int kSubHistGenes = 8192;      // LDS histograms up to this G
 
-__device__ inline double wave_sum(double v)
+// sum over the 16 lanes of a group, in a fixed order
+__device__ inline double group_sum(double v)
 {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, 16);
     return v;
 }
 
@@ -72,50 +73,65 @@ __global__ void __launch_bounds__(kSubThreads) k_sub_stats(Ws ws, SubArgs a)
         __syncthreads();
         const double* t0 = stage ? th : g0;
         const double* t1 = stage ? th + G : g1;
-        for (int64_t p = r0 + wave; p < r1; p += kSubThreads / 64) {
-            const int64_t i = ws.perm[p];
-            const int64_t b = ws.roff[i], e = ws.roff[i + 1];
+        // log of the eq. 8 weights: nbar_{k,r}, less one when the cell was in (k, r)
+        const long long n0 = (long long)ws.nsub_prev[2 * k], n1 = (long long)ws.nsub_prev[2 * k + 1];
+        auto logw = [](long long w) { return w > 0 ? log((double)w) : -INFINITY; };
+        const double l0 = logw(n0), l0m = logw(n0 - 1), l1 = logw(n1), l1m = logw(n1 - 1);
+        // 16 lanes per cell, 4 cells per wavefront in flight; the next cell's
+        // row descriptor is loaded while this one is processed
+        const int grp = lane >> 4;
+        const int l16 = lane & 15;
+        int64_t p = r0 + wave * 4 + grp;
+        uint4 d = p < r1 ? ws.srow[p] : make_uint4(0, 0, 0, 0);
+        for (; p < r1; p += kSubThreads / 16) {
+            const int64_t pn = p + kSubThreads / 16;
+            const uint4 dn = pn < r1 ? ws.srow[pn] : make_uint4(0, 0, 0, 0);
+            const int64_t i = d.x;
+            const int64_t b = (int64_t)(((uint64_t)d.z << 32) | d.y);
+            const int64_t e = b + d.w;
             int sub;
             double s0 = 0.0, s1 = 0.0;
+            // the first 256 entries of the row: four 16-byte loads per lane, all in flight
+            uint4 v[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t q = b + 4 * l16 + 64 * r;
+                v[r] = q < e ? *reinterpret_cast<const uint4*>(ws.ent + q) : make_uint4(kPadEntry, kPadEntry, kPadEntry, kPadEntry);
+            }
+            auto dot = [&](const uint4& u) {
+                const uint32_t en[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const uint32_t x = en[j] >> 16;
+                    if (!x) continue;
+                    const int g = (int)(en[j] & 0xFFFFu);
+                    s0 = fma((double)x, t0[g], s0);
+                    s1 = fma((double)x, t1[g], s1);
+                }
+            };
             if (reset) {
                 const Words w = philox(ws.seed, (uint32_t)i, 0u, a.step, kResub, 0u);
                 sub = (int)(w.w[0] >> 31);
             } else {
-                for (int64_t q = b + 4 * lane; q < e; q += 256) {
-                    const uint4 v = *reinterpret_cast<const uint4*>(ws.ent + q);
-                    const uint32_t en[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const uint32_t x = en[j] >> 16;
-                        if (!x) continue;
-                        const int g = (int)(en[j] & 0xFFFFu);
-                        s0 = fma((double)x, t0[g], s0);
-                        s1 = fma((double)x, t1[g], s1);
-                    }
-                }
-                s0 = wave_sum(s0);
-                s1 = wave_sum(s1);
+                for (int r = 0; r < 4; ++r) dot(v[r]);
+                for (int64_t q = b + 4 * l16 + 256; q < e; q += 64) dot(*reinterpret_cast<const uint4*>(ws.ent + q));
+                s0 = group_sum(s0);
+                s1 = group_sum(s1);
                 const int32_t c_old = a.c_old[i];
                 const int s_old = a.cs_old[i] & 1;
-                const long long w0 = (long long)ws.nsub_prev[2 * k] - ((c_old == k && s_old == 0) ? 1 : 0);
-                const long long w1 = (long long)ws.nsub_prev[2 * k + 1] - ((c_old == k && s_old == 1) ? 1 : 0);
-                double lw0, lw1;
-                if (w0 == 0 && w1 == 0) {
-                    lw0 = lw1 = 0.0;
-                } else {
-                    lw0 = w0 > 0 ? log((double)w0) : -INFINITY;
-                    lw1 = w1 > 0 ? log((double)w1) : -INFINITY;
-                }
+                double lw0 = (c_old == k && s_old == 0) ? l0m : l0;
+                double lw1 = (c_old == k && s_old == 1) ? l1m : l1;
+                if (!(lw0 > -INFINITY) && !(lw1 > -INFINITY)) lw0 = lw1 = 0.0;   // both weights zero: equal
                 const Words w = philox(ws.seed, (uint32_t)i, 0u, a.step, kGumbelS, 0u);
                 const double v0 = lw0 + s0 + (-log(-log(unit23d(w.w[0]))));
                 const double v1 = lw1 + s1 + (-log(-log(unit23d(w.w[1]))));
                 sub = v1 > v0 ? 1 : 0;
             }
-            // statistics of (k, sub)
+            // statistics of (k, sub), from the registers where the row already is
             unsigned long long* grow = ws.ssub + (int64_t)(2 * k + sub) * G;
-            for (int64_t q = b + 4 * lane; q < e; q += 256) {
-                const uint4 v = *reinterpret_cast<const uint4*>(ws.ent + q);
-                const uint32_t en[4] = {v.x, v.y, v.z, v.w};
+            auto add = [&](const uint4& u) {
+                const uint32_t en[4] = {u.x, u.y, u.z, u.w};
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const uint32_t x = en[j] >> 16;
@@ -124,8 +140,11 @@ __global__ void __launch_bounds__(kSubThreads) k_sub_stats(Ws ws, SubArgs a)
                     if (lhist) atomicAdd(&hist[sub * G + g], x);
                     else atomicAdd(&grow[g], (unsigned long long)x);
                 }
-            }
-            if (lane == 0) {
+            };
+#pragma unroll
+            for (int r = 0; r < 4; ++r) add(v[r]);
+            for (int64_t q = b + 4 * l16 + 256; q < e; q += 64) add(*reinterpret_cast<const uint4*>(ws.ent + q));
+            if (l16 == 0) {
                 atomicAdd(&ncnt[sub], 1u);
                 a.cs_new[i] = (uint8_t)sub;
                 if (a.dbg && K + 2 <= a.dbg_stride) {
@@ -133,6 +152,7 @@ __global__ void __launch_bounds__(kSubThreads) k_sub_stats(Ws ws, SubArgs a)
                     a.dbg[i * a.dbg_stride + K + 1] = reset ? __builtin_nanf("") : (float)s1;
                 }
             }
+            d = dn;
         }
         __syncthreads();
         if (lhist) {

@@ -17,6 +17,7 @@ import argparse
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -44,6 +45,26 @@ def alg_bytes(n_cells: int, nnz: int) -> int:
     # packed (gene | count) entries 4 B each, padded row offsets 8 B, labels
     # read and written (int32 cluster + uint8 sub-cluster each way)
     return 4 * nnz + 8 * (n_cells + 1) + 10 * n_cells
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_assign_bf16_c5_hbm_traffic.txt")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the matrix-core kernel from the committed
+    FETCH_SIZE / WRITE_SIZE summaries (copy-calibrated), or None when they are
+    missing or the kernel's sources changed since the counters were taken."""
+    from paper_1812_10048_amd.profsum import source_digest
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    text = open(TRAFFIC_FILE).read()
+    digests = set(re.findall(r"^source digest: (\w+)", text, re.M))
+    got = {}
+    for c, v in re.findall(r"^traffic (FETCH_SIZE|WRITE_SIZE) .*?: ([0-9.eE+-]+) bytes per dispatch", text, re.M):
+        got[c] = float(v)
+    if digests != {source_digest()} or set(got) != {"FETCH_SIZE", "WRITE_SIZE"}:
+        return None
+    return got["FETCH_SIZE"] + got["WRITE_SIZE"]
 
 
 def cpu_baseline(d, K_true, budget_s: float, seed: int):
@@ -174,8 +195,9 @@ def main() -> int:
     nbytes = alg_bytes(d.n_cells, d.nnz)
     achieved = nbytes / kernel_s / 1e9
     kname = {"split_bf16": "k_assign_bf16", "fp32": "k_assign_valu<float>", "fp64": "k_assign_valu<double>"}
+    traffic = measured_traffic() if args.precision == "split_bf16" and args.workload == "c5" else None
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "kernel": kname[args.precision], "alg_bytes_per_launch": nbytes,
                 "avg_launch_ms": kms / max(1, launches)}
 

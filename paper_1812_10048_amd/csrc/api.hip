@@ -60,7 +60,7 @@ Layout plan(int64_t N, int32_t G, int64_t nnz, int32_t k_max, int32_t precision)
     const int64_t ntiles = ((N > nseg ? N : nseg) + 4095) / 4096 + 1;
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o += align_up(bytes); return at; };
-    L.ent = take(4 * (size_t)nnz_pad);
+    L.ent = take(4 * (size_t)(nnz_pad + 4));   // + one 16-byte slot of slack
     L.roff = take(8 * (size_t)(N + 1));
     L.tiles = take(8 * (size_t)(ntiles + 1));
     L.c0 = take(4 * (size_t)N);
@@ -85,7 +85,7 @@ Layout plan(int64_t N, int32_t G, int64_t nnz, int32_t k_max, int32_t precision)
     L.grp_off = take(8 * (size_t)k_max + 4);
     L.grp_cur = take(8 * (size_t)k_max);
     L.nsub_prev = take(16 * (size_t)k_max);
-    L.blk_ent = take(blocked ? 4 * (size_t)(nnz + 3 * nseg) : 0);
+    L.blk_ent = take(blocked ? 4 * (size_t)(nnz + 3 * nseg + 4) : 0);   // + one 16-byte slot of slack
     L.blk_off = take(blocked ? 8 * (size_t)(nseg + 1) : 0);
     L.ovf_off = take(blocked ? 8 * (size_t)(num_blocks(N) + 1) : 0);
     L.ovf_ent = take(blocked ? 8 * (size_t)(nnz > 0 ? nnz : 1) : 0);   // at most every entry

@@ -100,26 +100,32 @@ __device__ void cluster_pass(const Ws& ws, const AssignArgs& a, T* tab, int64_t 
             }
         }
         if (!valid) continue;
-        Words w{};
+        // fully unrolled with guards (no early exit), four clusters per Philox
+        // call: every index into acc and the words is a constant, so both
+        // stay in registers
 #pragma unroll
-        for (int k = 0; k < KT; ++k) {
-            const int kk = kb + k;
-            if (kk >= K) break;
-            if ((k & 3) == 0) w = philox(ws.seed, (uint32_t)i, (uint32_t)(kk >> 2), a.step, kGumbelC, 0u);
-            const T lp = (T)ws.logpi[kk];
-            const T v = lp + acc[k] + gumbel_of<T>(w.w[k & 3]);
-            if (a.dbg && K + 2 <= a.dbg_stride) a.dbg[i * a.dbg_stride + kk] = (float)acc[k];
-            if (v > top.v1) {
-                top.v2 = top.v1; top.a2 = top.a1; top.p2 = top.p1;
-                top.v1 = v; top.a1 = acc[k]; top.p1 = lp; top.k1 = kk;
-            } else if (v > top.v2) {
-                top.v2 = v; top.a2 = acc[k]; top.p2 = lp;
+        for (int k4 = 0; k4 < KT; k4 += 4) {
+            if (kb + k4 >= K) continue;
+            const Words w = philox(ws.seed, (uint32_t)i, (uint32_t)((kb + k4) >> 2), a.step, kGumbelC, 0u);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int kk = kb + k4 + q;
+                if (kk >= K) continue;
+                const T lp = (T)ws.logpi[kk];
+                const T v = lp + acc[k4 + q] + gumbel_of<T>(w.w[q]);
+                if (a.dbg && K + 2 <= a.dbg_stride) a.dbg[i * a.dbg_stride + kk] = (float)acc[k4 + q];
+                if (v > top.v1) {
+                    top.v2 = top.v1; top.a2 = top.a1; top.p2 = top.p1;
+                    top.v1 = v; top.a1 = acc[k4 + q]; top.p1 = lp; top.k1 = kk;
+                } else if (v > top.v2) {
+                    top.v2 = v; top.a2 = acc[k4 + q]; top.p2 = lp;
+                }
             }
         }
     }
 }
 
-template <typename T>
+template <typename T, int KT>
 __global__ void __launch_bounds__(kAssignThreads) k_assign_valu(Ws ws, AssignArgs a)
 {
     __shared__ __attribute__((aligned(16))) T tab[kTabBytes / sizeof(T)];
@@ -135,10 +141,7 @@ __global__ void __launch_bounds__(kAssignThreads) k_assign_valu(Ws ws, AssignArg
     top.v1 = top.v2 = -INFINITY;
     top.a1 = top.a2 = top.p1 = top.p2 = 0;
     top.k1 = 0;
-    if (K <= 16) cluster_pass<T, 16>(ws, a, tab, i, valid, b, e, K, top);
-    else if (K <= 32) cluster_pass<T, 32>(ws, a, tab, i, valid, b, e, K, top);
-    else if (sizeof(T) == 4 && K <= 48) cluster_pass<T, 48>(ws, a, tab, i, valid, b, e, K, top);
-    else cluster_pass<T, (sizeof(T) == 4 ? 64 : 32)>(ws, a, tab, i, valid, b, e, K, top);
+    cluster_pass<T, KT>(ws, a, tab, i, valid, b, e, K, top);
 
     uint32_t flags = 0;
     if (valid && sizeof(T) == 4 && a.refine && K >= 2) {
@@ -157,16 +160,30 @@ __global__ void __launch_bounds__(kAssignThreads) k_assign_valu(Ws ws, AssignArg
     }
 }
 
+// The cluster-group width KT is fixed at launch while K lives on the device:
+// the host passes the last K it has seen (k_hint); a larger K is covered by
+// the kernel's loop over groups of KT clusters.
+template <typename T, int KT>
+static void launch_kt(const Ws& ws, const AssignArgs& a, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_assign_valu<T, KT>), dim3((unsigned)((ws.N + kAssignThreads - 1) / kAssignThreads)),
+                       dim3(kAssignThreads), 0, s, ws, a);
+}
+
 void launch_assign_fp32(const Ws& ws, const AssignArgs& a, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_assign_valu<float>, dim3((unsigned)((ws.N + kAssignThreads - 1) / kAssignThreads)),
-                       dim3(kAssignThreads), 0, s, ws, a);
+    const int k = a.k_hint > 0 ? a.k_hint : ws.k_max;
+    if (k <= 16) launch_kt<float, 16>(ws, a, s);
+    else if (k <= 32) launch_kt<float, 32>(ws, a, s);
+    else if (k <= 48) launch_kt<float, 48>(ws, a, s);
+    else launch_kt<float, 64>(ws, a, s);
 }
 
 void launch_assign_fp64(const Ws& ws, const AssignArgs& a, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_assign_valu<double>, dim3((unsigned)((ws.N + kAssignThreads - 1) / kAssignThreads)),
-                       dim3(kAssignThreads), 0, s, ws, a);
+    const int k = a.k_hint > 0 ? a.k_hint : ws.k_max;
+    if (k <= 16) launch_kt<double, 16>(ws, a, s);
+    else launch_kt<double, 32>(ws, a, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -59,8 +59,63 @@ __device__ inline float bf16_bound(float acc, float lp, int nsteps)
     return ((float)(nsteps + 40) * 0x1p-24f + 0x1p-17f) * (fabsf(acc) + fabsf(lp) + 20.0f) + 1e-5f;
 }
 
+// hi/lo rows of log theta for one chunk: 2 x 16 NT rows x 64 genes, one
+// 16-byte piece per thread and r
 template <int NT>
-__global__ void __launch_bounds__(kMfmaThreads) k_assign_bf16(Ws ws, AssignArgs a)
+struct BRows {
+    uint4 v[NT];
+};
+
+__device__ inline void brow_slot(int idx, int nt, int& tbl, int& row, int& sg)
+{
+    const int per = 16 * nt * (kBlkGenes / 8);
+    tbl = idx / per;
+    const int rem = idx - tbl * per;
+    row = rem / (kBlkGenes / 8);
+    sg = rem % (kBlkGenes / 8);
+}
+
+template <int NT>
+__device__ inline BRows<NT> load_brows(const Ws& ws, int kb, int jj, int t)
+{
+    BRows<NT> b;
+#pragma unroll
+    for (int r = 0; r < NT; ++r) {
+        int tbl, row, sg;
+        brow_slot(t + r * kMfmaThreads, NT, tbl, row, sg);
+        b.v[r] = *reinterpret_cast<const uint4*>((tbl ? ws.llo : ws.lhi) + (int64_t)(kb + row) * ws.Gpad +
+                                                 jj * kBlkGenes + sg * 8);
+    }
+    return b;
+}
+
+template <int NT>
+__device__ inline void store_brows(const BRows<NT>& b, uint16_t* bhi, uint16_t* blo, int t)
+{
+#pragma unroll
+    for (int r = 0; r < NT; ++r) {
+        int tbl, row, sg;
+        brow_slot(t + r * kMfmaThreads, NT, tbl, row, sg);
+        *reinterpret_cast<uint4*>((tbl ? blo : bhi) + row * kMfmaRow + sg * 8) = b.v[r];
+    }
+}
+
+// the first kPrefetch x 4 entries of a segment [f0, f1): unconditional loads
+// from a clamped index (the buffer has 16 bytes of slack past its last
+// segment), then a select of the values -- a select of addresses would put
+// the padding in private memory
+__device__ inline void load_segment(const uint32_t* bent, uint32_t f0, uint32_t f1, int t, uint4 (&seg)[kPrefetch])
+{
+#pragma unroll
+    for (int r = 0; r < kPrefetch; ++r) {
+        const uint32_t q = f0 + 4 * t + 4 * kMfmaThreads * r;
+        const uint4 v = *reinterpret_cast<const uint4*>(bent + (q < f1 ? q : f0));
+        seg[r] = q < f1 ? v : make_uint4(kPadSlot, kPadSlot, kPadSlot, kPadSlot);
+    }
+}
+
+template <int NT>
+__global__ void __launch_bounds__(kMfmaThreads) __attribute__((amdgpu_waves_per_eu(NT <= 2 ? 3 : 2))) k_assign_bf16(Ws ws, AssignArgs a)
 {
     extern __shared__ __attribute__((aligned(16))) char lds[];
     uint16_t* atile = reinterpret_cast<uint16_t*>(lds);
@@ -100,41 +155,17 @@ __global__ void __launch_bounds__(kMfmaThreads) k_assign_bf16(Ws ws, AssignArgs 
 
         // software pipeline: the next chunk's B rows and first kPrefetch x 4
         // segment entries are loaded into registers while this chunk computes
-        uint4 nb[NT], cur[kPrefetch], nxt[kPrefetch];
-        const uint4 pad4 = make_uint4(kPadSlot, kPadSlot, kPadSlot, kPadSlot);
+        BRows<NT> nb;
+        uint4 cur[kPrefetch], nxt[kPrefetch];
         uint32_t ce0 = 0, ce1 = 0, ne0 = 0, ne1 = s_off[1];
-        auto load_chunk = [&](int jj, uint4* seg, uint32_t f0, uint32_t f1) {
-#pragma unroll
-            for (int r = 0; r < NT; ++r) {
-                const int idx = t + r * kMfmaThreads;           // < 2 * 16 NT * 8
-                const int tbl = idx / (16 * NT * (kBlkGenes / 8));
-                const int rem = idx % (16 * NT * (kBlkGenes / 8));
-                const int row = rem / (kBlkGenes / 8);
-                const int sg = rem % (kBlkGenes / 8);
-                nb[r] = *reinterpret_cast<const uint4*>((tbl ? ws.llo : ws.lhi) + (int64_t)(kb + row) * ws.Gpad +
-                                                        jj * kBlkGenes + sg * 8);
-            }
-#pragma unroll
-            for (int r = 0; r < kPrefetch; ++r) {
-                const uint32_t q = f0 + 4 * t + 4 * kMfmaThreads * r;
-                seg[r] = q < f1 ? *reinterpret_cast<const uint4*>(bent + q) : pad4;
-            }
-        };
-        load_chunk(0, nxt, ne0, ne1);
+        nb = load_brows<NT>(ws, kb, 0, t);
+        load_segment(bent, ne0, ne1, t, nxt);
 
         for (int j = 0; j < ws.nch; ++j) {
             const int c0 = j * kBlkGenes;
             __syncthreads();
             // commit chunk j: B rows to LDS, entries into the tile
-#pragma unroll
-            for (int r = 0; r < NT; ++r) {
-                const int idx = t + r * kMfmaThreads;
-                const int tbl = idx / (16 * NT * (kBlkGenes / 8));
-                const int rem = idx % (16 * NT * (kBlkGenes / 8));
-                const int row = rem / (kBlkGenes / 8);
-                const int sg = rem % (kBlkGenes / 8);
-                *reinterpret_cast<uint4*>((tbl ? blo : bhi) + row * kMfmaRow + sg * 8) = nb[r];
-            }
+            store_brows<NT>(nb, bhi, blo, t);
             ce0 = ne0;
             ce1 = ne1;
 #pragma unroll
@@ -152,7 +183,8 @@ __global__ void __launch_bounds__(kMfmaThreads) k_assign_bf16(Ws ws, AssignArgs 
             if (j + 1 < ws.nch) {
                 ne0 = s_off[j + 1];
                 ne1 = s_off[j + 2];
-                load_chunk(j + 1, nxt, ne0, ne1);
+                nb = load_brows<NT>(ws, kb, j + 1, t);
+                load_segment(bent, ne0, ne1, t, nxt);
             }
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
@@ -209,21 +241,24 @@ __global__ void __launch_bounds__(kMfmaThreads) k_assign_bf16(Ws ws, AssignArgs 
         }
         __syncthreads();
         if (valid) {
-            Words w{};
+            // four clusters per Philox call; constant word indices keep the
+            // words in registers
+            for (int k4 = 0; k4 < 16 * NT && kb + k4 < K; k4 += 4) {
+                const Words w = philox(ws.seed, (uint32_t)i, (uint32_t)((kb + k4) >> 2), a.step, kGumbelC, 0u);
 #pragma unroll
-            for (int k = 0; k < 16 * NT; ++k) {
-                const int kk = kb + k;
-                if (kk >= K) break;
-                if ((k & 3) == 0) w = philox(ws.seed, (uint32_t)i, (uint32_t)(kk >> 2), a.step, kGumbelC, 0u);
-                const float s = sc[t * SS + k];
-                const float lp = (float)ws.logpi[kk];
-                const float v = lp + s + gumbel32(w.w[k & 3]);
-                if (a.dbg && K + 2 <= a.dbg_stride) a.dbg[i * a.dbg_stride + kk] = s;
-                if (v > t1) {
-                    t2 = t1; a2 = a1; p2 = p1;
-                    t1 = v; a1 = s; p1 = lp; k1 = kk;
-                } else if (v > t2) {
-                    t2 = v; a2 = s; p2 = lp;
+                for (int q = 0; q < 4; ++q) {
+                    const int kk = kb + k4 + q;
+                    if (kk >= K) break;
+                    const float s = sc[t * SS + k4 + q];
+                    const float lp = (float)ws.logpi[kk];
+                    const float v = lp + s + gumbel32(w.w[q]);
+                    if (a.dbg && K + 2 <= a.dbg_stride) a.dbg[i * a.dbg_stride + kk] = s;
+                    if (v > t1) {
+                        t2 = t1; a2 = a1; p2 = p1;
+                        t1 = v; a1 = s; p1 = lp; k1 = kk;
+                    } else if (v > t2) {
+                        t2 = v; a2 = s; p2 = lp;
+                    }
                 }
             }
         }

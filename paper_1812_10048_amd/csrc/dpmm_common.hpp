@@ -111,16 +111,27 @@ constexpr uint32_t kRefineMask = (1u << 30) - 1;
 // Row walker: entries are read 16 bytes at a time (rows start and end on
 // 16-byte boundaries) with the next block already in flight.
 #if defined(__HIPCC__)
+// Entries [q, q + 4) of a row ending at e, or four padding entries when
+// q >= e.  The load is unconditional, from q clamped to the row start b (the
+// entry array has 16 bytes of slack past its end), and the padding is chosen
+// as a value: a select between a load and a local would turn into a select of
+// addresses that puts the local in private memory.
+__device__ inline uint4 load_entries(const uint32_t* ent, int64_t q, int64_t b, int64_t e)
+{
+    const uint4 v = *reinterpret_cast<const uint4*>(ent + (q < e ? q : b));
+    return q < e ? v : make_uint4(kPadEntry, kPadEntry, kPadEntry, kPadEntry);
+}
+
 struct RowCursor {
-    int64_t pos, end;
+    int64_t pos, beg, end;
     uint4 cur, nxt;
     __device__ inline void start(const uint32_t* ent, int64_t b, int64_t e)
     {
         pos = b;
+        beg = b;
         end = e;
-        const uint4 pad = make_uint4(kPadEntry, kPadEntry, kPadEntry, kPadEntry);
-        cur = b < e ? *reinterpret_cast<const uint4*>(ent + b) : pad;
-        nxt = b + 4 < e ? *reinterpret_cast<const uint4*>(ent + b + 4) : pad;
+        cur = load_entries(ent, b, b, e);
+        nxt = load_entries(ent, b + 4, b, e);
     }
     __device__ inline uint32_t peek() const
     {
@@ -132,8 +143,7 @@ struct RowCursor {
         ++pos;
         if ((pos & 3) == 0) {
             cur = nxt;
-            nxt = pos + 4 < end ? *reinterpret_cast<const uint4*>(ent + pos + 4)
-                                : make_uint4(kPadEntry, kPadEntry, kPadEntry, kPadEntry);
+            nxt = load_entries(ent, pos + 4, beg, end);
         }
     }
 };

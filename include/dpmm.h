@@ -80,9 +80,14 @@ typedef struct dpmm_params {
     int32_t k_max;                 /* cluster capacity, 1..1024                   */
     int32_t precision;             /* dpmm_precision                               */
     uint32_t flags;                /* reserved, must be 0                          */
-    double refine_tol;             /* decisions whose relative Gumbel-max margin
-                                      is below this are re-scored in FP64;
-                                      < 0 selects the precision's default         */
+    double refine_tol;             /* FP32 and split-BF16 only.  A cluster
+                                      decision whose Gumbel gap is within the
+                                      certified rounding bound of its two best
+                                      scores is always re-scored in FP64; a
+                                      value > 0 also re-scores decisions whose
+                                      relative margin (top1 - top2) /
+                                      max(1, |top1|) is below it.  <= 0: the
+                                      bound alone                                  */
 } dpmm_params;
 
 typedef struct dpmm_ctx dpmm_ctx;

@@ -4,12 +4,14 @@
 // After the cluster draw, the cells are counting-sorted by their new cluster
 // (`perm`, offsets `grp_off`).  A workgroup takes kSubCells consecutive
 // sorted cells, i.e. one run (or a few) of a single cluster k.  For each run
-// it stages thetabar_{k,0} and thetabar_{k,1} (FP64) in LDS; each wavefront
-// then works on four cells at a time, 16 lanes per cell reading the row with
-// 16-byte loads, forms the two FP64 sub-cluster log-likelihoods (fixed-order
-// reduction over the 16 lanes), draws cbar_i by Gumbel-max with weights nbar_{k,r} less the
-// cell's own old membership, and adds the row's counts to the LDS histogram
-// of (k, cbar_i).  The histograms are flushed with one 64-bit atomic per
+// it stages delta_u = log thetabar_{k,1,u} - log thetabar_{k,0,u} (FP64) in
+// LDS: the draw compares the two sub-cluster scores, and their difference is
+// sum_u x_i^u delta_u, one product per entry.  Each wavefront then works on
+// four cells at a time, 16 lanes per cell reading the row with 16-byte loads,
+// forms that FP64 difference (fixed-order reduction over the 16 lanes), draws
+// cbar_i by Gumbel-max with weights nbar_{k,r} less the cell's own old
+// membership, and adds the row's counts to the LDS histogram of (k, cbar_i).
+// The two scores themselves are formed only for the debug dump.  The histograms are flushed with one 64-bit atomic per
 // non-zero gene.  The matrix is read once for both jobs.
 #include "dpmm_common.hpp"
 #include "kernels.hpp"
@@ -18,7 +20,7 @@ namespace dpmm {
 
 constexpr int kSubThreads = 256;
 constexpr int kSubCells = 1024;          // sorted cells per workgroup
-constexpr int kSubStageGenes = 2048;     // thetabar rows staged in LDS up to this G
+constexpr int kSubStageGenes = 4096;     // delta staged in LDS up to this G
 constexpr int kSubHistGenes = 8192;      // LDS histograms up to this G
 
 // sum over the 16 lanes of a group, in a fixed order
@@ -34,8 +36,8 @@ __global__ void __launch_bounds__(kSubThreads) k_sub_stats(Ws ws, SubArgs a)
     const int G = ws.G;
     const bool stage = G <= kSubStageGenes;
     const bool lhist = G <= kSubHistGenes;
-    double* th = reinterpret_cast<double*>(lds);                        // [2][G] if staged
-    uint32_t* hist = reinterpret_cast<uint32_t*>(lds + (stage ? 16 * (size_t)G : 0));   // [2][G]
+    double* dl = reinterpret_cast<double*>(lds);                        // [G] delta if staged
+    uint32_t* hist = reinterpret_cast<uint32_t*>(lds + (stage ? 8 * (size_t)G : 0));    // [2][G]
     __shared__ uint32_t ncnt[2];
     const int K = ws.st->K;
     const int lane = threadIdx.x & 63;
@@ -63,16 +65,11 @@ __global__ void __launch_bounds__(kSubThreads) k_sub_stats(Ws ws, SubArgs a)
         const double* g1 = g0 + G;
         __syncthreads();
         if (stage && !reset)
-            for (int u = threadIdx.x; u < G; u += kSubThreads) {
-                th[u] = g0[u];
-                th[G + u] = g1[u];
-            }
+            for (int u = threadIdx.x; u < G; u += kSubThreads) dl[u] = g1[u] - g0[u];
         if (lhist)
             for (int u = threadIdx.x; u < 2 * G; u += kSubThreads) hist[u] = 0;
         if (threadIdx.x < 2) ncnt[threadIdx.x] = 0;
         __syncthreads();
-        const double* t0 = stage ? th : g0;
-        const double* t1 = stage ? th + G : g1;
         // log of the eq. 8 weights: nbar_{k,r}, less one when the cell was in (k, r)
         const long long n0 = (long long)ws.nsub_prev[2 * k], n1 = (long long)ws.nsub_prev[2 * k + 1];
         auto logw = [](long long w) { return w > 0 ? log((double)w) : -INFINITY; };
@@ -90,7 +87,8 @@ __global__ void __launch_bounds__(kSubThreads) k_sub_stats(Ws ws, SubArgs a)
             const int64_t b = (int64_t)(((uint64_t)d.z << 32) | d.y);
             const int64_t e = b + d.w;
             int sub;
-            double s0 = 0.0, s1 = 0.0;
+            double df = 0.0, s0 = 0.0, s1 = 0.0;
+            const bool dump = a.dbg != nullptr;
             // the first 256 entries of the row: four 16-byte loads per lane, all in flight
             uint4 v[4];
 #pragma unroll
@@ -105,8 +103,11 @@ __global__ void __launch_bounds__(kSubThreads) k_sub_stats(Ws ws, SubArgs a)
                     const uint32_t x = en[j] >> 16;
                     if (!x) continue;
                     const int g = (int)(en[j] & 0xFFFFu);
-                    s0 = fma((double)x, t0[g], s0);
-                    s1 = fma((double)x, t1[g], s1);
+                    df = fma((double)x, stage ? dl[g] : g1[g] - g0[g], df);
+                    if (dump) {
+                        s0 = fma((double)x, g0[g], s0);
+                        s1 = fma((double)x, g1[g], s1);
+                    }
                 }
             };
             if (reset) {
@@ -116,16 +117,19 @@ __global__ void __launch_bounds__(kSubThreads) k_sub_stats(Ws ws, SubArgs a)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) dot(v[r]);
                 for (int64_t q = b + 4 * l16 + 256; q < e; q += 64) dot(*reinterpret_cast<const uint4*>(ws.ent + q));
-                s0 = group_sum(s0);
-                s1 = group_sum(s1);
+                df = group_sum(df);
+                if (dump) {
+                    s0 = group_sum(s0);
+                    s1 = group_sum(s1);
+                }
                 const int32_t c_old = a.c_old[i];
                 const int s_old = a.cs_old[i] & 1;
                 double lw0 = (c_old == k && s_old == 0) ? l0m : l0;
                 double lw1 = (c_old == k && s_old == 1) ? l1m : l1;
                 if (!(lw0 > -INFINITY) && !(lw1 > -INFINITY)) lw0 = lw1 = 0.0;   // both weights zero: equal
                 const Words w = philox(ws.seed, (uint32_t)i, 0u, a.step, kGumbelS, 0u);
-                const double v0 = lw0 + s0 + (-log(-log(unit23d(w.w[0]))));
-                const double v1 = lw1 + s1 + (-log(-log(unit23d(w.w[1]))));
+                const double v0 = lw0 + (-log(-log(unit23d(w.w[0]))));
+                const double v1 = lw1 + df + (-log(-log(unit23d(w.w[1]))));
                 sub = v1 > v0 ? 1 : 0;
             }
             // statistics of (k, sub), from the registers where the row already is
@@ -175,7 +179,7 @@ void launch_sub_stats(const Ws& ws, const SubArgs& a, hipStream_t s)
     hipMemsetAsync(ws.ssub, 0, sizeof(unsigned long long) * 2 * (size_t)ws.k_max * (size_t)ws.G, s);
     launch_sort(ws, a.c_new, a.cs_old, 1, s);
     size_t lds = 0;
-    if (ws.G <= kSubStageGenes) lds += 16 * (size_t)ws.G;
+    if (ws.G <= kSubStageGenes) lds += 8 * (size_t)ws.G;
     if (ws.G <= kSubHistGenes) lds += 8 * (size_t)ws.G;
     hipLaunchKernelGGL(k_sub_stats, dim3((unsigned)((ws.N + kSubCells - 1) / kSubCells)), dim3(kSubThreads), lds, s,
                        ws, a);

@@ -6,8 +6,9 @@ an EB step every 10 sweeps), through the C ABI.
     taken from the same labels;
   * at the end: the gradient of sum_j g_j logDM(s_j; beta) over the 3K count
     vectors (clusters, then sub-clusters) within 1e-9 of the FP64 oracle, and
-    within 1e-6 of central differences evaluated in mpmath (h = 1e-6, 40
-    digits) on 50 genes chosen with Philox draws.
+    within 1e-6 of central differences evaluated in mpmath (h = 1e-6 min(1,
+    beta_u), 40 digits: EB may drive a beta_u to its 1e-6 floor) on 50 genes
+    chosen with Philox draws.
 """
 import sys
 
@@ -45,6 +46,7 @@ def _fd(s, beta, g, u):
     S = s.sum(axis=1)
     B0 = mpmath.fsum(mpmath.mpf(float(b)) for b in beta)
     bu = mpmath.mpf(float(beta[u]))
+    h = H * min(1, bu)          # beta_u may sit at the 1e-6 floor of the EB clamp
 
     def f(delta):
         B, b = B0 + delta, bu + delta
@@ -52,7 +54,7 @@ def _fd(s, beta, g, u):
                                                      mpmath.loggamma(b + int(sj[u])) - mpmath.loggamma(b))
                            for sj, Sj, gj in zip(s, S, g))
 
-    return float((f(H) - f(-H)) / (2 * H))
+    return float((f(h) - f(-h)) / (2 * h))
 
 
 def test_c4_beta_gradient_and_empirical_bayes():

@@ -51,6 +51,7 @@ def _fd(s, beta, g, u):
     S = s.sum(axis=1)
     B0 = mpmath.fsum(mpmath.mpf(float(b)) for b in beta)
     bu = mpmath.mpf(float(beta[u]))
+    h = H * min(1, bu)          # beta_u may sit at the 1e-6 floor of the EB clamp
 
     def f(delta):
         B = B0 + delta
@@ -59,7 +60,7 @@ def _fd(s, beta, g, u):
                                                      mpmath.loggamma(b + int(sj[u])) - mpmath.loggamma(b))
                            for sj, Sj, gj in zip(s, S, g))
 
-    return float((f(H) - f(-H)) / (2 * H))
+    return float((f(h) - f(-h)) / (2 * h))
 
 
 @pytest.mark.parametrize("weights", ["all", "clusters"])

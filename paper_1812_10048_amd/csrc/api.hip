@@ -278,6 +278,8 @@ dpmm_status dpmm_init(const dpmm_csr* csr, const dpmm_params* params, void* work
         he = configure_assign_bf16();
         if (he != hipSuccess) return cleanup(fail(DPMM_ERR_HIP, "kernel attributes: %s", hipGetErrorString(he)));
     }
+    he = sub_stats_cells(ws.N, ws.G, &ws.sub_cells);
+    if (he != hipSuccess) return cleanup(fail(DPMM_ERR_HIP, "occupancy query: %s", hipGetErrorString(he)));
     he = hipMemsetAsync(ws.st, 0, sizeof(DevState), ctx->stream);
     if (he == hipSuccess) he = hipMemsetAsync(ws.lc32, 0, L.ls32 - L.lc32, ctx->stream);
     if (he == hipSuccess) he = hipMemsetAsync(ws.lhi, 0, L.refine - L.lhi, ctx->stream);

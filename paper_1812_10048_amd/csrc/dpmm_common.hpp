@@ -190,6 +190,7 @@ struct Ws {
     uint2* ovf_ent;        // (cell in block | gene << 8, count - its BF16 head)
     int32_t nblk;
     int32_t nch;
+    int32_t sub_cells;     // sorted cells per workgroup of the sub-cluster/statistics pass
     int32_t* relab_c;      // [2 k_max] new cluster of an old (k, r)
     uint8_t* relab_s;      // [2 k_max] new sub-label of an old (k, r); 0xFF keeps it
     double* sm_logr;       // [k_max + k_max (k_max - 1) / 2]

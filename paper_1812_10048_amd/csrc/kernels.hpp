@@ -28,6 +28,7 @@ struct SubArgs {
     int32_t dbg_stride;
 };
 void launch_sub_stats(const Ws& ws, const SubArgs& a, hipStream_t s);
+hipError_t sub_stats_cells(int64_t N, int G, int32_t* cells);
 void launch_compact(const Ws& ws, int after_sweep, hipStream_t s);
 void launch_relabel(const Ws& ws, int32_t* c, uint8_t* cs, hipStream_t s);
 void launch_check_labels(const Ws& ws, const int32_t* c, const uint8_t* cs, int32_t K, hipStream_t s);

@@ -2,7 +2,7 @@
 // integer sufficient statistics (step a4).
 //
 // After the cluster draw, the cells are counting-sorted by their new cluster
-// (`perm`, offsets `grp_off`).  A workgroup takes kSubCells consecutive
+// (`perm`, offsets `grp_off`).  A workgroup takes ws.sub_cells consecutive
 // sorted cells, i.e. one run (or a few) of a single cluster k.  For each run
 // it stages delta_u = log thetabar_{k,1,u} - log thetabar_{k,0,u} (FP64) in
 // LDS: the draw compares the two sub-cluster scores, and their difference is
@@ -19,7 +19,7 @@
 namespace dpmm {
 
 constexpr int kSubThreads = 256;
-constexpr int kSubCells = 1024;          // sorted cells per workgroup
+constexpr int kSubCellsMin = 256;       // sorted cells per workgroup, at least
 constexpr int kSubStageGenes = 4096;     // delta staged in LDS up to this G
 constexpr int kSubHistGenes = 8192;      // LDS histograms up to this G
 
@@ -42,8 +42,8 @@ __global__ void __launch_bounds__(kSubThreads) k_sub_stats(Ws ws, SubArgs a)
     const int K = ws.st->K;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int64_t p0 = (int64_t)blockIdx.x * kSubCells;
-    const int64_t p1 = min(ws.N, p0 + kSubCells);
+    const int64_t p0 = (int64_t)blockIdx.x * ws.sub_cells;
+    const int64_t p1 = min(ws.N, p0 + ws.sub_cells);
     if (p0 >= p1) return;
     // first cluster whose run reaches p0
     int k = 0;
@@ -171,6 +171,32 @@ __global__ void __launch_bounds__(kSubThreads) k_sub_stats(Ws ws, SubArgs a)
     }
 }
 
+static size_t sub_stats_lds(int G)
+{
+    size_t lds = 0;
+    if (G <= kSubStageGenes) lds += 8 * (size_t)G;
+    if (G <= kSubHistGenes) lds += 8 * (size_t)G;
+    return lds;
+}
+
+// Sorted cells per workgroup: the grid fills the device's resident workgroup
+// slots once (a second, partial round would leave most of the device idle).
+hipError_t sub_stats_cells(int64_t N, int G, int32_t* cells)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k_sub_stats),
+                                                         kSubThreads, sub_stats_lds(G));
+    if (e != hipSuccess) return e;
+    const int64_t slots = (int64_t)(cus > 0 ? cus : 1) * (per_cu > 0 ? per_cu : 1);
+    int64_t c = (N + slots - 1) / slots;
+    c = (c + 63) / 64 * 64;
+    *cells = (int32_t)(c < kSubCellsMin ? kSubCellsMin : c);
+    return hipSuccess;
+}
+
 void launch_sub_stats(const Ws& ws, const SubArgs& a, hipStream_t s)
 {
     // counts at the start of the sweep feed eq. 8; the new ones accumulate from zero
@@ -178,11 +204,8 @@ void launch_sub_stats(const Ws& ws, const SubArgs& a, hipStream_t s)
     hipMemsetAsync(ws.nsub, 0, sizeof(unsigned long long) * 2 * (size_t)ws.k_max, s);
     hipMemsetAsync(ws.ssub, 0, sizeof(unsigned long long) * 2 * (size_t)ws.k_max * (size_t)ws.G, s);
     launch_sort(ws, a.c_new, a.cs_old, 1, s);
-    size_t lds = 0;
-    if (ws.G <= kSubStageGenes) lds += 8 * (size_t)ws.G;
-    if (ws.G <= kSubHistGenes) lds += 8 * (size_t)ws.G;
-    hipLaunchKernelGGL(k_sub_stats, dim3((unsigned)((ws.N + kSubCells - 1) / kSubCells)), dim3(kSubThreads), lds, s,
-                       ws, a);
+    hipLaunchKernelGGL(k_sub_stats, dim3((unsigned)((ws.N + ws.sub_cells - 1) / ws.sub_cells)), dim3(kSubThreads),
+                       sub_stats_lds(ws.G), s, ws, a);
 }
 
 }  // namespace dpmm

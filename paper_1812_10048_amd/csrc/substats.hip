@@ -128,9 +128,20 @@ __global__ void __launch_bounds__(kSubThreads) k_sub_stats(Ws ws, SubArgs a)
                 double lw1 = (c_old == k && s_old == 1) ? l1m : l1;
                 if (!(lw0 > -INFINITY) && !(lw1 > -INFINITY)) lw0 = lw1 = 0.0;   // both weights zero: equal
                 const Words w = philox(ws.seed, (uint32_t)i, 0u, a.step, kGumbelS, 0u);
-                const double v0 = lw0 + (-log(-log(unit23d(w.w[0]))));
-                const double v1 = lw1 + df + (-log(-log(unit23d(w.w[1]))));
-                sub = v1 > v0 ? 1 : 0;
+                // The draw compares dd + g1 - g0 with 0.  FP32 noise is within
+                // 3e-6 of the FP64 noise, so when the FP32 difference clears
+                // tau its sign is the FP64 sign; otherwise (or with a zero
+                // weight) the FP64 comparison decides.
+                const double dd = lw1 - lw0 + df;
+                const float d32 = (float)dd + ((-logf(-logf(unit23f(w.w[1])))) - (-logf(-logf(unit23f(w.w[0])))));
+                const float tau = 1e-3f + 1e-5f * fabsf((float)dd);
+                if (isfinite(dd) && fabsf(d32) > tau) {
+                    sub = d32 > 0.0f ? 1 : 0;
+                } else {
+                    const double v0 = lw0 + (-log(-log(unit23d(w.w[0]))));
+                    const double v1 = lw1 + df + (-log(-log(unit23d(w.w[1]))));
+                    sub = v1 > v0 ? 1 : 0;
+                }
             }
             // statistics of (k, sub), from the registers where the row already is
             unsigned long long* grow = ws.ssub + (int64_t)(2 * k + sub) * G;

@@ -31,7 +31,7 @@ typedef __attribute__((__vector_size__(4 * sizeof(float)))) float floatx4_t;
 
 constexpr int kMfmaThreads = kBlkCells;       // 256: one thread per cell
 constexpr int kMfmaRow = kBlkRow;             // BF16 elements per LDS tile row (padded)
-constexpr int kPrefetch = 4;                  // segment entries held in registers: 4 x 4 per thread
+constexpr int kPrefetch = 2;                  // segment entries held in registers: 2 x 4 per thread
 constexpr uint32_t kPadSlot = (uint32_t)(kBlkGenes * 2) << 16;   // writes into a padding column
 constexpr int kMaxChunks = (65535 + kBlkGenes - 1) / kBlkGenes;
 

@@ -149,6 +149,10 @@ struct RowCursor {
 };
 #endif
 
+// Genes per workgroup of the parameter redraw, and the tiles of a row.
+constexpr int kRedrawGenes = 256;
+__host__ __device__ inline int redraw_tiles(int G) { return (G + kRedrawGenes - 1) / kRedrawGenes; }
+
 // ---------------------------------------------------------------------------
 // View of the workspace, passed by value to kernels.
 // ---------------------------------------------------------------------------
@@ -199,6 +203,7 @@ struct Ws {
     int32_t* mlist;        // same size: their pair indices
     double* dm_k;          // [k_max] logDM of each cluster's statistics
     double* eb_tmp;        // [k_max + G] scratch of the empirical-Bayes step
+    double2* rd_part;      // [3 k_max + 1][redraw_tiles(G)] (max, sum exp) of each gene tile of a redrawn row
 };
 
 }  // namespace dpmm

@@ -1,8 +1,10 @@
 // redraw.hip -- step a1: draw pi ~ Dir(n_1..n_K, alpha), theta_k ~ Dir(beta + s_k)
 // and thetabar_{k,r} ~ Dir(beta + s_{k,r}) (Section 2.1 eq. 4, first two
 // lines; Section 2.3 eq. 19 with lambdabar = lambda), in FP64 and in log space.
-// One workgroup per parameter row; the row is also written in the layouts the
-// assignment kernels read (FP32 gene-major tables, split-BF16 hi/lo).
+// Two passes over (row, tile of genes) workgroups: the Gamma variates with
+// per-tile partial sums, then the normalisation; each row is also written in
+// the layouts the assignment kernels read (FP32 gene-major tables, split-BF16
+// hi/lo).
 #include "dpmm_common.hpp"
 #include "kernels.hpp"
 
@@ -41,6 +43,7 @@ __device__ double log_gamma_draw(double a, uint64_t seed, uint32_t element, uint
 }
 
 constexpr int kRedrawThreads = 256;
+static_assert(kRedrawThreads == kRedrawGenes, "one gene per thread in the redraw passes");
 
 __device__ inline double block_max(double v, double* red)
 {
@@ -75,18 +78,48 @@ __device__ inline uint16_t bf16_bits(float f)
 }
 __device__ inline float bf16_value(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
-__global__ void __launch_bounds__(kRedrawThreads) k_redraw(Ws ws, uint32_t step, int write_split)
+// The row a workgroup redraws: cluster k (r < 0) or sub-cluster (k, r);
+// false when the row is past the current K.
+struct RedrawRow {
+    int k, r;
+    uint32_t philox_row;
+    double* out;
+};
+
+__device__ inline bool redraw_row(const Ws& ws, int row, int K, RedrawRow& rr)
+{
+    if (row < ws.k_max) {
+        if (row >= K) return false;
+        rr.k = row;
+        rr.r = -1;
+        rr.philox_row = (uint32_t)row;
+    } else {
+        const int q = row - ws.k_max;     // q = 2k + r
+        if (q >= 2 * K) return false;
+        rr.k = q >> 1;
+        rr.r = q & 1;
+        rr.philox_row = kSubRowBase + (uint32_t)q;
+    }
+    rr.out = ws.lt64 + (int64_t)row * ws.G;
+    return true;
+}
+
+// Pass 1, one workgroup per (row, tile of kRedrawGenes genes): the log Gamma
+// variates of the tile, and the tile's (max, sum exp(v - max)).  The last row
+// (3 k_max) is log pi, drawn and normalised by its first tile alone.
+__global__ void __launch_bounds__(kRedrawThreads) k_redraw_draw(Ws ws, uint32_t step)
 {
     __shared__ double red[kRedrawThreads / 64];
     const int K = ws.st->K;
     const int row = blockIdx.x;
+    const int tile = blockIdx.y;
     const int G = ws.G;
     const int t = threadIdx.x;
     int capped = 0;
 
     if (row == 3 * ws.k_max) {
+        if (tile != 0) return;
         if (t == 0) ws.st->counters[kCntEvals] += (unsigned long long)ws.N * (unsigned long long)(K + 2);
-        // mixing proportions: Gamma(n_k) for the K clusters and Gamma(alpha)
         double* lp = ws.logpi;
         double m = -INFINITY;
         double lga = -INFINITY;
@@ -112,63 +145,66 @@ __global__ void __launch_bounds__(kRedrawThreads) k_redraw(Ws ws, uint32_t step,
         return;
     }
 
-    int k, r = -1;
-    uint32_t philox_row;
-    double* out;
-    if (row < ws.k_max) {
-        k = row;
-        if (k >= K) return;
-        philox_row = (uint32_t)k;
-        out = ws.lt64 + (int64_t)k * G;
-    } else {
-        const int q = row - ws.k_max;     // q = 2k + r
-        if (q >= 2 * K) return;
-        k = q >> 1;
-        r = q & 1;
-        philox_row = kSubRowBase + (uint32_t)q;
-        out = ws.lt64 + (int64_t)row * G;
-    }
-    const unsigned long long* s0 = ws.ssub + (int64_t)(2 * k) * G;
+    RedrawRow rr;
+    if (!redraw_row(ws, row, K, rr)) return;
+    const unsigned long long* s0 = ws.ssub + (int64_t)(2 * rr.k) * G;
     const unsigned long long* s1 = s0 + G;
-
-    double m = -INFINITY;
-    for (int u = t; u < G; u += kRedrawThreads) {
-        const unsigned long long cnt = r < 0 ? s0[u] + s1[u] : (r == 0 ? s0[u] : s1[u]);
-        const double v = log_gamma_draw(ws.beta[u] + (double)cnt, ws.seed, (uint32_t)u, philox_row, step, kGamma,
-                                        &capped);
-        out[u] = v;
-        m = fmax(m, v);
+    const int u = tile * kRedrawGenes + t;
+    double v = -INFINITY;
+    if (u < G) {
+        const unsigned long long cnt = rr.r < 0 ? s0[u] + s1[u] : (rr.r == 0 ? s0[u] : s1[u]);
+        v = log_gamma_draw(ws.beta[u] + (double)cnt, ws.seed, (uint32_t)u, rr.philox_row, step, kGamma, &capped);
+        rr.out[u] = v;
     }
-    m = block_max(m, red);
-    double s = 0.0;
-    for (int u = t; u < G; u += kRedrawThreads) s += exp(out[u] - m);
-    const double lse = m + log(block_sum(s, red));
-    float* ls = reinterpret_cast<float*>(ws.ls32);
-    for (int u = t; u < G; u += kRedrawThreads) {
-        const double v = out[u] - lse;
-        out[u] = v;
-        if (r < 0) {
-            ws.lc32[(int64_t)u * ws.kpad + k] = (float)v;
-            if (write_split) {
-                // split-BF16: hi = bf16(v), lo = bf16(v - hi), cluster-major
-                // [k][Gpad] as the MFMA kernel stages them
-                const float f = (float)v;
-                const uint16_t hi = bf16_bits(f);
-                const uint16_t lo = bf16_bits((float)(v - (double)bf16_value(hi)));
-                ws.lhi[(int64_t)k * ws.Gpad + u] = hi;
-                ws.llo[(int64_t)k * ws.Gpad + u] = lo;
-            }
-        } else {
-            ls[((int64_t)u * ws.k_max + k) * 2 + r] = (float)v;
-        }
-    }
+    const double m = block_max(v, red);
+    const double s = block_sum(u < G ? exp(v - m) : 0.0, red);
+    if (t == 0) ws.rd_part[(int64_t)row * redraw_tiles(G) + tile] = make_double2(m, s);
     if (capped) atomicAdd(&ws.st->counters[kCntGammaCaps], 1ull);
+}
+
+// Pass 2, same grid: the row's log normaliser from its tiles' partials
+// (combined in tile order), then the tile's log theta in FP64 and in the
+// layouts the assignment kernels read.
+__global__ void __launch_bounds__(kRedrawThreads) k_redraw_norm(Ws ws, int write_split)
+{
+    const int K = ws.st->K;
+    const int row = blockIdx.x;
+    const int tile = blockIdx.y;
+    const int G = ws.G;
+    const int t = threadIdx.x;
+    RedrawRow rr;
+    if (row == 3 * ws.k_max || !redraw_row(ws, row, K, rr)) return;
+    const int nt = redraw_tiles(G);
+    const double2* part = ws.rd_part + (int64_t)row * nt;
+    double m = -INFINITY;
+    for (int q = 0; q < nt; ++q) m = fmax(m, part[q].x);
+    double s = 0.0;
+    for (int q = 0; q < nt; ++q) s += part[q].y * exp(part[q].x - m);
+    const double lse = m + log(s);
+    const int u = tile * kRedrawGenes + t;
+    if (u >= G) return;
+    const double v = rr.out[u] - lse;
+    rr.out[u] = v;
+    const int k = rr.k;
+    if (rr.r < 0) {
+        ws.lc32[(int64_t)u * ws.kpad + k] = (float)v;
+        if (write_split) {
+            const float f = (float)v;
+            const uint16_t hi = bf16_bits(f);
+            const uint16_t lo = bf16_bits((float)(v - (double)bf16_value(hi)));
+            ws.lhi[(int64_t)k * ws.Gpad + u] = hi;
+            ws.llo[(int64_t)k * ws.Gpad + u] = lo;
+        }
+    } else {
+        reinterpret_cast<float*>(ws.ls32)[((int64_t)u * ws.k_max + k) * 2 + rr.r] = (float)v;
+    }
 }
 
 void launch_redraw(const Ws& ws, uint32_t step, int write_split, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_redraw, dim3((unsigned)(3 * ws.k_max + 1)), dim3(kRedrawThreads), 0, s, ws, step,
-                       write_split);
+    const dim3 grid((unsigned)(3 * ws.k_max + 1), (unsigned)redraw_tiles(ws.G));
+    hipLaunchKernelGGL(k_redraw_draw, grid, dim3(kRedrawThreads), 0, s, ws, step);
+    hipLaunchKernelGGL(k_redraw_norm, grid, dim3(kRedrawThreads), 0, s, ws, write_split);
 }
 
 }  // namespace dpmm

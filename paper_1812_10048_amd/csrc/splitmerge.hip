@@ -17,7 +17,8 @@
 
 namespace dpmm {
 
-constexpr int kSmThreads = 256;
+constexpr int kSmThreads = 512;          // split and cluster passes: K workgroups, genes over 512 threads
+constexpr int kMergeThreads = 256;       // merge pass: K (K - 1) / 2 workgroups
 
 // Compensated accumulator (Neumaier): value = s + c.
 struct CSum {
@@ -43,14 +44,15 @@ struct SmRed {
     double beta;
 };
 
+template <int NT>
 __device__ inline SmRed block_reduce(SmRed v)
 {
-    __shared__ double ls[kSmThreads], lc[kSmThreads], lb[kSmThreads];
-    __shared__ long long la[kSmThreads], lbb[kSmThreads];
+    __shared__ double ls[NT], lc[NT], lb[NT];
+    __shared__ long long la[NT], lbb[NT];
     const int t = threadIdx.x;
     ls[t] = v.cs.s; lc[t] = v.cs.c; la[t] = v.a; lbb[t] = v.b; lb[t] = v.beta;
     __syncthreads();
-    for (int off = kSmThreads / 2; off > 0; off >>= 1) {
+    for (int off = NT / 2; off > 0; off >>= 1) {
         if (t < off) {
             CSum x; x.s = ls[t]; x.c = lc[t];
             CSum y; y.s = ls[t + off]; y.c = lc[t + off];
@@ -100,7 +102,7 @@ __global__ void __launch_bounds__(kSmThreads) k_split_ratios(Ws ws)
             r.cs.add(rising(bu, b));
             r.cs.add(-rising(bu, a + b));
         }
-        r = block_reduce(r);
+        r = block_reduce<kSmThreads>(r);
         if (threadIdx.x == 0) {
             const double B = r.beta;
             CSum tot = r.cs;
@@ -132,7 +134,7 @@ __global__ void __launch_bounds__(kSmThreads) k_cluster_logdm(Ws ws)
             r.a += v;
             r.cs.add(rising(bu, v));
         }
-        r = block_reduce(r);
+        r = block_reduce<kSmThreads>(r);
         if (threadIdx.x == 0) {
             CSum tot = r.cs;
             tot.add(lgamma(r.beta) - lgamma(r.beta + (double)r.a));
@@ -150,7 +152,7 @@ __device__ inline void pair_of(long long p, int* k1, int* k2)
     *k1 = (int)(p - (long long)b * (b - 1) / 2);
 }
 
-__global__ void __launch_bounds__(kSmThreads) k_merge_ratios(Ws ws)
+__global__ void __launch_bounds__(kMergeThreads) k_merge_ratios(Ws ws)
 {
     const int K = ws.st->K;
     const int G = ws.G;
@@ -163,14 +165,14 @@ __global__ void __launch_bounds__(kSmThreads) k_merge_ratios(Ws ws)
         SmRed r;
         r.a = r.b = 0;
         r.beta = 0.0;
-        for (int u = threadIdx.x; u < G; u += kSmThreads) {
+        for (int u = threadIdx.x; u < G; u += kMergeThreads) {
             const double bu = ws.beta[u];
             const long long v = (long long)(a0[u] + a0[u + G] + b0[u] + b0[u + G]);
             r.beta += bu;
             r.a += v;
             r.cs.add(rising(bu, v));
         }
-        r = block_reduce(r);
+        r = block_reduce<kMergeThreads>(r);
         if (threadIdx.x == 0) {
             const double n1 = (double)(ws.nsub[2 * k1] + ws.nsub[2 * k1 + 1]);
             const double n2 = (double)(ws.nsub[2 * k2] + ws.nsub[2 * k2 + 1]);
@@ -199,7 +201,7 @@ void launch_merge_ratios(const Ws& ws, hipStream_t s)
     hipLaunchKernelGGL(k_cluster_logdm, dim3(blocks), dim3(kSmThreads), 0, s, ws);
     const long long np = (long long)ws.k_max * (ws.k_max - 1) / 2;
     const int mb = np < 4096 ? (int)(np > 0 ? np : 1) : 4096;
-    hipLaunchKernelGGL(k_merge_ratios, dim3(mb), dim3(kSmThreads), 0, s, ws);
+    hipLaunchKernelGGL(k_merge_ratios, dim3(mb), dim3(kMergeThreads), 0, s, ws);
 }
 
 // ---------------------------------------------------------------------------

@@ -338,3 +338,32 @@ def test_split_bf16_tables_are_hi_lo_of_log_theta():
     assert torch.equal(lo.view(torch.bfloat16), exp_lo)
     resid = (lt - hi_f - lo_f).abs()
     assert bool((resid <= 2.0 ** -17 * lt.abs() + 1e-300).all())
+
+
+@pytest.mark.parametrize("n_genes", [6000, 20000])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "split_bf16"])
+def test_wide_matrices_take_the_global_memory_paths(precision, n_genes):
+    """More genes than the LDS tables hold: above 4096 the sub-cluster pass
+    reads its parameters from global memory, above 8192 its histograms are
+    global atomics, above 16384 the initial statistics use the atomic kernel;
+    the split-BF16 kernel walks a few hundred gene chunks."""
+    _say("wide", precision, n_genes)
+    rec = synth.Recipe("wide", 2500, n_genes, "fixed:900,700,500,400", 0.02, 3000.0, 0.5)
+    d = synth.generate(rec, seed=3)
+    kw = dict(alpha=1.0, beta=1.0, seed=17, k_max=16, k_init=3)
+    o = _oracle(d, **kw)
+    s = _sampler(d, precision, **kw)
+    _compare_stats(o, s)
+    for it in range(3):
+        o.sweep()
+        s.sweep(1)
+        _compare_params(o, s)
+        if _compare_labels(o, s, f"wide sweep {it}"):
+            break
+        _compare_stats(o, s)
+        o.split_merge()
+        s.split_merge()
+        _compare_hastings(o, s)
+        if _compare_labels(o, s, f"wide sm {it}"):
+            break
+        _compare_stats(o, s)

@@ -367,3 +367,36 @@ def test_wide_matrices_take_the_global_memory_paths(precision, n_genes):
         if _compare_labels(o, s, f"wide sm {it}"):
             break
         _compare_stats(o, s)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
+def test_two_hundred_clusters(precision):
+    """About 200 clusters of k_max = 256, started from the true partition of
+    a 200-cluster matrix: several column groups in both assignment kernels and
+    ~20k merge candidates in the single-workgroup decision."""
+    _say("k200", precision)
+    rec = synth.Recipe("k200", 20000, 500, "dirichlet:200", 0.05, 2000.0, 0.5)
+    d = synth.generate(rec, seed=8)
+    kw = dict(alpha=1.0, beta=1.0, seed=19, k_max=256, k_init=1)
+    o = _oracle(d, **kw)
+    s = _sampler(d, precision, **kw)
+    cs0 = np.random.default_rng(2).integers(0, 2, size=d.n_cells)
+    reset = np.ones(d.n_true, dtype=np.uint8)
+    o.set_state(0, d.n_true, d.z, cs0, reset)
+    s.set_state(0, d.n_true, torch.from_numpy(d.z), torch.from_numpy(cs0), reset)
+    _compare_stats(o, s)
+    assert o.K > 150
+    merges = 0
+    for it in range(4):
+        o.sweep()
+        s.sweep(1)
+        _compare_params(o, s)
+        assert _compare_labels(o, s, f"k200 sweep {it}") == 0
+        _compare_stats(o, s)
+        o.split_merge()
+        s.split_merge()
+        _compare_hastings(o, s)
+        merges += o.sm_pass == 1
+        assert _compare_labels(o, s, f"k200 sm {it}") == 0
+        _compare_stats(o, s)
+    _say("k200 K", o.K, "merge passes", merges)

@@ -35,7 +35,6 @@ dpmm_status fail(dpmm_status st, const char* fmt, ...)
 
 constexpr size_t kAlign = 256;
 constexpr int kMaxTimed = 4096;
-constexpr int kMfmaGeneTile = 64;      // gene chunk of the split-BF16 kernel
 constexpr int kTablePadRows = 64;      // spare cluster rows read by its last column group
 
 size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
@@ -46,14 +45,21 @@ struct Layout {
 };
 
 int32_t num_blocks(int64_t N) { return (int32_t)((N + kBlkCells - 1) / kBlkCells); }
-int32_t num_chunks(int32_t G) { return (G + kBlkGenes - 1) / kBlkGenes; }
+// gene chunks of the split-BF16 kernel: an even number, so that its pipeline
+// (two register stages, unrolled by two) has no conditional chunk; the chunks
+// past G hold no entries and zero log theta
+int32_t num_chunks(int32_t G)
+{
+    const int32_t n = (G + kBlkGenes - 1) / kBlkGenes;
+    return (n + 1) / 2 * 2;
+}
 
 Layout plan(int64_t N, int32_t G, int64_t nnz, int32_t k_max, int32_t precision)
 {
     Layout L{};
     const int64_t nnz_pad = nnz + 3 * N;
     const int64_t kpad = (k_max + 15) / 16 * 16;
-    const int64_t Gpad = (G + kMfmaGeneTile - 1) / kMfmaGeneTile * kMfmaGeneTile;
+    const int64_t Gpad = (int64_t)num_chunks(G) * kBlkGenes;
     const int64_t ncand = (int64_t)k_max + (int64_t)k_max * (k_max - 1) / 2;
     const bool blocked = precision == DPMM_SPLIT_BF16;
     const int64_t nseg = blocked ? (int64_t)num_blocks(N) * num_chunks(G) : 0;
@@ -224,7 +230,7 @@ dpmm_status dpmm_init(const dpmm_csr* csr, const dpmm_params* params, void* work
     ws.G = csr->n_genes;
     ws.k_max = params->k_max;
     ws.kpad = (params->k_max + 15) / 16 * 16;
-    ws.Gpad = (csr->n_genes + kMfmaGeneTile - 1) / kMfmaGeneTile * kMfmaGeneTile;
+    ws.Gpad = num_chunks(csr->n_genes) * kBlkGenes;
     ws.alpha = params->alpha;
     ws.seed = params->seed;
     ws.ent = (const uint32_t*)(base + L.ent);

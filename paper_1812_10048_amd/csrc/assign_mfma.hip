@@ -32,7 +32,6 @@ typedef __attribute__((__vector_size__(4 * sizeof(float)))) float floatx4_t;
 constexpr int kMfmaThreads = kBlkCells;       // 256: one thread per cell
 constexpr int kMfmaRow = kBlkRow;             // BF16 elements per LDS tile row (padded)
 constexpr int kPrefetch = 2;                  // segment entries held in registers: 2 x 4 per thread
-constexpr uint32_t kPadSlot = (uint32_t)(kBlkGenes * 2) << 16;   // writes into a padding column
 constexpr int kMaxChunks = (65535 + kBlkGenes - 1) / kBlkGenes;
 
 __host__ __device__ constexpr size_t mfma_main_bytes(int nt)
@@ -100,17 +99,28 @@ __device__ inline void store_brows(const BRows<NT>& b, uint16_t* bhi, uint16_t* 
     }
 }
 
-// the first kPrefetch x 4 entries of a segment [f0, f1): unconditional loads
-// from a clamped index (the buffer has 16 bytes of slack past its last
-// segment), then a select of the values -- a select of addresses would put
-// the padding in private memory
-__device__ inline void load_segment(const uint32_t* bent, uint32_t f0, uint32_t f1, int t, uint4 (&seg)[kPrefetch])
+// raw buffer resource over n bytes at p (gfx9 descriptor word 3); loads past
+// n bytes return zeros
+constexpr int kBufWord3 = 0x00020000;
+constexpr int kOutOfRange = 0x7FFFFFF0;
+__device__ inline __amdgpu_buffer_rsrc_t buffer_of(const void* p, uint32_t n)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)n, kBufWord3);
+}
+
+// The first kPrefetch x 4 entries of a segment [f0, f1), through a buffer
+// resource over the block's entries: a lane past the segment end asks for an
+// offset beyond the resource and reads the entry 0, which writes into a
+// padding column.  The loads are unconditional, so the compiler waits for
+// exactly the loads a use needs.
+__device__ inline void load_segment(__amdgpu_buffer_rsrc_t ent, uint32_t f0, uint32_t f1, int t, uint4 (&seg)[kPrefetch])
 {
 #pragma unroll
     for (int r = 0; r < kPrefetch; ++r) {
         const uint32_t q = f0 + 4 * t + 4 * kMfmaThreads * r;
-        const uint4 v = *reinterpret_cast<const uint4*>(bent + (q < f1 ? q : f0));
-        seg[r] = q < f1 ? v : make_uint4(kPadSlot, kPadSlot, kPadSlot, kPadSlot);
+        const int off = q < f1 ? (int)(4 * q) : kOutOfRange;
+        const auto v = __builtin_amdgcn_raw_buffer_load_b128(ent, off, 0, 0);
+        seg[r] = make_uint4(v[0], v[1], v[2], v[3]);
     }
 }
 
@@ -133,6 +143,7 @@ __global__ void __launch_bounds__(kMfmaThreads) __attribute__((amdgpu_waves_per_
     const bool valid = i < ws.N;
     const int64_t* soff = ws.blk_off + (int64_t)blk * ws.nch;
     const uint32_t* bent = ws.blk_ent + soff[0];       // this block's entries, 32-bit offsets below
+    const __amdgpu_buffer_rsrc_t bres = buffer_of(bent, (uint32_t)(4 * (soff[ws.nch] - soff[0])));
     // the block's segment offsets, relative to its first entry, once into LDS
     __shared__ uint32_t s_off[kMaxChunks + 1];
     for (int q = t; q <= ws.nch; q += kMfmaThreads) s_off[q] = (uint32_t)(soff[q] - soff[0]);
@@ -153,46 +164,45 @@ __global__ void __launch_bounds__(kMfmaThreads) __attribute__((amdgpu_waves_per_
         for (int g = 0; g < kMfmaRow; g += 8)
             *reinterpret_cast<uint4*>(atile + t * kMfmaRow + g) = make_uint4(0, 0, 0, 0);
 
-        // software pipeline: the next chunk's B rows and first kPrefetch x 4
-        // segment entries are loaded into registers while this chunk computes
-        BRows<NT> nb;
-        uint4 cur[kPrefetch], nxt[kPrefetch];
-        uint32_t ce0 = 0, ce1 = 0, ne0 = 0, ne1 = s_off[1];
-        nb = load_brows<NT>(ws, kb, 0, t);
-        load_segment(bent, ne0, ne1, t, nxt);
+        // Software pipeline with two register stages (chunks of even and odd
+        // index): a stage holds its chunk's B rows and first kPrefetch x 4
+        // segment entries; after the chunk has been multiplied and its
+        // entries wiped, the stage is reloaded with the chunk two ahead, so
+        // the loads have a whole chunk to arrive.  The chunk count is even
+        // and past the last chunk the index is clamped, so no stage is
+        // conditional and every path issues the same loads.
+        const int last = ws.nch - 1;
+        BRows<NT> nb0 = load_brows<NT>(ws, kb, 0, t);
+        uint4 sg0[kPrefetch];
+        uint32_t f00 = s_off[0], f01 = s_off[1];
+        load_segment(bres, f00, f01, t, sg0);
+        BRows<NT> nb1 = load_brows<NT>(ws, kb, 1, t);
+        uint4 sg1[kPrefetch];
+        uint32_t f10 = s_off[1], f11 = s_off[2];
+        load_segment(bres, f10, f11, t, sg1);
+        char* tileb = reinterpret_cast<char*>(atile);
 
-        for (int j = 0; j < ws.nch; ++j) {
-            const int c0 = j * kBlkGenes;
+        auto phase = [&](int j, BRows<NT>& nb, uint4 (&sg)[kPrefetch], uint32_t& f0, uint32_t& f1)
+            __attribute__((always_inline)) {
             __syncthreads();
             // commit chunk j: B rows to LDS, entries into the tile
             store_brows<NT>(nb, bhi, blo, t);
-            ce0 = ne0;
-            ce1 = ne1;
-#pragma unroll
-            for (int r = 0; r < kPrefetch; ++r) cur[r] = nxt[r];
-            char* tileb = reinterpret_cast<char*>(atile);
 #pragma unroll
             for (int r = 0; r < kPrefetch; ++r) {
-                put(tileb, cur[r].x); put(tileb, cur[r].y); put(tileb, cur[r].z); put(tileb, cur[r].w);
+                put(tileb, sg[r].x); put(tileb, sg[r].y); put(tileb, sg[r].z); put(tileb, sg[r].w);
             }
-            for (uint32_t q = ce0 + 4 * t + 4 * kMfmaThreads * kPrefetch; q < ce1; q += 4 * kMfmaThreads) {
+            for (uint32_t q = f0 + 4 * t + 4 * kMfmaThreads * kPrefetch; q < f1; q += 4 * kMfmaThreads) {
                 const uint4 v = *reinterpret_cast<const uint4*>(bent + q);
                 put(tileb, v.x); put(tileb, v.y); put(tileb, v.z); put(tileb, v.w);
             }
             __syncthreads();
-            if (j + 1 < ws.nch) {
-                ne0 = s_off[j + 1];
-                ne1 = s_off[j + 2];
-                nb = load_brows<NT>(ws, kb, j + 1, t);
-                load_segment(bent, ne0, ne1, t, nxt);
-            }
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
                 const int col = 32 * s + 8 * (lane >> 4);
                 bf16x8_t af[4];
 #pragma unroll
                 for (int m = 0; m < 4; ++m)
-                    af[m] = *reinterpret_cast<const bf16x8_t*>(atile + (64 * wave + 16 * m + (lane & 15)) * kMfmaRow + col);
+                    af[m] = *reinterpret_cast<const bf16x8_t*>(atile + (64 * wave + 16 * m + (lane & 15)) * kMfmaRow + kBlkLead + col);
 #pragma unroll
                 for (int n = 0; n < NT; ++n) {
                     const bf16x8_t bh = *reinterpret_cast<const bf16x8_t*>(bhi + (16 * n + (lane & 15)) * kMfmaRow + col);
@@ -209,15 +219,25 @@ __global__ void __launch_bounds__(kMfmaThreads) __attribute__((amdgpu_waves_per_
                 }
             }
             __syncthreads();
-            // clear the written entries: the first ones are still in registers
+            // clear the written entries (the first ones are still in the stage)
 #pragma unroll
             for (int r = 0; r < kPrefetch; ++r) {
-                wipe(tileb, cur[r].x); wipe(tileb, cur[r].y); wipe(tileb, cur[r].z); wipe(tileb, cur[r].w);
+                wipe(tileb, sg[r].x); wipe(tileb, sg[r].y); wipe(tileb, sg[r].z); wipe(tileb, sg[r].w);
             }
-            for (uint32_t q = ce0 + 4 * t + 4 * kMfmaThreads * kPrefetch; q < ce1; q += 4 * kMfmaThreads) {
+            for (uint32_t q = f0 + 4 * t + 4 * kMfmaThreads * kPrefetch; q < f1; q += 4 * kMfmaThreads) {
                 const uint4 v = *reinterpret_cast<const uint4*>(bent + q);
                 wipe(tileb, v.x); wipe(tileb, v.y); wipe(tileb, v.z); wipe(tileb, v.w);
             }
+            // reload the stage with the chunk two ahead
+            const int jn = min(j + 2, last);
+            f0 = s_off[jn];
+            f1 = s_off[jn + 1];
+            nb = load_brows<NT>(ws, kb, jn, t);
+            load_segment(bres, f0, f1, t, sg);
+        };
+        for (int j = 0; j < ws.nch; j += 2) {
+            phase(j, nb0, sg0, f00, f01);
+            phase(j + 1, nb1, sg1, f10, f11);
         }
         __syncthreads();
         // scores through LDS: lane l holds, for row tile m and column tile n,

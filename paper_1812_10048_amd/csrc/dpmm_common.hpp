@@ -101,7 +101,8 @@ constexpr uint32_t kPadEntry = 0x0000FFFFu;   // gene 0xFFFF, count 0
 
 constexpr int kBlkCells = 256;
 constexpr int kBlkGenes = 64;
-constexpr int kBlkRow = kBlkGenes + 8;   // BF16 elements per row of the dense LDS tile (padded)
+constexpr int kBlkLead = 8;              // padding columns at the start of a dense tile row
+constexpr int kBlkRow = kBlkLead + kBlkGenes;   // BF16 elements per row of the dense LDS tile
 
 // Refine-queue flags (high bits of a queued cell index).
 constexpr uint32_t kRefineCluster = 1u << 31;
@@ -160,7 +161,7 @@ struct Ws {
     int64_t N;
     int32_t G;
     int32_t k_max;
-    int32_t Gpad;          // G rounded up to the split-BF16 gene tile
+    int32_t Gpad;          // nch x kBlkGenes: G rounded up to an even number of gene chunks
     int32_t kpad;          // k_max rounded up to a multiple of 16
     double alpha;
     uint64_t seed;

@@ -9,8 +9,10 @@
 //   low 16 bits   BF16 value of the count (of its top 8 significant bits
 //                 when the count exceeds 256),
 //   high 16 bits  byte offset of (cell, gene) in the tile.
-// Segments are padded to a multiple of four with entries that write zero into
-// a padding column of the tile, so the scatter needs no test.  Counts above
+// Each tile row starts with kBlkLead padding columns, so the entry 0 (BF16
+// zero at byte offset 0) writes into a padding column: segments are padded to
+// a multiple of four with it, so the scatter needs no test, and a load that
+// returns zeros is harmless too.  Counts above
 // 256 also go to a per-block list (cell, gene, count - head) whose FP32
 // corrections the kernel adds to the scores.
 #include "dpmm_common.hpp"
@@ -31,7 +33,7 @@ __device__ inline uint32_t encode_entry(int cell, int g_local, uint32_t x)
 {
     // a count with at most 8 significant bits is exact in FP32 and BF16
     const uint32_t bf = __float_as_uint((float)count_head(x)) >> 16;
-    const uint32_t off = (uint32_t)(cell * kBlkRow + g_local) * 2u;
+    const uint32_t off = (uint32_t)(cell * kBlkRow + kBlkLead + g_local) * 2u;
     return bf | (off << 16);
 }
 
@@ -89,7 +91,7 @@ __global__ void __launch_bounds__(kLayThreads) k_seg_fill(Ws ws)
     const int64_t rb = i < ws.N ? ws.roff[i] : 0;
     const int64_t end = i < ws.N ? ws.roff[i + 1] : 0;
     uint32_t* out = const_cast<uint32_t*>(ws.blk_ent);
-    const uint32_t pad = (uint32_t)(kBlkGenes * 2) << 16;   // zero into cell 0's padding column
+    const uint32_t pad = 0u;                 // zero into cell 0's first padding column
     int64_t pos = rb;
     for (int j = 0; j < ws.nch; ++j) {
         const int hi = (j + 1) * kBlkGenes;

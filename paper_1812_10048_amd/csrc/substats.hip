@@ -6,12 +6,14 @@
 // sorted cells, i.e. one run (or a few) of a single cluster k.  For each run
 // it stages delta_u = log thetabar_{k,1,u} - log thetabar_{k,0,u} (FP64) in
 // LDS: the draw compares the two sub-cluster scores, and their difference is
-// sum_u x_i^u delta_u, one product per entry.  Each wavefront then works on
-// four cells at a time, 16 lanes per cell reading the row with 16-byte loads,
-// forms that FP64 difference (fixed-order reduction over the 16 lanes), draws
-// cbar_i by Gumbel-max with weights nbar_{k,r} less the cell's own old
-// membership, and adds the row's counts to the LDS histogram of (k, cbar_i).
-// The two scores themselves are formed only for the debug dump.  The histograms are flushed with one 64-bit atomic per
+// sum_u x_i^u delta_u, one product per entry.  Each wavefront takes 64 sorted
+// cells at a time: one lane per cell first forms the cell's Philox words and
+// FP32 Gumbel noise difference, then 16 lanes per cell, four cells at a time,
+// read the rows with 16-byte loads, form the FP64 difference (fixed-order
+// reduction over the 16 lanes), draw cbar_i by Gumbel-max with weights
+// nbar_{k,r} less the cell's own old membership, and add the row's counts to
+// the LDS histogram of (k, cbar_i).  The two scores themselves are formed only
+// for the debug dump.  The histograms are flushed with one 64-bit atomic per
 // non-zero gene.  The matrix is read once for both jobs.
 #include "dpmm_common.hpp"
 #include "kernels.hpp"
@@ -30,12 +32,15 @@ __device__ inline double group_sum(double v)
     return v;
 }
 
-__global__ void __launch_bounds__(kSubThreads) k_sub_stats(Ws ws, SubArgs a)
+// STAGE: delta in LDS; LHIST: histograms in LDS; DUMP: also form the two
+// scores for the debug dump.  The flags are template arguments so that the
+// loop over a row's entries is straight-line code.
+template <bool STAGE, bool LHIST, bool DUMP>
+__global__ void __launch_bounds__(kSubThreads) __attribute__((amdgpu_waves_per_eu(4))) k_sub_stats(Ws ws, SubArgs a)
 {
     extern __shared__ __attribute__((aligned(16))) char lds[];
     const int G = ws.G;
-    const bool stage = G <= kSubStageGenes;
-    const bool lhist = G <= kSubHistGenes;
+    constexpr bool stage = STAGE, lhist = LHIST, dump = DUMP;
     double* dl = reinterpret_cast<double*>(lds);                        // [G] delta if staged
     uint32_t* hist = reinterpret_cast<uint32_t*>(lds + (stage ? 8 * (size_t)G : 0));    // [2][G]
     __shared__ uint32_t ncnt[2];
@@ -74,100 +79,123 @@ __global__ void __launch_bounds__(kSubThreads) k_sub_stats(Ws ws, SubArgs a)
         const long long n0 = (long long)ws.nsub_prev[2 * k], n1 = (long long)ws.nsub_prev[2 * k + 1];
         auto logw = [](long long w) { return w > 0 ? log((double)w) : -INFINITY; };
         const double l0 = logw(n0), l0m = logw(n0 - 1), l1 = logw(n1), l1m = logw(n1 - 1);
-        // 16 lanes per cell, 4 cells per wavefront in flight; the next cell's
-        // row descriptor is loaded while this one is processed
+        // Each wavefront takes 64 sorted cells at a time.  First one lane per
+        // cell forms what depends on the cell alone (its row descriptor, its
+        // old membership, the Philox words and the FP32 noise difference);
+        // then 16 lanes per cell, four cells at a time, read the rows, and
+        // the per-cell values come by lane shuffles.
         const int grp = lane >> 4;
         const int l16 = lane & 15;
-        int64_t p = r0 + wave * 4 + grp;
-        uint4 d = p < r1 ? ws.srow[p] : make_uint4(0, 0, 0, 0);
-        for (; p < r1; p += kSubThreads / 16) {
-            const int64_t pn = p + kSubThreads / 16;
-            const uint4 dn = pn < r1 ? ws.srow[pn] : make_uint4(0, 0, 0, 0);
-            const int64_t i = d.x;
-            const int64_t b = (int64_t)(((uint64_t)d.z << 32) | d.y);
-            const int64_t e = b + d.w;
-            int sub;
-            double df = 0.0, s0 = 0.0, s1 = 0.0;
-            const bool dump = a.dbg != nullptr;
-            // the first 256 entries of the row: four 16-byte loads per lane, all in flight
-            uint4 v[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t q = b + 4 * l16 + 64 * r;
-                v[r] = q < e ? *reinterpret_cast<const uint4*>(ws.ent + q) : make_uint4(kPadEntry, kPadEntry, kPadEntry, kPadEntry);
+        for (int64_t base = r0 + 64 * wave; base < r1; base += 64 * (kSubThreads / 64)) {
+            const int ncell = (int)min((int64_t)64, r1 - base);
+            uint4 dsc = make_uint4(0, 0, 0, 0);
+            float nd = 0.0f;      // FP32 Gumbel noise of sub-cluster 1 less that of 0
+            int code = 0;         // reset: the fair draw; else 1 + old sub-label if the cell was in k, 0 if not
+            if (lane < ncell) {
+                dsc = ws.srow[base + lane];
+                const uint32_t i = dsc.x;
+                if (reset) {
+                    code = (int)(philox(ws.seed, i, 0u, a.step, kResub, 0u).w[0] >> 31);
+                } else {
+                    const Words w = philox(ws.seed, i, 0u, a.step, kGumbelS, 0u);
+                    nd = (-logf(-logf(unit23f(w.w[1])))) - (-logf(-logf(unit23f(w.w[0]))));
+                    code = a.c_old[i] == k ? 1 + (a.cs_old[i] & 1) : 0;
+                }
             }
-            auto dot = [&](const uint4& u) {
-                const uint32_t en[4] = {u.x, u.y, u.z, u.w};
+            for (int c4 = 0; c4 < ncell; c4 += 4) {
+                const int src = c4 + grp;
+                const bool live = src < ncell;
+                const int64_t i = (int64_t)(uint32_t)__shfl((int)dsc.x, src);
+                const int64_t b = (int64_t)(((uint64_t)(uint32_t)__shfl((int)dsc.z, src) << 32) |
+                                            (uint32_t)__shfl((int)dsc.y, src));
+                const uint32_t len = (uint32_t)__shfl((int)dsc.w, src);
+                const int64_t e = live ? b + len : b;
+                const float ndc = __shfl(nd, src);
+                const int cc = __shfl(code, src);
+                int sub;
+                double df = 0.0, s0 = 0.0, s1 = 0.0;
+                // the first 256 entries of the row: four 16-byte loads per lane, all in flight
+                uint4 v[4];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const uint32_t x = en[j] >> 16;
-                    if (!x) continue;
-                    const int g = (int)(en[j] & 0xFFFFu);
-                    df = fma((double)x, stage ? dl[g] : g1[g] - g0[g], df);
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t q = b + 4 * l16 + 64 * r;
+                    v[r] = q < e ? *reinterpret_cast<const uint4*>(ws.ent + q) : make_uint4(kPadEntry, kPadEntry, kPadEntry, kPadEntry);
+                }
+                auto dot = [&](const uint4& u) {
+                    const uint32_t en[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const uint32_t x = en[j] >> 16;
+                        if constexpr (STAGE && !DUMP) {
+                            // a pad entry adds 0 x delta_0 (log theta is finite)
+                            const int g = x ? (int)(en[j] & 0xFFFFu) : 0;
+                            df = fma((double)x, dl[g], df);
+                            continue;
+                        }
+                        if (!x) continue;
+                        const int g = (int)(en[j] & 0xFFFFu);
+                        df = fma((double)x, stage ? dl[g] : g1[g] - g0[g], df);
+                        if (dump) {
+                            s0 = fma((double)x, g0[g], s0);
+                            s1 = fma((double)x, g1[g], s1);
+                        }
+                    }
+                };
+                if (reset) {
+                    sub = cc;
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) dot(v[r]);
+                    for (int64_t q = b + 4 * l16 + 256; q < e; q += 64) dot(*reinterpret_cast<const uint4*>(ws.ent + q));
+                    df = group_sum(df);
                     if (dump) {
-                        s0 = fma((double)x, g0[g], s0);
-                        s1 = fma((double)x, g1[g], s1);
+                        s0 = group_sum(s0);
+                        s1 = group_sum(s1);
+                    }
+                    double lw0 = cc == 1 ? l0m : l0;
+                    double lw1 = cc == 2 ? l1m : l1;
+                    if (!(lw0 > -INFINITY) && !(lw1 > -INFINITY)) lw0 = lw1 = 0.0;   // both weights zero: equal
+                    // The draw compares dd + g1 - g0 with 0.  FP32 noise is within
+                    // 3e-6 of the FP64 noise, so when the FP32 difference clears
+                    // tau its sign is the FP64 sign; otherwise (or with a zero
+                    // weight) the FP64 comparison decides.
+                    const double dd = lw1 - lw0 + df;
+                    const float d32 = (float)dd + ndc;
+                    const float tau = 1e-3f + 1e-5f * fabsf((float)dd);
+                    if (isfinite(dd) && fabsf(d32) > tau) {
+                        sub = d32 > 0.0f ? 1 : 0;
+                    } else {
+                        const Words w = philox(ws.seed, (uint32_t)i, 0u, a.step, kGumbelS, 0u);
+                        const double v0 = lw0 + (-log(-log(unit23d(w.w[0]))));
+                        const double v1 = lw1 + df + (-log(-log(unit23d(w.w[1]))));
+                        sub = v1 > v0 ? 1 : 0;
                     }
                 }
-            };
-            if (reset) {
-                const Words w = philox(ws.seed, (uint32_t)i, 0u, a.step, kResub, 0u);
-                sub = (int)(w.w[0] >> 31);
-            } else {
+                // statistics of (k, sub), from the registers where the row already is
+                unsigned long long* grow = ws.ssub + (int64_t)(2 * k + sub) * G;
+                auto add = [&](const uint4& u) {
+                    const uint32_t en[4] = {u.x, u.y, u.z, u.w};
 #pragma unroll
-                for (int r = 0; r < 4; ++r) dot(v[r]);
-                for (int64_t q = b + 4 * l16 + 256; q < e; q += 64) dot(*reinterpret_cast<const uint4*>(ws.ent + q));
-                df = group_sum(df);
-                if (dump) {
-                    s0 = group_sum(s0);
-                    s1 = group_sum(s1);
-                }
-                const int32_t c_old = a.c_old[i];
-                const int s_old = a.cs_old[i] & 1;
-                double lw0 = (c_old == k && s_old == 0) ? l0m : l0;
-                double lw1 = (c_old == k && s_old == 1) ? l1m : l1;
-                if (!(lw0 > -INFINITY) && !(lw1 > -INFINITY)) lw0 = lw1 = 0.0;   // both weights zero: equal
-                const Words w = philox(ws.seed, (uint32_t)i, 0u, a.step, kGumbelS, 0u);
-                // The draw compares dd + g1 - g0 with 0.  FP32 noise is within
-                // 3e-6 of the FP64 noise, so when the FP32 difference clears
-                // tau its sign is the FP64 sign; otherwise (or with a zero
-                // weight) the FP64 comparison decides.
-                const double dd = lw1 - lw0 + df;
-                const float d32 = (float)dd + ((-logf(-logf(unit23f(w.w[1])))) - (-logf(-logf(unit23f(w.w[0])))));
-                const float tau = 1e-3f + 1e-5f * fabsf((float)dd);
-                if (isfinite(dd) && fabsf(d32) > tau) {
-                    sub = d32 > 0.0f ? 1 : 0;
-                } else {
-                    const double v0 = lw0 + (-log(-log(unit23d(w.w[0]))));
-                    const double v1 = lw1 + df + (-log(-log(unit23d(w.w[1]))));
-                    sub = v1 > v0 ? 1 : 0;
+                    for (int j = 0; j < 4; ++j) {
+                        const uint32_t x = en[j] >> 16;
+                        if (!x) continue;
+                        const uint32_t g = en[j] & 0xFFFFu;
+                        if (lhist) atomicAdd(&hist[sub * G + g], x);
+                        else atomicAdd(&grow[g], (unsigned long long)x);
+                    }
+                };
+#pragma unroll
+                for (int r = 0; r < 4; ++r) add(v[r]);
+                for (int64_t q = b + 4 * l16 + 256; q < e; q += 64) add(*reinterpret_cast<const uint4*>(ws.ent + q));
+                if (l16 == 0 && live) {
+                    atomicAdd(&ncnt[sub], 1u);
+                    a.cs_new[i] = (uint8_t)sub;
+                    if (a.dbg && K + 2 <= a.dbg_stride) {
+                        a.dbg[i * a.dbg_stride + K] = reset ? __builtin_nanf("") : (float)s0;
+                        a.dbg[i * a.dbg_stride + K + 1] = reset ? __builtin_nanf("") : (float)s1;
+                    }
                 }
             }
-            // statistics of (k, sub), from the registers where the row already is
-            unsigned long long* grow = ws.ssub + (int64_t)(2 * k + sub) * G;
-            auto add = [&](const uint4& u) {
-                const uint32_t en[4] = {u.x, u.y, u.z, u.w};
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const uint32_t x = en[j] >> 16;
-                    if (!x) continue;
-                    const uint32_t g = en[j] & 0xFFFFu;
-                    if (lhist) atomicAdd(&hist[sub * G + g], x);
-                    else atomicAdd(&grow[g], (unsigned long long)x);
-                }
-            };
-#pragma unroll
-            for (int r = 0; r < 4; ++r) add(v[r]);
-            for (int64_t q = b + 4 * l16 + 256; q < e; q += 64) add(*reinterpret_cast<const uint4*>(ws.ent + q));
-            if (l16 == 0) {
-                atomicAdd(&ncnt[sub], 1u);
-                a.cs_new[i] = (uint8_t)sub;
-                if (a.dbg && K + 2 <= a.dbg_stride) {
-                    a.dbg[i * a.dbg_stride + K] = reset ? __builtin_nanf("") : (float)s0;
-                    a.dbg[i * a.dbg_stride + K + 1] = reset ? __builtin_nanf("") : (float)s1;
-                }
-            }
-            d = dn;
         }
         __syncthreads();
         if (lhist) {
@@ -190,6 +218,15 @@ static size_t sub_stats_lds(int G)
     return lds;
 }
 
+using SubKernel = void (*)(Ws, SubArgs);
+
+static SubKernel sub_stats_kernel(int G, bool dump)
+{
+    if (G <= kSubStageGenes) return dump ? k_sub_stats<true, true, true> : k_sub_stats<true, true, false>;
+    if (G <= kSubHistGenes) return dump ? k_sub_stats<false, true, true> : k_sub_stats<false, true, false>;
+    return dump ? k_sub_stats<false, false, true> : k_sub_stats<false, false, false>;
+}
+
 // Sorted cells per workgroup: the grid fills the device's resident workgroup
 // slots once (a second, partial round would leave most of the device idle).
 hipError_t sub_stats_cells(int64_t N, int G, int32_t* cells)
@@ -198,7 +235,7 @@ hipError_t sub_stats_cells(int64_t N, int G, int32_t* cells)
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k_sub_stats),
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(sub_stats_kernel(G, false)),
                                                          kSubThreads, sub_stats_lds(G));
     if (e != hipSuccess) return e;
     const int64_t slots = (int64_t)(cus > 0 ? cus : 1) * (per_cu > 0 ? per_cu : 1);
@@ -215,7 +252,7 @@ void launch_sub_stats(const Ws& ws, const SubArgs& a, hipStream_t s)
     hipMemsetAsync(ws.nsub, 0, sizeof(unsigned long long) * 2 * (size_t)ws.k_max, s);
     hipMemsetAsync(ws.ssub, 0, sizeof(unsigned long long) * 2 * (size_t)ws.k_max * (size_t)ws.G, s);
     launch_sort(ws, a.c_new, a.cs_old, 1, s);
-    hipLaunchKernelGGL(k_sub_stats, dim3((unsigned)((ws.N + ws.sub_cells - 1) / ws.sub_cells)), dim3(kSubThreads),
+    hipLaunchKernelGGL(sub_stats_kernel(ws.G, a.dbg != nullptr), dim3((unsigned)((ws.N + ws.sub_cells - 1) / ws.sub_cells)), dim3(kSubThreads),
                        sub_stats_lds(ws.G), s, ws, a);
 }
 

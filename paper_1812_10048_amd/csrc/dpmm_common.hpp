@@ -30,15 +30,6 @@ constexpr int kGammaTries = 64;
 
 struct Words { uint32_t w[4]; };
 
-__host__ __device__ inline uint32_t mul_hi32(uint32_t a, uint32_t b)
-{
-#if defined(__HIP_DEVICE_COMPILE__)
-    return __umulhi(a, b);
-#else
-    return (uint32_t)(((uint64_t)a * (uint64_t)b) >> 32);
-#endif
-}
-
 __host__ __device__ inline Words philox(uint64_t seed, uint32_t element, uint32_t sub, uint32_t step,
                                         uint32_t stream, uint32_t call)
 {
@@ -46,8 +37,10 @@ __host__ __device__ inline Words philox(uint64_t seed, uint32_t element, uint32_
     uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t hi0 = mul_hi32(0xD2511F53u, x0), lo0 = 0xD2511F53u * x0;
-        const uint32_t hi1 = mul_hi32(0xCD9E8D57u, x2), lo1 = 0xCD9E8D57u * x2;
+        // one 32 x 32 -> 64-bit product gives both halves (v_mad_u64_u32)
+        const uint64_t p0 = (uint64_t)0xD2511F53u * x0, p1 = (uint64_t)0xCD9E8D57u * x2;
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
         x0 = hi1 ^ x1 ^ k0;
         x1 = lo1;
         x2 = hi0 ^ x3 ^ k1;

@@ -284,6 +284,7 @@ dpmm_status dpmm_init(const dpmm_csr* csr, const dpmm_params* params, void* work
     *ctx->k_host = params->k_init;
     if (params->precision == DPMM_SPLIT_BF16) {
         he = configure_assign_bf16();
+        if (he == hipSuccess) he = configure_layout();
         if (he != hipSuccess) return cleanup(fail(DPMM_ERR_HIP, "kernel attributes: %s", hipGetErrorString(he)));
     }
     he = sub_stats_cells(ws.N, ws.G, &ws.sub_cells);

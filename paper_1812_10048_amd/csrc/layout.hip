@@ -15,6 +15,15 @@
 // returns zeros is harmless too.  Counts above
 // 256 also go to a per-block list (cell, gene, count - head) whose FP32
 // corrections the kernel adds to the scores.
+//
+// The order of the entries inside a segment is free (each carries its own
+// offset).  The matrix-core kernel reads a segment with 16-byte loads, thread
+// t taking positions 1024r + 4t + c, so one wavefront store instruction
+// (wave w, r, c) writes the entries at 1024r + 256w + 4l + c, l < 64.  A
+// last pass reorders each segment so that such an instruction writes
+// entries of distinct LDS banks: the entries are taken round-robin over the
+// banks (rank within the bank, then bank) and dealt to the store
+// instructions in turn, 64 consecutive ones each.
 #include "dpmm_common.hpp"
 #include "kernels.hpp"
 
@@ -52,7 +61,8 @@ __global__ void __launch_bounds__(kLayThreads) k_seg_count(Ws ws)
         for (int64_t p = ws.roff[i]; p < ws.roff[i + 1]; ++p) {
             const uint32_t en = ws.ent[p];
             const uint32_t x = en >> 16;
-            if (!x) continue;
+            // (a gene past G is invalid input, reported by the row check)
+            if (!x || (en & 0xFFFFu) >= (uint32_t)ws.G) continue;
             atomicAdd(&cnt[(en & 0xFFFFu) / kBlkGenes], 1u);
             if (count_head(x) != x) atomicAdd(&novf, 1u);
         }
@@ -131,6 +141,74 @@ __global__ void __launch_bounds__(kLayThreads) k_seg_fill(Ws ws)
     }
 }
 
+constexpr int kBalThreads = 256;
+constexpr int kLdsBanks = 64;                       // LDS banks of 4 bytes
+constexpr int kMaxSegEntries = kBlkCells * kBlkGenes;   // every (cell, gene) of a block and chunk
+
+// position of the k-th entry of the round-robin order in a segment of n
+// entries (n a multiple of 4): the store instructions (r, w, c) in turn, each
+// with m = min(64, (n - 1024r - 256w) / 4) lanes
+__device__ inline uint32_t balanced_position(uint32_t k, uint32_t n)
+{
+    uint32_t base = 0;
+    for (uint32_t rw = 0;; ++rw) {
+        const uint32_t start = 256u * rw;     // 1024r + 256w
+        const uint32_t m = min(64u, (n - start) / 4u);
+        if (k < base + 4u * m) {
+            const uint32_t c = (k - base) / m;
+            const uint32_t l = (k - base) - c * m;
+            return start + 4u * l + c;
+        }
+        base += 4u * m;
+    }
+}
+
+__global__ void __launch_bounds__(kBalThreads) k_seg_balance(Ws ws)
+{
+    extern __shared__ uint32_t buf[];           // [kMaxSegEntries] the segment
+    __shared__ uint32_t cnt[kLdsBanks], rank[kLdsBanks], npad;
+    const int64_t sg = blockIdx.x;
+    const int64_t b0 = ws.blk_off[sg];
+    const uint32_t n = (uint32_t)(ws.blk_off[sg + 1] - b0);
+    // (a longer segment only comes from invalid input, reported by the row check)
+    if (n == 0 || n > (uint32_t)kMaxSegEntries) return;
+    uint32_t* seg = const_cast<uint32_t*>(ws.blk_ent) + b0;
+    const int t = threadIdx.x;
+    if (t < kLdsBanks) { cnt[t] = 0; rank[t] = 0; }
+    if (t == 0) npad = 0;
+    for (uint32_t q = t; q < n; q += kBalThreads) buf[q] = seg[q];
+    __syncthreads();
+    for (uint32_t q = t; q < n; q += kBalThreads) {
+        const uint32_t en = buf[q];
+        if (en & 0xFFFFu) atomicAdd(&cnt[(en >> 18) & (kLdsBanks - 1)], 1u);
+    }
+    __syncthreads();
+    uint32_t nreal = 0;
+    for (int b = 0; b < kLdsBanks; ++b) nreal += cnt[b];
+    for (uint32_t q = t; q < n; q += kBalThreads) {
+        const uint32_t en = buf[q];
+        uint32_t k;
+        if (en & 0xFFFFu) {
+            const uint32_t b = (en >> 18) & (kLdsBanks - 1);
+            const uint32_t r = atomicAdd(&rank[b], 1u);
+            // entries before (r, b): min(cnt, r) of every bank, and one of each
+            // earlier bank that reaches rank r
+            k = 0;
+            for (uint32_t b2 = 0; b2 < (uint32_t)kLdsBanks; ++b2)
+                k += min(cnt[b2], r) + (b2 < b && cnt[b2] > r ? 1u : 0u);
+        } else {
+            k = nreal + atomicAdd(&npad, 1u);    // padding (zero) entries last
+        }
+        seg[balanced_position(k, n)] = en;
+    }
+}
+
+hipError_t configure_layout()
+{
+    return hipFuncSetAttribute((const void*)k_seg_balance, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)(sizeof(uint32_t) * (size_t)kMaxSegEntries));
+}
+
 void launch_build_blocked(const Ws& ws, int64_t* tile_sums, hipStream_t s)
 {
     const int64_t nseg = (int64_t)ws.nblk * ws.nch;
@@ -138,6 +216,8 @@ void launch_build_blocked(const Ws& ws, int64_t* tile_sums, hipStream_t s)
     launch_exclusive_scan(ws.blk_off, nseg, tile_sums, s);
     launch_exclusive_scan(ws.ovf_off, ws.nblk, tile_sums, s);
     hipLaunchKernelGGL(k_seg_fill, dim3(ws.nblk), dim3(kLayThreads), 0, s, ws);
+    hipLaunchKernelGGL(k_seg_balance, dim3((unsigned)nseg), dim3(kBalThreads), sizeof(uint32_t) * (size_t)kMaxSegEntries,
+                       s, ws);
 }
 
 }  // namespace dpmm

@@ -24,6 +24,7 @@ constexpr int kSubThreads = 256;
 constexpr int kSubCellsMin = 256;       // sorted cells per workgroup, at least
 constexpr int kSubStageGenes = 4096;     // delta staged in LDS up to this G
 constexpr int kSubHistGenes = 8192;      // LDS histograms up to this G
+constexpr int kSubLoads = 5;             // 16-byte loads per lane in flight: the first 320 entries of a row
 
 // sum over the 16 lanes of a group, in a fixed order
 __device__ inline double group_sum(double v)
@@ -114,10 +115,11 @@ __global__ void __launch_bounds__(kSubThreads) __attribute__((amdgpu_waves_per_e
                 const int cc = __shfl(code, src);
                 int sub;
                 double df = 0.0, s0 = 0.0, s1 = 0.0;
-                // the first 256 entries of the row: four 16-byte loads per lane, all in flight
-                uint4 v[4];
+                // the first 64 kSubLoads entries of the row (nearly every row),
+                // all loads in flight together
+                uint4 v[kSubLoads];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
+                for (int r = 0; r < kSubLoads; ++r) {
                     const int64_t q = b + 4 * l16 + 64 * r;
                     v[r] = q < e ? *reinterpret_cast<const uint4*>(ws.ent + q) : make_uint4(kPadEntry, kPadEntry, kPadEntry, kPadEntry);
                 }
@@ -145,8 +147,8 @@ __global__ void __launch_bounds__(kSubThreads) __attribute__((amdgpu_waves_per_e
                     sub = cc;
                 } else {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) dot(v[r]);
-                    for (int64_t q = b + 4 * l16 + 256; q < e; q += 64) dot(*reinterpret_cast<const uint4*>(ws.ent + q));
+                    for (int r = 0; r < kSubLoads; ++r) dot(v[r]);
+                    for (int64_t q = b + 4 * l16 + 64 * kSubLoads; q < e; q += 64) dot(*reinterpret_cast<const uint4*>(ws.ent + q));
                     df = group_sum(df);
                     if (dump) {
                         s0 = group_sum(s0);
@@ -185,8 +187,8 @@ __global__ void __launch_bounds__(kSubThreads) __attribute__((amdgpu_waves_per_e
                     }
                 };
 #pragma unroll
-                for (int r = 0; r < 4; ++r) add(v[r]);
-                for (int64_t q = b + 4 * l16 + 256; q < e; q += 64) add(*reinterpret_cast<const uint4*>(ws.ent + q));
+                for (int r = 0; r < kSubLoads; ++r) add(v[r]);
+                for (int64_t q = b + 4 * l16 + 64 * kSubLoads; q < e; q += 64) add(*reinterpret_cast<const uint4*>(ws.ent + q));
                 if (l16 == 0 && live) {
                     atomicAdd(&ncnt[sub], 1u);
                     a.cs_new[i] = (uint8_t)sub;

@@ -43,7 +43,7 @@ __global__ void __launch_bounds__(kSubThreads) __attribute__((amdgpu_waves_per_e
     const int G = ws.G;
     constexpr bool stage = STAGE, lhist = LHIST, dump = DUMP;
     double* dl = reinterpret_cast<double*>(lds);                        // [G] delta if staged
-    uint32_t* hist = reinterpret_cast<uint32_t*>(lds + (stage ? 8 * (size_t)G : 0));    // [2][G]
+    uint32_t* hist = reinterpret_cast<uint32_t*>(lds + (stage ? 8 * (size_t)G : 0));    // [2][G], then a spare slot per lane
     __shared__ uint32_t ncnt[2];
     const int K = ws.st->K;
     const int lane = threadIdx.x & 63;
@@ -180,10 +180,14 @@ __global__ void __launch_bounds__(kSubThreads) __attribute__((amdgpu_waves_per_e
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
                         const uint32_t x = en[j] >> 16;
-                        if (!x) continue;
                         const uint32_t g = en[j] & 0xFFFFu;
-                        if (lhist) atomicAdd(&hist[sub * G + g], x);
-                        else atomicAdd(&grow[g], (unsigned long long)x);
+                        if constexpr (LHIST) {
+                            // a pad entry adds 0 to the lane's spare slot
+                            atomicAdd(&hist[x ? sub * G + g : 2 * G + lane], x);
+                        } else {
+                            if (!x) continue;
+                            atomicAdd(&grow[g], (unsigned long long)x);
+                        }
                     }
                 };
 #pragma unroll
@@ -216,7 +220,7 @@ static size_t sub_stats_lds(int G)
 {
     size_t lds = 0;
     if (G <= kSubStageGenes) lds += 8 * (size_t)G;
-    if (G <= kSubHistGenes) lds += 8 * (size_t)G;
+    if (G <= kSubHistGenes) lds += 8 * (size_t)G + 4 * 64;   // + a spare slot per lane
     return lds;
 }
 

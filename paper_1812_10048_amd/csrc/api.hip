@@ -40,7 +40,7 @@ constexpr int kTablePadRows = 64;      // spare cluster rows read by its last co
 size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
 struct Layout {
-    size_t ent, roff, tiles, c0, c1, cs0, cs1, st, reset, nsub, ssub, beta, logpi, lt64, lc32, ls32, lhi, llo,
+    size_t ent, roff, tiles, c0, c1, cs0, cs1, st, reset, nsub, ssub, beta, lgbeta, logpi, lt64, lc32, ls32, lhi, llo,
         refine, perm, srow, grp_cnt, grp_off, grp_cur, nsub_prev, blk_ent, blk_off, ovf_off, ovf_ent, relab_c, relab_s, sm_logr, sm_acc, mkey, mlist, dm_k, eb_tmp, rd_part, total;
 };
 
@@ -78,6 +78,7 @@ Layout plan(int64_t N, int32_t G, int64_t nnz, int32_t k_max, int32_t precision)
     L.nsub = take(16 * (size_t)k_max);
     L.ssub = take(16 * (size_t)k_max * (size_t)G);
     L.beta = take(8 * (size_t)G);
+    L.lgbeta = take(8 * (size_t)G);
     L.logpi = take(8 * (size_t)k_max);
     L.lt64 = take(24 * (size_t)k_max * (size_t)G);
     L.lc32 = take(4 * ((size_t)G * (size_t)kpad + kTablePadRows));
@@ -240,6 +241,7 @@ dpmm_status dpmm_init(const dpmm_csr* csr, const dpmm_params* params, void* work
     ws.nsub = (unsigned long long*)(base + L.nsub);
     ws.ssub = (unsigned long long*)(base + L.ssub);
     ws.beta = (double*)(base + L.beta);
+    ws.lgbeta = (double*)(base + L.lgbeta);
     ws.logpi = (double*)(base + L.logpi);
     ws.lt64 = (double*)(base + L.lt64);
     ws.lc32 = (float*)(base + L.lc32);

@@ -70,10 +70,21 @@ __device__ inline SmRed block_reduce(SmRed v)
     return r;
 }
 
-// lgamma(beta + v) - lgamma(beta), zero for v = 0
-__device__ inline double rising(double beta, long long v)
+// lgamma(beta + v) - lgamma(beta), zero for v = 0 (lgb = lgamma(beta))
+__device__ inline double rising(double beta, double lgb, long long v)
 {
-    return v ? lgamma(beta + (double)v) - lgamma(beta) : 0.0;
+    return v ? lgamma(beta + (double)v) - lgb : 0.0;
+}
+
+__global__ void k_lgamma_beta(Ws ws)
+{
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u < ws.G) ws.lgbeta[u] = lgamma(ws.beta[u]);
+}
+
+static void launch_lgamma_beta(const Ws& ws, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_lgamma_beta, dim3((unsigned)((ws.G + 255) / 256)), dim3(256), 0, s, ws);
 }
 
 __global__ void __launch_bounds__(kSmThreads) k_split_ratios(Ws ws)
@@ -92,15 +103,15 @@ __global__ void __launch_bounds__(kSmThreads) k_split_ratios(Ws ws)
         r.a = r.b = 0;
         r.beta = 0.0;
         for (int u = threadIdx.x; u < G; u += kSmThreads) {
-            const double bu = ws.beta[u];
+            const double bu = ws.beta[u], lgb = ws.lgbeta[u];
             const long long a = (long long)s0[u], b = (long long)s1[u];
             r.beta += bu;
             r.a += a;
             r.b += b;
             if (a + b == 0) continue;
-            r.cs.add(rising(bu, a));
-            r.cs.add(rising(bu, b));
-            r.cs.add(-rising(bu, a + b));
+            r.cs.add(rising(bu, lgb, a));
+            r.cs.add(rising(bu, lgb, b));
+            r.cs.add(-rising(bu, lgb, a + b));
         }
         r = block_reduce<kSmThreads>(r);
         if (threadIdx.x == 0) {
@@ -132,7 +143,7 @@ __global__ void __launch_bounds__(kSmThreads) k_cluster_logdm(Ws ws)
             const long long v = (long long)(s0[u] + s1[u]);
             r.beta += bu;
             r.a += v;
-            r.cs.add(rising(bu, v));
+            r.cs.add(rising(bu, ws.lgbeta[u], v));
         }
         r = block_reduce<kSmThreads>(r);
         if (threadIdx.x == 0) {
@@ -170,7 +181,7 @@ __global__ void __launch_bounds__(kMergeThreads) k_merge_ratios(Ws ws)
             const long long v = (long long)(a0[u] + a0[u + G] + b0[u] + b0[u + G]);
             r.beta += bu;
             r.a += v;
-            r.cs.add(rising(bu, v));
+            r.cs.add(rising(bu, ws.lgbeta[u], v));
         }
         r = block_reduce<kMergeThreads>(r);
         if (threadIdx.x == 0) {
@@ -192,12 +203,14 @@ __global__ void __launch_bounds__(kMergeThreads) k_merge_ratios(Ws ws)
 void launch_split_ratios(const Ws& ws, hipStream_t s)
 {
     const int blocks = ws.k_max < 1024 ? ws.k_max : 1024;
+    launch_lgamma_beta(ws, s);
     hipLaunchKernelGGL(k_split_ratios, dim3(blocks), dim3(kSmThreads), 0, s, ws);
 }
 
 void launch_merge_ratios(const Ws& ws, hipStream_t s)
 {
     const int blocks = ws.k_max < 1024 ? ws.k_max : 1024;
+    launch_lgamma_beta(ws, s);
     hipLaunchKernelGGL(k_cluster_logdm, dim3(blocks), dim3(kSmThreads), 0, s, ws);
     const long long np = (long long)ws.k_max * (ws.k_max - 1) / 2;
     const int mb = np < 4096 ? (int)(np > 0 ? np : 1) : 4096;

@@ -174,7 +174,7 @@ void launch_init_labels(const Ws& ws, int32_t k_init, int32_t* c, uint8_t* cs, h
 // the cells of one cluster together.
 // ---------------------------------------------------------------------------
 constexpr int kSortThreads = 1024;
-constexpr int kSortCellsPerBlock = 16384;
+constexpr int kSortCellsPerBlock = 2048;
 constexpr int kStatThreads = 256;
 constexpr int kStatCells = 2048;
 constexpr int kStatMaxGenes = 16384;

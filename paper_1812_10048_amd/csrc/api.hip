@@ -281,9 +281,11 @@ dpmm_status dpmm_init(const dpmm_csr* csr, const dpmm_params* params, void* work
         delete ctx;
         return st;
     };
-    he = hipHostMalloc((void**)&ctx->k_host, sizeof(int32_t), hipHostMallocDefault);
+    he = hipHostMalloc((void**)&ctx->k_host, sizeof(int32_t), hipHostMallocMapped);
     if (he != hipSuccess) { ctx->k_host = nullptr; return cleanup(fail(DPMM_ERR_HIP, "hipHostMalloc: %s", hipGetErrorString(he))); }
     *ctx->k_host = params->k_init;
+    he = hipHostGetDevicePointer((void**)&ws.k_hint, ctx->k_host, 0);
+    if (he != hipSuccess) return cleanup(fail(DPMM_ERR_HIP, "hipHostGetDevicePointer: %s", hipGetErrorString(he)));
     if (params->precision == DPMM_SPLIT_BF16) {
         he = configure_assign_bf16();
         if (he == hipSuccess) he = configure_layout();
@@ -347,8 +349,7 @@ dpmm_status dpmm_sweep(dpmm_ctx* ctx, int32_t n_sweeps)
     for (int32_t n = 0; n < n_sweeps; ++n) {
         const int nxt = 1 - ctx->cur;
         const uint32_t step = (uint32_t)ctx->step;
-        launch_redraw(ws, step, ctx->precision == DPMM_SPLIT_BF16, ctx->stream);
-        HIP_TRY(hipMemsetAsync(&ws.st->n_refine, 0, sizeof(int32_t), ctx->stream));
+        launch_redraw(ws, step, ctx->precision == DPMM_SPLIT_BF16, ctx->stream);   // also empties the re-score queue
         AssignArgs a{};
         a.c_old = ctx->c[ctx->cur];
         a.cs_old = ctx->cs[ctx->cur];
@@ -381,9 +382,7 @@ dpmm_status dpmm_sweep(dpmm_ctx* ctx, int32_t n_sweeps)
         launch_sub_stats(ws, sa, ctx->stream);
         launch_compact(ws, 1, ctx->stream);
         launch_relabel(ws, ctx->c[nxt], ctx->cs[nxt], ctx->stream);
-        HIP_TRY(hipGetLastError());
-        s = refresh_k_hint(ctx);
-        if (s != DPMM_OK) return s;
+        HIP_TRY(hipGetLastError());     // (k_compact has written the K hint)
         ctx->cur = nxt;
         ctx->step += 1;
         ctx->sweeps += 1;
@@ -405,9 +404,7 @@ dpmm_status dpmm_split_merge(dpmm_ctx* ctx)
     else launch_split_ratios(ctx->ws, ctx->stream);
     launch_sm_decide(ctx->ws, merge_pass, step, ctx->stream);
     launch_relabel(ctx->ws, ctx->c[ctx->cur], ctx->cs[ctx->cur], ctx->stream);
-    HIP_TRY(hipGetLastError());
-    s = refresh_k_hint(ctx);
-    if (s != DPMM_OK) return s;
+    HIP_TRY(hipGetLastError());     // (k_sm_decide has written the K hint)
     ctx->last_pass = merge_pass;
     ctx->step += 1;
     ctx->sm_calls += 1;

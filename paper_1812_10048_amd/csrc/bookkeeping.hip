@@ -333,10 +333,11 @@ __global__ void k_stats_atomic(Ws ws, const int32_t* __restrict__ c, const uint8
     }
 }
 
-void launch_sort(const Ws& ws, const int32_t* c, const uint8_t* cs, int by_cluster, hipStream_t s)
+void launch_sort(const Ws& ws, const int32_t* c, const uint8_t* cs, int by_cluster, hipStream_t s,
+                 bool counts_cleared)
 {
     const int ng = by_cluster ? ws.k_max : 2 * ws.k_max;
-    hipMemsetAsync(ws.grp_cnt, 0, sizeof(int32_t) * (size_t)ng, s);
+    if (!counts_cleared) hipMemsetAsync(ws.grp_cnt, 0, sizeof(int32_t) * (size_t)ng, s);
     const unsigned sb = (unsigned)((ws.N + kSortCellsPerBlock - 1) / kSortCellsPerBlock);
     hipLaunchKernelGGL(k_group_count, dim3(sb), dim3(kSortThreads), sizeof(uint32_t) * (size_t)ng, s, ws, c, cs,
                        by_cluster);
@@ -421,6 +422,7 @@ __global__ void __launch_bounds__(1024) k_compact(Ws ws, int after_sweep)
     if (t == 0) {
         ws.st->K = nk;
         ws.st->relabel = s_changed;
+        if (ws.k_hint) __hip_atomic_store(ws.k_hint, nk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }
 

@@ -190,6 +190,8 @@ struct Ws {
     int32_t nblk;
     int32_t nch;
     int32_t sub_cells;     // sorted cells per workgroup of the sub-cluster/statistics pass
+    int32_t* k_hint;       // mapped pinned host word: K after the last compaction or split/merge
+                           // (a launch-size hint for the host; written by the kernels that set K)
     int32_t* relab_c;      // [2 k_max] new cluster of an old (k, r)
     uint8_t* relab_s;      // [2 k_max] new sub-label of an old (k, r); 0xFF keeps it
     double* sm_logr;       // [k_max + k_max (k_max - 1) / 2]

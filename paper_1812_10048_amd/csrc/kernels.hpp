@@ -12,7 +12,8 @@ void launch_pack(const int64_t* row_ptr, const int32_t* col, const int32_t* val,
                  int64_t* roff, int64_t* tile_sums, uint32_t* ent, DevState* st, hipStream_t s);
 void launch_init_labels(const Ws& ws, int32_t k_init, int32_t* c, uint8_t* cs, hipStream_t s);
 void launch_stats(const Ws& ws, const int32_t* c, const uint8_t* cs, hipStream_t s);
-void launch_sort(const Ws& ws, const int32_t* c, const uint8_t* cs, int by_cluster, hipStream_t s);
+void launch_sort(const Ws& ws, const int32_t* c, const uint8_t* cs, int by_cluster, hipStream_t s,
+                 bool counts_cleared = false);
 
 // layout.hip
 void launch_build_blocked(const Ws& ws, int64_t* tile_sums, hipStream_t s);

@@ -168,6 +168,8 @@ __global__ void __launch_bounds__(kRedrawThreads) k_redraw_draw(Ws ws, uint32_t 
 __global__ void __launch_bounds__(kRedrawThreads) k_redraw_norm(Ws ws, int write_split)
 {
     const int K = ws.st->K;
+    // the re-score queue of the sweep that follows starts empty
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) ws.st->n_refine = 0;
     const int row = blockIdx.x;
     const int tile = blockIdx.y;
     const int G = ws.G;

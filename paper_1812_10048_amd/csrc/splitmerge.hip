@@ -311,6 +311,7 @@ __global__ void __launch_bounds__(kDecideThreads) k_sm_decide(Ws ws, int merge_p
         }
         if (t == 0) {
             ws.st->K = s_K;
+            if (ws.k_hint) __hip_atomic_store(ws.k_hint, s_K, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
             ws.st->relabel = s_any;
             ws.st->sm_pass = 0;
             ws.st->sm_n = K;
@@ -432,6 +433,7 @@ __global__ void __launch_bounds__(kDecideThreads) k_sm_decide(Ws ws, int merge_p
     }
     if (t == 0) {
         ws.st->K = nk;
+        if (ws.k_hint) __hip_atomic_store(ws.k_hint, nk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         ws.st->relabel = merges > 0;
         ws.st->sm_pass = 1;
         ws.st->sm_n = (int32_t)npairs;

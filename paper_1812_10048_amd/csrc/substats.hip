@@ -251,13 +251,26 @@ hipError_t sub_stats_cells(int64_t N, int G, int32_t* cells)
     return hipSuccess;
 }
 
+// One launch instead of a copy and three fills: the counts at the start of the
+// sweep (which feed eq. 8) move to nsub_prev, and the new counts, statistics
+// and sort counters start from zero.
+__global__ void k_sub_prep(Ws ws)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nt = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t q = t; q < 2 * (int64_t)ws.k_max; q += nt) {
+        ws.nsub_prev[q] = ws.nsub[q];
+        ws.nsub[q] = 0;
+    }
+    for (int64_t q = t; q < ws.k_max; q += nt) ws.grp_cnt[q] = 0;
+    ulonglong2* sv = reinterpret_cast<ulonglong2*>(ws.ssub);      // 2 k_max G is even
+    for (int64_t q = t; q < (int64_t)ws.k_max * ws.G; q += nt) sv[q] = make_ulonglong2(0ull, 0ull);
+}
+
 void launch_sub_stats(const Ws& ws, const SubArgs& a, hipStream_t s)
 {
-    // counts at the start of the sweep feed eq. 8; the new ones accumulate from zero
-    hipMemcpyAsync(ws.nsub_prev, ws.nsub, sizeof(unsigned long long) * 2 * (size_t)ws.k_max, hipMemcpyDeviceToDevice, s);
-    hipMemsetAsync(ws.nsub, 0, sizeof(unsigned long long) * 2 * (size_t)ws.k_max, s);
-    hipMemsetAsync(ws.ssub, 0, sizeof(unsigned long long) * 2 * (size_t)ws.k_max * (size_t)ws.G, s);
-    launch_sort(ws, a.c_new, a.cs_old, 1, s);
+    hipLaunchKernelGGL(k_sub_prep, dim3(256), dim3(256), 0, s, ws);
+    launch_sort(ws, a.c_new, a.cs_old, 1, s, true);
     hipLaunchKernelGGL(sub_stats_kernel(ws.G, a.dbg != nullptr), dim3((unsigned)((ws.N + ws.sub_cells - 1) / ws.sub_cells)), dim3(kSubThreads),
                        sub_stats_lds(ws.G), s, ws, a);
 }

@@ -92,7 +92,9 @@ def counters(root: str, copy_bytes: int, kernel: str | None) -> None:
     def total(k):
         return sum(sum(v.values()) for v in per[k].values())
     print(f"{'kernel':60s} {'disp':>5s}  counter: mean / max per dispatch (KiB for *_SIZE)")
-    for k in sorted(per, key=lambda k: -total(k))[:25]:
+    ranked = sorted(per, key=lambda k: -total(k))
+    shown = ranked[:25] + [k for k in ranked[25:] if "dpmm::" in k]   # every library kernel
+    for k in shown:
         parts = []
         n = 0
         for c, dv in sorted(per[k].items()):

@@ -26,6 +26,10 @@ _LIB = os.path.join(_HERE, "liboracle_dpmm.so")
 ST_INIT, ST_GAMMA, ST_PI, ST_GUMBEL_C, ST_GUMBEL_S, ST_RESUB, ST_CHAIN, ST_SPLIT, ST_MERGE = range(1, 10)
 SUB_ROW_BASE = 0x10000
 
+# Flags of the chain (dpmm_oracle.c): the split ratio carries the proposal
+# term -Q_k = -sum_{i in k} log p(cbar_i) of Section 2.3.
+SPLIT_Q = 1
+
 COUNTER_NAMES = [
     "gamma_caps", "gamma_near_ties", "splits_proposed", "splits_accepted",
     "merges_proposed", "merges_accepted", "kmax_skips", "sweeps", "sm_calls",
@@ -68,10 +72,10 @@ class _State(ctypes.Structure):
         ("n_cells", _I64), ("n_genes", _I32), ("k_max", _I32),
         ("row_ptr", _P), ("col", _P), ("val", _P),
         ("alpha", _D), ("beta", _P), ("seed", _U64),
-        ("step", _I64), ("K", _I32), ("pad_", _I32),
+        ("step", _I64), ("K", _I32), ("flags", _U32),
         ("c", _P), ("cs", _P), ("reset", _P), ("nsub", _P), ("ssub", _P),
         ("logpi", _P), ("logtheta", _P),
-        ("margin_c", _P), ("margin_s", _P),
+        ("margin_c", _P), ("margin_s", _P), ("lpsub", _P),
         ("sm_logr", _P), ("sm_scale", _P), ("sm_accept", _P),
         ("sm_pass", _I32), ("sm_n", _I32),
         ("counters", _I64 * 16),
@@ -220,7 +224,8 @@ class Oracle:
     """
 
     def __init__(self, row_ptr, col, val, n_genes: int, alpha: float = 1.0, beta=1.0,
-                 seed: int = 0, k_max: int = 64, k_init: int = 1, init: bool = True):
+                 seed: int = 0, k_max: int = 64, k_init: int = 1, init: bool = True,
+                 split_q: bool = False):
         self.row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
         self.col = np.ascontiguousarray(col, dtype=np.int32)
         self.val = np.ascontiguousarray(val, dtype=np.int32)
@@ -238,6 +243,7 @@ class Oracle:
         self.logtheta = np.zeros((3 * self.k_max, G), dtype=np.float64)
         self.margin_c = np.zeros(N, dtype=np.float64)
         self.margin_s = np.zeros(N, dtype=np.float64)
+        self.lpsub = np.zeros(N, dtype=np.float64)
         ncand = self.k_max + self.k_max * (self.k_max - 1) // 2
         self.sm_logr = np.zeros(ncand, dtype=np.float64)
         self.sm_scale = np.zeros(ncand, dtype=np.float64)
@@ -247,8 +253,9 @@ class Oracle:
         st.row_ptr, st.col, st.val = _ptr(self.row_ptr), _ptr(self.col), _ptr(self.val)
         st.alpha, st.beta, st.seed = float(alpha), _ptr(self.beta), int(seed) & 0xFFFFFFFFFFFFFFFF
         st.step, st.K = 0, 0
+        st.flags = SPLIT_Q if split_q else 0
         for name in ("c", "cs", "reset", "nsub", "ssub", "logpi", "logtheta", "margin_c",
-                     "margin_s", "sm_logr", "sm_scale", "sm_accept"):
+                     "margin_s", "lpsub", "sm_logr", "sm_scale", "sm_accept"):
             setattr(st, name, _ptr(getattr(self, name)))
         self._st = st
         if init:

@@ -273,6 +273,8 @@ void oracle_dm_logmarginal(const int64_t* s, int32_t J, int32_t G, const double*
 /* Sampler state.  All arrays are owned by the caller.                      */
 /* ------------------------------------------------------------------------ */
 
+enum { ORACLE_SPLIT_Q = 1u };
+
 enum {
     CNT_GAMMA_CAPS = 0,
     CNT_GAMMA_NEAR_TIES = 1,
@@ -301,7 +303,8 @@ typedef struct {
     /* chain state */
     int64_t step;
     int32_t K;
-    int32_t pad_;
+    uint32_t flags;           /* ORACLE_SPLIT_Q: the split ratio carries the
+                                 proposal term of Section 2.3                  */
     int32_t* c;               /* [N]                                          */
     uint8_t* cs;              /* [N] sub-cluster labels                       */
     uint8_t* reset;           /* [k_max] sub-labels to be re-drawn at random  */
@@ -313,6 +316,8 @@ typedef struct {
     /* diagnostics of the last sweep / split-merge call */
     double* margin_c;         /* [N] relative Gumbel-max margin, cluster      */
     double* margin_s;         /* [N] relative Gumbel-max margin, sub-cluster  */
+    double* lpsub;            /* [N] log p(cbar_i) of eq. 8 in the last sweep
+                                 (0 for a reset cluster or before any sweep)  */
     double* sm_logr;          /* [k_max + k_max (k_max - 1) / 2] log ratios   */
     double* sm_scale;         /* same size: sum of |terms| of each ratio      */
     uint8_t* sm_accept;       /* same size: 1 if accepted                     */
@@ -385,6 +390,7 @@ void oracle_init(oracle_state* st, int32_t k_init)
         st->cs[i] = 0;
     }
     st->K = k_init <= 1 ? 1 : k_init;
+    memset(st->lpsub, 0, sizeof(double) * (size_t)st->n_cells);
     memset(st->reset, 0, (size_t)st->k_max);
     for (int32_t k = 0; k < st->K; ++k) st->reset[k] = 1;
     st->step = 0;
@@ -399,6 +405,7 @@ void oracle_set_state(oracle_state* st, int64_t step, int32_t K)
 {
     st->step = step;
     st->K = K;
+    memset(st->lpsub, 0, sizeof(double) * (size_t)st->n_cells);
     oracle_stats(st);
 }
 
@@ -538,6 +545,7 @@ void oracle_assign(oracle_state* st)
             draw_words(st->seed, (uint32_t)i, 0u, st->step, ST_RESUB, 0u, w);
             sub = (int32_t)(w[0] >> 31);
             st->margin_s[i] = INFINITY;
+            st->lpsub[i] = 0.0;
         } else {
             int64_t wt[2];
             for (int r = 0; r < 2; ++r) wt[r] = st->nsub[2 * k + r] - ((c_old == k && s_old == r) ? 1 : 0);
@@ -547,12 +555,16 @@ void oracle_assign(oracle_state* st)
                 else lw[r] = wt[r] > 0 ? log((double)wt[r]) : -INFINITY;
             }
             draw_words(st->seed, (uint32_t)i, 0u, st->step, ST_GUMBEL_S, 0u, w);
-            double v[2];
-            for (int r = 0; r < 2; ++r)
-                v[r] = lw[r] + cell_loglik(st, i, st->logtheta + (int64_t)(st->k_max + 2 * k + r) * G) +
-                       gumbel(oracle_u23(w[r]));
+            double ll[2], v[2];
+            for (int r = 0; r < 2; ++r) {
+                ll[r] = lw[r] + cell_loglik(st, i, st->logtheta + (int64_t)(st->k_max + 2 * k + r) * G);
+                v[r] = ll[r] + gumbel(oracle_u23(w[r]));
+            }
             sub = v[1] > v[0] ? 1 : 0;
             st->margin_s[i] = rel_margin(fmax(v[0], v[1]), fmin(v[0], v[1]));
+            /* the eq. 8 probability of the drawn sub-label: a two-way softmax */
+            const double m = fmax(ll[0], ll[1]);
+            st->lpsub[i] = ll[sub] - (m + log(exp(ll[0] - m) + exp(ll[1] - m)));
         }
         st->c[i] = k;
         st->cs[i] = (uint8_t)sub;
@@ -682,6 +694,12 @@ void oracle_split_merge(oracle_state* st)
         st->sm_n = K;
         int32_t K_new = K;
         int32_t* newlab = (int32_t*)malloc(sizeof(int32_t) * (size_t)(K > 0 ? K : 1));
+        /* Section 2.3: the split proposes the current sub-clusters, with
+         * probability q = prod_{i in k} p(cbar_i) (eq. 8), and the reverse merge
+         * is certain; with ORACLE_SPLIT_Q the ratio carries -Q_k = -log q. */
+        double* Q = (double*)calloc((size_t)(K > 0 ? K : 1), sizeof(double));
+        if (st->flags & ORACLE_SPLIT_Q)
+            for (int64_t i = 0; i < st->n_cells; ++i) Q[st->c[i]] += st->lpsub[i];
 #pragma omp parallel for schedule(dynamic, 1)
         for (int32_t k = 0; k < K; ++k) {
             const int64_t n0 = st->nsub[2 * k], n1 = st->nsub[2 * k + 1];
@@ -691,8 +709,11 @@ void oracle_split_merge(oracle_state* st)
                 continue;
             }
             st->sm_logr[k] = oracle_split_logr(st->ssub + (int64_t)(2 * k) * G, st->ssub + (int64_t)(2 * k + 1) * G,
-                                               n0, n1, st->beta, G, st->alpha, &st->sm_scale[k]);
+                                               n0, n1, st->beta, G, st->alpha, &st->sm_scale[k]) -
+                             Q[k];
+            st->sm_scale[k] += fabs(Q[k]);
         }
+        free(Q);
         for (int32_t k = 0; k < K; ++k) {
             newlab[k] = -1;
             st->sm_accept[k] = 0;

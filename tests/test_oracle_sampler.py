@@ -7,6 +7,8 @@
   steps equal the exact categorical probabilities computed here with numpy,
   for the cluster choice, the sub-cluster choice with its n_{r,-i} weights,
   the equal-weight case and the reset coin.
+* The split proposal term (SPLIT_Q): the per-cell log p(cbar_i) matches the
+  frequency of the draws, and enters the split ratio as -sum over the cluster.
 * Statistics and compaction: conservation and consistency invariants.
 * Split and merge application: acceptance frequency equals min(1, R); moved
   statistics equal statistics recomputed from the moved labels.
@@ -192,6 +194,83 @@ def test_subcluster_equal_weights_and_reset_coin():
     p1 = 1.0 / (1.0 + np.exp(sc[0] - sc[1]))
     assert _chi2_ok([T - ones[0], ones[0]], [1 - p1, p1])[0]
     assert _chi2_ok([T - ones[1], ones[1]], [0.5, 0.5])[0]
+
+
+def test_logp_of_the_drawn_subcluster_matches_its_frequency():
+    """lpsub (log p(cbar_i), eq. 8) is tied to the draws themselves: with fixed
+    parameters, the probability of cbar_i = 1 implied by lpsub is the same at
+    every step and equals the empirical frequency of cbar_i = 1; a reset
+    cluster's coin carries log p = 0 (no proposal term)."""
+    rng = np.random.default_rng(21)
+    N, G = 5, 3
+    X = rng.integers(0, 3, size=(N, G))
+    X[:, 0] += 1
+    o = _dense_oracle(X, k_max=4)
+    c = np.zeros(N, dtype=np.int32)
+    cs = np.array([0, 1, 1, 0, 0], dtype=np.uint8)        # nbar = (3, 2)
+    o.set_state(0, 2, c, cs, np.zeros(2))
+    assert np.all(o.lpsub == 0.0)
+    lsub = np.log(rng.dirichlet(np.ones(G) * 2, size=2))
+    T = 20000
+    ones = np.zeros(N)
+    p1 = np.full((T, N), np.nan)
+    for t in range(T):
+        o.logpi[:2] = [0.0, -1e6]                          # cluster 1 is never chosen
+        o.logtheta[:2] = np.log(1.0 / G)
+        o.logtheta[4:6] = lsub
+        o.c[:] = c
+        o.cs[:] = cs
+        o.step = t
+        o.assign()
+        assert np.all(o.c == 0)
+        ones += o.cs
+        pd = np.exp(o.lpsub)                               # probability of the drawn label
+        assert np.all((pd > 0) & (pd <= 1.0))
+        p1[t] = np.where(o.cs == 1, pd, 1.0 - pd)
+    for i in range(N):
+        assert np.ptp(p1[:, i]) < 1e-12, i
+        ok, info = _chi2_ok([T - ones[i], ones[i]], [1 - p1[0, i], p1[0, i]])
+        assert ok, (i, info)
+    # a reset cluster draws a fair coin and carries no proposal term
+    o.reset[0] = 1
+    o.c[:] = c
+    o.cs[:] = cs
+    o.step = T
+    o.assign()
+    assert np.all(o.lpsub == 0.0)
+
+
+def test_split_q_adds_minus_the_summed_logp_to_the_split_ratio():
+    """With SPLIT_Q the split ratio of every eligible cluster exceeds the plain
+    one by -Q_k = -sum_{i in k} log p(cbar_i) (Section 2.3, q(S*|S) = prod p(cbar_i),
+    q(S|S*) = 1); merge passes are unchanged, so the two chains agree up to the
+    first split pass."""
+    d = synth.generate("c1", seed=3)
+    rp, col, val = d.host_arrays()
+    chains = [oracle.Oracle(rp, col, val, d.n_genes, seed=5, k_max=16, init=False, split_q=q) for q in (False, True)]
+    cs0 = np.random.default_rng(2).integers(0, 2, size=d.n_cells)
+    for o in chains:
+        o.set_state(0, d.n_true, d.z, cs0, np.ones(d.n_true, dtype=np.uint8))
+    for it in range(12):
+        for o in chains:
+            o.sweep()
+        a, b = chains
+        assert np.array_equal(a.c, b.c) and np.array_equal(a.lpsub, b.lpsub)
+        K = b.K
+        Q = np.bincount(b.c, weights=b.lpsub, minlength=K)
+        for o in chains:
+            o.split_merge()
+        if b.sm_pass == 1:
+            assert np.array_equal(a.sm_logr[: a.sm_n], b.sm_logr[: b.sm_n], equal_nan=True)
+            continue
+        plain, withq = a.sm_logr[:K], b.sm_logr[:K]
+        live = ~np.isnan(plain)
+        assert live.any()
+        assert np.array_equal(np.isnan(withq), ~live)
+        assert np.allclose(withq[live] - plain[live], -Q[live], rtol=1e-9, atol=1e-9 * b.sm_scale[:K][live].max())
+        assert np.all(-Q[live] >= 0)
+        return
+    pytest.fail("no split pass in 12 iterations")
 
 
 # --------------------------------------------------------------------------

@@ -68,6 +68,16 @@ typedef struct dpmm_csr {
     const int32_t* val;       /* device, nnz counts                                */
 } dpmm_csr;
 
+/* dpmm_params.flags.  DPMM_FLAG_SPLIT_Q: the split ratio carries the
+ * proposal term of Section 2.3.  A split proposes the current sub-clusters,
+ * drawn with the eq. 8 probabilities p(cbar_i) of the last sweep, and the
+ * reverse merge is certain, so log R gains -sum_{i in k} log p(cbar_i).
+ * Without the flag the ratio is the collapsed one alone.  The per-cell
+ * log p(cbar_i) are kept from the last sweep (8 bytes per cell of workspace),
+ * are 0 for a cluster that re-drew its sub-labels at random, and are 0 after
+ * dpmm_init and dpmm_set_state. */
+#define DPMM_FLAG_SPLIT_Q 1u
+
 /* Hyper-parameters and sampler settings, copied at dpmm_init. */
 typedef struct dpmm_params {
     double alpha;                  /* CRP parameter alpha (Section 2.1), > 0      */
@@ -79,7 +89,7 @@ typedef struct dpmm_params {
                                       uniformly when > 1)                         */
     int32_t k_max;                 /* cluster capacity, 1..1024                   */
     int32_t precision;             /* dpmm_precision                               */
-    uint32_t flags;                /* reserved, must be 0                          */
+    uint32_t flags;                /* 0 or DPMM_FLAG_SPLIT_Q                       */
     double refine_tol;             /* FP32 and split-BF16 only.  A cluster
                                       decision whose Gumbel gap is within the
                                       certified rounding bound of its two best

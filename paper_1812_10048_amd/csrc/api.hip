@@ -41,7 +41,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
 struct Layout {
     size_t ent, roff, tiles, c0, c1, cs0, cs1, st, reset, nsub, ssub, beta, lgbeta, logpi, lt64, lc32, ls32, lhi, llo,
-        refine, perm, srow, grp_cnt, grp_off, grp_cur, nsub_prev, blk_ent, blk_off, ovf_off, ovf_ent, relab_c, relab_s, sm_logr, sm_acc, mkey, mlist, dm_k, eb_tmp, rd_part, total;
+        lpsub, qsub, refine, perm, srow, grp_cnt, grp_off, grp_cur, nsub_prev, blk_ent, blk_off, ovf_off, ovf_ent, relab_c, relab_s, sm_logr, sm_acc, mkey, mlist, dm_k, eb_tmp, rd_part, total;
 };
 
 int32_t num_blocks(int64_t N) { return (int32_t)((N + kBlkCells - 1) / kBlkCells); }
@@ -54,7 +54,7 @@ int32_t num_chunks(int32_t G)
     return (n + 1) / 2 * 2;
 }
 
-Layout plan(int64_t N, int32_t G, int64_t nnz, int32_t k_max, int32_t precision)
+Layout plan(int64_t N, int32_t G, int64_t nnz, int32_t k_max, int32_t precision, uint32_t flags)
 {
     Layout L{};
     const int64_t nnz_pad = nnz + 3 * N;
@@ -79,6 +79,8 @@ Layout plan(int64_t N, int32_t G, int64_t nnz, int32_t k_max, int32_t precision)
     L.ssub = take(16 * (size_t)k_max * (size_t)G);
     L.beta = take(8 * (size_t)G);
     L.lgbeta = take(8 * (size_t)G);
+    L.lpsub = take((flags & kFlagSplitQ) ? 8 * (size_t)N : 0);
+    L.qsub = take(8 * (size_t)k_max);
     L.logpi = take(8 * (size_t)k_max);
     L.lt64 = take(24 * (size_t)k_max * (size_t)G);
     L.lc32 = take(4 * ((size_t)G * (size_t)kpad + kTablePadRows));
@@ -121,7 +123,7 @@ dpmm_status check_args(const dpmm_csr* csr, const dpmm_params* p)
     if (p->k_max < 1 || p->k_max > 1024) return fail(DPMM_ERR_ARG, "k_max must be in [1, 1024]");
     if (p->k_init < 1 || p->k_init > p->k_max) return fail(DPMM_ERR_ARG, "k_init must be in [1, k_max]");
     if (p->precision < DPMM_FP64 || p->precision > DPMM_SPLIT_BF16) return fail(DPMM_ERR_ARG, "unknown precision");
-    if (p->flags != 0) return fail(DPMM_ERR_ARG, "flags must be 0");
+    if (p->flags & ~DPMM_FLAG_SPLIT_Q) return fail(DPMM_ERR_ARG, "unknown flags");
     return DPMM_OK;
 }
 
@@ -177,6 +179,8 @@ int32_t k_hint(const dpmm_ctx* ctx) { return *reinterpret_cast<volatile int32_t*
 // statistics from the current labels, then compaction without touching flags
 dpmm_status recompute_stats(dpmm_ctx* ctx)
 {
+    // no sweep has drawn these labels: no proposal term yet
+    if (ctx->ws.lpsub) HIP_TRY(hipMemsetAsync(ctx->ws.lpsub, 0, 8 * (size_t)ctx->N, ctx->stream));
     launch_stats(ctx->ws, ctx->c[ctx->cur], ctx->cs[ctx->cur], ctx->stream);
     launch_compact(ctx->ws, 0, ctx->stream);
     launch_relabel(ctx->ws, ctx->c[ctx->cur], ctx->cs[ctx->cur], ctx->stream);
@@ -195,7 +199,7 @@ dpmm_status dpmm_workspace_size(const dpmm_csr* csr, const dpmm_params* params, 
     dpmm_status s = check_args(csr, params);
     if (s != DPMM_OK) return s;
     if (!bytes) return fail(DPMM_ERR_ARG, "null bytes");
-    *bytes = plan(csr->n_cells, csr->n_genes, csr->nnz, params->k_max, params->precision).total;
+    *bytes = plan(csr->n_cells, csr->n_genes, csr->nnz, params->k_max, params->precision, params->flags).total;
     return DPMM_OK;
 }
 
@@ -209,7 +213,7 @@ dpmm_status dpmm_init(const dpmm_csr* csr, const dpmm_params* params, void* work
     *out = nullptr;
     if (!workspace || ((uintptr_t)workspace & (kAlign - 1))) return fail(DPMM_ERR_ARG, "workspace must be 256-byte aligned");
     if (!csr->row_ptr || (csr->nnz > 0 && (!csr->col || !csr->val))) return fail(DPMM_ERR_ARG, "null CSR array");
-    const Layout L = plan(csr->n_cells, csr->n_genes, csr->nnz, params->k_max, params->precision);
+    const Layout L = plan(csr->n_cells, csr->n_genes, csr->nnz, params->k_max, params->precision, params->flags);
     if (workspace_bytes < L.total)
         return fail(DPMM_ERR_NOMEM, "workspace of %zu bytes, %zu needed", workspace_bytes, L.total);
 
@@ -242,6 +246,9 @@ dpmm_status dpmm_init(const dpmm_csr* csr, const dpmm_params* params, void* work
     ws.ssub = (unsigned long long*)(base + L.ssub);
     ws.beta = (double*)(base + L.beta);
     ws.lgbeta = (double*)(base + L.lgbeta);
+    ws.flags = params->flags;
+    ws.lpsub = (params->flags & kFlagSplitQ) ? (double*)(base + L.lpsub) : nullptr;
+    ws.qsub = (double*)(base + L.qsub);
     ws.logpi = (double*)(base + L.logpi);
     ws.lt64 = (double*)(base + L.lt64);
     ws.lc32 = (float*)(base + L.lc32);
@@ -401,7 +408,7 @@ dpmm_status dpmm_split_merge(dpmm_ctx* ctx)
     const Words w = philox(ctx->ws.seed, 0u, 0u, step, kChain, 0u);
     const int merge_pass = unit52(w.w[0], w.w[1]) < 0.5 ? 0 : 1;
     if (merge_pass) launch_merge_ratios(ctx->ws, ctx->stream);
-    else launch_split_ratios(ctx->ws, ctx->stream);
+    else launch_split_ratios(ctx->ws, ctx->c[ctx->cur], ctx->stream);
     launch_sm_decide(ctx->ws, merge_pass, step, ctx->stream);
     launch_relabel(ctx->ws, ctx->c[ctx->cur], ctx->cs[ctx->cur], ctx->stream);
     HIP_TRY(hipGetLastError());     // (k_sm_decide has written the K hint)

@@ -93,6 +93,7 @@ struct DevState {
 constexpr uint32_t kPadEntry = 0x0000FFFFu;   // gene 0xFFFF, count 0
 
 constexpr int kBlkCells = 256;
+constexpr uint32_t kFlagSplitQ = 1u;          // dpmm_params.flags bit of the split proposal term
 constexpr int kBlkGenes = 64;
 constexpr int kBlkLead = 8;              // padding columns at the start of a dense tile row
 constexpr int kBlkRow = kBlkLead + kBlkGenes;   // BF16 elements per row of the dense LDS tile
@@ -190,6 +191,9 @@ struct Ws {
     int32_t nblk;
     int32_t nch;
     int32_t sub_cells;     // sorted cells per workgroup of the sub-cluster/statistics pass
+    uint32_t flags;        // kFlagSplitQ: the split ratio carries -sum log p(cbar_i)
+    double* lpsub;         // [N] log p(cbar_i) of eq. 8 in the last sweep (with kFlagSplitQ only)
+    double* qsub;          // [k_max] sum of lpsub over the cells of each cluster (split pass)
     int32_t* k_hint;       // mapped pinned host word: K after the last compaction or split/merge
                            // (a launch-size hint for the host; written by the kernels that set K)
     int32_t* relab_c;      // [2 k_max] new cluster of an old (k, r)

@@ -122,6 +122,7 @@ __global__ void __launch_bounds__(kSmThreads) k_split_ratios(Ws ws)
             tot.add(lB - lgamma(B + (double)r.b));
             tot.add(-(lB - lgamma(B + (double)(r.a + r.b))));
             tot.add(log(ws.alpha) + lgamma((double)n0) + lgamma((double)n1) - lgamma((double)(n0 + n1)));
+            if (ws.flags & kFlagSplitQ) tot.add(-ws.qsub[k]);     // proposal term, Section 2.3
             ws.sm_logr[k] = tot.value();
         }
     }
@@ -200,9 +201,32 @@ __global__ void __launch_bounds__(kMergeThreads) k_merge_ratios(Ws ws)
     }
 }
 
-void launch_split_ratios(const Ws& ws, hipStream_t s)
+// Q_k = sum over the cells now in cluster k of log p(cbar_i) from the last
+// sweep (the split proposal term of Section 2.3): per-workgroup LDS sums, then
+// one FP64 atomic per cluster.
+constexpr int kQThreads = 256;
+__global__ void __launch_bounds__(kQThreads) k_split_q(Ws ws, const int32_t* __restrict__ c)
+{
+    extern __shared__ double qacc[];     // [K]
+    const int K = ws.st->K;
+    for (int k = threadIdx.x; k < K; k += kQThreads) qacc[k] = 0.0;
+    __syncthreads();
+    for (int64_t i = (int64_t)blockIdx.x * kQThreads + threadIdx.x; i < ws.N; i += (int64_t)gridDim.x * kQThreads) {
+        const int k = c[i];
+        if (k >= 0 && k < K) atomicAdd(&qacc[k], ws.lpsub[i]);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < K; k += kQThreads)
+        if (qacc[k] != 0.0) atomicAdd(&ws.qsub[k], qacc[k]);
+}
+
+void launch_split_ratios(const Ws& ws, const int32_t* c, hipStream_t s)
 {
     const int blocks = ws.k_max < 1024 ? ws.k_max : 1024;
+    if (ws.flags & kFlagSplitQ) {
+        hipMemsetAsync(ws.qsub, 0, sizeof(double) * (size_t)ws.k_max, s);
+        hipLaunchKernelGGL(k_split_q, dim3(256), dim3(kQThreads), sizeof(double) * (size_t)ws.k_max, s, ws, c);
+    }
     launch_lgamma_beta(ws, s);
     hipLaunchKernelGGL(k_split_ratios, dim3(blocks), dim3(kSmThreads), 0, s, ws);
 }

@@ -34,9 +34,10 @@ __device__ inline double group_sum(double v)
 }
 
 // STAGE: delta in LDS; LHIST: histograms in LDS; DUMP: also form the two
-// scores for the debug dump.  The flags are template arguments so that the
-// loop over a row's entries is straight-line code.
-template <bool STAGE, bool LHIST, bool DUMP>
+// scores for the debug dump; SPLITQ: keep log p(cbar_i) for the split
+// proposal term.  The flags are template arguments so that the loop over a
+// row's entries is straight-line code.
+template <bool STAGE, bool LHIST, bool DUMP, bool SPLITQ>
 __global__ void __launch_bounds__(kSubThreads) __attribute__((amdgpu_waves_per_eu(4))) k_sub_stats(Ws ws, SubArgs a)
 {
     extern __shared__ __attribute__((aligned(16))) char lds[];
@@ -115,6 +116,7 @@ __global__ void __launch_bounds__(kSubThreads) __attribute__((amdgpu_waves_per_e
                 const int cc = __shfl(code, src);
                 int sub;
                 double df = 0.0, s0 = 0.0, s1 = 0.0;
+                double dd = 0.0;        // score of sub-cluster 1 less that of 0 (with the weights)
                 // the first 64 kSubLoads entries of the row (nearly every row),
                 // all loads in flight together
                 uint4 v[kSubLoads];
@@ -161,7 +163,7 @@ __global__ void __launch_bounds__(kSubThreads) __attribute__((amdgpu_waves_per_e
                     // 3e-6 of the FP64 noise, so when the FP32 difference clears
                     // tau its sign is the FP64 sign; otherwise (or with a zero
                     // weight) the FP64 comparison decides.
-                    const double dd = lw1 - lw0 + df;
+                    dd = lw1 - lw0 + df;
                     const float d32 = (float)dd + ndc;
                     const float tau = 1e-3f + 1e-5f * fabsf((float)dd);
                     if (isfinite(dd) && fabsf(d32) > tau) {
@@ -196,6 +198,16 @@ __global__ void __launch_bounds__(kSubThreads) __attribute__((amdgpu_waves_per_e
                 if (l16 == 0 && live) {
                     atomicAdd(&ncnt[sub], 1u);
                     a.cs_new[i] = (uint8_t)sub;
+                    if constexpr (SPLITQ) {
+                        // log p(cbar_i) of eq. 8 for the split proposal term: a
+                        // two-way softmax of the scores, whose difference is dd
+                        double lp = 0.0;
+                        if (!reset) {
+                            const double x = sub ? -dd : dd;
+                            lp = -(fmax(x, 0.0) + log1p(exp(-fabs(x))));
+                        }
+                        ws.lpsub[i] = lp;
+                    }
                     if (a.dbg && K + 2 <= a.dbg_stride) {
                         a.dbg[i * a.dbg_stride + K] = reset ? __builtin_nanf("") : (float)s0;
                         a.dbg[i * a.dbg_stride + K + 1] = reset ? __builtin_nanf("") : (float)s1;
@@ -226,11 +238,19 @@ static size_t sub_stats_lds(int G)
 
 using SubKernel = void (*)(Ws, SubArgs);
 
-static SubKernel sub_stats_kernel(int G, bool dump)
+template <bool SPLITQ>
+static SubKernel sub_stats_variant(int G, bool dump)
 {
-    if (G <= kSubStageGenes) return dump ? k_sub_stats<true, true, true> : k_sub_stats<true, true, false>;
-    if (G <= kSubHistGenes) return dump ? k_sub_stats<false, true, true> : k_sub_stats<false, true, false>;
-    return dump ? k_sub_stats<false, false, true> : k_sub_stats<false, false, false>;
+    if (G <= kSubStageGenes)
+        return dump ? k_sub_stats<true, true, true, SPLITQ> : k_sub_stats<true, true, false, SPLITQ>;
+    if (G <= kSubHistGenes)
+        return dump ? k_sub_stats<false, true, true, SPLITQ> : k_sub_stats<false, true, false, SPLITQ>;
+    return dump ? k_sub_stats<false, false, true, SPLITQ> : k_sub_stats<false, false, false, SPLITQ>;
+}
+
+static SubKernel sub_stats_kernel(int G, bool dump, bool split_q)
+{
+    return split_q ? sub_stats_variant<true>(G, dump) : sub_stats_variant<false>(G, dump);
 }
 
 // Sorted cells per workgroup: the grid fills the device's resident workgroup
@@ -241,7 +261,7 @@ hipError_t sub_stats_cells(int64_t N, int G, int32_t* cells)
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(sub_stats_kernel(G, false)),
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(sub_stats_kernel(G, false, false)),
                                                          kSubThreads, sub_stats_lds(G));
     if (e != hipSuccess) return e;
     const int64_t slots = (int64_t)(cus > 0 ? cus : 1) * (per_cu > 0 ? per_cu : 1);
@@ -271,7 +291,7 @@ void launch_sub_stats(const Ws& ws, const SubArgs& a, hipStream_t s)
 {
     hipLaunchKernelGGL(k_sub_prep, dim3(256), dim3(256), 0, s, ws);
     launch_sort(ws, a.c_new, a.cs_old, 1, s, true);
-    hipLaunchKernelGGL(sub_stats_kernel(ws.G, a.dbg != nullptr), dim3((unsigned)((ws.N + ws.sub_cells - 1) / ws.sub_cells)), dim3(kSubThreads),
+    hipLaunchKernelGGL(sub_stats_kernel(ws.G, a.dbg != nullptr, ws.lpsub != nullptr), dim3((unsigned)((ws.N + ws.sub_cells - 1) / ws.sub_cells)), dim3(kSubThreads),
                        sub_stats_lds(ws.G), s, ws, a);
 }
 

@@ -140,6 +140,36 @@ def test_chain_lockstep_small_recipe(precision):
     _say("K", st["K"], "refined", st["refined"], "splits", st["splits_accepted"], "merges", st["merges_accepted"])
 
 
+@pytest.mark.parametrize("precision", ["fp64", "split_bf16"])
+def test_split_q_chain_lockstep(precision):
+    """With the split proposal term (DPMM_FLAG_SPLIT_Q, Section 2.3) on both
+    sides: split ratios within the condition-aware tolerance of the oracle's,
+    the same accept decisions and labels, for several split passes."""
+    _say("split_q lockstep", precision)
+    d = synth.generate("c1", seed=4)
+    kw = dict(alpha=1.0, beta=1.0, seed=17, k_max=64, k_init=1)
+    o = _oracle(d, split_q=True, **kw)
+    s = _sampler(d, precision, split_q=True, **kw)
+    splits = 0
+    for it in range(25):
+        o.sweep()
+        s.sweep(1)
+        _compare_params(o, s)
+        if _compare_labels(o, s, f"sweep {it}"):
+            break
+        _compare_stats(o, s)
+        o.split_merge()
+        s.split_merge()
+        _compare_hastings(o, s)
+        if o.sm_pass == 0 and np.any(~np.isnan(o.sm_logr[: o.sm_n])):
+            splits += 1
+        if _compare_labels(o, s, f"split/merge {it}"):
+            break
+        _compare_stats(o, s)
+    assert splits >= 2
+    _say("K", s.stats()["K"], "split passes compared", splits)
+
+
 SCORE_TOL = {"fp32": 1e-4, "split_bf16": 3e-5}
 
 

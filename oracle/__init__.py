@@ -29,6 +29,8 @@ SUB_ROW_BASE = 0x10000
 # Flags of the chain (dpmm_oracle.c): the split ratio carries the proposal
 # term -Q_k = -sum_{i in k} log p(cbar_i) of Section 2.3.
 SPLIT_Q = 1
+# ... and the sweep's Gibbs step runs over K + 1 clusters, the last one new (eq. 4).
+NEW_CLUSTER = 2
 
 COUNTER_NAMES = [
     "gamma_caps", "gamma_near_ties", "splits_proposed", "splits_accepted",
@@ -77,7 +79,7 @@ class _State(ctypes.Structure):
         ("logpi", _P), ("logtheta", _P),
         ("margin_c", _P), ("margin_s", _P), ("lpsub", _P),
         ("sm_logr", _P), ("sm_scale", _P), ("sm_accept", _P),
-        ("sm_pass", _I32), ("sm_n", _I32),
+        ("sm_pass", _I32), ("sm_n", _I32), ("has_new", _I32), ("pad2_", _I32),
         ("counters", _I64 * 16),
     ]
 
@@ -108,7 +110,7 @@ def _declare(L: ctypes.CDLL) -> None:
     L.oracle_split_logr.restype = _D
     L.oracle_merge_logr.argtypes = [_P, _P, _I64, _I64, _P, _I32, _D, _P]
     L.oracle_merge_logr.restype = _D
-    for name in ("oracle_stats", "oracle_redraw", "oracle_assign", "oracle_assign_only",
+    for name in ("oracle_stats", "oracle_redraw", "oracle_assign", "oracle_assign_only", "oracle_extend",
                  "oracle_sweep", "oracle_split_merge", "oracle_eb_update"):
         getattr(L, name).argtypes = [S]
         getattr(L, name).restype = None
@@ -225,7 +227,7 @@ class Oracle:
 
     def __init__(self, row_ptr, col, val, n_genes: int, alpha: float = 1.0, beta=1.0,
                  seed: int = 0, k_max: int = 64, k_init: int = 1, init: bool = True,
-                 split_q: bool = False):
+                 split_q: bool = False, new_cluster: bool = False):
         self.row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
         self.col = np.ascontiguousarray(col, dtype=np.int32)
         self.val = np.ascontiguousarray(val, dtype=np.int32)
@@ -253,7 +255,7 @@ class Oracle:
         st.row_ptr, st.col, st.val = _ptr(self.row_ptr), _ptr(self.col), _ptr(self.val)
         st.alpha, st.beta, st.seed = float(alpha), _ptr(self.beta), int(seed) & 0xFFFFFFFFFFFFFFFF
         st.step, st.K = 0, 0
-        st.flags = SPLIT_Q if split_q else 0
+        st.flags = (SPLIT_Q if split_q else 0) | (NEW_CLUSTER if new_cluster else 0)
         for name in ("c", "cs", "reset", "nsub", "ssub", "logpi", "logtheta", "margin_c",
                      "margin_s", "lpsub", "sm_logr", "sm_scale", "sm_accept"):
             setattr(st, name, _ptr(getattr(self, name)))
@@ -309,6 +311,14 @@ class Oracle:
 
     def redraw(self) -> None:
         lib().oracle_redraw(ctypes.byref(self._st))
+
+    def extend(self) -> None:
+        """Append the empty new cluster of the Gibbs step over K + 1 (with NEW_CLUSTER)."""
+        lib().oracle_extend(ctypes.byref(self._st))
+
+    @property
+    def has_new(self) -> bool:
+        return bool(self._st.has_new)
 
     def assign(self) -> None:
         lib().oracle_assign_only(ctypes.byref(self._st))

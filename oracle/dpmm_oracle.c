@@ -273,7 +273,7 @@ void oracle_dm_logmarginal(const int64_t* s, int32_t J, int32_t G, const double*
 /* Sampler state.  All arrays are owned by the caller.                      */
 /* ------------------------------------------------------------------------ */
 
-enum { ORACLE_SPLIT_Q = 1u };
+enum { ORACLE_SPLIT_Q = 1u, ORACLE_NEW_CLUSTER = 2u };
 
 enum {
     CNT_GAMMA_CAPS = 0,
@@ -304,7 +304,9 @@ typedef struct {
     int64_t step;
     int32_t K;
     uint32_t flags;           /* ORACLE_SPLIT_Q: the split ratio carries the
-                                 proposal term of Section 2.3                  */
+                                 proposal term of Section 2.3;
+                                 ORACLE_NEW_CLUSTER: the sweep draws over K + 1
+                                 clusters (eq. 4), the last one new           */
     int32_t* c;               /* [N]                                          */
     uint8_t* cs;              /* [N] sub-cluster labels                       */
     uint8_t* reset;           /* [k_max] sub-labels to be re-drawn at random  */
@@ -323,6 +325,9 @@ typedef struct {
     uint8_t* sm_accept;       /* same size: 1 if accepted                     */
     int32_t sm_pass;          /* 0 split pass, 1 merge pass                   */
     int32_t sm_n;             /* number of candidates of the last call        */
+    int32_t has_new;          /* 1 while cluster K - 1 is the new cluster of
+                                 the current sweep (ORACLE_NEW_CLUSTER)       */
+    int32_t pad2_;
     int64_t counters[N_COUNTERS];
 } oracle_state;
 
@@ -394,6 +399,7 @@ void oracle_init(oracle_state* st, int32_t k_init)
     memset(st->reset, 0, (size_t)st->k_max);
     for (int32_t k = 0; k < st->K; ++k) st->reset[k] = 1;
     st->step = 0;
+    st->has_new = 0;
     memset(st->counters, 0, sizeof(st->counters));
     oracle_stats(st);
     compact(st);
@@ -405,6 +411,7 @@ void oracle_set_state(oracle_state* st, int64_t step, int32_t K)
 {
     st->step = step;
     st->K = K;
+    st->has_new = 0;
     memset(st->lpsub, 0, sizeof(double) * (size_t)st->n_cells);
     oracle_stats(st);
 }
@@ -438,21 +445,25 @@ void oracle_redraw(oracle_state* st)
     const int32_t K = st->K;
     gamma_diag diag = {0, 0};
 
-    /* mixing proportions: K cluster weights plus the alpha component */
+    /* mixing proportions: K cluster weights plus the alpha component; with a
+     * new cluster in the sweep (eq. 4 over K + 1), the alpha component is its
+     * weight pi_{K+1} */
     {
+        const int32_t Kc = st->has_new ? K - 1 : K;     /* clusters with cells */
         double lg_alpha;
         double m = -INFINITY, tot = 0.0;
-        for (int32_t k = 0; k < K; ++k) {
+        for (int32_t k = 0; k < Kc; ++k) {
             const double n = (double)(st->nsub[2 * k] + st->nsub[2 * k + 1]);
             st->logpi[k] = log_gamma_variate(n, st->seed, (uint32_t)k, 0u, st->step, ST_PI, &diag);
             if (st->logpi[k] > m) m = st->logpi[k];
         }
         lg_alpha = log_gamma_variate(st->alpha, st->seed, 0xFFFFFFFFu, 0u, st->step, ST_PI, &diag);
         if (lg_alpha > m) m = lg_alpha;
-        for (int32_t k = 0; k < K; ++k) tot += exp(st->logpi[k] - m);
+        for (int32_t k = 0; k < Kc; ++k) tot += exp(st->logpi[k] - m);
         tot += exp(lg_alpha - m);
         const double lse = m + log(tot);
-        for (int32_t k = 0; k < K; ++k) st->logpi[k] -= lse;
+        for (int32_t k = 0; k < Kc; ++k) st->logpi[k] -= lse;
+        if (st->has_new) st->logpi[Kc] = lg_alpha - lse;
     }
 
     const int32_t nrows = 3 * K;
@@ -575,6 +586,7 @@ void oracle_assign(oracle_state* st)
  * clusters of at least two cells with an empty sub-cluster for reset. */
 static void finish_sweep(oracle_state* st)
 {
+    st->has_new = 0;
     memset(st->reset, 0, (size_t)st->k_max);
     compact(st);
     for (int32_t k = 0; k < st->K; ++k) {
@@ -583,9 +595,27 @@ static void finish_sweep(oracle_state* st)
     }
 }
 
+/* With ORACLE_NEW_CLUSTER the sweep's Gibbs step runs over K + 1 clusters
+ * (eq. 4): cluster K is appended empty, so its theta is a draw from the prior
+ * Dir(beta) and its weight is the alpha component of pi; it re-draws its
+ * sub-labels at random like any new cluster, and compaction drops it again
+ * if no cell chose it.  Nothing is appended at k_max. */
+void oracle_extend(oracle_state* st)
+{
+    st->has_new = 0;
+    if (!(st->flags & ORACLE_NEW_CLUSTER) || st->K >= st->k_max) return;
+    const int32_t k = st->K;
+    st->nsub[2 * k] = st->nsub[2 * k + 1] = 0;
+    memset(st->ssub + (int64_t)(2 * k) * st->n_genes, 0, sizeof(int64_t) * 2 * (size_t)st->n_genes);
+    st->reset[k] = 1;
+    st->K = k + 1;
+    st->has_new = 1;
+}
+
 /* One sweep: redraw (a1), assign (a2-a3), statistics (a4), compaction. */
 void oracle_sweep(oracle_state* st)
 {
+    oracle_extend(st);
     oracle_redraw(st);
     oracle_assign(st);
     oracle_stats(st);

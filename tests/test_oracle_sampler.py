@@ -9,6 +9,8 @@
   the equal-weight case and the reset coin.
 * The split proposal term (SPLIT_Q): the per-cell log p(cbar_i) matches the
   frequency of the draws, and enters the split ratio as -sum over the cluster.
+* The Gibbs step over K + 1 clusters (NEW_CLUSTER): the new cluster's weight
+  and theta have the Dirichlet means of the alpha component and the prior.
 * Statistics and compaction: conservation and consistency invariants.
 * Split and merge application: acceptance frequency equals min(1, R); moved
   statistics equal statistics recomputed from the moved labels.
@@ -271,6 +273,64 @@ def test_split_q_adds_minus_the_summed_logp_to_the_split_ratio():
         assert np.all(-Q[live] >= 0)
         return
     pytest.fail("no split pass in 12 iterations")
+
+
+def test_new_cluster_takes_the_alpha_weight_and_a_prior_theta():
+    """NEW_CLUSTER (eq. 4 over K + 1): the appended cluster's weight is the
+    alpha component of pi ~ Dir(n_1..n_K, alpha), so its mean is
+    alpha / (N + alpha), and its theta is a draw from the prior Dir(beta),
+    whose mean is beta_u / sum(beta).  Nothing is appended at k_max."""
+    rng = np.random.default_rng(8)
+    N, G, alpha = 20, 5, 1.5
+    X = rng.integers(0, 4, size=(N, G))
+    X[:, 0] += 1
+    d = synth.from_dense(X)
+    rp, col, val = d.host_arrays()
+    beta = np.array([0.5, 1.0, 1.5, 2.0, 3.0])
+    o = oracle.Oracle(rp, col, val, G, alpha=alpha, beta=beta, seed=4, k_max=4, init=False, new_cluster=True)
+    c = np.zeros(N, dtype=np.int32)
+    cs = (np.arange(N) % 2).astype(np.uint8)
+    T = 4000
+    pin, th = np.zeros(T), np.zeros((T, G))
+    for t in range(T):
+        o.set_state(t, 1, c, cs, np.zeros(1))
+        o.extend()
+        assert o.K == 2 and o.has_new and o.reset[1] == 1
+        o.redraw()
+        pin[t] = np.exp(o.logpi[1])
+        th[t] = np.exp(o.logtheta[1])
+        assert abs(np.exp(o.logpi[:2]).sum() - 1.0) < 1e-12        # pi_{K+1} is the alpha component itself
+    m, v = alpha / (N + alpha), alpha * N / ((N + alpha) ** 2 * (N + alpha + 1))
+    assert abs(pin.mean() - m) < 5 * np.sqrt(v / T), (pin.mean(), m)
+    pm = beta / beta.sum()
+    pv = pm * (1 - pm) / (beta.sum() + 1)
+    assert np.all(np.abs(th.mean(axis=0) - pm) < 5 * np.sqrt(pv / T)), (th.mean(axis=0), pm)
+    # at capacity nothing is appended
+    o.set_state(0, 4, np.arange(N, dtype=np.int32) % 4, cs, np.zeros(4))
+    o.extend()
+    assert o.K == 4 and not o.has_new
+
+
+def test_gibbs_over_k_plus_one_opens_clusters_and_keeps_statistics():
+    """With NEW_CLUSTER and no split/merge at all, sweeps from one cluster
+    open new clusters by the Gibbs step alone (three groups of cells on three
+    genes, a sparse prior), and the statistics stay those of the labels."""
+    rng = np.random.default_rng(13)
+    grp = np.repeat(np.arange(3), 20)
+    X = rng.poisson(0.3, size=(60, 3))
+    X[np.arange(60), grp] += 8
+    d = synth.from_dense(X)
+    rp, col, val = d.host_arrays()
+    o = oracle.Oracle(rp, col, val, 3, alpha=2.0, beta=0.2, seed=9, k_max=16, k_init=1, new_cluster=True)
+    assert o.K == 1
+    for _ in range(30):
+        o.sweep()
+        n, s_ = _recomputed_stats(o)
+        assert np.array_equal(n, o.nsub[: 2 * o.K]) and np.array_equal(s_, o.ssub[: 2 * o.K])
+        assert not o.has_new and n.sum() == 60
+        if o.K > 1:
+            return
+    pytest.fail("no cluster opened in 30 sweeps")
 
 
 # --------------------------------------------------------------------------

@@ -77,6 +77,13 @@ typedef struct dpmm_csr {
  * are 0 for a cluster that re-drew its sub-labels at random, and are 0 after
  * dpmm_init and dpmm_set_state. */
 #define DPMM_FLAG_SPLIT_Q 1u
+/* DPMM_FLAG_NEW_CLUSTER: every sweep's Gibbs step runs over K + 1 clusters
+ * (eq. 4).  Cluster K is appended empty, so its theta is drawn from the prior
+ * Dir(beta) and its weight is the alpha component of pi ~ Dir(n_1..n_K,
+ * alpha); it re-draws its sub-labels at random, and compaction drops it again
+ * if no cell chose it.  Nothing is appended when K = k_max.  Without the flag
+ * new clusters arise from splits only. */
+#define DPMM_FLAG_NEW_CLUSTER 2u
 
 /* Hyper-parameters and sampler settings, copied at dpmm_init. */
 typedef struct dpmm_params {
@@ -89,7 +96,7 @@ typedef struct dpmm_params {
                                       uniformly when > 1)                         */
     int32_t k_max;                 /* cluster capacity, 1..1024                   */
     int32_t precision;             /* dpmm_precision                               */
-    uint32_t flags;                /* 0 or DPMM_FLAG_SPLIT_Q                       */
+    uint32_t flags;                /* DPMM_FLAG_SPLIT_Q | DPMM_FLAG_NEW_CLUSTER    */
     double refine_tol;             /* FP32 and split-BF16 only.  A cluster
                                       decision whose Gumbel gap is within the
                                       certified rounding bound of its two best

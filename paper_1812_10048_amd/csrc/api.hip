@@ -123,7 +123,7 @@ dpmm_status check_args(const dpmm_csr* csr, const dpmm_params* p)
     if (p->k_max < 1 || p->k_max > 1024) return fail(DPMM_ERR_ARG, "k_max must be in [1, 1024]");
     if (p->k_init < 1 || p->k_init > p->k_max) return fail(DPMM_ERR_ARG, "k_init must be in [1, k_max]");
     if (p->precision < DPMM_FP64 || p->precision > DPMM_SPLIT_BF16) return fail(DPMM_ERR_ARG, "unknown precision");
-    if (p->flags & ~DPMM_FLAG_SPLIT_Q) return fail(DPMM_ERR_ARG, "unknown flags");
+    if (p->flags & ~(DPMM_FLAG_SPLIT_Q | DPMM_FLAG_NEW_CLUSTER)) return fail(DPMM_ERR_ARG, "unknown flags");
     return DPMM_OK;
 }
 
@@ -356,6 +356,7 @@ dpmm_status dpmm_sweep(dpmm_ctx* ctx, int32_t n_sweeps)
     for (int32_t n = 0; n < n_sweeps; ++n) {
         const int nxt = 1 - ctx->cur;
         const uint32_t step = (uint32_t)ctx->step;
+        if (ws.flags & kFlagNewCluster) launch_extend(ws, ctx->stream);
         launch_redraw(ws, step, ctx->precision == DPMM_SPLIT_BF16, ctx->stream);   // also empties the re-score queue
         AssignArgs a{};
         a.c_old = ctx->c[ctx->cur];

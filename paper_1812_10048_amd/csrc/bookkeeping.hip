@@ -421,9 +421,34 @@ __global__ void __launch_bounds__(1024) k_compact(Ws ws, int after_sweep)
     }
     if (t == 0) {
         ws.st->K = nk;
+        ws.st->has_new = 0;
         ws.st->relabel = s_changed;
         if (ws.k_hint) __hip_atomic_store(ws.k_hint, nk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
+}
+
+// The Gibbs step over K + 1 clusters (eq. 4): append cluster K empty, with
+// its sub-labels to be drawn at random; the redraw then gives it a prior theta
+// and the alpha component of pi.  Nothing is appended at k_max.
+__global__ void k_extend(Ws ws)
+{
+    const int K = ws.st->K;
+    if (K >= ws.k_max) {
+        if (threadIdx.x == 0) ws.st->has_new = 0;
+        return;
+    }
+    for (int u = threadIdx.x; u < 2 * ws.G; u += blockDim.x) ws.ssub[(int64_t)2 * K * ws.G + u] = 0;
+    if (threadIdx.x == 0) {
+        ws.nsub[2 * K] = ws.nsub[2 * K + 1] = 0;
+        ws.reset[K] = 1;
+        ws.st->K = K + 1;
+        ws.st->has_new = 1;
+    }
+}
+
+void launch_extend(const Ws& ws, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_extend, dim3(1), dim3(256), 0, s, ws);
 }
 
 void launch_compact(const Ws& ws, int after_sweep, hipStream_t s)

@@ -84,7 +84,8 @@ struct DevState {
     int32_t sm_n;         // candidates of the last split/merge call
     int32_t n_refine;     // cells queued for FP64 re-scoring in the current sweep
     int32_t data_error;   // CSR validation failures
-    int32_t pad[2];
+    int32_t has_new;      // 1 while cluster K - 1 is the new cluster of the current sweep
+    int32_t pad;
     unsigned long long counters[kNumCounters];
 };
 
@@ -94,6 +95,7 @@ constexpr uint32_t kPadEntry = 0x0000FFFFu;   // gene 0xFFFF, count 0
 
 constexpr int kBlkCells = 256;
 constexpr uint32_t kFlagSplitQ = 1u;          // dpmm_params.flags bit of the split proposal term
+constexpr uint32_t kFlagNewCluster = 2u;      // ... and of the Gibbs step over K + 1 clusters
 constexpr int kBlkGenes = 64;
 constexpr int kBlkLead = 8;              // padding columns at the start of a dense tile row
 constexpr int kBlkRow = kBlkLead + kBlkGenes;   // BF16 elements per row of the dense LDS tile

@@ -18,6 +18,7 @@ void launch_sort(const Ws& ws, const int32_t* c, const uint8_t* cs, int by_clust
 // layout.hip
 void launch_build_blocked(const Ws& ws, int64_t* tile_sums, hipStream_t s);
 hipError_t configure_layout();
+void launch_extend(const Ws& ws, hipStream_t s);
 
 // substats.hip
 struct SubArgs {

@@ -121,25 +121,30 @@ __global__ void __launch_bounds__(kRedrawThreads) k_redraw_draw(Ws ws, uint32_t 
         if (tile != 0) return;
         if (t == 0) ws.st->counters[kCntEvals] += (unsigned long long)ws.N * (unsigned long long)(K + 2);
         double* lp = ws.logpi;
+        // with a new cluster in the sweep (eq. 4 over K + 1) the alpha
+        // component is its weight
+        const int Kc = ws.st->has_new ? K - 1 : K;     // clusters with cells
         double m = -INFINITY;
         double lga = -INFINITY;
-        for (int k = t; k <= K; k += kRedrawThreads) {
+        for (int k = t; k <= Kc; k += kRedrawThreads) {
             double v;
-            if (k < K) {
+            if (k < Kc) {
                 const double n = (double)(ws.nsub[2 * k] + ws.nsub[2 * k + 1]);
                 v = log_gamma_draw(n, ws.seed, (uint32_t)k, 0u, step, kPi, &capped);
                 lp[k] = v;
             } else {
                 v = log_gamma_draw(ws.alpha, ws.seed, kAlphaElement, 0u, step, kPi, &capped);
                 lga = v;
+                if (Kc < K) lp[Kc] = v;
             }
             m = fmax(m, v);
         }
         m = block_max(m, red);
         double s = 0.0;
-        for (int k = t; k < K; k += kRedrawThreads) s += exp(lp[k] - m);
-        if (K % kRedrawThreads == t) s += exp(lga - m);
+        for (int k = t; k < Kc; k += kRedrawThreads) s += exp(lp[k] - m);
+        if (Kc % kRedrawThreads == t) s += exp(lga - m);
         const double lse = m + log(block_sum(s, red));
+        __syncthreads();
         for (int k = t; k < K; k += kRedrawThreads) lp[k] -= lse;
         if (capped) atomicAdd(&ws.st->counters[kCntGammaCaps], 1ull);
         return;

@@ -25,6 +25,7 @@ STATUS_NAMES = {0: "DPMM_OK", -1: "DPMM_ERR_ARG", -2: "DPMM_ERR_HIP", -3: "DPMM_
 DPMM_FP64, DPMM_FP32, DPMM_SPLIT_BF16 = 0, 1, 2
 PRECISIONS = {"fp64": DPMM_FP64, "fp32": DPMM_FP32, "split_bf16": DPMM_SPLIT_BF16}
 FLAG_SPLIT_Q = 1     # DPMM_FLAG_SPLIT_Q
+FLAG_NEW_CLUSTER = 2     # DPMM_FLAG_NEW_CLUSTER
 
 
 class DpmmError(RuntimeError):

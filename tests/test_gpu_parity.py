@@ -170,6 +170,54 @@ def test_split_q_chain_lockstep(precision):
     _say("K", s.stats()["K"], "split passes compared", splits)
 
 
+def _three_groups():
+    rng = np.random.default_rng(13)
+    grp = np.repeat(np.arange(3), 40)
+    X = rng.poisson(0.3, size=(120, 3))
+    X[np.arange(120), grp] += 8
+    return synth.from_dense(X)
+
+
+@pytest.mark.parametrize("case", ["three_groups-fp64", "three_groups-split_bf16", "c1-fp32"])
+def test_new_cluster_chain_lockstep(case):
+    """With the Gibbs step over K + 1 clusters (DPMM_FLAG_NEW_CLUSTER, eq. 4) on
+    both sides (and the split proposal term on c1): parameters, labels,
+    statistics and Hastings ratios in lockstep with the oracle; on the
+    three-group data the Gibbs step itself opens clusters."""
+    data, precision = case.split("-")
+    _say("new_cluster lockstep", case)
+    if data == "c1":
+        d = synth.generate("c1", seed=7)
+        kw = dict(alpha=1.0, beta=1.0, seed=23, k_max=64, k_init=1, new_cluster=True, split_q=True)
+    else:
+        d = _three_groups()
+        kw = dict(alpha=2.0, beta=0.2, seed=9, k_max=16, k_init=1, new_cluster=True)
+    o = _oracle(d, **kw)
+    s = _sampler(d, precision, **kw)
+    opened = 0
+    compared = 0
+    for it in range(30):
+        k0 = o.K
+        o.sweep()
+        s.sweep(1)
+        _compare_params(o, s)
+        if _compare_labels(o, s, f"sweep {it}"):
+            break
+        _compare_stats(o, s)
+        opened += o.K > k0
+        o.split_merge()
+        s.split_merge()
+        _compare_hastings(o, s)
+        if _compare_labels(o, s, f"split/merge {it}"):
+            break
+        _compare_stats(o, s)
+        compared += 1
+    assert compared >= 10
+    if data == "three_groups":
+        assert opened >= 1
+    _say("K", s.stats()["K"], "sweeps that opened a cluster", opened)
+
+
 SCORE_TOL = {"fp32": 1e-4, "split_bf16": 3e-5}
 
 

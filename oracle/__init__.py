@@ -23,7 +23,7 @@ _SRC = os.path.join(_HERE, "dpmm_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle_dpmm.so")
 
 # Philox stream identifiers (the counter's top byte); see dpmm_oracle.c.
-ST_INIT, ST_GAMMA, ST_PI, ST_GUMBEL_C, ST_GUMBEL_S, ST_RESUB, ST_CHAIN, ST_SPLIT, ST_MERGE = range(1, 10)
+ST_INIT, ST_GAMMA, ST_PI, ST_GUMBEL_C, ST_GUMBEL_S, ST_RESUB, ST_CHAIN, ST_SPLIT, ST_MERGE, ST_RSPLIT = range(1, 11)
 SUB_ROW_BASE = 0x10000
 
 # Flags of the chain (dpmm_oracle.c): the split ratio carries the proposal
@@ -31,6 +31,8 @@ SUB_ROW_BASE = 0x10000
 SPLIT_Q = 1
 # ... and the sweep's Gibbs step runs over K + 1 clusters, the last one new (eq. 4).
 NEW_CLUSTER = 2
+# ... and split/merge calls may run a pass of random splits (chain B, Section 2.4).
+RANDOM_SPLIT = 4
 
 COUNTER_NAMES = [
     "gamma_caps", "gamma_near_ties", "splits_proposed", "splits_accepted",
@@ -227,7 +229,7 @@ class Oracle:
 
     def __init__(self, row_ptr, col, val, n_genes: int, alpha: float = 1.0, beta=1.0,
                  seed: int = 0, k_max: int = 64, k_init: int = 1, init: bool = True,
-                 split_q: bool = False, new_cluster: bool = False):
+                 split_q: bool = False, new_cluster: bool = False, random_split: bool = False):
         self.row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
         self.col = np.ascontiguousarray(col, dtype=np.int32)
         self.val = np.ascontiguousarray(val, dtype=np.int32)
@@ -255,7 +257,8 @@ class Oracle:
         st.row_ptr, st.col, st.val = _ptr(self.row_ptr), _ptr(self.col), _ptr(self.val)
         st.alpha, st.beta, st.seed = float(alpha), _ptr(self.beta), int(seed) & 0xFFFFFFFFFFFFFFFF
         st.step, st.K = 0, 0
-        st.flags = (SPLIT_Q if split_q else 0) | (NEW_CLUSTER if new_cluster else 0)
+        st.flags = ((SPLIT_Q if split_q else 0) | (NEW_CLUSTER if new_cluster else 0) |
+                    (RANDOM_SPLIT if random_split else 0))
         for name in ("c", "cs", "reset", "nsub", "ssub", "logpi", "logtheta", "margin_c",
                      "margin_s", "lpsub", "sm_logr", "sm_scale", "sm_accept"):
             setattr(st, name, _ptr(getattr(self, name)))

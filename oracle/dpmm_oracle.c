@@ -54,7 +54,8 @@ enum {
     ST_RESUB = 6,     /* random sub-cluster labels of a reset cluster     */
     ST_CHAIN = 7,     /* which move chain a split/merge call runs         */
     ST_SPLIT = 8,     /* split acceptance uniforms                        */
-    ST_MERGE = 9      /* merge acceptance uniforms and visiting order     */
+    ST_MERGE = 9,     /* merge acceptance uniforms and visiting order     */
+    ST_RSPLIT = 10    /* the per-cell coins of a random split             */
 };
 
 #define GAMMA_MAX_TRIES 64u
@@ -273,7 +274,7 @@ void oracle_dm_logmarginal(const int64_t* s, int32_t J, int32_t G, const double*
 /* Sampler state.  All arrays are owned by the caller.                      */
 /* ------------------------------------------------------------------------ */
 
-enum { ORACLE_SPLIT_Q = 1u, ORACLE_NEW_CLUSTER = 2u };
+enum { ORACLE_SPLIT_Q = 1u, ORACLE_NEW_CLUSTER = 2u, ORACLE_RANDOM_SPLIT = 4u };
 
 enum {
     CNT_GAMMA_CAPS = 0,
@@ -306,7 +307,9 @@ typedef struct {
     uint32_t flags;           /* ORACLE_SPLIT_Q: the split ratio carries the
                                  proposal term of Section 2.3;
                                  ORACLE_NEW_CLUSTER: the sweep draws over K + 1
-                                 clusters (eq. 4), the last one new           */
+                                 clusters (eq. 4), the last one new;
+                                 ORACLE_RANDOM_SPLIT: a third pass of random
+                                 splits (Section 2.4, chain B)                */
     int32_t* c;               /* [N]                                          */
     uint8_t* cs;              /* [N] sub-cluster labels                       */
     uint8_t* reset;           /* [k_max] sub-labels to be re-drawn at random  */
@@ -323,7 +326,7 @@ typedef struct {
     double* sm_logr;          /* [k_max + k_max (k_max - 1) / 2] log ratios   */
     double* sm_scale;         /* same size: sum of |terms| of each ratio      */
     uint8_t* sm_accept;       /* same size: 1 if accepted                     */
-    int32_t sm_pass;          /* 0 split pass, 1 merge pass                   */
+    int32_t sm_pass;          /* 0 split pass, 1 merge pass, 2 random splits  */
     int32_t sm_n;             /* number of candidates of the last call        */
     int32_t has_new;          /* 1 while cluster K - 1 is the new cluster of
                                  the current sweep (ORACLE_NEW_CLUSTER)       */
@@ -712,8 +715,14 @@ void oracle_split_merge(oracle_state* st)
     const int32_t K = st->K;
     uint32_t w[4];
     draw_words(st->seed, 0u, 0u, st->step, ST_CHAIN, 0u, w);
-    const int split_pass = oracle_u52(w[0], w[1]) < 0.5;
-    st->sm_pass = split_pass ? 0 : 1;
+    /* pass 0: split into the sub-clusters; 1: merges; 2: random splits (only
+     * with ORACLE_RANDOM_SPLIT, the three then equally likely) */
+    const double coin = oracle_u52(w[0], w[1]);
+    int pass;
+    if (st->flags & ORACLE_RANDOM_SPLIT) pass = coin < 1.0 / 3.0 ? 0 : (coin < 2.0 / 3.0 ? 2 : 1);
+    else pass = coin < 0.5 ? 0 : 1;
+    const int split_pass = pass != 1;
+    st->sm_pass = pass;
 
     int64_t* s_k = (int64_t*)malloc(sizeof(int64_t) * (size_t)(K > 0 ? K : 1) * (size_t)G);
     for (int32_t k = 0; k < K; ++k)
@@ -724,6 +733,26 @@ void oracle_split_merge(oracle_state* st)
         st->sm_n = K;
         int32_t K_new = K;
         int32_t* newlab = (int32_t*)malloc(sizeof(int32_t) * (size_t)(K > 0 ? K : 1));
+        /* The two halves of each cluster: its sub-clusters (pass 0), or
+         * (pass 2, chain B of Section 2.4) a fair coin per cell, whose split is
+         * the reverse of the eq. 23 merge: log R gains (n - 2) log 2. */
+        const int64_t N = st->n_cells;
+        int64_t* hn = st->nsub;
+        int64_t* hs = st->ssub;
+        uint8_t* side = NULL;
+        if (pass == 2) {
+            side = (uint8_t*)malloc((size_t)(N > 0 ? N : 1));
+            hn = (int64_t*)calloc(2 * (size_t)(K > 0 ? K : 1), sizeof(int64_t));
+            hs = (int64_t*)calloc(2 * (size_t)(K > 0 ? K : 1) * (size_t)G, sizeof(int64_t));
+            for (int64_t i = 0; i < N; ++i) {
+                uint32_t cw[4];
+                draw_words(st->seed, (uint32_t)i, 0u, st->step, ST_RSPLIT, 0u, cw);
+                side[i] = (uint8_t)(cw[0] >> 31);
+                const int64_t h = 2 * (int64_t)st->c[i] + side[i];
+                hn[h] += 1;
+                for (int64_t e = row_begin(st, i); e < row_end(st, i); ++e) hs[h * G + st->col[e]] += st->val[e];
+            }
+        }
         /* Section 2.3: the split proposes the current sub-clusters, with
          * probability q = prod_{i in k} p(cbar_i) (eq. 8), and the reverse merge
          * is certain; with ORACLE_SPLIT_Q the ratio carries -Q_k = -log q. */
@@ -732,16 +761,17 @@ void oracle_split_merge(oracle_state* st)
             for (int64_t i = 0; i < st->n_cells; ++i) Q[st->c[i]] += st->lpsub[i];
 #pragma omp parallel for schedule(dynamic, 1)
         for (int32_t k = 0; k < K; ++k) {
-            const int64_t n0 = st->nsub[2 * k], n1 = st->nsub[2 * k + 1];
-            if (st->reset[k] || n0 < 1 || n1 < 1) {
+            const int64_t n0 = hn[2 * k], n1 = hn[2 * k + 1];
+            if ((pass == 0 && st->reset[k]) || n0 < 1 || n1 < 1) {
                 st->sm_logr[k] = NAN;
                 st->sm_scale[k] = 0.0;
                 continue;
             }
-            st->sm_logr[k] = oracle_split_logr(st->ssub + (int64_t)(2 * k) * G, st->ssub + (int64_t)(2 * k + 1) * G,
-                                               n0, n1, st->beta, G, st->alpha, &st->sm_scale[k]) -
-                             Q[k];
-            st->sm_scale[k] += fabs(Q[k]);
+            const double extra = pass == 2 ? (double)(n0 + n1 - 2) * log(2.0) : -Q[k];
+            st->sm_logr[k] = oracle_split_logr(hs + (int64_t)(2 * k) * G, hs + (int64_t)(2 * k + 1) * G,
+                                               n0, n1, st->beta, G, st->alpha, &st->sm_scale[k]) +
+                             extra;
+            st->sm_scale[k] += fabs(extra);
         }
         free(Q);
         for (int32_t k = 0; k < K; ++k) {
@@ -761,20 +791,23 @@ void oracle_split_merge(oracle_state* st)
                 }
             }
         }
-        /* sub-cluster 1 of each accepted cluster becomes the new cluster */
-        for (int64_t i = 0; i < st->n_cells; ++i) {
+        /* half 1 of each accepted cluster becomes the new cluster */
+        for (int64_t i = 0; i < N; ++i) {
             const int32_t j = newlab[st->c[i]];
             if (j < 0) continue;
-            if (st->cs[i] == 1) st->c[i] = j;
+            if ((side ? side[i] : st->cs[i]) == 1) st->c[i] = j;
             st->cs[i] = 0;
         }
         for (int32_t k = 0; k < K; ++k) {
             const int32_t j = newlab[k];
             if (j < 0) continue;
-            st->nsub[2 * j] = st->nsub[2 * k + 1];
+            st->nsub[2 * j] = hn[2 * k + 1];
             st->nsub[2 * j + 1] = 0;
+            st->nsub[2 * k] = hn[2 * k];
             st->nsub[2 * k + 1] = 0;
-            memcpy(st->ssub + (int64_t)(2 * j) * G, st->ssub + (int64_t)(2 * k + 1) * G, sizeof(int64_t) * (size_t)G);
+            memcpy(st->ssub + (int64_t)(2 * j) * G, hs + (int64_t)(2 * k + 1) * G, sizeof(int64_t) * (size_t)G);
+            if (hs != st->ssub)
+                memcpy(st->ssub + (int64_t)(2 * k) * G, hs + (int64_t)(2 * k) * G, sizeof(int64_t) * (size_t)G);
             memset(st->ssub + (int64_t)(2 * j + 1) * G, 0, sizeof(int64_t) * (size_t)G);
             memset(st->ssub + (int64_t)(2 * k + 1) * G, 0, sizeof(int64_t) * (size_t)G);
             st->reset[k] = 1;
@@ -782,6 +815,11 @@ void oracle_split_merge(oracle_state* st)
         }
         st->K = K_new;
         free(newlab);
+        if (side) {
+            free(side);
+            free(hn);
+            free(hs);
+        }
     } else {
         const int64_t npairs = (int64_t)K * (K - 1) / 2;
         st->sm_n = (int32_t)npairs;

@@ -11,6 +11,8 @@
   frequency of the draws, and enters the split ratio as -sum over the cluster.
 * The Gibbs step over K + 1 clusters (NEW_CLUSTER): the new cluster's weight
   and theta have the Dirichlet means of the alpha component and the prior.
+* Random splits (RANDOM_SPLIT): coin halves, ratio = collapsed + (n - 2) log 2 =
+  minus the eq. 23 merge ratio of the halves, application along the coins.
 * Statistics and compaction: conservation and consistency invariants.
 * Split and merge application: acceptance frequency equals min(1, R); moved
   statistics equal statistics recomputed from the moved labels.
@@ -331,6 +333,86 @@ def test_gibbs_over_k_plus_one_opens_clusters_and_keeps_statistics():
         if o.K > 1:
             return
     pytest.fail("no cluster opened in 30 sweeps")
+
+
+def test_random_split_pass_halves_by_coins_and_reverses_the_merge():
+    """RANDOM_SPLIT (chain B of Section 2.4): in a random-split pass each cell's
+    half is its Philox coin (stream RSPLIT); each ratio is the collapsed split
+    ratio of the coin halves plus (n - 2) log 2, which is exactly minus the
+    eq. 23 merge ratio of the two halves; an accepted cluster splits along the
+    coins, and the statistics are those of the new labels."""
+    d = synth.generate("c1", seed=12)
+    rp, col, val = d.host_arrays()
+    seed = 31
+    o = oracle.Oracle(rp, col, val, d.n_genes, seed=seed, k_max=32, init=False, random_split=True)
+    rng = np.random.default_rng(4)
+    # the truth with two clusters merged, so that splitting them is attractive
+    z = np.where(d.z == 3, 2, d.z).astype(np.int32)
+    o.set_state(0, 3, z, rng.integers(0, 2, size=d.n_cells), np.zeros(3, dtype=np.uint8))
+    X = np.zeros((d.n_cells, d.n_genes), dtype=np.int64)
+    for i in range(d.n_cells):
+        X[i, col[rp[i]:rp[i + 1]]] = val[rp[i]:rp[i + 1]]
+    seen = 0
+    for it in range(40):
+        step, c_before, K = o.step, o.c.copy(), o.K
+        o.split_merge()
+        if o.sm_pass != 2:
+            o.sweep()
+            continue
+        seen += 1
+        bits = np.array([oracle.philox4x32_10(seed, [i, 0, step, (oracle.ST_RSPLIT << 24)])[0] >> 31
+                         for i in range(d.n_cells)], dtype=np.int64)
+        accepted = [k for k in range(K) if o.sm_accept[k]]
+        for k in range(K):
+            h = [(c_before == k) & (bits == b) for b in (0, 1)]
+            n0, n1 = int(h[0].sum()), int(h[1].sum())
+            if n0 < 1 or n1 < 1:
+                assert np.isnan(o.sm_logr[k])
+                continue
+            s0, s1 = X[h[0]].sum(axis=0), X[h[1]].sum(axis=0)
+            ref, scale = oracle.split_logr(s0, s1, n0, n1, o.beta, o.alpha)
+            ref += (n0 + n1 - 2) * np.log(2.0)
+            assert abs(o.sm_logr[k] - ref) <= 1e-9 * max(1.0, scale), (k, o.sm_logr[k], ref)
+            back, bscale = oracle.merge_logr(s0, s1, n0, n1, o.beta, o.alpha)
+            assert abs(o.sm_logr[k] + back) <= 1e-9 * max(1.0, bscale)
+        for j, k in enumerate(accepted):
+            moved = (c_before == k) & (bits == 1)
+            assert np.all(o.c[moved] == K + j) and np.all(o.c[(c_before == k) & (bits == 0)] == k)
+            assert o.reset[k] == 1 and o.reset[K + j] == 1
+        n, s_ = _recomputed_stats(o)
+        assert np.array_equal(n, o.nsub[: 2 * o.K]) and np.array_equal(s_, o.ssub[: 2 * o.K])
+        if seen >= 3:
+            break
+        o.sweep()
+    assert seen >= 3
+
+
+def test_accepted_random_split_follows_the_coins():
+    """A tiny cluster under a large alpha: random splits are accepted, the new
+    cluster holds exactly the coin-1 cells, both parts re-draw their
+    sub-labels, and the statistics are those of the labels."""
+    rng = np.random.default_rng(3)
+    X = rng.integers(1, 4, size=(8, 3))
+    d = synth.from_dense(X)
+    rp, col, val = d.host_arrays()
+    seed = 5
+    o = oracle.Oracle(rp, col, val, 3, alpha=200.0, seed=seed, k_max=8, init=False, random_split=True)
+    o.set_state(0, 1, np.zeros(8, dtype=np.int32), np.zeros(8, dtype=np.uint8), np.zeros(1, dtype=np.uint8))
+    for it in range(60):
+        step, c_before, K = o.step, o.c.copy(), o.K
+        o.split_merge()
+        if o.sm_pass != 2 or not o.sm_accept[:K].any():
+            o.set_state(o.step, 1, np.zeros(8, dtype=np.int32), np.zeros(8, dtype=np.uint8), np.zeros(1, dtype=np.uint8))
+            continue
+        bits = np.array([oracle.philox4x32_10(seed, [i, 0, step, (oracle.ST_RSPLIT << 24)])[0] >> 31
+                         for i in range(8)])
+        assert K == 1 and o.K == 2
+        assert np.array_equal(o.c, bits) and np.all(o.cs == 0)
+        assert o.reset[0] == 1 and o.reset[1] == 1
+        n, s_ = _recomputed_stats(o)
+        assert np.array_equal(n, o.nsub[:4]) and np.array_equal(s_, o.ssub[:4])
+        return
+    pytest.fail("no accepted random split in 60 calls")
 
 
 # --------------------------------------------------------------------------

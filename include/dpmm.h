@@ -84,6 +84,15 @@ typedef struct dpmm_csr {
  * if no cell chose it.  Nothing is appended when K = k_max.  Without the flag
  * new clusters arise from splits only. */
 #define DPMM_FLAG_NEW_CLUSTER 2u
+/* DPMM_FLAG_RANDOM_SPLIT: a split/merge call runs a sub-cluster split pass, a
+ * random-split pass or a merge pass, each with probability 1/3 (without the
+ * flag: split or merge, 1/2 each).  A random split (chain B of Section 2.4)
+ * halves every cluster by a fair Philox coin per cell; its ratio is the
+ * collapsed split ratio of the two halves plus (n - 2) log 2, the reverse of
+ * the eq. 23 merge.  An accepted cluster splits along the coins and both parts
+ * re-draw their sub-labels.  dpmm_get_hastings reports the pass as 2.  Costs
+ * one extra byte per cell and 16 k_max G bytes of workspace. */
+#define DPMM_FLAG_RANDOM_SPLIT 4u
 
 /* Hyper-parameters and sampler settings, copied at dpmm_init. */
 typedef struct dpmm_params {
@@ -96,7 +105,8 @@ typedef struct dpmm_params {
                                       uniformly when > 1)                         */
     int32_t k_max;                 /* cluster capacity, 1..1024                   */
     int32_t precision;             /* dpmm_precision                               */
-    uint32_t flags;                /* DPMM_FLAG_SPLIT_Q | DPMM_FLAG_NEW_CLUSTER    */
+    uint32_t flags;                /* DPMM_FLAG_SPLIT_Q | DPMM_FLAG_NEW_CLUSTER |
+                                      DPMM_FLAG_RANDOM_SPLIT                      */
     double refine_tol;             /* FP32 and split-BF16 only.  A cluster
                                       decision whose Gumbel gap is within the
                                       certified rounding bound of its two best

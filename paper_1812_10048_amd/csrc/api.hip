@@ -41,7 +41,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
 struct Layout {
     size_t ent, roff, tiles, c0, c1, cs0, cs1, st, reset, nsub, ssub, beta, lgbeta, logpi, lt64, lc32, ls32, lhi, llo,
-        lpsub, qsub, refine, perm, srow, grp_cnt, grp_off, grp_cur, nsub_prev, blk_ent, blk_off, ovf_off, ovf_ent, relab_c, relab_s, sm_logr, sm_acc, mkey, mlist, dm_k, eb_tmp, rd_part, total;
+        lpsub, qsub, rbits, rssub, rnsub, refine, perm, srow, grp_cnt, grp_off, grp_cur, nsub_prev, blk_ent, blk_off, ovf_off, ovf_ent, relab_c, relab_s, sm_logr, sm_acc, mkey, mlist, dm_k, eb_tmp, rd_part, total;
 };
 
 int32_t num_blocks(int64_t N) { return (int32_t)((N + kBlkCells - 1) / kBlkCells); }
@@ -81,6 +81,10 @@ Layout plan(int64_t N, int32_t G, int64_t nnz, int32_t k_max, int32_t precision,
     L.lgbeta = take(8 * (size_t)G);
     L.lpsub = take((flags & kFlagSplitQ) ? 8 * (size_t)N : 0);
     L.qsub = take(8 * (size_t)k_max);
+    const bool rsplit = (flags & kFlagRandomSplit) != 0;
+    L.rbits = take(rsplit ? (size_t)N : 0);
+    L.rssub = take(rsplit ? 16 * (size_t)k_max * (size_t)G : 0);
+    L.rnsub = take(rsplit ? 16 * (size_t)k_max : 0);
     L.logpi = take(8 * (size_t)k_max);
     L.lt64 = take(24 * (size_t)k_max * (size_t)G);
     L.lc32 = take(4 * ((size_t)G * (size_t)kpad + kTablePadRows));
@@ -123,7 +127,8 @@ dpmm_status check_args(const dpmm_csr* csr, const dpmm_params* p)
     if (p->k_max < 1 || p->k_max > 1024) return fail(DPMM_ERR_ARG, "k_max must be in [1, 1024]");
     if (p->k_init < 1 || p->k_init > p->k_max) return fail(DPMM_ERR_ARG, "k_init must be in [1, k_max]");
     if (p->precision < DPMM_FP64 || p->precision > DPMM_SPLIT_BF16) return fail(DPMM_ERR_ARG, "unknown precision");
-    if (p->flags & ~(DPMM_FLAG_SPLIT_Q | DPMM_FLAG_NEW_CLUSTER)) return fail(DPMM_ERR_ARG, "unknown flags");
+    if (p->flags & ~(DPMM_FLAG_SPLIT_Q | DPMM_FLAG_NEW_CLUSTER | DPMM_FLAG_RANDOM_SPLIT))
+        return fail(DPMM_ERR_ARG, "unknown flags");
     return DPMM_OK;
 }
 
@@ -249,6 +254,10 @@ dpmm_status dpmm_init(const dpmm_csr* csr, const dpmm_params* params, void* work
     ws.flags = params->flags;
     ws.lpsub = (params->flags & kFlagSplitQ) ? (double*)(base + L.lpsub) : nullptr;
     ws.qsub = (double*)(base + L.qsub);
+    const bool rsplit = (params->flags & kFlagRandomSplit) != 0;
+    ws.rbits = rsplit ? (uint8_t*)(base + L.rbits) : nullptr;
+    ws.rssub = rsplit ? (unsigned long long*)(base + L.rssub) : nullptr;
+    ws.rnsub = rsplit ? (unsigned long long*)(base + L.rnsub) : nullptr;
     ws.logpi = (double*)(base + L.logpi);
     ws.lt64 = (double*)(base + L.lt64);
     ws.lc32 = (float*)(base + L.lc32);
@@ -406,14 +415,25 @@ dpmm_status dpmm_split_merge(dpmm_ctx* ctx)
     if (s != DPMM_OK) return s;
     const uint32_t step = (uint32_t)ctx->step;
     // the chain coin depends only on (seed, step): drawn here, without a sync
+    // pass 0: split into the sub-clusters; 1: merges; 2: random splits (only
+    // with DPMM_FLAG_RANDOM_SPLIT, the three then equally likely)
     const Words w = philox(ctx->ws.seed, 0u, 0u, step, kChain, 0u);
-    const int merge_pass = unit52(w.w[0], w.w[1]) < 0.5 ? 0 : 1;
-    if (merge_pass) launch_merge_ratios(ctx->ws, ctx->stream);
-    else launch_split_ratios(ctx->ws, ctx->c[ctx->cur], ctx->stream);
-    launch_sm_decide(ctx->ws, merge_pass, step, ctx->stream);
+    const double coin = unit52(w.w[0], w.w[1]);
+    int pass;
+    if (ctx->ws.flags & kFlagRandomSplit) pass = coin < 1.0 / 3.0 ? 0 : (coin < 2.0 / 3.0 ? 2 : 1);
+    else pass = coin < 0.5 ? 0 : 1;
+    if (pass == 1) {
+        launch_merge_ratios(ctx->ws, ctx->stream);
+        launch_sm_decide(ctx->ws, 1, step, ctx->stream);
+    } else if (pass == 0) {
+        launch_split_ratios(ctx->ws, ctx->c[ctx->cur], ctx->stream);
+        launch_sm_decide(ctx->ws, 0, step, ctx->stream);
+    } else {
+        launch_random_split(ctx->ws, ctx->c[ctx->cur], ctx->cs[ctx->cur], step, ctx->stream);
+    }
     launch_relabel(ctx->ws, ctx->c[ctx->cur], ctx->cs[ctx->cur], ctx->stream);
     HIP_TRY(hipGetLastError());     // (k_sm_decide has written the K hint)
-    ctx->last_pass = merge_pass;
+    ctx->last_pass = pass;
     ctx->step += 1;
     ctx->sm_calls += 1;
     return DPMM_OK;

@@ -21,7 +21,8 @@ enum Stream : uint32_t {
     kResub = 6,     // fair coins of a reset cluster's sub-labels
     kChain = 7,     // split chain or merge chain
     kSplit = 8,     // split acceptance
-    kMerge = 9      // merge acceptance and visiting order
+    kMerge = 9,     // merge acceptance and visiting order
+    kRSplit = 10    // per-cell coins of a random split
 };
 
 constexpr uint32_t kSubRowBase = 0x10000u;   // Philox row id of thetabar_{k,r} = base + 2k + r
@@ -96,6 +97,7 @@ constexpr uint32_t kPadEntry = 0x0000FFFFu;   // gene 0xFFFF, count 0
 constexpr int kBlkCells = 256;
 constexpr uint32_t kFlagSplitQ = 1u;          // dpmm_params.flags bit of the split proposal term
 constexpr uint32_t kFlagNewCluster = 2u;      // ... and of the Gibbs step over K + 1 clusters
+constexpr uint32_t kFlagRandomSplit = 4u;     // ... and of the random-split pass
 constexpr int kBlkGenes = 64;
 constexpr int kBlkLead = 8;              // padding columns at the start of a dense tile row
 constexpr int kBlkRow = kBlkLead + kBlkGenes;   // BF16 elements per row of the dense LDS tile
@@ -196,6 +198,9 @@ struct Ws {
     uint32_t flags;        // kFlagSplitQ: the split ratio carries -sum log p(cbar_i)
     double* lpsub;         // [N] log p(cbar_i) of eq. 8 in the last sweep (with kFlagSplitQ only)
     double* qsub;          // [k_max] sum of lpsub over the cells of each cluster (split pass)
+    uint8_t* rbits;        // [N] coins of the last random-split pass (with kFlagRandomSplit)
+    unsigned long long* rssub;   // [2 k_max G] statistics of the coin halves
+    unsigned long long* rnsub;   // [2 k_max] sizes of the coin halves
     int32_t* k_hint;       // mapped pinned host word: K after the last compaction or split/merge
                            // (a launch-size hint for the host; written by the kernels that set K)
     int32_t* relab_c;      // [2 k_max] new cluster of an old (k, r)

@@ -87,13 +87,16 @@ static void launch_lgamma_beta(const Ws& ws, hipStream_t s)
     hipLaunchKernelGGL(k_lgamma_beta, dim3((unsigned)((ws.G + 255) / 256)), dim3(256), 0, s, ws);
 }
 
-__global__ void __launch_bounds__(kSmThreads) k_split_ratios(Ws ws)
+// random = 0: split into the sub-clusters (not for a reset cluster);
+// random = 1: split into the coin halves held in ws.ssub / ws.nsub by the
+// caller, with the (n - 2) log 2 that reverses the eq. 23 merge
+__global__ void __launch_bounds__(kSmThreads) k_split_ratios(Ws ws, int random)
 {
     const int K = ws.st->K;
     const int G = ws.G;
     for (int k = blockIdx.x; k < K; k += gridDim.x) {
         const unsigned long long n0 = ws.nsub[2 * k], n1 = ws.nsub[2 * k + 1];
-        if (ws.reset[k] || n0 < 1 || n1 < 1) {
+        if ((!random && ws.reset[k]) || n0 < 1 || n1 < 1) {
             if (threadIdx.x == 0) ws.sm_logr[k] = __builtin_nan("");
             continue;
         }
@@ -122,7 +125,8 @@ __global__ void __launch_bounds__(kSmThreads) k_split_ratios(Ws ws)
             tot.add(lB - lgamma(B + (double)r.b));
             tot.add(-(lB - lgamma(B + (double)(r.a + r.b))));
             tot.add(log(ws.alpha) + lgamma((double)n0) + lgamma((double)n1) - lgamma((double)(n0 + n1)));
-            if (ws.flags & kFlagSplitQ) tot.add(-ws.qsub[k]);     // proposal term, Section 2.3
+            if (random) tot.add((double)(n0 + n1 - 2) * log(2.0));   // chain B, Section 2.4
+            else if (ws.flags & kFlagSplitQ) tot.add(-ws.qsub[k]);     // proposal term, Section 2.3
             ws.sm_logr[k] = tot.value();
         }
     }
@@ -228,7 +232,65 @@ void launch_split_ratios(const Ws& ws, const int32_t* c, hipStream_t s)
         hipLaunchKernelGGL(k_split_q, dim3(256), dim3(kQThreads), sizeof(double) * (size_t)ws.k_max, s, ws, c);
     }
     launch_lgamma_beta(ws, s);
-    hipLaunchKernelGGL(k_split_ratios, dim3(blocks), dim3(kSmThreads), 0, s, ws);
+    hipLaunchKernelGGL(k_split_ratios, dim3(blocks), dim3(kSmThreads), 0, s, ws, 0);
+}
+
+// ---------------------------------------------------------------------------
+// Random splits (chain B of Section 2.4).  Each cell draws a fair coin; the
+// statistics of the coin halves go to rssub / rnsub through the statistics
+// pass (a copy of the workspace view with those arrays in place of ssub /
+// nsub), the ratios and decisions run on that view, and the accepted
+// clusters' rows and their cells' sub-labels are then committed.
+// ---------------------------------------------------------------------------
+__global__ void k_rsplit_coins(Ws ws, uint32_t step)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ws.N; i += (int64_t)gridDim.x * blockDim.x)
+        ws.rbits[i] = (uint8_t)(philox(ws.seed, (uint32_t)i, 0u, step, kRSplit, 0u).w[0] >> 31);
+}
+
+// After the decisions: the split clusters' statistics from the halves (the
+// decision kernel has moved half 1 to the new cluster in rssub / rnsub), and
+// every cell of a split cluster takes its coin as sub-label, so that the
+// relabel sends coin 1 to the new cluster.
+__global__ void k_rsplit_apply(Ws ws, const int32_t* __restrict__ c, uint8_t* __restrict__ cs)
+{
+    const int K0 = ws.st->sm_n;          // clusters before the pass
+    const int G = ws.G;
+    if (blockIdx.x == 0) {
+        for (int k = 0; k < K0; ++k) {
+            if (!ws.sm_acc[k]) continue;
+            const int j = ws.relab_c[2 * k + 1];
+            for (int u = threadIdx.x; u < 2 * G; u += blockDim.x) {
+                ws.ssub[(int64_t)2 * k * G + u] = ws.rssub[(int64_t)2 * k * G + u];
+                ws.ssub[(int64_t)2 * j * G + u] = ws.rssub[(int64_t)2 * j * G + u];
+            }
+            if (threadIdx.x < 2) {
+                ws.nsub[2 * k + threadIdx.x] = ws.rnsub[2 * k + threadIdx.x];
+                ws.nsub[2 * j + threadIdx.x] = ws.rnsub[2 * j + threadIdx.x];
+            }
+        }
+        if (threadIdx.x == 0) ws.st->sm_pass = 2;
+    }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ws.N; i += (int64_t)gridDim.x * blockDim.x) {
+        const int k = c[i];
+        if (k >= 0 && k < K0 && ws.sm_acc[k]) cs[i] = ws.rbits[i];
+    }
+}
+
+void launch_random_split(const Ws& ws, const int32_t* c, uint8_t* cs, uint32_t step, hipStream_t s)
+{
+    int64_t cb = (ws.N + 255) / 256;
+    if (cb > 4096) cb = 4096;
+    hipLaunchKernelGGL(k_rsplit_coins, dim3((unsigned)cb), dim3(256), 0, s, ws, step);
+    Ws halves = ws;
+    halves.ssub = ws.rssub;
+    halves.nsub = ws.rnsub;
+    launch_stats(halves, c, ws.rbits, s);
+    launch_lgamma_beta(ws, s);
+    const int blocks = ws.k_max < 1024 ? ws.k_max : 1024;
+    hipLaunchKernelGGL(k_split_ratios, dim3(blocks), dim3(kSmThreads), 0, s, halves, 1);
+    launch_sm_decide(halves, 0, step, s);
+    hipLaunchKernelGGL(k_rsplit_apply, dim3((unsigned)cb), dim3(256), 0, s, ws, c, cs);
 }
 
 void launch_merge_ratios(const Ws& ws, hipStream_t s)

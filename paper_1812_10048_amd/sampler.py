@@ -27,12 +27,14 @@ class Sampler:
     or a length-G tensor of per-gene concentrations.  ``precision`` is one of
     "fp64", "fp32", "split_bf16".  ``split_q`` sets DPMM_FLAG_SPLIT_Q (the
     split ratio carries the proposal term of Section 2.3); ``new_cluster``
-    sets DPMM_FLAG_NEW_CLUSTER (the Gibbs step runs over K + 1 clusters).
+    sets DPMM_FLAG_NEW_CLUSTER (the Gibbs step runs over K + 1 clusters);
+    ``random_split`` sets DPMM_FLAG_RANDOM_SPLIT (a third pass of random
+    splits, chain B of Section 2.4).
     """
 
     def __init__(self, row_ptr, col, val, n_genes: int, *, alpha: float = 1.0, beta=1.0, seed: int = 0,
                  k_init: int = 1, k_max: int = 128, precision: str = "fp32", refine_tol: float = -1.0,
-                 split_q: bool = False, new_cluster: bool = False):
+                 split_q: bool = False, new_cluster: bool = False, random_split: bool = False):
         if not torch.cuda.is_available():
             raise RuntimeError("libdpmm needs a GPU")
         rp = _dev(torch.as_tensor(row_ptr), torch.int64)
@@ -52,8 +54,8 @@ class Sampler:
             beta_scalar = 0.0
         params = C.dpmm_params(float(alpha), beta_scalar, beta_t.data_ptr() if beta_t is not None else None,
                                int(seed) & 0xFFFFFFFFFFFFFFFF, int(k_init), self.k_max, C.PRECISIONS[precision],
-                               (C.FLAG_SPLIT_Q if split_q else 0) | (C.FLAG_NEW_CLUSTER if new_cluster else 0),
-                               float(refine_tol))
+                               (C.FLAG_SPLIT_Q if split_q else 0) | (C.FLAG_NEW_CLUSTER if new_cluster else 0) |
+                               (C.FLAG_RANDOM_SPLIT if random_split else 0), float(refine_tol))
         nbytes = C.dpmm_workspace_size(csr, params)
         # 256-byte alignment inside a slightly larger buffer
         self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")

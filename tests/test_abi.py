@@ -53,7 +53,7 @@ def test_workspace_size_is_a_host_function():
     dict(csr=dict(N=0)), dict(csr=dict(G=0)), dict(csr=dict(G=70000)), dict(csr=dict(nnz=-1)),
     dict(params=dict(alpha=0.0)), dict(params=dict(beta=-1.0)), dict(params=dict(k_max=0)),
     dict(params=dict(k_max=2000)), dict(params=dict(k_init=0)), dict(params=dict(k_init=17)),
-    dict(params=dict(precision=7)), dict(params=dict(flags=4)),
+    dict(params=dict(precision=7)), dict(params=dict(flags=8)),
 ])
 def test_invalid_arguments_are_rejected_with_a_message(bad):
     csr = _csr(**bad.get("csr", {}))

@@ -218,6 +218,46 @@ def test_new_cluster_chain_lockstep(case):
     _say("K", s.stats()["K"], "sweeps that opened a cluster", opened)
 
 
+@pytest.mark.parametrize("case", ["c1-split_bf16", "c1-fp64", "tiny-fp64"])
+def test_random_split_chain_lockstep(case):
+    """With the random-split pass (DPMM_FLAG_RANDOM_SPLIT, chain B of Section
+    2.4) on both sides: the pass chosen, the ratios of every pass, the accept
+    decisions, labels and statistics in lockstep with the oracle; on the tiny
+    high-alpha data random splits are accepted."""
+    data, precision = case.split("-")
+    _say("random_split lockstep", case)
+    if data == "c1":
+        d = synth.generate("c1", seed=12)
+        kw = dict(alpha=1.0, beta=1.0, seed=31, k_max=64, k_init=1, random_split=True)
+    else:
+        X = np.random.default_rng(3).integers(1, 4, size=(24, 3))
+        d = synth.from_dense(X)
+        kw = dict(alpha=200.0, beta=1.0, seed=5, k_max=16, k_init=1, random_split=True)
+    o = _oracle(d, **kw)
+    s = _sampler(d, precision, **kw)
+    rpasses = accepted = 0
+    for it in range(30):
+        o.sweep()
+        s.sweep(1)
+        _compare_params(o, s)
+        if _compare_labels(o, s, f"sweep {it}"):
+            break
+        _compare_stats(o, s)
+        o.split_merge()
+        s.split_merge()
+        _compare_hastings(o, s)
+        if o.sm_pass == 2:
+            rpasses += 1
+            accepted += int(o.sm_accept[: o.sm_n].sum())
+        if _compare_labels(o, s, f"split/merge {it}"):
+            break
+        _compare_stats(o, s)
+    assert rpasses >= 3
+    if data == "tiny":
+        assert accepted >= 1
+    _say("K", s.stats()["K"], "random passes", rpasses, "accepted", accepted)
+
+
 SCORE_TOL = {"fp32": 1e-4, "split_bf16": 3e-5}
 
 

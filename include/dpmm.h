@@ -263,6 +263,27 @@ dpmm_status dpmm_dm_logmarginal(const int64_t* s, int32_t J, int32_t G, const do
 dpmm_status dpmm_dm_grad(const int64_t* s, int32_t J, int32_t G, const double* beta,
                          const double* g, double* grad_beta, void* stream);
 
+/* Preprocessing (Section 3 keeps the genes of largest standard deviation
+ * across cells).  Exact per-gene moments of a cell-major CSR:
+ *   sum[u] = sum_i x_iu,  sumsq[u] = sum_i x_iu^2,
+ * as uint64 (no rounding; x <= 65535 and N < 2^30 keep both below 2^63).
+ * sum_dev, sumsq_dev: DEVICE, G entries, overwritten.  Entries with a gene
+ * outside [0, G) or a count < 1 are skipped (dpmm_init rejects such data).
+ * The CSR is not otherwise validated.  Stateless; async on stream. */
+dpmm_status dpmm_gene_moments(const dpmm_csr* csr, uint64_t* sum_dev, uint64_t* sumsq_dev, void* stream);
+
+/* The CSR restricted to the genes u with map[u] >= 0, renumbered to map[u]
+ * (map: DEVICE int32[G]; its kept values must increase with u, so that the
+ * rows stay sorted, and lie in [0, G_out)).  Two calls:
+ *   1. col_out == NULL: row_ptr_out (DEVICE, N + 1 entries) receives the new
+ *      row offsets and *nnz_out (HOST) the new number of entries; this call
+ *      synchronises the stream;
+ *   2. col_out, val_out (DEVICE, *nnz_out entries each): the entries, in their
+ *      row order; row_ptr_out must hold the offsets of call 1.
+ * The caller owns every buffer. */
+dpmm_status dpmm_filter_genes(const dpmm_csr* csr, const int32_t* map_dev, int64_t* row_ptr_out,
+                              int32_t* col_out, int32_t* val_out, int64_t* nnz_out, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -356,3 +356,38 @@ class Oracle:
         return dict(step=self.step, K=K, c=self.c.copy(), cs=self.cs.copy(),
                     reset=self.reset[:K].copy(), nsub=self.nsub[: 2 * K].copy(),
                     ssub=self.ssub[: 2 * K].copy(), beta=self.beta.copy())
+
+
+# ----------------------------------------------------------------------------
+# Preprocessing (Section 3 keeps the genes of largest standard deviation)
+# ----------------------------------------------------------------------------
+
+def gene_moments(row_ptr, col, val, n_genes: int):
+    """Exact per-gene sum_i x_iu and sum_i x_iu^2 (int64), entry by entry."""
+    col = np.asarray(col, dtype=np.int64)
+    val = np.asarray(val, dtype=np.int64)
+    s = np.zeros(n_genes, dtype=np.int64)
+    q = np.zeros(n_genes, dtype=np.int64)
+    np.add.at(s, col, val)
+    np.add.at(q, col, val * val)
+    return s, q
+
+
+def filter_csr(row_ptr, col, val, genes):
+    """The cell-major CSR restricted to the increasing gene list ``genes``,
+    genes renumbered to their position in it, row by row."""
+    row_ptr = np.asarray(row_ptr, dtype=np.int64)
+    col = np.asarray(col)
+    val = np.asarray(val)
+    pos = {int(g): j for j, g in enumerate(genes)}
+    out_ptr = [0]
+    out_col, out_val = [], []
+    for i in range(row_ptr.size - 1):
+        for e in range(row_ptr[i], row_ptr[i + 1]):
+            j = pos.get(int(col[e]))
+            if j is not None:
+                out_col.append(j)
+                out_val.append(int(val[e]))
+        out_ptr.append(len(out_col))
+    return (np.array(out_ptr, dtype=np.int64), np.array(out_col, dtype=np.int32),
+            np.array(out_val, dtype=np.int32))

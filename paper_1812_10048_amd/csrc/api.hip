@@ -653,6 +653,40 @@ dpmm_status dpmm_timing_read(dpmm_ctx* ctx, double* total_ms, int64_t* launches)
     return DPMM_OK;
 }
 
+dpmm_status dpmm_gene_moments(const dpmm_csr* csr, uint64_t* sum_dev, uint64_t* sumsq_dev, void* stream)
+{
+    if (!csr || !sum_dev || !sumsq_dev) return fail(DPMM_ERR_ARG, "null argument");
+    if (csr->n_genes < 1 || csr->n_genes > 65535) return fail(DPMM_ERR_ARG, "n_genes must be in [1, 65535]");
+    if (csr->nnz < 0 || (csr->nnz > 0 && (!csr->col || !csr->val))) return fail(DPMM_ERR_ARG, "bad entries");
+    launch_gene_moments(csr->col, csr->val, csr->nnz, csr->n_genes, reinterpret_cast<unsigned long long*>(sum_dev),
+                        reinterpret_cast<unsigned long long*>(sumsq_dev), (hipStream_t)stream);
+    HIP_TRY(hipGetLastError());
+    return DPMM_OK;
+}
+
+dpmm_status dpmm_filter_genes(const dpmm_csr* csr, const int32_t* map_dev, int64_t* row_ptr_out, int32_t* col_out,
+                              int32_t* val_out, int64_t* nnz_out, void* stream)
+{
+    if (!csr || !map_dev || !row_ptr_out) return fail(DPMM_ERR_ARG, "null argument");
+    if (csr->n_cells < 1 || csr->n_cells >= (1ll << 30)) return fail(DPMM_ERR_ARG, "n_cells must be in [1, 2^30)");
+    if (csr->n_genes < 1 || csr->n_genes > 65535) return fail(DPMM_ERR_ARG, "n_genes must be in [1, 65535]");
+    if (!csr->row_ptr || (csr->nnz > 0 && (!csr->col || !csr->val))) return fail(DPMM_ERR_ARG, "bad CSR");
+    const hipStream_t s = (hipStream_t)stream;
+    if (!col_out) {
+        if (!nnz_out) return fail(DPMM_ERR_ARG, "nnz_out is needed by the first call");
+        launch_filter_count(csr->row_ptr, csr->col, csr->n_cells, csr->n_genes, map_dev, row_ptr_out, s);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(nnz_out, row_ptr_out + csr->n_cells, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        return DPMM_OK;
+    }
+    if (!val_out) return fail(DPMM_ERR_ARG, "null val_out");
+    launch_filter_fill(csr->row_ptr, csr->col, csr->val, csr->n_cells, csr->n_genes, map_dev, row_ptr_out, col_out,
+                       val_out, s);
+    HIP_TRY(hipGetLastError());
+    return DPMM_OK;
+}
+
 dpmm_status dpmm_dm_logmarginal(const int64_t* sv, int32_t J, int32_t G, const double* beta, double* out, void* stream)
 {
     if (J < 0 || G < 1) return fail(DPMM_ERR_ARG, "J must be >= 0 and G >= 1");

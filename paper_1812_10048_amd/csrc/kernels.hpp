@@ -19,6 +19,12 @@ void launch_sort(const Ws& ws, const int32_t* c, const uint8_t* cs, int by_clust
 void launch_build_blocked(const Ws& ws, int64_t* tile_sums, hipStream_t s);
 hipError_t configure_layout();
 void launch_extend(const Ws& ws, hipStream_t s);
+void launch_gene_moments(const int32_t* col, const int32_t* val, int64_t nnz, int32_t G, unsigned long long* sum,
+                         unsigned long long* sumsq, hipStream_t s);
+void launch_filter_count(const int64_t* row_ptr, const int32_t* col, int64_t N, int32_t G, const int32_t* map,
+                         int64_t* out_ptr, hipStream_t s);
+void launch_filter_fill(const int64_t* row_ptr, const int32_t* col, const int32_t* val, int64_t N, int32_t G,
+                        const int32_t* map, const int64_t* out_ptr, int32_t* col_out, int32_t* val_out, hipStream_t s);
 
 // substats.hip
 struct SubArgs {

@@ -83,6 +83,8 @@ _SIGNATURES = {
     "dpmm_timing_read": ([_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)], _S),
     "dpmm_dm_logmarginal": ([_P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P], _S),
     "dpmm_dm_grad": ([_P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P], _S),
+    "dpmm_gene_moments": ([ctypes.POINTER(dpmm_csr), _P, _P, _P], _S),
+    "dpmm_filter_genes": ([ctypes.POINTER(dpmm_csr), _P, _P, _P, _P, ctypes.POINTER(ctypes.c_int64), _P], _S),
 }
 
 _lib = None
@@ -203,3 +205,14 @@ def dpmm_dm_logmarginal(s_dev: int, J: int, G: int, beta_dev: int, out_dev: int,
 
 def dpmm_dm_grad(s_dev: int, J: int, G: int, beta_dev: int, g_dev: int, grad_dev: int, stream: int) -> None:
     _check(lib().dpmm_dm_grad(s_dev, J, G, beta_dev, g_dev, grad_dev, stream))
+
+
+def dpmm_gene_moments(csr: dpmm_csr, sum_dev: int, sumsq_dev: int, stream: int) -> None:
+    _check(lib().dpmm_gene_moments(ctypes.byref(csr), sum_dev, sumsq_dev, stream))
+
+
+def dpmm_filter_genes(csr: dpmm_csr, map_dev: int, row_ptr_out: int, col_out, val_out, stream: int) -> int:
+    """First call with col_out = None returns the new nnz; the second fills."""
+    n = ctypes.c_int64(0)
+    _check(lib().dpmm_filter_genes(ctypes.byref(csr), map_dev, row_ptr_out, col_out, val_out, ctypes.byref(n), stream))
+    return int(n.value)

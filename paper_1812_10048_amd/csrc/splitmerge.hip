@@ -70,10 +70,30 @@ __device__ inline SmRed block_reduce(SmRed v)
     return r;
 }
 
+// log Gamma(x) for x > 0, for the per-gene terms: Stirling's series with the
+// Bernoulli-number terms through x^-7 once x >= 16 (the first omitted term,
+// 1 / (1188 x^9), is below 1.2e-14 there), reached from a smaller x by the
+// recurrence log Gamma(x) = log Gamma(x + m) - log(x (x + 1) ... (x + m - 1)).
+__device__ inline double lgamma_pos(double x)
+{
+    double shift = 0.0;
+    if (x < 16.0) {
+        double p = 1.0;
+        while (x < 16.0) {
+            p *= x;
+            x += 1.0;
+        }
+        shift = -log(p);
+    }
+    const double r = 1.0 / x, r2 = r * r;
+    const double series = r * (1.0 / 12.0 - r2 * (1.0 / 360.0 - r2 * (1.0 / 1260.0 - r2 * (1.0 / 1680.0))));
+    return (x - 0.5) * log(x) - x + 0.91893853320467274178 + series + shift;   // 0.5 log(2 pi)
+}
+
 // lgamma(beta + v) - lgamma(beta), zero for v = 0 (lgb = lgamma(beta))
 __device__ inline double rising(double beta, double lgb, long long v)
 {
-    return v ? lgamma(beta + (double)v) - lgb : 0.0;
+    return v ? lgamma_pos(beta + (double)v) - lgb : 0.0;
 }
 
 __global__ void k_lgamma_beta(Ws ws)

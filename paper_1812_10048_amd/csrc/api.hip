@@ -41,7 +41,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
 struct Layout {
     size_t ent, roff, tiles, c0, c1, cs0, cs1, st, reset, nsub, ssub, beta, lgbeta, logpi, lt64, lc32, ls32, lhi, llo,
-        lpsub, qsub, rbits, rssub, rnsub, refine, perm, srow, grp_cnt, grp_off, grp_cur, nsub_prev, blk_ent, blk_off, ovf_off, ovf_ent, relab_c, relab_s, sm_logr, sm_acc, mkey, mlist, dm_k, eb_tmp, rd_part, total;
+        lpsub, qsub, rbits, rssub, rnsub, refine, perm, srow, grp_cnt, grp_off, grp_cur, nsub_prev, blk_ent, blk_off, ovf_off, ovf_ent, relab_c, relab_s, sm_logr, sm_acc, mkey, mlist, dm_k, eb_tmp, rd_part, sm_part, total;
 };
 
 int32_t num_blocks(int64_t N) { return (int32_t)((N + kBlkCells - 1) / kBlkCells); }
@@ -111,6 +111,7 @@ Layout plan(int64_t N, int32_t G, int64_t nnz, int32_t k_max, int32_t precision,
     L.dm_k = take(8 * (size_t)k_max);
     L.eb_tmp = take(8 * ((size_t)k_max + (size_t)G));
     L.rd_part = take(16 * (size_t)(3 * k_max + 1) * (size_t)redraw_tiles(G));
+    L.sm_part = take(sizeof(SmPart) * (size_t)k_max * (size_t)sm_tiles(G));
     L.total = o;
     return L;
 }
@@ -286,6 +287,7 @@ dpmm_status dpmm_init(const dpmm_csr* csr, const dpmm_params* params, void* work
     ws.dm_k = (double*)(base + L.dm_k);
     ws.eb_tmp = (double*)(base + L.eb_tmp);
     ws.rd_part = (double2*)(base + L.rd_part);
+    ws.sm_part = (SmPart*)(base + L.sm_part);
     ctx->c[0] = (int32_t*)(base + L.c0);
     ctx->c[1] = (int32_t*)(base + L.c1);
     ctx->cs[0] = (uint8_t*)(base + L.cs0);

@@ -152,6 +152,16 @@ struct RowCursor {
 constexpr int kRedrawGenes = 256;
 __host__ __device__ inline int redraw_tiles(int G) { return (G + kRedrawGenes - 1) / kRedrawGenes; }
 
+// Genes per workgroup of the split-ratio and cluster-logDM passes, the tiles of
+// a cluster, and one tile's partial result (compensated sum s + c of the
+// per-gene terms, sum of beta_u, and the count sums of the two halves).
+constexpr int kSmGenes = 512;
+__host__ __device__ inline int sm_tiles(int G) { return (G + kSmGenes - 1) / kSmGenes; }
+struct SmPart {
+    double s, c, beta;
+    long long a, b;
+};
+
 // ---------------------------------------------------------------------------
 // View of the workspace, passed by value to kernels.
 // ---------------------------------------------------------------------------
@@ -212,6 +222,7 @@ struct Ws {
     double* dm_k;          // [k_max] logDM of each cluster's statistics
     double* eb_tmp;        // [k_max + G] scratch of the empirical-Bayes step
     double2* rd_part;      // [3 k_max + 1][redraw_tiles(G)] (max, sum exp) of each gene tile of a redrawn row
+    SmPart* sm_part;       // [k_max][sm_tiles(G)] partial results of the split-ratio / logDM passes
 };
 
 }  // namespace dpmm

@@ -10,14 +10,15 @@
 //   merge of k1 < k2 (reverse of a random split, eq. 23):
 //     log R = -[log alpha + lgamma(n_1) + lgamma(n_2) - lgamma(n_1 + n_2)
 //             + logDM(s_1) + logDM(s_2) - logDM(s_1 + s_2)] + (n_1 + n_2 - 2) log 1/2.
-// Each candidate is one workgroup reducing over genes in FP64 with
-// compensated sums; the decisions are taken by a single workgroup.
+// The per-gene sums are FP64 with compensated accumulation, over workgroups of
+// (candidate, gene tile) combined in tile order; the decisions are taken by a
+// single workgroup.
 #include "dpmm_common.hpp"
 #include "kernels.hpp"
 
 namespace dpmm {
 
-constexpr int kSmThreads = 512;          // split and cluster passes: K workgroups, genes over 512 threads
+constexpr int kSmThreads = 512;          // split and cluster passes: K x gene-tile workgroups
 constexpr int kMergeThreads = 256;       // merge pass: K (K - 1) / 2 workgroups
 
 // Compensated accumulator (Neumaier): value = s + c.
@@ -107,76 +108,132 @@ static void launch_lgamma_beta(const Ws& ws, hipStream_t s)
     hipLaunchKernelGGL(k_lgamma_beta, dim3((unsigned)((ws.G + 255) / 256)), dim3(256), 0, s, ws);
 }
 
-// random = 0: split into the sub-clusters (not for a reset cluster);
-// random = 1: split into the coin halves held in ws.ssub / ws.nsub by the
-// caller, with the (n - 2) log 2 that reverses the eq. 23 merge
-__global__ void __launch_bounds__(kSmThreads) k_split_ratios(Ws ws, int random)
+// The split ratios and the clusters' logDM in two passes, so that K clusters
+// spread over K x tiles workgroups: pass 1 reduces one tile of kSmThreads genes
+// of one cluster (a compensated sum and the count and beta sums); pass 2
+// combines a cluster's tiles in tile order and adds the per-cluster terms.
+// mode 0: split into the sub-clusters (not for a reset cluster); 1: split
+// into the coin halves held in ws.ssub / ws.nsub by the caller, with the
+// (n - 2) log 2 that reverses the eq. 23 merge; 2: logDM(s_{k,0} + s_{k,1}).
+static_assert(kSmGenes == kSmThreads, "one gene per thread of a tile");
+
+__device__ inline bool split_eligible(const Ws& ws, int k, int mode)
+{
+    const unsigned long long n0 = ws.nsub[2 * k], n1 = ws.nsub[2 * k + 1];
+    return !((mode == 0 && ws.reset[k]) || n0 < 1 || n1 < 1);
+}
+
+__global__ void __launch_bounds__(kSmThreads) k_sm_tiles(Ws ws, int mode)
 {
     const int K = ws.st->K;
     const int G = ws.G;
+    const int T = gridDim.y;
+    const int u = blockIdx.y * kSmThreads + threadIdx.x;
     for (int k = blockIdx.x; k < K; k += gridDim.x) {
-        const unsigned long long n0 = ws.nsub[2 * k], n1 = ws.nsub[2 * k + 1];
-        if ((!random && ws.reset[k]) || n0 < 1 || n1 < 1) {
-            if (threadIdx.x == 0) ws.sm_logr[k] = __builtin_nan("");
-            continue;
-        }
+        if (mode != 2 && !split_eligible(ws, k, mode)) continue;
         const unsigned long long* s0 = ws.ssub + (int64_t)(2 * k) * G;
         const unsigned long long* s1 = s0 + G;
         SmRed r;
         r.a = r.b = 0;
         r.beta = 0.0;
-        for (int u = threadIdx.x; u < G; u += kSmThreads) {
+        if (u < G) {
             const double bu = ws.beta[u], lgb = ws.lgbeta[u];
-            const long long a = (long long)s0[u], b = (long long)s1[u];
-            r.beta += bu;
-            r.a += a;
-            r.b += b;
-            if (a + b == 0) continue;
-            r.cs.add(rising(bu, lgb, a));
-            r.cs.add(rising(bu, lgb, b));
-            r.cs.add(-rising(bu, lgb, a + b));
+            r.beta = bu;
+            if (mode == 2) {
+                const long long v = (long long)(s0[u] + s1[u]);
+                r.a = v;
+                r.cs.add(rising(bu, lgb, v));
+            } else {
+                const long long x0 = (long long)s0[u], x1 = (long long)s1[u];
+                r.a = x0;
+                r.b = x1;
+                if (x0 + x1 != 0) {
+                    r.cs.add(rising(bu, lgb, x0));
+                    r.cs.add(rising(bu, lgb, x1));
+                    r.cs.add(-rising(bu, lgb, x0 + x1));
+                }
+            }
         }
         r = block_reduce<kSmThreads>(r);
         if (threadIdx.x == 0) {
-            const double B = r.beta;
-            CSum tot = r.cs;
-            const double lB = lgamma(B);
-            tot.add(lB - lgamma(B + (double)r.a));
-            tot.add(lB - lgamma(B + (double)r.b));
-            tot.add(-(lB - lgamma(B + (double)(r.a + r.b))));
-            tot.add(log(ws.alpha) + lgamma((double)n0) + lgamma((double)n1) - lgamma((double)(n0 + n1)));
-            if (random) tot.add((double)(n0 + n1 - 2) * log(2.0));   // chain B, Section 2.4
-            else if (ws.flags & kFlagSplitQ) tot.add(-ws.qsub[k]);     // proposal term, Section 2.3
-            ws.sm_logr[k] = tot.value();
+            SmPart& o = ws.sm_part[(int64_t)k * T + blockIdx.y];
+            o.s = r.cs.s;
+            o.c = r.cs.c;
+            o.beta = r.beta;
+            o.a = r.a;
+            o.b = r.b;
         }
     }
 }
 
-// logDM of every cluster's statistics s_k = s_{k,0} + s_{k,1}
-__global__ void __launch_bounds__(kSmThreads) k_cluster_logdm(Ws ws)
+// One wavefront per cluster: every lane sums the tiles' B and counts in tile
+// order, lane j evaluates the j-th log-gamma term, and lane 0 adds them to the
+// tiles' compensated sums in a fixed order.
+__global__ void __launch_bounds__(64) k_sm_finish(Ws ws, int mode, int T)
 {
     const int K = ws.st->K;
-    const int G = ws.G;
+    const int lane = threadIdx.x;
     for (int k = blockIdx.x; k < K; k += gridDim.x) {
-        const unsigned long long* s0 = ws.ssub + (int64_t)(2 * k) * G;
-        const unsigned long long* s1 = s0 + G;
-        SmRed r;
-        r.a = r.b = 0;
-        r.beta = 0.0;
-        for (int u = threadIdx.x; u < G; u += kSmThreads) {
-            const double bu = ws.beta[u];
-            const long long v = (long long)(s0[u] + s1[u]);
-            r.beta += bu;
-            r.a += v;
-            r.cs.add(rising(bu, ws.lgbeta[u], v));
+        if (mode != 2 && !split_eligible(ws, k, mode)) {
+            if (lane == 0) ws.sm_logr[k] = __builtin_nan("");
+            continue;
         }
-        r = block_reduce<kSmThreads>(r);
-        if (threadIdx.x == 0) {
-            CSum tot = r.cs;
-            tot.add(lgamma(r.beta) - lgamma(r.beta + (double)r.a));
-            ws.dm_k[k] = tot.value();
+        const SmPart* part = ws.sm_part + (int64_t)k * T;
+        double B = 0.0;
+        long long a = 0, b = 0;
+        for (int q = 0; q < T; ++q) {
+            B += part[q].beta;
+            a += part[q].a;
+            b += part[q].b;
+        }
+        const unsigned long long n0 = ws.nsub[2 * k], n1 = ws.nsub[2 * k + 1];
+        // the argument per lane, then one log-gamma call shared by all lanes
+        // (a different call per lane would run one after another)
+        double arg = 1.0;
+        switch (lane) {
+        case 0: arg = B; break;
+        case 1: arg = B + (double)a; break;
+        case 2: arg = B + (double)b; break;
+        case 3: arg = B + (double)(a + b); break;
+        case 4: arg = (double)n0; break;
+        case 5: arg = (double)n1; break;
+        case 6: arg = (double)(n0 + n1); break;
+        default: break;
+        }
+        double x = lgamma(arg);
+        if (lane == 7) x = log(ws.alpha);
+        double lg[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) lg[j] = __shfl(x, j);
+        if (lane == 0) {
+            CSum tot;
+            for (int q = 0; q < T; ++q) {
+                CSum y;
+                y.s = part[q].s;
+                y.c = part[q].c;
+                tot.merge(y);
+            }
+            tot.add(lg[0] - lg[1]);
+            if (mode == 2) {
+                ws.dm_k[k] = tot.value();
+            } else {
+                tot.add(lg[0] - lg[2]);
+                tot.add(-(lg[0] - lg[3]));
+                tot.add(lg[7] + lg[4] + lg[5] - lg[6]);
+                if (mode == 1) tot.add((double)(n0 + n1 - 2) * log(2.0));    // chain B, Section 2.4
+                else if (ws.flags & kFlagSplitQ) tot.add(-ws.qsub[k]);      // proposal term, Section 2.3
+                ws.sm_logr[k] = tot.value();
+            }
         }
     }
+}
+
+static void launch_sm_pair(const Ws& ws, int mode, hipStream_t s)
+{
+    const int T = sm_tiles(ws.G);
+    const int kb = ws.k_max < 1024 ? ws.k_max : 1024;
+    hipLaunchKernelGGL(k_sm_tiles, dim3((unsigned)kb, (unsigned)T), dim3(kSmThreads), 0, s, ws, mode);
+    hipLaunchKernelGGL(k_sm_finish, dim3((unsigned)kb), dim3(64), 0, s, ws, mode, T);
 }
 
 __device__ inline void pair_of(long long p, int* k1, int* k2)
@@ -209,18 +266,34 @@ __global__ void __launch_bounds__(kMergeThreads) k_merge_ratios(Ws ws)
             r.cs.add(rising(bu, ws.lgbeta[u], v));
         }
         r = block_reduce<kMergeThreads>(r);
-        if (threadIdx.x == 0) {
+        if (threadIdx.x < 64) {     // wavefront 0: one log-gamma term per lane, as in k_sm_finish
+            const int lane = threadIdx.x;
             const double n1 = (double)(ws.nsub[2 * k1] + ws.nsub[2 * k1 + 1]);
             const double n2 = (double)(ws.nsub[2 * k2] + ws.nsub[2 * k2 + 1]);
-            CSum split;   // log R of splitting the union into k1 and k2
-            split.add(log(ws.alpha) + lgamma(n1) + lgamma(n2) - lgamma(n1 + n2));
-            split.add(ws.dm_k[k1]);
-            split.add(ws.dm_k[k2]);
-            CSum dm12 = r.cs;
-            dm12.add(lgamma(r.beta) - lgamma(r.beta + (double)r.a));
-            split.add(-dm12.s);
-            split.add(-dm12.c);
-            ws.sm_logr[p] = -split.value() + (n1 + n2 - 2.0) * log(0.5);
+            double arg = 1.0;
+            switch (lane) {
+            case 0: arg = n1; break;
+            case 1: arg = n2; break;
+            case 2: arg = n1 + n2; break;
+            case 3: arg = r.beta; break;
+            case 4: arg = r.beta + (double)r.a; break;
+            default: break;
+            }
+            const double x = lgamma(arg);
+            double lg[5];
+#pragma unroll
+            for (int j = 0; j < 5; ++j) lg[j] = __shfl(x, j);
+            if (lane == 0) {
+                CSum split;   // log R of splitting the union into k1 and k2
+                split.add(log(ws.alpha) + lg[0] + lg[1] - lg[2]);
+                split.add(ws.dm_k[k1]);
+                split.add(ws.dm_k[k2]);
+                CSum dm12 = r.cs;
+                dm12.add(lg[3] - lg[4]);
+                split.add(-dm12.s);
+                split.add(-dm12.c);
+                ws.sm_logr[p] = -split.value() + (n1 + n2 - 2.0) * log(0.5);
+            }
         }
     }
 }
@@ -246,13 +319,12 @@ __global__ void __launch_bounds__(kQThreads) k_split_q(Ws ws, const int32_t* __r
 
 void launch_split_ratios(const Ws& ws, const int32_t* c, hipStream_t s)
 {
-    const int blocks = ws.k_max < 1024 ? ws.k_max : 1024;
     if (ws.flags & kFlagSplitQ) {
         hipMemsetAsync(ws.qsub, 0, sizeof(double) * (size_t)ws.k_max, s);
         hipLaunchKernelGGL(k_split_q, dim3(256), dim3(kQThreads), sizeof(double) * (size_t)ws.k_max, s, ws, c);
     }
     launch_lgamma_beta(ws, s);
-    hipLaunchKernelGGL(k_split_ratios, dim3(blocks), dim3(kSmThreads), 0, s, ws, 0);
+    launch_sm_pair(ws, 0, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -307,17 +379,15 @@ void launch_random_split(const Ws& ws, const int32_t* c, uint8_t* cs, uint32_t s
     halves.nsub = ws.rnsub;
     launch_stats(halves, c, ws.rbits, s);
     launch_lgamma_beta(ws, s);
-    const int blocks = ws.k_max < 1024 ? ws.k_max : 1024;
-    hipLaunchKernelGGL(k_split_ratios, dim3(blocks), dim3(kSmThreads), 0, s, halves, 1);
+    launch_sm_pair(halves, 1, s);
     launch_sm_decide(halves, 0, step, s);
     hipLaunchKernelGGL(k_rsplit_apply, dim3((unsigned)cb), dim3(256), 0, s, ws, c, cs);
 }
 
 void launch_merge_ratios(const Ws& ws, hipStream_t s)
 {
-    const int blocks = ws.k_max < 1024 ? ws.k_max : 1024;
     launch_lgamma_beta(ws, s);
-    hipLaunchKernelGGL(k_cluster_logdm, dim3(blocks), dim3(kSmThreads), 0, s, ws);
+    launch_sm_pair(ws, 2, s);
     const long long np = (long long)ws.k_max * (ws.k_max - 1) / 2;
     const int mb = np < 4096 ? (int)(np > 0 ? np : 1) : 4096;
     hipLaunchKernelGGL(k_merge_ratios, dim3(mb), dim3(kMergeThreads), 0, s, ws);

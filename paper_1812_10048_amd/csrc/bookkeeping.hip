@@ -174,12 +174,37 @@ void launch_init_labels(const Ws& ws, int32_t k_init, int32_t* c, uint8_t* cs, h
 // the cells of one cluster together.
 // ---------------------------------------------------------------------------
 constexpr int kSortThreads = 1024;
-constexpr int kSortCellsPerBlock = 2048;
+constexpr int kSortPerThread = 8;
+constexpr int kSortCellsPerBlock = kSortThreads * kSortPerThread;
 constexpr int kStatThreads = 256;
 constexpr int kStatCells = 2048;
 constexpr int kStatMaxGenes = 16384;
 
 __device__ inline int sort_group(int32_t k, uint8_t r, int by_cluster) { return by_cluster ? k : 2 * k + (r & 1); }
+
+// A thread's cells are i = b0 + j kSortThreads + t, j < kSortPerThread; their
+// labels are loaded together, one round trip per pass.
+struct SortCells {
+    int32_t g[kSortPerThread];      // group of each cell, -1 if none
+};
+
+__device__ inline SortCells load_groups(const Ws& ws, const int32_t* __restrict__ c, const uint8_t* __restrict__ cs,
+                                        int by_cluster, int64_t b0, int64_t b1)
+{
+    SortCells sc;
+    int32_t k[kSortPerThread];
+    uint8_t r[kSortPerThread];
+#pragma unroll
+    for (int j = 0; j < kSortPerThread; ++j) {
+        const int64_t i = b0 + (int64_t)j * kSortThreads + threadIdx.x;
+        k[j] = i < b1 ? c[i] : -1;
+        r[j] = (i < b1 && !by_cluster) ? cs[i] : 0;
+    }
+#pragma unroll
+    for (int j = 0; j < kSortPerThread; ++j)
+        sc.g[j] = (k[j] >= 0 && k[j] < ws.k_max) ? sort_group(k[j], r[j], by_cluster) : -1;
+    return sc;
+}
 
 __global__ void __launch_bounds__(kSortThreads) k_group_count(Ws ws, const int32_t* __restrict__ c,
                                                               const uint8_t* __restrict__ cs, int by_cluster)
@@ -187,13 +212,13 @@ __global__ void __launch_bounds__(kSortThreads) k_group_count(Ws ws, const int32
     extern __shared__ uint32_t hist[];   // [groups]
     const int ng = by_cluster ? ws.k_max : 2 * ws.k_max;
     for (int q = threadIdx.x; q < ng; q += kSortThreads) hist[q] = 0;
-    __syncthreads();
     const int64_t b0 = (int64_t)blockIdx.x * kSortCellsPerBlock;
     const int64_t b1 = min(ws.N, b0 + kSortCellsPerBlock);
-    for (int64_t i = b0 + threadIdx.x; i < b1; i += kSortThreads) {
-        const int32_t k = c[i];
-        if (k >= 0 && k < ws.k_max) atomicAdd(&hist[sort_group(k, cs[i], by_cluster)], 1u);
-    }
+    const SortCells sc = load_groups(ws, c, cs, by_cluster, b0, b1);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kSortPerThread; ++j)
+        if (sc.g[j] >= 0) atomicAdd(&hist[sc.g[j]], 1u);
     __syncthreads();
     for (int q = threadIdx.x; q < ng; q += kSortThreads)
         if (hist[q]) atomicAdd(&ws.grp_cnt[q], (int32_t)hist[q]);
@@ -235,31 +260,37 @@ __global__ void __launch_bounds__(kSortThreads) k_group_scatter(Ws ws, const int
     uint32_t* cnt = lds_u;
     uint32_t* base = lds_u + ng;
     for (int q = threadIdx.x; q < ng; q += kSortThreads) cnt[q] = 0;
-    __syncthreads();
     const int64_t b0 = (int64_t)blockIdx.x * kSortCellsPerBlock;
     const int64_t b1 = min(ws.N, b0 + kSortCellsPerBlock);
+    const SortCells sc = load_groups(ws, c, cs, by_cluster, b0, b1);
+    __syncthreads();
     // pass 1: block-local counts; pass 2: one reservation per group; pass 3: ranks
-    for (int64_t i = b0 + threadIdx.x; i < b1; i += kSortThreads) {
-        const int32_t k = c[i];
-        if (k >= 0 && k < ws.k_max) atomicAdd(&cnt[sort_group(k, cs[i], by_cluster)], 1u);
-    }
+#pragma unroll
+    for (int j = 0; j < kSortPerThread; ++j)
+        if (sc.g[j] >= 0) atomicAdd(&cnt[sc.g[j]], 1u);
     __syncthreads();
     for (int q = threadIdx.x; q < ng; q += kSortThreads) {
         base[q] = cnt[q] ? (uint32_t)(ws.grp_off[q] + atomicAdd(&ws.grp_cur[q], (int32_t)cnt[q])) : 0u;
         cnt[q] = 0;
     }
     __syncthreads();
-    for (int64_t i = b0 + threadIdx.x; i < b1; i += kSortThreads) {
-        const int32_t k = c[i];
-        if (k < 0 || k >= ws.k_max) continue;
-        const int q = sort_group(k, cs[i], by_cluster);
-        const uint32_t pos = base[q] + atomicAdd(&cnt[q], 1u);
-        if (pos < (uint32_t)ws.N) {
-            ws.perm[pos] = (int32_t)i;
+    uint32_t pos[kSortPerThread];
+    int64_t r0[kSortPerThread], r1[kSortPerThread];
+#pragma unroll
+    for (int j = 0; j < kSortPerThread; ++j) {
+        const int64_t i = b0 + (int64_t)j * kSortThreads + threadIdx.x;
+        pos[j] = sc.g[j] >= 0 ? base[sc.g[j]] + atomicAdd(&cnt[sc.g[j]], 1u) : 0xFFFFFFFFu;
+        r0[j] = sc.g[j] >= 0 ? ws.roff[i] : 0;
+        r1[j] = sc.g[j] >= 0 ? ws.roff[i + 1] : 0;
+    }
+#pragma unroll
+    for (int j = 0; j < kSortPerThread; ++j) {
+        const int64_t i = b0 + (int64_t)j * kSortThreads + threadIdx.x;
+        if (pos[j] < (uint32_t)ws.N) {
+            ws.perm[pos[j]] = (int32_t)i;
             // the row of the sorted cell, so that kernels walking the sorted
             // order reach it with one load
-            const int64_t r0 = ws.roff[i];
-            ws.srow[pos] = make_uint4((uint32_t)i, (uint32_t)r0, (uint32_t)(r0 >> 32), (uint32_t)(ws.roff[i + 1] - r0));
+            ws.srow[pos[j]] = make_uint4((uint32_t)i, (uint32_t)r0[j], (uint32_t)(r0[j] >> 32), (uint32_t)(r1[j] - r0[j]));
         }
     }
 }

@@ -8,9 +8,11 @@
 // LDS: the draw compares the two sub-cluster scores, and their difference is
 // sum_u x_i^u delta_u, one product per entry.  Each wavefront takes 64 sorted
 // cells at a time: one lane per cell first forms the cell's Philox words and
-// FP32 Gumbel noise difference, then 16 lanes per cell, four cells at a time,
-// read the rows with 16-byte loads, form the FP64 difference (fixed-order
-// reduction over the 16 lanes), draw cbar_i by Gumbel-max with weights
+// FP32 Gumbel noise difference, then 8 lanes per cell, eight cells at a time,
+// read the rows with 16-byte loads (ten per lane in flight: eight rows of up to
+// 320 entries per round trip; the row reads bound the kernel, so the more rows
+// in flight the better), form the FP64 difference (fixed-order reduction over
+// the 8 lanes), draw cbar_i by Gumbel-max with weights
 // nbar_{k,r} less the cell's own old membership, and add the row's counts to
 // the LDS histogram of (k, cbar_i).  The two scores themselves are formed only
 // for the debug dump.  The histograms are flushed with one 64-bit atomic per
@@ -24,12 +26,13 @@ constexpr int kSubThreads = 256;
 constexpr int kSubCellsMin = 256;       // sorted cells per workgroup, at least
 constexpr int kSubStageGenes = 4096;     // delta staged in LDS up to this G
 constexpr int kSubHistGenes = 8192;      // LDS histograms up to this G
-constexpr int kSubLoads = 5;             // 16-byte loads per lane in flight: the first 320 entries of a row
+constexpr int kSubLanes = 8;             // lanes per cell: eight cells of a wavefront read their rows together
+constexpr int kSubLoads = 10;            // 16-byte loads per lane in flight: the first 320 entries of a row
 
-// sum over the 16 lanes of a group, in a fixed order
+// sum over the kSubLanes lanes of a cell, in a fixed order
 __device__ inline double group_sum(double v)
 {
-    for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, 16);
+    for (int o = kSubLanes / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kSubLanes);
     return v;
 }
 
@@ -38,7 +41,7 @@ __device__ inline double group_sum(double v)
 // proposal term.  The flags are template arguments so that the loop over a
 // row's entries is straight-line code.
 template <bool STAGE, bool LHIST, bool DUMP, bool SPLITQ>
-__global__ void __launch_bounds__(kSubThreads) __attribute__((amdgpu_waves_per_eu(4))) k_sub_stats(Ws ws, SubArgs a)
+__global__ void __launch_bounds__(kSubThreads) __attribute__((amdgpu_waves_per_eu(3))) k_sub_stats(Ws ws, SubArgs a)
 {
     extern __shared__ __attribute__((aligned(16))) char lds[];
     const int G = ws.G;
@@ -84,10 +87,10 @@ __global__ void __launch_bounds__(kSubThreads) __attribute__((amdgpu_waves_per_e
         // Each wavefront takes 64 sorted cells at a time.  First one lane per
         // cell forms what depends on the cell alone (its row descriptor, its
         // old membership, the Philox words and the FP32 noise difference);
-        // then 16 lanes per cell, four cells at a time, read the rows, and
-        // the per-cell values come by lane shuffles.
-        const int grp = lane >> 4;
-        const int l16 = lane & 15;
+        // then kSubLanes lanes per cell, 64 / kSubLanes cells at a time, read
+        // the rows, and the per-cell values come by lane shuffles.
+        const int grp = lane / kSubLanes;
+        const int lg = lane % kSubLanes;
         for (int64_t base = r0 + 64 * wave; base < r1; base += 64 * (kSubThreads / 64)) {
             const int ncell = (int)min((int64_t)64, r1 - base);
             uint4 dsc = make_uint4(0, 0, 0, 0);
@@ -104,8 +107,8 @@ __global__ void __launch_bounds__(kSubThreads) __attribute__((amdgpu_waves_per_e
                     code = a.c_old[i] == k ? 1 + (a.cs_old[i] & 1) : 0;
                 }
             }
-            for (int c4 = 0; c4 < ncell; c4 += 4) {
-                const int src = c4 + grp;
+            for (int c0 = 0; c0 < ncell; c0 += 64 / kSubLanes) {
+                const int src = c0 + grp;
                 const bool live = src < ncell;
                 const int64_t i = (int64_t)(uint32_t)__shfl((int)dsc.x, src);
                 const int64_t b = (int64_t)(((uint64_t)(uint32_t)__shfl((int)dsc.z, src) << 32) |
@@ -122,7 +125,7 @@ __global__ void __launch_bounds__(kSubThreads) __attribute__((amdgpu_waves_per_e
                 uint4 v[kSubLoads];
 #pragma unroll
                 for (int r = 0; r < kSubLoads; ++r) {
-                    const int64_t q = b + 4 * l16 + 64 * r;
+                    const int64_t q = b + 4 * lg + 4 * kSubLanes * r;
                     v[r] = q < e ? *reinterpret_cast<const uint4*>(ws.ent + q) : make_uint4(kPadEntry, kPadEntry, kPadEntry, kPadEntry);
                 }
                 auto dot = [&](const uint4& u) {
@@ -150,7 +153,7 @@ __global__ void __launch_bounds__(kSubThreads) __attribute__((amdgpu_waves_per_e
                 } else {
 #pragma unroll
                     for (int r = 0; r < kSubLoads; ++r) dot(v[r]);
-                    for (int64_t q = b + 4 * l16 + 64 * kSubLoads; q < e; q += 64) dot(*reinterpret_cast<const uint4*>(ws.ent + q));
+                    for (int64_t q = b + 4 * lg + 4 * kSubLanes * kSubLoads; q < e; q += 4 * kSubLanes) dot(*reinterpret_cast<const uint4*>(ws.ent + q));
                     df = group_sum(df);
                     if (dump) {
                         s0 = group_sum(s0);
@@ -194,8 +197,8 @@ __global__ void __launch_bounds__(kSubThreads) __attribute__((amdgpu_waves_per_e
                 };
 #pragma unroll
                 for (int r = 0; r < kSubLoads; ++r) add(v[r]);
-                for (int64_t q = b + 4 * l16 + 64 * kSubLoads; q < e; q += 64) add(*reinterpret_cast<const uint4*>(ws.ent + q));
-                if (l16 == 0 && live) {
+                for (int64_t q = b + 4 * lg + 4 * kSubLanes * kSubLoads; q < e; q += 4 * kSubLanes) add(*reinterpret_cast<const uint4*>(ws.ent + q));
+                if (lg == 0 && live) {
                     atomicAdd(&ncnt[sub], 1u);
                     a.cs_new[i] = (uint8_t)sub;
                     if constexpr (SPLITQ) {

@@ -323,6 +323,7 @@ dpmm_status dpmm_init(const dpmm_csr* csr, const dpmm_params* params, void* work
     else
         launch_fill(ws.beta, ws.G, params->beta, ctx->stream);
     if (he != hipSuccess) return cleanup(fail(DPMM_ERR_HIP, "beta copy: %s", hipGetErrorString(he)));
+    launch_lgamma_beta(ws, ctx->stream);
     launch_init_labels(ws, params->k_init, ctx->c[0], ctx->cs[0], ctx->stream);
     he = hipGetLastError();
     if (he != hipSuccess) return cleanup(fail(DPMM_ERR_HIP, "init launch: %s", hipGetErrorString(he)));
@@ -573,6 +574,8 @@ dpmm_status dpmm_set_beta(dpmm_ctx* ctx, const double* beta_dev)
     dpmm_status s = set_device(ctx);
     if (s != DPMM_OK) return s;
     HIP_TRY(hipMemcpyAsync(ctx->ws.beta, beta_dev, 8 * (size_t)ctx->G, hipMemcpyDeviceToDevice, ctx->stream));
+    launch_lgamma_beta(ctx->ws, ctx->stream);
+    HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     return DPMM_OK;
 }

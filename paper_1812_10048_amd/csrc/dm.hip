@@ -172,6 +172,7 @@ void launch_eb_update(const Ws& ws, hipStream_t s)
     hipLaunchKernelGGL(k_eb_denominator, dim3(kb), dim3(kDmThreads), 0, s, ws);
     const int blocks = (ws.G + kDmThreads - 1) / kDmThreads;
     hipLaunchKernelGGL(k_eb_update, dim3(blocks), dim3(kDmThreads), 0, s, ws);
+    launch_lgamma_beta(ws, s);
 }
 
 __global__ void k_fill(double* p, int64_t n, double v)

@@ -181,7 +181,7 @@ struct Ws {
     unsigned long long* nsub;   // [2 k_max]
     unsigned long long* ssub;   // [2 k_max G]   (k, r, u) at (2k + r) G + u
     double* beta;          // [G]
-    double* lgbeta;        // [G] lgamma(beta_u), refreshed before each split/merge pass
+    double* lgbeta;        // [G] lgamma(beta_u), refreshed wherever beta is written (init, set_beta, EB update)
     double* logpi;         // [k_max]
     double* lt64;          // [3 k_max G]: rows k, then k_max + 2k + r
     float* lc32;           // [G][kpad] cluster log theta, gene-major

@@ -65,6 +65,7 @@ hipError_t configure_assign_bf16();
 void launch_refine(const Ws& ws, const AssignArgs& a, hipStream_t s);
 
 // splitmerge.hip
+void launch_lgamma_beta(const Ws& ws, hipStream_t s);   // lgbeta = lgamma(beta), wherever beta changes
 void launch_split_ratios(const Ws& ws, const int32_t* c, hipStream_t s);
 void launch_random_split(const Ws& ws, const int32_t* c, uint8_t* cs, uint32_t step, hipStream_t s);
 void launch_merge_ratios(const Ws& ws, hipStream_t s);

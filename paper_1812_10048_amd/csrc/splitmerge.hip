@@ -103,7 +103,7 @@ __global__ void k_lgamma_beta(Ws ws)
     if (u < ws.G) ws.lgbeta[u] = lgamma(ws.beta[u]);
 }
 
-static void launch_lgamma_beta(const Ws& ws, hipStream_t s)
+void launch_lgamma_beta(const Ws& ws, hipStream_t s)
 {
     hipLaunchKernelGGL(k_lgamma_beta, dim3((unsigned)((ws.G + 255) / 256)), dim3(256), 0, s, ws);
 }
@@ -323,7 +323,6 @@ void launch_split_ratios(const Ws& ws, const int32_t* c, hipStream_t s)
         hipMemsetAsync(ws.qsub, 0, sizeof(double) * (size_t)ws.k_max, s);
         hipLaunchKernelGGL(k_split_q, dim3(256), dim3(kQThreads), sizeof(double) * (size_t)ws.k_max, s, ws, c);
     }
-    launch_lgamma_beta(ws, s);
     launch_sm_pair(ws, 0, s);
 }
 
@@ -378,7 +377,6 @@ void launch_random_split(const Ws& ws, const int32_t* c, uint8_t* cs, uint32_t s
     halves.ssub = ws.rssub;
     halves.nsub = ws.rnsub;
     launch_stats(halves, c, ws.rbits, s);
-    launch_lgamma_beta(ws, s);
     launch_sm_pair(halves, 1, s);
     launch_sm_decide(halves, 0, step, s);
     hipLaunchKernelGGL(k_rsplit_apply, dim3((unsigned)cb), dim3(256), 0, s, ws, c, cs);
@@ -386,7 +384,6 @@ void launch_random_split(const Ws& ws, const int32_t* c, uint8_t* cs, uint32_t s
 
 void launch_merge_ratios(const Ws& ws, hipStream_t s)
 {
-    launch_lgamma_beta(ws, s);
     launch_sm_pair(ws, 2, s);
     const long long np = (long long)ws.k_max * (ws.k_max - 1) / 2;
     const int mb = np < 4096 ? (int)(np > 0 ? np : 1) : 4096;

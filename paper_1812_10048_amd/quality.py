@@ -9,7 +9,10 @@ iterations.
 
     python -m paper_1812_10048_amd.quality --config c2 --iters 200 --alpha 0.1 0.5 1
 
-prints one JSON line per scored iteration.
+prints one JSON line per scored iteration.  ``--lib-mean`` reruns the recipe at
+other mean library sizes (Section 4 relates clustering quality to sequencing
+depth), and ``--conc`` changes the Dirichlet concentration of the true
+profiles (larger is closer clusters, a harder problem).
 """
 from __future__ import annotations
 
@@ -67,8 +70,26 @@ def hubert_index(a, b) -> float:
     return 2.0 * rand_index(a, b) - 1.0
 
 
+def recipe_variant(config: str, lib_mean: float | None = None, conc: float | None = None):
+    """The named recipe with its mean library size and/or profile
+    concentration replaced, named after the change."""
+    import dataclasses
+
+    from . import synth
+
+    r = synth.RECIPES[config]
+    name = r.name
+    if lib_mean is not None:
+        r = dataclasses.replace(r, lib_mean=float(lib_mean))
+        name += f"-lib{lib_mean:g}"
+    if conc is not None:
+        r = dataclasses.replace(r, conc=float(conc))
+        name += f"-conc{conc:g}"
+    return dataclasses.replace(r, name=name)
+
+
 def run(config: str, iters: int, alpha: float, precision: str, seed: int, every: int, k_max: int,
-        split_q: bool, new_cluster: bool, data=None):
+        split_q: bool, new_cluster: bool, data=None, extra=None):
     import torch
 
     from . import synth
@@ -87,7 +108,7 @@ def run(config: str, iters: int, alpha: float, precision: str, seed: int, every:
             el = time.perf_counter() - t0
             c, _ = s.labels()
             c = c.cpu().numpy()
-            rec = dict(config=config, alpha=alpha, precision=precision, iter=it, K=int(s.stats()["K"]),
+            rec = dict(config=config, **(extra or {}), alpha=alpha, precision=precision, iter=it, K=int(s.stats()["K"]),
                        ari=adjusted_rand_index(d.z, c), ri=rand_index(d.z, c), hi=hubert_index(d.z, c),
                        seconds=round(el, 3))
             out.append(rec)
@@ -108,11 +129,17 @@ def main() -> None:
     ap.add_argument("--k-max", type=int, default=128)
     ap.add_argument("--split-q", action="store_true")
     ap.add_argument("--new-cluster", action="store_true")
+    ap.add_argument("--lib-mean", type=float, nargs="+", default=None)
+    ap.add_argument("--conc", type=float, default=None)
     a = ap.parse_args()
     from . import synth
-    data = synth.generate(a.config, seed=a.seed, device="cuda")
-    for alpha in a.alpha:
-        run(a.config, a.iters, alpha, a.precision, a.seed, a.every, a.k_max, a.split_q, a.new_cluster, data)
+    for lib in (a.lib_mean or [None]):
+        rec = recipe_variant(a.config, lib, a.conc)
+        data = synth.generate(rec, seed=a.seed, device="cuda")
+        extra = dict(lib_mean=rec.lib_mean, conc=rec.conc, zeros=round(data.zero_fraction(), 4))
+        for alpha in a.alpha:
+            run(rec.name, a.iters, alpha, a.precision, a.seed, a.every, a.k_max, a.split_q, a.new_cluster, data,
+                extra)
 
 
 if __name__ == "__main__":

@@ -29,3 +29,22 @@ def test_hand_counted_example_and_invariances():
     perm = rng.permutation(6)
     assert quality.adjusted_rand_index(z, perm[z] + 100) == 1.0
     assert quality.rand_index(z, z) == 1.0
+
+
+def test_recipe_variants_change_only_the_named_field():
+    import dataclasses
+
+    from paper_1812_10048_amd import synth
+    from paper_1812_10048_amd.quality import recipe_variant
+
+    base = synth.RECIPES["c2"]
+    r = recipe_variant("c2", lib_mean=250)
+    assert (r.lib_mean, r.conc, r.n_cells, r.sizes) == (250.0, base.conc, base.n_cells, base.sizes)
+    assert r.name == "c2-lib250"
+    r = recipe_variant("c2", conc=0.5)
+    assert (r.lib_mean, r.conc, r.name) == (base.lib_mean, 0.5, "c2-conc0.5")
+    assert recipe_variant("c1") == synth.RECIPES["c1"]
+    # a shallower library gives sparser rows at the same seed
+    small = synth.generate(dataclasses.replace(synth.RECIPES["c1"], lib_mean=100.0), seed=0, n_cells=300)
+    deep = synth.generate(synth.RECIPES["c1"], seed=0, n_cells=300)
+    assert small.nnz < deep.nnz

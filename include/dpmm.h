@@ -38,7 +38,7 @@ typedef enum dpmm_status {
     DPMM_ERR_HIP = -2,          /* a HIP runtime call failed; message has its text  */
     DPMM_ERR_NOMEM = -3,        /* the workspace is smaller than required           */
     DPMM_ERR_STATE = -4,        /* context not usable for this call                 */
-    DPMM_ERR_UNSUPPORTED = -5,  /* valid input outside what this build supports     */
+    DPMM_ERR_UNSUPPORTED = -5,  /* valid input outside what the library supports   */
     DPMM_ERR_DATA = -6          /* the CSR content failed validation on the device  */
 } dpmm_status;
 

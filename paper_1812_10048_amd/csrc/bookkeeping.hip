@@ -186,23 +186,29 @@ __device__ inline int sort_group(int32_t k, uint8_t r, int by_cluster) { return 
 // labels are loaded together, one round trip per pass.
 struct SortCells {
     int32_t g[kSortPerThread];      // group of each cell, -1 if none
+    uint32_t old[kSortPerThread];   // with c_prev: 1 + the old sub-label if the cell stays in its cluster, else 0
 };
 
 __device__ inline SortCells load_groups(const Ws& ws, const int32_t* __restrict__ c, const uint8_t* __restrict__ cs,
-                                        int by_cluster, int64_t b0, int64_t b1)
+                                        int by_cluster, int64_t b0, int64_t b1,
+                                        const int32_t* __restrict__ c_prev = nullptr)
 {
     SortCells sc;
-    int32_t k[kSortPerThread];
+    int32_t k[kSortPerThread], kp[kSortPerThread];
     uint8_t r[kSortPerThread];
+    const bool want_old = c_prev && by_cluster;
 #pragma unroll
     for (int j = 0; j < kSortPerThread; ++j) {
         const int64_t i = b0 + (int64_t)j * kSortThreads + threadIdx.x;
         k[j] = i < b1 ? c[i] : -1;
-        r[j] = (i < b1 && !by_cluster) ? cs[i] : 0;
+        r[j] = (i < b1 && (!by_cluster || want_old)) ? cs[i] : 0;
+        kp[j] = (i < b1 && want_old) ? c_prev[i] : -1;
     }
 #pragma unroll
-    for (int j = 0; j < kSortPerThread; ++j)
+    for (int j = 0; j < kSortPerThread; ++j) {
         sc.g[j] = (k[j] >= 0 && k[j] < ws.k_max) ? sort_group(k[j], r[j], by_cluster) : -1;
+        sc.old[j] = (sc.g[j] >= 0 && want_old && kp[j] == k[j]) ? 1u + (r[j] & 1u) : 0u;
+    }
     return sc;
 }
 
@@ -253,7 +259,8 @@ __global__ void __launch_bounds__(kSortThreads) k_group_scan(Ws ws, int by_clust
 }
 
 __global__ void __launch_bounds__(kSortThreads) k_group_scatter(Ws ws, const int32_t* __restrict__ c,
-                                                                const uint8_t* __restrict__ cs, int by_cluster)
+                                                                const uint8_t* __restrict__ cs, int by_cluster,
+                                                                const int32_t* __restrict__ c_prev)
 {
     extern __shared__ uint32_t lds_u[];      // [groups] counts, then [groups] bases
     const int ng = by_cluster ? ws.k_max : 2 * ws.k_max;
@@ -262,7 +269,7 @@ __global__ void __launch_bounds__(kSortThreads) k_group_scatter(Ws ws, const int
     for (int q = threadIdx.x; q < ng; q += kSortThreads) cnt[q] = 0;
     const int64_t b0 = (int64_t)blockIdx.x * kSortCellsPerBlock;
     const int64_t b1 = min(ws.N, b0 + kSortCellsPerBlock);
-    const SortCells sc = load_groups(ws, c, cs, by_cluster, b0, b1);
+    const SortCells sc = load_groups(ws, c, cs, by_cluster, b0, b1, c_prev);
     __syncthreads();
     // pass 1: block-local counts; pass 2: one reservation per group; pass 3: ranks
 #pragma unroll
@@ -279,9 +286,10 @@ __global__ void __launch_bounds__(kSortThreads) k_group_scatter(Ws ws, const int
 #pragma unroll
     for (int j = 0; j < kSortPerThread; ++j) {
         const int64_t i = b0 + (int64_t)j * kSortThreads + threadIdx.x;
-        pos[j] = sc.g[j] >= 0 ? base[sc.g[j]] + atomicAdd(&cnt[sc.g[j]], 1u) : 0xFFFFFFFFu;
-        r0[j] = sc.g[j] >= 0 ? ws.roff[i] : 0;
-        r1[j] = sc.g[j] >= 0 ? ws.roff[i + 1] : 0;
+        const bool in = sc.g[j] >= 0;
+        pos[j] = in ? base[sc.g[j]] + atomicAdd(&cnt[sc.g[j]], 1u) : 0xFFFFFFFFu;
+        r0[j] = in ? ws.roff[i] : 0;
+        r1[j] = in ? ws.roff[i + 1] : 0;
     }
 #pragma unroll
     for (int j = 0; j < kSortPerThread; ++j) {
@@ -289,8 +297,10 @@ __global__ void __launch_bounds__(kSortThreads) k_group_scatter(Ws ws, const int
         if (pos[j] < (uint32_t)ws.N) {
             ws.perm[pos[j]] = (int32_t)i;
             // the row of the sorted cell, so that kernels walking the sorted
-            // order reach it with one load
-            ws.srow[pos[j]] = make_uint4((uint32_t)i, (uint32_t)r0[j], (uint32_t)(r0[j] >> 32), (uint32_t)(r1[j] - r0[j]));
+            // order reach it (and the cell's old membership) with one load;
+            // a padded row holds at most 65536 entries, below bit 30
+            ws.srow[pos[j]] = make_uint4((uint32_t)i, (uint32_t)r0[j], (uint32_t)(r0[j] >> 32),
+                                         (uint32_t)(r1[j] - r0[j]) | (sc.old[j] << kSrowOldShift));
         }
     }
 }
@@ -365,7 +375,7 @@ __global__ void k_stats_atomic(Ws ws, const int32_t* __restrict__ c, const uint8
 }
 
 void launch_sort(const Ws& ws, const int32_t* c, const uint8_t* cs, int by_cluster, hipStream_t s,
-                 bool counts_cleared)
+                 bool counts_cleared, const int32_t* c_prev)
 {
     const int ng = by_cluster ? ws.k_max : 2 * ws.k_max;
     if (!counts_cleared) hipMemsetAsync(ws.grp_cnt, 0, sizeof(int32_t) * (size_t)ng, s);
@@ -374,7 +384,7 @@ void launch_sort(const Ws& ws, const int32_t* c, const uint8_t* cs, int by_clust
                        by_cluster);
     hipLaunchKernelGGL(k_group_scan, dim3(1), dim3(kSortThreads), 0, s, ws, by_cluster);
     hipLaunchKernelGGL(k_group_scatter, dim3(sb), dim3(kSortThreads), 2 * sizeof(uint32_t) * (size_t)ng, s, ws, c,
-                       cs, by_cluster);
+                       cs, by_cluster, c_prev);
 }
 
 void launch_stats(const Ws& ws, const int32_t* c, const uint8_t* cs, hipStream_t s)

@@ -148,6 +148,11 @@ struct RowCursor {
 };
 #endif
 
+// Top bits of srow.w after a sort by new cluster: 1 + the cell's sub-label
+// before the sweep if it was already in that cluster, else 0.
+constexpr int kSrowOldShift = 30;
+constexpr uint32_t kSrowLenMask = (1u << kSrowOldShift) - 1u;
+
 // Genes per workgroup of the parameter redraw, and the tiles of a row.
 constexpr int kRedrawGenes = 256;
 __host__ __device__ inline int redraw_tiles(int G) { return (G + kRedrawGenes - 1) / kRedrawGenes; }
@@ -190,7 +195,7 @@ struct Ws {
     uint16_t* llo;
     uint32_t* refine;      // [N] queued cells with flags
     int32_t* perm;         // [N] cells sorted by group 2k + r (processing order of a sweep)
-    uint4* srow;           // [N] per sorted position: (cell, row offset lo, hi, row length)
+    uint4* srow;           // [N] per sorted position: (cell, row offset lo, hi, row length | old << kSrowOldShift)
     int32_t* grp_cnt;      // [2 k_max] group sizes
     int32_t* grp_off;      // [2 k_max + 1] group offsets in perm
     int32_t* grp_cur;      // [2 k_max] scatter cursors

@@ -12,8 +12,10 @@ void launch_pack(const int64_t* row_ptr, const int32_t* col, const int32_t* val,
                  int64_t* roff, int64_t* tile_sums, uint32_t* ent, DevState* st, hipStream_t s);
 void launch_init_labels(const Ws& ws, int32_t k_init, int32_t* c, uint8_t* cs, hipStream_t s);
 void launch_stats(const Ws& ws, const int32_t* c, const uint8_t* cs, hipStream_t s);
+// c_prev (by cluster only, may be null): the labels before the sweep, whose
+// membership of the cell's new cluster goes into the top bits of srow.w
 void launch_sort(const Ws& ws, const int32_t* c, const uint8_t* cs, int by_cluster, hipStream_t s,
-                 bool counts_cleared = false);
+                 bool counts_cleared = false, const int32_t* c_prev = nullptr);
 
 // layout.hip
 void launch_build_blocked(const Ws& ws, int64_t* tile_sums, hipStream_t s);

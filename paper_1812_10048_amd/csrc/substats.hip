@@ -85,8 +85,9 @@ __global__ void __launch_bounds__(kSubThreads) __attribute__((amdgpu_waves_per_e
         auto logw = [](long long w) { return w > 0 ? log((double)w) : -INFINITY; };
         const double l0 = logw(n0), l0m = logw(n0 - 1), l1 = logw(n1), l1m = logw(n1 - 1);
         // Each wavefront takes 64 sorted cells at a time.  First one lane per
-        // cell forms what depends on the cell alone (its row descriptor, its
-        // old membership, the Philox words and the FP32 noise difference);
+        // cell forms what depends on the cell alone (its row descriptor, which
+        // also carries its old membership, so that one load serves; the
+        // Philox words and the FP32 noise difference);
         // then kSubLanes lanes per cell, 64 / kSubLanes cells at a time, read
         // the rows, and the per-cell values come by lane shuffles.
         const int grp = lane / kSubLanes;
@@ -104,7 +105,7 @@ __global__ void __launch_bounds__(kSubThreads) __attribute__((amdgpu_waves_per_e
                 } else {
                     const Words w = philox(ws.seed, i, 0u, a.step, kGumbelS, 0u);
                     nd = (-logf(-logf(unit23f(w.w[1])))) - (-logf(-logf(unit23f(w.w[0]))));
-                    code = a.c_old[i] == k ? 1 + (a.cs_old[i] & 1) : 0;
+                    code = (int)(dsc.w >> kSrowOldShift);      // written by the sort
                 }
             }
             for (int c0 = 0; c0 < ncell; c0 += 64 / kSubLanes) {
@@ -113,7 +114,7 @@ __global__ void __launch_bounds__(kSubThreads) __attribute__((amdgpu_waves_per_e
                 const int64_t i = (int64_t)(uint32_t)__shfl((int)dsc.x, src);
                 const int64_t b = (int64_t)(((uint64_t)(uint32_t)__shfl((int)dsc.z, src) << 32) |
                                             (uint32_t)__shfl((int)dsc.y, src));
-                const uint32_t len = (uint32_t)__shfl((int)dsc.w, src);
+                const uint32_t len = (uint32_t)__shfl((int)dsc.w, src) & kSrowLenMask;
                 const int64_t e = live ? b + len : b;
                 const float ndc = __shfl(nd, src);
                 const int cc = __shfl(code, src);
@@ -293,7 +294,7 @@ __global__ void k_sub_prep(Ws ws)
 void launch_sub_stats(const Ws& ws, const SubArgs& a, hipStream_t s)
 {
     hipLaunchKernelGGL(k_sub_prep, dim3(256), dim3(256), 0, s, ws);
-    launch_sort(ws, a.c_new, a.cs_old, 1, s, true);
+    launch_sort(ws, a.c_new, a.cs_old, 1, s, true, a.c_old);
     hipLaunchKernelGGL(sub_stats_kernel(ws.G, a.dbg != nullptr, ws.lpsub != nullptr), dim3((unsigned)((ws.N + ws.sub_cells - 1) / ws.sub_cells)), dim3(kSubThreads),
                        sub_stats_lds(ws.G), s, ws, a);
 }

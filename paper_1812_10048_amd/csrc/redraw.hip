@@ -170,11 +170,27 @@ __global__ void __launch_bounds__(kRedrawThreads) k_redraw_draw(Ws ws, uint32_t 
 // Pass 2, same grid: the row's log normaliser from its tiles' partials
 // (combined in tile order), then the tile's log theta in FP64 and in the
 // layouts the assignment kernels read.
+//
+// The whole grid also prepares the sweep's counts (saving a launch): the
+// counts at the start of the sweep, which feed eq. 8, move to nsub_prev, and
+// the new counts, statistics and sort counters start from zero.  Pass 1 has
+// read them; nothing else reads them before the sub-cluster pass rebuilds them.
 __global__ void __launch_bounds__(kRedrawThreads) k_redraw_norm(Ws ws, int write_split)
 {
     const int K = ws.st->K;
     // the re-score queue of the sweep that follows starts empty
     if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) ws.st->n_refine = 0;
+    {
+        const int64_t nt = (int64_t)gridDim.x * gridDim.y * blockDim.x;
+        const int64_t t0 = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * blockDim.x + threadIdx.x;
+        for (int64_t q = t0; q < 2 * (int64_t)ws.k_max; q += nt) {
+            ws.nsub_prev[q] = ws.nsub[q];
+            ws.nsub[q] = 0;
+        }
+        for (int64_t q = t0; q < ws.k_max; q += nt) ws.grp_cnt[q] = 0;
+        ulonglong2* sv = reinterpret_cast<ulonglong2*>(ws.ssub);      // 2 k_max G is even
+        for (int64_t q = t0; q < (int64_t)ws.k_max * ws.G; q += nt) sv[q] = make_ulonglong2(0ull, 0ull);
+    }
     const int row = blockIdx.x;
     const int tile = blockIdx.y;
     const int G = ws.G;

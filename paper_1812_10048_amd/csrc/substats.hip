@@ -275,25 +275,9 @@ hipError_t sub_stats_cells(int64_t N, int G, int32_t* cells)
     return hipSuccess;
 }
 
-// One launch instead of a copy and three fills: the counts at the start of the
-// sweep (which feed eq. 8) move to nsub_prev, and the new counts, statistics
-// and sort counters start from zero.
-__global__ void k_sub_prep(Ws ws)
-{
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t nt = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t q = t; q < 2 * (int64_t)ws.k_max; q += nt) {
-        ws.nsub_prev[q] = ws.nsub[q];
-        ws.nsub[q] = 0;
-    }
-    for (int64_t q = t; q < ws.k_max; q += nt) ws.grp_cnt[q] = 0;
-    ulonglong2* sv = reinterpret_cast<ulonglong2*>(ws.ssub);      // 2 k_max G is even
-    for (int64_t q = t; q < (int64_t)ws.k_max * ws.G; q += nt) sv[q] = make_ulonglong2(0ull, 0ull);
-}
-
 void launch_sub_stats(const Ws& ws, const SubArgs& a, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_sub_prep, dim3(256), dim3(256), 0, s, ws);
+    // the counts were cleared by the redraw of the same sweep (k_redraw_norm)
     launch_sort(ws, a.c_new, a.cs_old, 1, s, true, a.c_old);
     hipLaunchKernelGGL(sub_stats_kernel(ws.G, a.dbg != nullptr, ws.lpsub != nullptr), dim3((unsigned)((ws.N + ws.sub_cells - 1) / ws.sub_cells)), dim3(kSubThreads),
                        sub_stats_lds(ws.G), s, ws, a);

@@ -41,7 +41,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
 struct Layout {
     size_t ent, roff, tiles, c0, c1, cs0, cs1, st, reset, nsub, ssub, beta, lgbeta, logpi, lt64, lc32, ls32, lhi, llo,
-        lpsub, qsub, rbits, rssub, rnsub, refine, perm, srow, grp_cnt, grp_off, grp_cur, nsub_prev, blk_ent, blk_off, ovf_off, ovf_ent, relab_c, relab_s, sm_logr, sm_acc, mkey, mlist, dm_k, eb_tmp, rd_part, sm_part, total;
+        lgrise, lpsub, qsub, rbits, rssub, rnsub, refine, perm, srow, grp_cnt, grp_off, grp_cur, nsub_prev, blk_ent, blk_off, ovf_off, ovf_ent, relab_c, relab_s, sm_logr, sm_acc, mkey, mlist, dm_k, eb_tmp, rd_part, sm_part, total;
 };
 
 int32_t num_blocks(int64_t N) { return (int32_t)((N + kBlkCells - 1) / kBlkCells); }
@@ -79,6 +79,7 @@ Layout plan(int64_t N, int32_t G, int64_t nnz, int32_t k_max, int32_t precision,
     L.ssub = take(16 * (size_t)k_max * (size_t)G);
     L.beta = take(8 * (size_t)G);
     L.lgbeta = take(8 * (size_t)G);
+    L.lgrise = take(8 * (size_t)kRiseTab * (size_t)G);
     L.lpsub = take((flags & kFlagSplitQ) ? 8 * (size_t)N : 0);
     L.qsub = take(8 * (size_t)k_max);
     const bool rsplit = (flags & kFlagRandomSplit) != 0;
@@ -252,6 +253,7 @@ dpmm_status dpmm_init(const dpmm_csr* csr, const dpmm_params* params, void* work
     ws.ssub = (unsigned long long*)(base + L.ssub);
     ws.beta = (double*)(base + L.beta);
     ws.lgbeta = (double*)(base + L.lgbeta);
+    ws.lgrise = (double*)(base + L.lgrise);
     ws.flags = params->flags;
     ws.lpsub = (params->flags & kFlagSplitQ) ? (double*)(base + L.lpsub) : nullptr;
     ws.qsub = (double*)(base + L.qsub);

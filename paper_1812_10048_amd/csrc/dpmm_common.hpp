@@ -161,6 +161,9 @@ __host__ __device__ inline int redraw_tiles(int G) { return (G + kRedrawGenes - 
 // a cluster, and one tile's partial result (compensated sum s + c of the
 // per-gene terms, sum of beta_u, and the count sums of the two halves).
 constexpr int kSmGenes = 512;
+// Counts below kRiseTab take lgamma(beta_u + v) - lgamma(beta_u) from a
+// per-gene table (refreshed with lgbeta) instead of the recurrence.
+constexpr int kRiseTab = 16;
 __host__ __device__ inline int sm_tiles(int G) { return (G + kSmGenes - 1) / kSmGenes; }
 struct SmPart {
     double s, c, beta;
@@ -187,6 +190,7 @@ struct Ws {
     unsigned long long* ssub;   // [2 k_max G]   (k, r, u) at (2k + r) G + u
     double* beta;          // [G]
     double* lgbeta;        // [G] lgamma(beta_u), refreshed wherever beta is written (init, set_beta, EB update)
+    double* lgrise;        // [G][kRiseTab] lgamma(beta_u + v) - lgamma(beta_u), 0 at v = 0; refreshed with lgbeta
     double* logpi;         // [k_max]
     double* lt64;          // [3 k_max G]: rows k, then k_max + 2k + r
     float* lc32;           // [G][kpad] cluster log theta, gene-major

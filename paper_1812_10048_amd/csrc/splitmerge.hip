@@ -91,21 +91,33 @@ __device__ inline double lgamma_pos(double x)
     return (x - 0.5) * log(x) - x + 0.91893853320467274178 + series + shift;   // 0.5 log(2 pi)
 }
 
-// lgamma(beta + v) - lgamma(beta), zero for v = 0 (lgb = lgamma(beta))
-__device__ inline double rising(double beta, double lgb, long long v)
+// lgamma(beta_u + v) - lgamma(beta_u) of gene u, zero for v = 0
+// (lgb = lgamma(beta_u)); small counts come from the gene's table, which
+// holds the same expression evaluated by k_lgamma_beta
+__device__ inline double rising(const Ws& ws, int u, double beta, double lgb, long long v)
 {
-    return v ? lgamma_pos(beta + (double)v) - lgb : 0.0;
+    if ((unsigned long long)v < (unsigned long long)kRiseTab) return ws.lgrise[(int64_t)u * kRiseTab + v];
+    return lgamma_pos(beta + (double)v) - lgb;
 }
 
+// One thread per (gene, v < kRiseTab): lgbeta and the gene's table.  Each
+// thread evaluates lgamma(beta_u) itself (the same value in all of them).
 __global__ void k_lgamma_beta(Ws ws)
 {
-    const int u = blockIdx.x * blockDim.x + threadIdx.x;
-    if (u < ws.G) ws.lgbeta[u] = lgamma(ws.beta[u]);
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= (int64_t)ws.G * kRiseTab) return;
+    const int u = (int)(q / kRiseTab);
+    const int v = (int)(q % kRiseTab);
+    const double b = ws.beta[u];
+    const double lgb = lgamma(b);
+    if (v == 0) ws.lgbeta[u] = lgb;
+    ws.lgrise[q] = v ? lgamma_pos(b + (double)v) - lgb : 0.0;
 }
 
 void launch_lgamma_beta(const Ws& ws, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_lgamma_beta, dim3((unsigned)((ws.G + 255) / 256)), dim3(256), 0, s, ws);
+    const int64_t n = (int64_t)ws.G * kRiseTab;
+    hipLaunchKernelGGL(k_lgamma_beta, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, ws);
 }
 
 // The split ratios and the clusters' logDM in two passes, so that K clusters
@@ -142,15 +154,15 @@ __global__ void __launch_bounds__(kSmThreads) k_sm_tiles(Ws ws, int mode)
             if (mode == 2) {
                 const long long v = (long long)(s0[u] + s1[u]);
                 r.a = v;
-                r.cs.add(rising(bu, lgb, v));
+                r.cs.add(rising(ws, u, bu, lgb, v));
             } else {
                 const long long x0 = (long long)s0[u], x1 = (long long)s1[u];
                 r.a = x0;
                 r.b = x1;
                 if (x0 + x1 != 0) {
-                    r.cs.add(rising(bu, lgb, x0));
-                    r.cs.add(rising(bu, lgb, x1));
-                    r.cs.add(-rising(bu, lgb, x0 + x1));
+                    r.cs.add(rising(ws, u, bu, lgb, x0));
+                    r.cs.add(rising(ws, u, bu, lgb, x1));
+                    r.cs.add(-rising(ws, u, bu, lgb, x0 + x1));
                 }
             }
         }
@@ -263,7 +275,7 @@ __global__ void __launch_bounds__(kMergeThreads) k_merge_ratios(Ws ws)
             const long long v = (long long)(a0[u] + a0[u + G] + b0[u] + b0[u + G]);
             r.beta += bu;
             r.a += v;
-            r.cs.add(rising(bu, ws.lgbeta[u], v));
+            r.cs.add(rising(ws, u, bu, ws.lgbeta[u], v));
         }
         r = block_reduce<kMergeThreads>(r);
         if (threadIdx.x < 64) {     // wavefront 0: one log-gamma term per lane, as in k_sm_finish

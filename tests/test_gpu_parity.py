@@ -324,6 +324,20 @@ def test_empirical_bayes_step_matches_oracle():
         s.eb_update()
         b = s.beta.cpu().numpy()
         assert np.all(np.abs(b - o.beta) <= 1e-9 * np.abs(o.beta)), np.max(np.abs(b - o.beta) / o.beta)
+    # the Hastings sums read per-gene log-gamma tables, which must follow beta
+    # wherever it is written: after the EB steps, and after set_beta
+    o.split_merge()
+    s.split_merge()
+    _compare_hastings(o, s)
+    assert _compare_labels(o, s, "eb split/merge") == 0
+    nb = np.random.default_rng(3).uniform(0.05, 3.0, size=d.n_genes)
+    o.beta[:] = nb
+    s.beta = torch.from_numpy(nb).cuda()
+    for it in range(2):
+        o.split_merge()
+        s.split_merge()
+        _compare_hastings(o, s)
+        assert _compare_labels(o, s, f"set_beta split/merge {it}") == 0
 
 
 def test_dm_logmarginal_and_gradient_match_oracle():

@@ -27,6 +27,7 @@ constexpr int kSubCellsMin = 256;       // sorted cells per workgroup, at least
 constexpr int kSubStageGenes = 4096;     // delta staged in LDS up to this G
 constexpr int kSubHistGenes = 8192;      // LDS histograms up to this G
 constexpr int kSubLanes = 8;             // lanes per cell: eight cells of a wavefront read their rows together
+constexpr int kStageBatch = 8;           // genes per thread whose delta loads are in flight together
 constexpr int kSubLoads = 10;            // 16-byte loads per lane in flight: the first 320 entries of a row
 
 // sum over the kSubLanes lanes of a cell, in a fixed order
@@ -74,8 +75,23 @@ __global__ void __launch_bounds__(kSubThreads) __attribute__((amdgpu_waves_per_e
         const double* g0 = ws.lt64 + (int64_t)(ws.k_max + 2 * k) * G;
         const double* g1 = g0 + G;
         __syncthreads();
-        if (stage && !reset)
-            for (int u = threadIdx.x; u < G; u += kSubThreads) dl[u] = g1[u] - g0[u];
+        if (stage && !reset) {
+            // kStageBatch genes per thread at a time, their loads issued together
+            for (int u0 = threadIdx.x; u0 < G; u0 += kSubThreads * kStageBatch) {
+                double h1[kStageBatch], h0[kStageBatch];
+#pragma unroll
+                for (int j = 0; j < kStageBatch; ++j) {
+                    const int u = u0 + j * kSubThreads;
+                    h1[j] = u < G ? g1[u] : 0.0;
+                    h0[j] = u < G ? g0[u] : 0.0;
+                }
+#pragma unroll
+                for (int j = 0; j < kStageBatch; ++j) {
+                    const int u = u0 + j * kSubThreads;
+                    if (u < G) dl[u] = h1[j] - h0[j];
+                }
+            }
+        }
         if (lhist)
             for (int u = threadIdx.x; u < 2 * G; u += kSubThreads) hist[u] = 0;
         if (threadIdx.x < 2) ncnt[threadIdx.x] = 0;
@@ -121,8 +137,8 @@ __global__ void __launch_bounds__(kSubThreads) __attribute__((amdgpu_waves_per_e
                 int sub;
                 double df = 0.0, s0 = 0.0, s1 = 0.0;
                 double dd = 0.0;        // score of sub-cluster 1 less that of 0 (with the weights)
-                // the first 64 kSubLoads entries of the row (nearly every row),
-                // all loads in flight together
+                // the first 4 kSubLanes kSubLoads (320) entries of the row
+                // (nearly every row), all loads in flight together
                 uint4 v[kSubLoads];
 #pragma unroll
                 for (int r = 0; r < kSubLoads; ++r) {

@@ -413,11 +413,13 @@ __global__ void __launch_bounds__(1024) k_compact(Ws ws, int after_sweep)
     __shared__ int32_t s_nk, s_changed;
     const int K = ws.st->K;
     const int t = threadIdx.x;
+    // which clusters have cells, read by all threads; then the map in order
+    for (int k = t; k < K; k += blockDim.x) lds_map[k] = (ws.nsub[2 * k] + ws.nsub[2 * k + 1]) > 0 ? 1 : 0;
+    __syncthreads();
     if (t == 0) {
         int nk = 0, changed = 0;
         for (int k = 0; k < K; ++k) {
-            const unsigned long long n = ws.nsub[2 * k] + ws.nsub[2 * k + 1];
-            lds_map[k] = n > 0 ? nk++ : -1;
+            lds_map[k] = lds_map[k] ? nk++ : -1;
             if (lds_map[k] != k) changed = 1;
         }
         s_nk = nk;

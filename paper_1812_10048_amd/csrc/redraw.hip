@@ -119,7 +119,7 @@ __global__ void __launch_bounds__(kRedrawThreads) k_redraw_draw(Ws ws, uint32_t 
 
     if (row == 3 * ws.k_max) {
         if (tile != 0) return;
-        if (t == 0) ws.st->counters[kCntEvals] += (unsigned long long)ws.N * (unsigned long long)(K + 2);
+        if (t == 0) atomicAdd(&ws.st->counters[kCntEvals], (unsigned long long)ws.N * (unsigned long long)(K + 2));
         double* lp = ws.logpi;
         // with a new cluster in the sweep (eq. 4 over K + 1) the alpha
         // component is its weight

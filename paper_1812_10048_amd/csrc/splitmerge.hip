@@ -463,9 +463,10 @@ __global__ void __launch_bounds__(kDecideThreads) k_sm_decide(Ws ws, int merge_p
                     }
                 }
             }
-            ws.st->counters[kCntSplitsProposed] += prop;
-            ws.st->counters[kCntSplitsAccepted] += acc;
-            ws.st->counters[kCntKmaxSkips] += skip;
+            // counters by atomics that return nothing: no round trip before the barrier
+            atomicAdd(&ws.st->counters[kCntSplitsProposed], prop);
+            atomicAdd(&ws.st->counters[kCntSplitsAccepted], acc);
+            atomicAdd(&ws.st->counters[kCntKmaxSkips], skip);
             s_K = knew;
             s_any = acc > 0;
         }
@@ -590,8 +591,8 @@ __global__ void __launch_bounds__(kDecideThreads) k_sm_decide(Ws ws, int merge_p
             cmap[k] = gone ? -1 : nk++;
         }
         s_K = nk;
-        ws.st->counters[kCntMergesProposed] += (unsigned long long)npairs;
-        ws.st->counters[kCntMergesAccepted] += merges;
+        atomicAdd(&ws.st->counters[kCntMergesProposed], (unsigned long long)npairs);
+        atomicAdd(&ws.st->counters[kCntMergesAccepted], merges);
     }
     __syncthreads();
     const int nk = s_K;

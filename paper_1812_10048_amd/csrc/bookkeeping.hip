@@ -270,6 +270,14 @@ __global__ void __launch_bounds__(kSortThreads) k_group_scatter(Ws ws, const int
     const int64_t b0 = (int64_t)blockIdx.x * kSortCellsPerBlock;
     const int64_t b1 = min(ws.N, b0 + kSortCellsPerBlock);
     const SortCells sc = load_groups(ws, c, cs, by_cluster, b0, b1, c_prev);
+    // the row offsets depend only on the cell: loaded with the labels
+    int64_t r0[kSortPerThread], r1[kSortPerThread];
+#pragma unroll
+    for (int j = 0; j < kSortPerThread; ++j) {
+        const int64_t i = b0 + (int64_t)j * kSortThreads + threadIdx.x;
+        r0[j] = sc.g[j] >= 0 ? ws.roff[i] : 0;
+        r1[j] = sc.g[j] >= 0 ? ws.roff[i + 1] : 0;
+    }
     __syncthreads();
     // pass 1: block-local counts; pass 2: one reservation per group; pass 3: ranks
 #pragma unroll
@@ -282,15 +290,9 @@ __global__ void __launch_bounds__(kSortThreads) k_group_scatter(Ws ws, const int
     }
     __syncthreads();
     uint32_t pos[kSortPerThread];
-    int64_t r0[kSortPerThread], r1[kSortPerThread];
 #pragma unroll
-    for (int j = 0; j < kSortPerThread; ++j) {
-        const int64_t i = b0 + (int64_t)j * kSortThreads + threadIdx.x;
-        const bool in = sc.g[j] >= 0;
-        pos[j] = in ? base[sc.g[j]] + atomicAdd(&cnt[sc.g[j]], 1u) : 0xFFFFFFFFu;
-        r0[j] = in ? ws.roff[i] : 0;
-        r1[j] = in ? ws.roff[i + 1] : 0;
-    }
+    for (int j = 0; j < kSortPerThread; ++j)
+        pos[j] = sc.g[j] >= 0 ? base[sc.g[j]] + atomicAdd(&cnt[sc.g[j]], 1u) : 0xFFFFFFFFu;
 #pragma unroll
     for (int j = 0; j < kSortPerThread; ++j) {
         const int64_t i = b0 + (int64_t)j * kSortThreads + threadIdx.x;

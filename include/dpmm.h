@@ -93,6 +93,14 @@ typedef struct dpmm_csr {
  * re-draw their sub-labels.  dpmm_get_hastings reports the pass as 2.  Costs
  * one extra byte per cell and 16 k_max G bytes of workspace. */
 #define DPMM_FLAG_RANDOM_SPLIT 4u
+/* The moves as Sections 2.1-2.4 state them: the split ratio with its
+ * Section 2.3 proposal term, the Gibbs step over K + 1 clusters of eq. 4, and
+ * chain B's random splits beside the eq. 23 merge.  This is the recommended
+ * setting; flags = 0 keeps the collapsed split ratio alone.  Neither setting
+ * has the exact posterior as its stationary distribution on a handful of
+ * cells (parallel passes, clusters emptied by the parallel sweep, and a
+ * sub-cluster split whose reverse cannot be computed). */
+#define DPMM_FLAGS_PAPER (DPMM_FLAG_SPLIT_Q | DPMM_FLAG_NEW_CLUSTER | DPMM_FLAG_RANDOM_SPLIT)
 
 /* Hyper-parameters and sampler settings, copied at dpmm_init. */
 typedef struct dpmm_params {

@@ -33,10 +33,15 @@ SPLIT_Q = 1
 NEW_CLUSTER = 2
 # ... and split/merge calls may run a pass of random splits (chain B, Section 2.4).
 RANDOM_SPLIT = 4
+# The exact chain (alone): sweeps that would empty a cluster are undone, and
+# each split/merge call makes one atomic chain-B move with the Hastings ratio
+# of its own proposal probabilities.  Its stationary distribution over
+# partitions is p(c | x); the tests check that by enumeration.
+EXACT = 8
 
 COUNTER_NAMES = [
     "gamma_caps", "gamma_near_ties", "splits_proposed", "splits_accepted",
-    "merges_proposed", "merges_accepted", "kmax_skips", "sweeps", "sm_calls",
+    "merges_proposed", "merges_accepted", "kmax_skips", "sweeps", "sm_calls", "sweep_reverts",
 ]
 
 
@@ -116,6 +121,8 @@ def _declare(L: ctypes.CDLL) -> None:
                  "oracle_sweep", "oracle_split_merge", "oracle_eb_update"):
         getattr(L, name).argtypes = [S]
         getattr(L, name).restype = None
+    L.oracle_iterate.argtypes = [S, _I64]
+    L.oracle_iterate.restype = None
     L.oracle_init.argtypes = [S, _I32]
     L.oracle_init.restype = None
     L.oracle_set_state.argtypes = [S, _I64, _I32]
@@ -229,7 +236,10 @@ class Oracle:
 
     def __init__(self, row_ptr, col, val, n_genes: int, alpha: float = 1.0, beta=1.0,
                  seed: int = 0, k_max: int = 64, k_init: int = 1, init: bool = True,
-                 split_q: bool = False, new_cluster: bool = False, random_split: bool = False):
+                 split_q: bool = True, new_cluster: bool = True, random_split: bool = True,
+                 exact: bool = False):
+        if exact:
+            split_q = new_cluster = random_split = False
         self.row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
         self.col = np.ascontiguousarray(col, dtype=np.int32)
         self.val = np.ascontiguousarray(val, dtype=np.int32)
@@ -258,7 +268,7 @@ class Oracle:
         st.alpha, st.beta, st.seed = float(alpha), _ptr(self.beta), int(seed) & 0xFFFFFFFFFFFFFFFF
         st.step, st.K = 0, 0
         st.flags = ((SPLIT_Q if split_q else 0) | (NEW_CLUSTER if new_cluster else 0) |
-                    (RANDOM_SPLIT if random_split else 0))
+                    (RANDOM_SPLIT if random_split else 0) | (EXACT if exact else 0))
         for name in ("c", "cs", "reset", "nsub", "ssub", "logpi", "logtheta", "margin_c",
                      "margin_s", "lpsub", "sm_logr", "sm_scale", "sm_accept"):
             setattr(st, name, _ptr(getattr(self, name)))
@@ -334,10 +344,8 @@ class Oracle:
         lib().oracle_split_merge(ctypes.byref(self._st))
 
     def iterate(self, n: int = 1) -> None:
-        """n iterations of (sweep, split/merge)."""
-        for _ in range(n):
-            self.sweep()
-            self.split_merge()
+        """n iterations of (sweep, split/merge), looped in C."""
+        lib().oracle_iterate(ctypes.byref(self._st), int(n))
 
     def eb_update(self) -> None:
         lib().oracle_eb_update(ctypes.byref(self._st))

@@ -26,7 +26,12 @@
  *     partition prior of eq. 10 with Gamma(alpha) restored;
  *   - the sub-cluster Gibbs step (eq. 8) uses the counts frozen at the start of
  *     the sweep, minus the cell's own old membership;
- *   - one move chain is chosen per split/merge call by a fair coin (Section 2.4).
+ *   - one move chain is chosen per split/merge call by a fair coin (Section 2.4);
+ *   - ORACLE_EXACT: a chain built from the same pieces whose stationary
+ *     distribution over partitions is exactly p(c | x): sweeps that would empty
+ *     a cluster are undone, and each split/merge call makes one atomic chain-B
+ *     move whose ratio carries its own proposal probabilities.  The tests
+ *     check it by enumerating every partition of five and six cells.
  *
  * Build: gcc -O2 -fopenmp -fPIC -shared -o liboracle_dpmm.so dpmm_oracle.c -lm
  */
@@ -274,7 +279,7 @@ void oracle_dm_logmarginal(const int64_t* s, int32_t J, int32_t G, const double*
 /* Sampler state.  All arrays are owned by the caller.                      */
 /* ------------------------------------------------------------------------ */
 
-enum { ORACLE_SPLIT_Q = 1u, ORACLE_NEW_CLUSTER = 2u, ORACLE_RANDOM_SPLIT = 4u };
+enum { ORACLE_SPLIT_Q = 1u, ORACLE_NEW_CLUSTER = 2u, ORACLE_RANDOM_SPLIT = 4u, ORACLE_EXACT = 8u };
 
 enum {
     CNT_GAMMA_CAPS = 0,
@@ -286,6 +291,7 @@ enum {
     CNT_KMAX_SKIPS = 6,
     CNT_SWEEPS = 7,
     CNT_SM_CALLS = 8,
+    CNT_SWEEP_REVERTS = 9,
     N_COUNTERS = 16
 };
 
@@ -309,7 +315,9 @@ typedef struct {
                                  ORACLE_NEW_CLUSTER: the sweep draws over K + 1
                                  clusters (eq. 4), the last one new;
                                  ORACLE_RANDOM_SPLIT: a third pass of random
-                                 splits (Section 2.4, chain B)                */
+                                 splits (Section 2.4, chain B);
+                                 ORACLE_EXACT (alone): the exact chain, see
+                                 exact_sweep_check and exact_split_merge     */
     int32_t* c;               /* [N]                                          */
     uint8_t* cs;              /* [N] sub-cluster labels                       */
     uint8_t* reset;           /* [k_max] sub-labels to be re-drawn at random  */
@@ -615,13 +623,49 @@ void oracle_extend(oracle_state* st)
     st->has_new = 1;
 }
 
+/* ORACLE_EXACT, the sweep.  Given (pi, theta), the labels' exact conditional
+ * under the joint p(c, x) p(pi | c) p(theta | c, x) is prod_i pi_{c_i}
+ * f(x_i | theta_{c_i}) restricted to labelings that keep all K clusters
+ * non-empty: the Dirichlet Dir(n_1..n_K, alpha) of eq. 4 has no density at a
+ * zero count, so a labeling that empties a cluster has conditional
+ * probability 0.  The cells' independent draws (Section 2.2) are then an
+ * independence proposal from the unrestricted product, and its
+ * Metropolis-Hastings acceptance is 1 when every cluster keeps a cell and 0
+ * otherwise: such a sweep is undone as a whole.  Returns 1 if undone. */
+static int exact_sweep_check(oracle_state* st, const int32_t* c_before, const uint8_t* cs_before)
+{
+    for (int32_t k = 0; k < st->K; ++k) {
+        if (st->nsub[2 * k] + st->nsub[2 * k + 1] > 0) continue;
+        memcpy(st->c, c_before, sizeof(int32_t) * (size_t)st->n_cells);
+        memcpy(st->cs, cs_before, (size_t)st->n_cells);
+        oracle_stats(st);
+        st->counters[CNT_SWEEP_REVERTS] += 1;
+        return 1;
+    }
+    return 0;
+}
+
 /* One sweep: redraw (a1), assign (a2-a3), statistics (a4), compaction. */
 void oracle_sweep(oracle_state* st)
 {
+    const int exact = (st->flags & ORACLE_EXACT) != 0;
+    int32_t* c_before = NULL;
+    uint8_t* cs_before = NULL;
     oracle_extend(st);
     oracle_redraw(st);
+    if (exact) {
+        c_before = (int32_t*)malloc(sizeof(int32_t) * (size_t)(st->n_cells > 0 ? st->n_cells : 1));
+        cs_before = (uint8_t*)malloc((size_t)(st->n_cells > 0 ? st->n_cells : 1));
+        memcpy(c_before, st->c, sizeof(int32_t) * (size_t)st->n_cells);
+        memcpy(cs_before, st->cs, (size_t)st->n_cells);
+    }
     oracle_assign(st);
     oracle_stats(st);
+    if (exact) {
+        exact_sweep_check(st, c_before, cs_before);
+        free(c_before);
+        free(cs_before);
+    }
     finish_sweep(st);
     st->counters[CNT_SWEEPS] += 1;
     st->step += 1;
@@ -709,6 +753,106 @@ static int cmp_cand(const void* x, const void* y)
     return a->p < b->p ? -1 : (a->p > b->p ? 1 : 0);
 }
 
+/* ORACLE_EXACT, the moves.  One atomic move per call (Section 2.4: atomic
+ * moves picked at random), from chain B only: with probability 1/2 a random
+ * split of one cluster k picked uniformly among the K, every cell of k taking
+ * a fair Philox coin (stream RSPLIT), else a merge of one pair picked
+ * uniformly among the K (K - 1) / 2.  A labelled split {A, B} of n cells
+ * comes from two coin vectors, so its proposal probability is
+ * (1/2) (1/K) 2^(1-n), and its reverse, the merge of A and B from K + 1
+ * clusters, has (1/2) / C(K + 1, 2).  Eq. 7 with the collapsed joint (eq. 10
+ * with Gamma(alpha) restored, eq. 12 integrated against eq. 28) then gives
+ *   log R_split = logR_c(A, B) + n log 2 - log(K + 1),
+ *   log R_merge = -logR_c(A, B) - n log 2 + log K   (K counted before),
+ * logR_c the collapsed ratio of oracle_split_logr.  A coin vector with an
+ * empty side, a split at k_max and a merge at K = 1 leave the state as it
+ * is.  The candidate's ratio is reported as sm_logr[0] (NaN if none). */
+static void exact_split_merge(oracle_state* st, double coin)
+{
+    const int32_t G = st->n_genes;
+    const int32_t K = st->K;
+    const int64_t N = st->n_cells;
+    uint32_t q[4];
+    draw_words(st->seed, 1u, 0u, st->step, ST_CHAIN, 0u, q);
+    const double u_pick = oracle_u52(q[0], q[1]);
+    const double u_acc = oracle_u52(q[2], q[3]);
+    st->sm_n = 1;
+    st->sm_logr[0] = NAN;
+    st->sm_scale[0] = 0.0;
+    st->sm_accept[0] = 0;
+    if (coin < 0.5) {
+        st->sm_pass = 2;
+        const int32_t k = (int32_t)(u_pick * (double)K);
+        int64_t hn[2] = {0, 0};
+        int64_t* hs = (int64_t*)calloc(2 * (size_t)G, sizeof(int64_t));
+        uint8_t* side = (uint8_t*)calloc((size_t)(N > 0 ? N : 1), 1);
+        for (int64_t i = 0; i < N; ++i) {
+            if (st->c[i] != k) continue;
+            uint32_t cw[4];
+            draw_words(st->seed, (uint32_t)i, 0u, st->step, ST_RSPLIT, 0u, cw);
+            side[i] = (uint8_t)(cw[0] >> 31);
+            hn[side[i]] += 1;
+            for (int64_t e = row_begin(st, i); e < row_end(st, i); ++e) hs[side[i] * G + st->col[e]] += st->val[e];
+        }
+        if (hn[0] > 0 && hn[1] > 0 && K < st->k_max) {
+            st->counters[CNT_SPLITS_PROPOSED] += 1;
+            double sc;
+            const double lr = oracle_split_logr(hs, hs + G, hn[0], hn[1], st->beta, G, st->alpha, &sc) +
+                              (double)(hn[0] + hn[1]) * log(2.0) - log((double)(K + 1));
+            st->sm_logr[0] = lr;
+            st->sm_scale[0] = sc + (double)(hn[0] + hn[1]) * log(2.0) + log((double)(K + 1));
+            if (log(u_acc) < lr) {
+                for (int64_t i = 0; i < N; ++i)
+                    if (st->c[i] == k && side[i]) st->c[i] = K;
+                st->K = K + 1;
+                st->reset[k] = 1;
+                st->reset[K] = 1;
+                st->sm_accept[0] = 1;
+                st->counters[CNT_SPLITS_ACCEPTED] += 1;
+            }
+        }
+        free(side);
+        free(hs);
+    } else {
+        st->sm_pass = 1;
+        if (K >= 2) {
+            const int64_t npairs = (int64_t)K * (K - 1) / 2;
+            const int64_t p = (int64_t)(u_pick * (double)npairs);
+            int32_t k2 = 1;
+            while ((int64_t)(k2 + 1) * k2 / 2 <= p) k2++;
+            const int32_t k1 = (int32_t)(p - (int64_t)k2 * (k2 - 1) / 2);
+            int64_t* sk = (int64_t*)calloc(2 * (size_t)G, sizeof(int64_t));
+            for (int32_t u = 0; u < G; ++u) {
+                sk[u] = st->ssub[(int64_t)(2 * k1) * G + u] + st->ssub[(int64_t)(2 * k1 + 1) * G + u];
+                sk[G + u] = st->ssub[(int64_t)(2 * k2) * G + u] + st->ssub[(int64_t)(2 * k2 + 1) * G + u];
+            }
+            const int64_t n1 = st->nsub[2 * k1] + st->nsub[2 * k1 + 1];
+            const int64_t n2 = st->nsub[2 * k2] + st->nsub[2 * k2 + 1];
+            st->counters[CNT_MERGES_PROPOSED] += 1;
+            double sc;
+            const double lr = -oracle_split_logr(sk, sk + G, n1, n2, st->beta, G, st->alpha, &sc) -
+                              (double)(n1 + n2) * log(2.0) + log((double)K);
+            st->sm_logr[0] = lr;
+            st->sm_scale[0] = sc + (double)(n1 + n2) * log(2.0) + log((double)K);
+            if (log(u_acc) < lr) {
+                /* as in the merge pass: the merged cluster's sub-clusters are
+                 * its two parts */
+                for (int64_t i = 0; i < N; ++i) {
+                    if (st->c[i] == k1) st->cs[i] = 0;
+                    else if (st->c[i] == k2) { st->c[i] = k1; st->cs[i] = 1; }
+                }
+                st->reset[k1] = 0;
+                st->reset[k2] = 0;
+                st->sm_accept[0] = 1;
+                st->counters[CNT_MERGES_ACCEPTED] += 1;
+            }
+            free(sk);
+        }
+    }
+    oracle_stats(st);
+    compact(st);
+}
+
 void oracle_split_merge(oracle_state* st)
 {
     const int32_t G = st->n_genes;
@@ -718,6 +862,12 @@ void oracle_split_merge(oracle_state* st)
     /* pass 0: split into the sub-clusters; 1: merges; 2: random splits (only
      * with ORACLE_RANDOM_SPLIT, the three then equally likely) */
     const double coin = oracle_u52(w[0], w[1]);
+    if (st->flags & ORACLE_EXACT) {
+        exact_split_merge(st, coin);
+        st->counters[CNT_SM_CALLS] += 1;
+        st->step += 1;
+        return;
+    }
     int pass;
     if (st->flags & ORACLE_RANDOM_SPLIT) pass = coin < 1.0 / 3.0 ? 0 : (coin < 2.0 / 3.0 ? 2 : 1);
     else pass = coin < 0.5 ? 0 : 1;
@@ -895,6 +1045,15 @@ void oracle_split_merge(oracle_state* st)
     free(s_k);
     st->counters[CNT_SM_CALLS] += 1;
     st->step += 1;
+}
+
+/* n iterations of (sweep, split/merge), for long chains on tiny data. */
+void oracle_iterate(oracle_state* st, int64_t n)
+{
+    for (int64_t t = 0; t < n; ++t) {
+        oracle_sweep(st);
+        oracle_split_merge(st);
+    }
 }
 
 /* ---- Steps a6-a7: empirical-Bayes update of the per-gene beta ----------- */

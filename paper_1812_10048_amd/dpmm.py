@@ -27,6 +27,7 @@ PRECISIONS = {"fp64": DPMM_FP64, "fp32": DPMM_FP32, "split_bf16": DPMM_SPLIT_BF1
 FLAG_SPLIT_Q = 1     # DPMM_FLAG_SPLIT_Q
 FLAG_NEW_CLUSTER = 2     # DPMM_FLAG_NEW_CLUSTER
 FLAG_RANDOM_SPLIT = 4     # DPMM_FLAG_RANDOM_SPLIT
+FLAGS_PAPER = FLAG_SPLIT_Q | FLAG_NEW_CLUSTER | FLAG_RANDOM_SPLIT     # DPMM_FLAGS_PAPER
 
 
 class DpmmError(RuntimeError):

@@ -27,14 +27,16 @@ class Sampler:
     or a length-G tensor of per-gene concentrations.  ``precision`` is one of
     "fp64", "fp32", "split_bf16".  ``split_q`` sets DPMM_FLAG_SPLIT_Q (the
     split ratio carries the proposal term of Section 2.3); ``new_cluster``
-    sets DPMM_FLAG_NEW_CLUSTER (the Gibbs step runs over K + 1 clusters);
-    ``random_split`` sets DPMM_FLAG_RANDOM_SPLIT (a third pass of random
-    splits, chain B of Section 2.4).
+    sets DPMM_FLAG_NEW_CLUSTER (the Gibbs step runs over K + 1 clusters,
+    eq. 4); ``random_split`` sets DPMM_FLAG_RANDOM_SPLIT (a third pass of
+    random splits, chain B of Section 2.4).  All three are on by default
+    (DPMM_FLAGS_PAPER, the moves as the paper states them); all off gives the
+    collapsed split ratio alone.
     """
 
     def __init__(self, row_ptr, col, val, n_genes: int, *, alpha: float = 1.0, beta=1.0, seed: int = 0,
                  k_init: int = 1, k_max: int = 128, precision: str = "fp32", refine_tol: float = -1.0,
-                 split_q: bool = False, new_cluster: bool = False, random_split: bool = False):
+                 split_q: bool = True, new_cluster: bool = True, random_split: bool = True):
         if not torch.cuda.is_available():
             raise RuntimeError("libdpmm needs a GPU")
         rp = _dev(torch.as_tensor(row_ptr), torch.int64)

@@ -30,10 +30,16 @@ import oracle
 from paper_1812_10048_amd import synth
 
 
-def _dense_oracle(X, k_max=8, beta=1.0, alpha=1.0, seed=0):
+# the plain passes (sub-cluster split or merge, one fair coin), for the pins
+# of one pass at a time
+COLLAPSED = dict(split_q=False, new_cluster=False, random_split=False)
+
+
+def _dense_oracle(X, k_max=8, beta=1.0, alpha=1.0, seed=0, **flags):
     d = synth.from_dense(X)
     rp, col, val = d.host_arrays()
-    return oracle.Oracle(rp, col, val, X.shape[1], alpha=alpha, beta=beta, seed=seed, k_max=k_max, init=False)
+    return oracle.Oracle(rp, col, val, X.shape[1], alpha=alpha, beta=beta, seed=seed, k_max=k_max, init=False,
+                         **{**COLLAPSED, **flags})
 
 
 def _chi2_ok(counts, probs, min_p=1e-4):
@@ -53,7 +59,7 @@ def _chi2_ok(counts, probs, min_p=1e-4):
 def test_stats_invariants():
     d = synth.generate("c1", seed=3, n_cells=600)
     rp, col, val = d.host_arrays()
-    o = oracle.Oracle(rp, col, val, d.n_genes, seed=1, k_max=16, init=False)
+    o = oracle.Oracle(rp, col, val, d.n_genes, seed=1, k_max=16, init=False, **COLLAPSED)
     rng = np.random.default_rng(0)
     K = 5
     c = rng.integers(0, K, size=d.n_cells)
@@ -251,7 +257,8 @@ def test_split_q_adds_minus_the_summed_logp_to_the_split_ratio():
     first split pass."""
     d = synth.generate("c1", seed=3)
     rp, col, val = d.host_arrays()
-    chains = [oracle.Oracle(rp, col, val, d.n_genes, seed=5, k_max=16, init=False, split_q=q) for q in (False, True)]
+    chains = [oracle.Oracle(rp, col, val, d.n_genes, seed=5, k_max=16, init=False,
+                            **{**COLLAPSED, "split_q": q}) for q in (False, True)]
     cs0 = np.random.default_rng(2).integers(0, 2, size=d.n_cells)
     for o in chains:
         o.set_state(0, d.n_true, d.z, cs0, np.ones(d.n_true, dtype=np.uint8))
@@ -289,7 +296,8 @@ def test_new_cluster_takes_the_alpha_weight_and_a_prior_theta():
     d = synth.from_dense(X)
     rp, col, val = d.host_arrays()
     beta = np.array([0.5, 1.0, 1.5, 2.0, 3.0])
-    o = oracle.Oracle(rp, col, val, G, alpha=alpha, beta=beta, seed=4, k_max=4, init=False, new_cluster=True)
+    o = oracle.Oracle(rp, col, val, G, alpha=alpha, beta=beta, seed=4, k_max=4, init=False,
+                      **{**COLLAPSED, "new_cluster": True})
     c = np.zeros(N, dtype=np.int32)
     cs = (np.arange(N) % 2).astype(np.uint8)
     T = 4000
@@ -323,7 +331,8 @@ def test_gibbs_over_k_plus_one_opens_clusters_and_keeps_statistics():
     X[np.arange(60), grp] += 8
     d = synth.from_dense(X)
     rp, col, val = d.host_arrays()
-    o = oracle.Oracle(rp, col, val, 3, alpha=2.0, beta=0.2, seed=9, k_max=16, k_init=1, new_cluster=True)
+    o = oracle.Oracle(rp, col, val, 3, alpha=2.0, beta=0.2, seed=9, k_max=16, k_init=1,
+                      **{**COLLAPSED, "new_cluster": True})
     assert o.K == 1
     for _ in range(30):
         o.sweep()
@@ -344,7 +353,8 @@ def test_random_split_pass_halves_by_coins_and_reverses_the_merge():
     d = synth.generate("c1", seed=12)
     rp, col, val = d.host_arrays()
     seed = 31
-    o = oracle.Oracle(rp, col, val, d.n_genes, seed=seed, k_max=32, init=False, random_split=True)
+    o = oracle.Oracle(rp, col, val, d.n_genes, seed=seed, k_max=32, init=False,
+                      **{**COLLAPSED, "random_split": True})
     rng = np.random.default_rng(4)
     # the truth with two clusters merged, so that splitting them is attractive
     z = np.where(d.z == 3, 2, d.z).astype(np.int32)
@@ -396,7 +406,8 @@ def test_accepted_random_split_follows_the_coins():
     d = synth.from_dense(X)
     rp, col, val = d.host_arrays()
     seed = 5
-    o = oracle.Oracle(rp, col, val, 3, alpha=200.0, seed=seed, k_max=8, init=False, random_split=True)
+    o = oracle.Oracle(rp, col, val, 3, alpha=200.0, seed=seed, k_max=8, init=False,
+                      **{**COLLAPSED, "random_split": True})
     o.set_state(0, 1, np.zeros(8, dtype=np.int32), np.zeros(8, dtype=np.uint8), np.zeros(1, dtype=np.uint8))
     for it in range(60):
         step, c_before, K = o.step, o.c.copy(), o.K

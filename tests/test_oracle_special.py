@@ -5,7 +5,7 @@
   the beta = 1 closed form in exact integer arithmetic, normalisation over all
   count vectors of a given total, and the beta-binomial special case.
 * The partition prior of eq. 10 (with Gamma(alpha)): sums to one over every
-  set partition of N <= 7 points and agrees with the Chinese-restaurant
+  set partition of N <= 8 points (Bell(8) = 4140) and agrees with the Chinese-restaurant
   sequential rule.
 * The split and merge Hastings ratios against the collapsed joint computed
   independently in mpmath.
@@ -134,7 +134,7 @@ def _set_partitions(n):
 
 
 @pytest.mark.parametrize("alpha", [0.3, 1.0, 2.5])
-@pytest.mark.parametrize("n", [1, 3, 5, 7])
+@pytest.mark.parametrize("n", [1, 3, 5, 7, 8])
 def test_partition_prior_sums_to_one(alpha, n):
     tot = math.fsum(math.exp(oracle.log_partition_prior([len(b) for b in p], alpha))
                     for p in _set_partitions(n))

@@ -143,7 +143,27 @@ typedef struct dpmm_stats_out {
     int64_t gamma_caps;         /* Gamma draws that hit the rejection cap (64)    */
     int64_t evals;              /* cell x cluster log-likelihood evaluations:
                                    the sum over sweeps of N (K + 2)              */
+    int64_t near_tie;           /* cluster decisions whose FP64 relative Gumbel-max
+                                   margin (top1 - top2) / max(1, |top1|) was
+                                   below 1e-6 (always taken in FP64)             */
+    double log_joint;           /* log p(c) + sum_k logDM(s_k) of the current
+                                   partition (eq. 10 with Gamma(alpha) restored,
+                                   eq. 12 integrated against eq. 28, multinomial
+                                   coefficients dropped as in eq. 26), FP64     */
 } dpmm_stats_out;
+
+/* Stages of a sweep, a split/merge call and an empirical-Bayes step, for
+ * dpmm_timing_stages. */
+enum {
+    DPMM_STAGE_REDRAW = 0,       /* a1 + a8: pi, theta, thetabar and the BF16 tables   */
+    DPMM_STAGE_ASSIGN = 1,       /* a2 + a3: cluster log-likelihoods and draws         */
+    DPMM_STAGE_REFINE = 2,       /* a3: FP64 re-score of uncertain decisions           */
+    DPMM_STAGE_SUBCLUSTER = 3,   /* a3 + a4: sort by cluster, sub-cluster draws, stats  */
+    DPMM_STAGE_COMPACT = 4,      /* empty clusters dropped, labels rewritten           */
+    DPMM_STAGE_SPLIT_MERGE = 5,  /* a5: ratios, decisions, relabelling                 */
+    DPMM_STAGE_EB = 6,           /* a6 + a7: empirical-Bayes beta step                 */
+    DPMM_NUM_STAGES = 7
+};
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* dpmm_last_error(void);
@@ -197,7 +217,7 @@ dpmm_status dpmm_split_merge(dpmm_ctx* ctx);
  * clamped to [1e-6, 1e6].  Async. */
 dpmm_status dpmm_eb_update(dpmm_ctx* ctx);
 
-/* Counters into *out (HOST).  If nsub_host is not NULL it receives 2K int64
+/* Counters and the log joint into *out (HOST).  If nsub_host is not NULL it receives 2K int64
  * entries n_{k,r} at 2k + r (HOST, capacity 2 k_max).  If ssub_dev is not
  * NULL it receives the 2K x G int64 statistics s_{k,r,u} at (2k + r) G + u
  * (DEVICE, capacity 2 k_max G).  Sync. */
@@ -237,22 +257,38 @@ dpmm_status dpmm_get_hastings(dpmm_ctx* ctx, int32_t* pass, int32_t* n, double* 
 
 /* Debug output of the sweep's own log-likelihood arithmetic: while set, every
  * sweep writes, per cell i, x_i . log theta_k for k < K followed by the two
- * sub-clusters of the cell's new cluster, as FP32 into a DEVICE buffer of
- * N x (k_cap + 2) entries (row stride k_cap + 2; requires K <= k_cap).  The
- * values are the ones the decisions were taken on (before any FP64
- * re-scoring).  NULL disables.  Sync. */
-dpmm_status dpmm_set_debug_scores(dpmm_ctx* ctx, float* scores_dev, int32_t k_cap);
+ * sub-clusters of the cell's new cluster into a DEVICE buffer of
+ * N x (k_cap + 2) entries (row stride k_cap + 2; requires K <= k_cap),
+ * FP32 (fp64 = 0) or FP64 (fp64 = 1) elements.  The values are the ones the
+ * decisions were taken on, before any FP64 re-scoring: FP64 for the FP64
+ * precision, FP32 or split-BF16 accumulations otherwise; the two sub-cluster
+ * scores are FP64 in every precision (NaN for a cluster that re-drew its
+ * sub-labels at random).  NULL disables.  Sync. */
+dpmm_status dpmm_set_debug_scores(dpmm_ctx* ctx, void* scores_dev, int32_t k_cap, int32_t fp64);
+
+/* FP64 log-likelihoods of m listed cells against the parameters of the last
+ * sweep's redraw (eq. 26, multinomial coefficient dropped): for the j-th
+ * listed cell i, out[j (K + 2) + k] = x_i . log theta_k for k < K, then
+ * x_i . log thetabar_{c_i,0} and x_i . log thetabar_{c_i,1} for its current
+ * cluster c_i.  cells_dev: DEVICE int32[m], in [0, N); out_dev: DEVICE
+ * FP64[m (K + 2)].  DPMM_ERR_STATE before the context's first sweep.
+ * Sync. */
+dpmm_status dpmm_dump_scores(dpmm_ctx* ctx, const int32_t* cells_dev, int32_t m, double* out_dev);
 
 /* Split-BF16 tables of the last sweep (precision DPMM_SPLIT_BF16 only): the
  * bit patterns of hi = bf16(log theta) and lo = bf16(log theta - hi) for the
  * K clusters, K x G uint16 each, DEVICE.  Sync. */
 dpmm_status dpmm_get_split_tables(dpmm_ctx* ctx, uint16_t* hi_dev, uint16_t* lo_dev);
 
-/* Kernel timing with HIP events on the context's stream.  While enabled,
- * every sweep records an event pair around its log-likelihood/assignment
- * kernel; dpmm_timing_read returns the summed milliseconds and the number of
- * launches since the last reset (sync) and resets the accumulator. */
+/* Stage timing with HIP events on the context's stream.  While enabled,
+ * every stage of a sweep, split/merge call and empirical-Bayes step (the
+ * DPMM_STAGE_* list) is bracketed by an event pair (up to 16384 intervals
+ * between two reads).  dpmm_timing_stages fills stage_ms and stage_count
+ * (HOST, DPMM_NUM_STAGES entries each) with the summed milliseconds and the
+ * number of intervals per stage since the last read, and resets them (sync);
+ * dpmm_timing_read does the same for DPMM_STAGE_ASSIGN alone. */
 dpmm_status dpmm_timing_enable(dpmm_ctx* ctx, int32_t enable);
+dpmm_status dpmm_timing_stages(dpmm_ctx* ctx, double* stage_ms, int64_t* stage_count);
 dpmm_status dpmm_timing_read(dpmm_ctx* ctx, double* total_ms, int64_t* launches);
 
 /* Log Dirichlet-multinomial marginal of J count vectors (the per-cluster

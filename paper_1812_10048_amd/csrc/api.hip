@@ -34,7 +34,7 @@ dpmm_status fail(dpmm_status st, const char* fmt, ...)
     } while (0)
 
 constexpr size_t kAlign = 256;
-constexpr int kMaxTimed = 4096;
+constexpr int kMaxTimed = 16384;       // timed stage intervals kept between two reads
 constexpr int kTablePadRows = 64;      // spare cluster rows read by its last column group
 
 size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
@@ -151,10 +151,12 @@ struct dpmm_ctx {
     int32_t* c[2] = {nullptr, nullptr};
     uint8_t* cs[2] = {nullptr, nullptr};
     int64_t* tiles = nullptr;
-    float* dbg = nullptr;
+    void* dbg = nullptr;
     int32_t dbg_cap = 0;
+    int32_t dbg64 = 0;
     bool timing = false;
     std::vector<hipEvent_t> ev;        // pairs (start, stop)
+    std::vector<int> ev_stage;         // stage of each pair
     int n_timed = 0;
     int32_t* k_host = nullptr;         // pinned copy of K, refreshed after every call
 };
@@ -166,6 +168,24 @@ dpmm_status set_device(dpmm_ctx* ctx)
     HIP_TRY(hipSetDevice(ctx->device));
     return DPMM_OK;
 }
+
+// Stage timing: while enabled, each stage of a sweep, split/merge call or
+// empirical-Bayes step is bracketed by a pair of events on the stream.
+struct StageTimer {
+    dpmm_ctx* ctx;
+    int pair = -1;
+    StageTimer(dpmm_ctx* c, int stage) : ctx(c)
+    {
+        if (!ctx->timing || ctx->n_timed >= kMaxTimed) return;
+        pair = ctx->n_timed++;
+        ctx->ev_stage[pair] = stage;
+        if (hipEventRecord(ctx->ev[2 * pair], ctx->stream) != hipSuccess) pair = -1;
+    }
+    ~StageTimer()
+    {
+        if (pair >= 0) hipEventRecord(ctx->ev[2 * pair + 1], ctx->stream);
+    }
+};
 
 dpmm_status read_state(dpmm_ctx* ctx, DevState* out)
 {
@@ -370,8 +390,11 @@ dpmm_status dpmm_sweep(dpmm_ctx* ctx, int32_t n_sweeps)
     for (int32_t n = 0; n < n_sweeps; ++n) {
         const int nxt = 1 - ctx->cur;
         const uint32_t step = (uint32_t)ctx->step;
-        if (ws.flags & kFlagNewCluster) launch_extend(ws, ctx->stream);
-        launch_redraw(ws, step, ctx->precision == DPMM_SPLIT_BF16, ctx->stream);   // also empties the re-score queue
+        {
+            StageTimer st(ctx, DPMM_STAGE_REDRAW);
+            if (ws.flags & kFlagNewCluster) launch_extend(ws, ctx->stream);
+            launch_redraw(ws, step, ctx->precision == DPMM_SPLIT_BF16, ctx->stream);   // also empties the re-score queue
+        }
         AssignArgs a{};
         a.c_old = ctx->c[ctx->cur];
         a.cs_old = ctx->cs[ctx->cur];
@@ -380,19 +403,20 @@ dpmm_status dpmm_sweep(dpmm_ctx* ctx, int32_t n_sweeps)
         a.step = step;
         a.dbg = ctx->dbg;
         a.dbg_stride = ctx->dbg_cap + 2;
+        a.dbg64 = ctx->dbg64;
         a.refine = ctx->precision != DPMM_FP64;
         a.refine_tol = (float)ctx->refine_tol;
         a.k_hint = k_hint(ctx);
-        const bool timed = ctx->timing && ctx->n_timed < kMaxTimed;
-        if (timed) HIP_TRY(hipEventRecord(ctx->ev[2 * ctx->n_timed], ctx->stream));
-        if (ctx->precision == DPMM_FP64) launch_assign_fp64(ws, a, ctx->stream);
-        else if (ctx->precision == DPMM_FP32) launch_assign_fp32(ws, a, ctx->stream);
-        else launch_assign_bf16(ws, a, ctx->stream);
-        if (timed) {
-            HIP_TRY(hipEventRecord(ctx->ev[2 * ctx->n_timed + 1], ctx->stream));
-            ctx->n_timed++;
+        {
+            StageTimer st(ctx, DPMM_STAGE_ASSIGN);
+            if (ctx->precision == DPMM_FP64) launch_assign_fp64(ws, a, ctx->stream);
+            else if (ctx->precision == DPMM_FP32) launch_assign_fp32(ws, a, ctx->stream);
+            else launch_assign_bf16(ws, a, ctx->stream);
         }
-        if (a.refine) launch_refine(ws, a, ctx->stream);
+        if (a.refine) {
+            StageTimer st(ctx, DPMM_STAGE_REFINE);
+            launch_refine(ws, a, ctx->stream);
+        }
         SubArgs sa{};
         sa.c_old = ctx->c[ctx->cur];
         sa.cs_old = ctx->cs[ctx->cur];
@@ -401,9 +425,16 @@ dpmm_status dpmm_sweep(dpmm_ctx* ctx, int32_t n_sweeps)
         sa.step = step;
         sa.dbg = ctx->dbg;
         sa.dbg_stride = ctx->dbg_cap + 2;
-        launch_sub_stats(ws, sa, ctx->stream);
-        launch_compact(ws, 1, ctx->stream);
-        launch_relabel(ws, ctx->c[nxt], ctx->cs[nxt], ctx->stream);
+        sa.dbg64 = ctx->dbg64;
+        {
+            StageTimer st(ctx, DPMM_STAGE_SUBCLUSTER);
+            launch_sub_stats(ws, sa, ctx->stream);
+        }
+        {
+            StageTimer st(ctx, DPMM_STAGE_COMPACT);
+            launch_compact(ws, 1, ctx->stream);
+            launch_relabel(ws, ctx->c[nxt], ctx->cs[nxt], ctx->stream);
+        }
         HIP_TRY(hipGetLastError());     // (k_compact has written the K hint)
         ctx->cur = nxt;
         ctx->step += 1;
@@ -427,6 +458,7 @@ dpmm_status dpmm_split_merge(dpmm_ctx* ctx)
     int pass;
     if (ctx->ws.flags & kFlagRandomSplit) pass = coin < 1.0 / 3.0 ? 0 : (coin < 2.0 / 3.0 ? 2 : 1);
     else pass = coin < 0.5 ? 0 : 1;
+    StageTimer st(ctx, DPMM_STAGE_SPLIT_MERGE);
     if (pass == 1) {
         launch_merge_ratios(ctx->ws, ctx->stream);
         launch_sm_decide(ctx->ws, 1, step, ctx->stream);
@@ -449,7 +481,10 @@ dpmm_status dpmm_eb_update(dpmm_ctx* ctx)
     if (!ctx) return fail(DPMM_ERR_ARG, "null ctx");
     dpmm_status s = set_device(ctx);
     if (s != DPMM_OK) return s;
-    launch_eb_update(ctx->ws, ctx->stream);
+    {
+        StageTimer st(ctx, DPMM_STAGE_EB);
+        launch_eb_update(ctx->ws, ctx->stream);
+    }
     HIP_TRY(hipGetLastError());
     return DPMM_OK;
 }
@@ -459,6 +494,8 @@ dpmm_status dpmm_stats(dpmm_ctx* ctx, dpmm_stats_out* out, int64_t* nsub_host, i
     if (!ctx || !out) return fail(DPMM_ERR_ARG, "null argument");
     dpmm_status s = set_device(ctx);
     if (s != DPMM_OK) return s;
+    launch_log_joint(ctx->ws, ctx->stream);
+    HIP_TRY(hipGetLastError());
     DevState d;
     s = read_state(ctx, &d);
     if (s != DPMM_OK) return s;
@@ -476,6 +513,8 @@ dpmm_status dpmm_stats(dpmm_ctx* ctx, dpmm_stats_out* out, int64_t* nsub_host, i
     out->refined = (int64_t)d.counters[kCntRefined];
     out->gamma_caps = (int64_t)d.counters[kCntGammaCaps];
     out->evals = (int64_t)d.counters[kCntEvals];
+    out->near_tie = (int64_t)d.counters[kCntNearTie];
+    out->log_joint = d.log_joint;
     if (nsub_host)
         HIP_TRY(hipMemcpy(nsub_host, ctx->ws.nsub, 16 * (size_t)d.K, hipMemcpyDeviceToHost));
     if (ssub_dev)
@@ -597,7 +636,7 @@ dpmm_status dpmm_get_hastings(dpmm_ctx* ctx, int32_t* pass, int32_t* n, double* 
     return DPMM_OK;
 }
 
-dpmm_status dpmm_set_debug_scores(dpmm_ctx* ctx, float* scores_dev, int32_t k_cap)
+dpmm_status dpmm_set_debug_scores(dpmm_ctx* ctx, void* scores_dev, int32_t k_cap, int32_t fp64)
 {
     if (!ctx) return fail(DPMM_ERR_ARG, "null ctx");
     if (scores_dev && (k_cap < 1 || k_cap > ctx->k_max)) return fail(DPMM_ERR_ARG, "k_cap must be in [1, k_max]");
@@ -606,6 +645,21 @@ dpmm_status dpmm_set_debug_scores(dpmm_ctx* ctx, float* scores_dev, int32_t k_ca
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     ctx->dbg = scores_dev;
     ctx->dbg_cap = scores_dev ? k_cap : 0;
+    ctx->dbg64 = fp64 ? 1 : 0;
+    return DPMM_OK;
+}
+
+dpmm_status dpmm_dump_scores(dpmm_ctx* ctx, const int32_t* cells_dev, int32_t m, double* out_dev)
+{
+    if (!ctx) return fail(DPMM_ERR_ARG, "null ctx");
+    if (m < 0) return fail(DPMM_ERR_ARG, "m must be >= 0");
+    if (m > 0 && (!cells_dev || !out_dev)) return fail(DPMM_ERR_ARG, "null argument");
+    if (!ctx->tables_valid) return fail(DPMM_ERR_STATE, "no sweep has drawn parameters yet");
+    dpmm_status s = set_device(ctx);
+    if (s != DPMM_OK) return s;
+    if (m > 0) launch_dump_scores(ctx->ws, ctx->c[ctx->cur], cells_dev, m, out_dev, ctx->stream);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
     return DPMM_OK;
 }
 
@@ -636,27 +690,42 @@ dpmm_status dpmm_timing_enable(dpmm_ctx* ctx, int32_t enable)
     if (s != DPMM_OK) return s;
     if (enable && ctx->ev.empty()) {
         ctx->ev.resize(2 * kMaxTimed);
+        ctx->ev_stage.assign(kMaxTimed, 0);
         for (auto& e : ctx->ev) HIP_TRY(hipEventCreate(&e));
     }
     ctx->timing = enable != 0;
     return DPMM_OK;
 }
 
-dpmm_status dpmm_timing_read(dpmm_ctx* ctx, double* total_ms, int64_t* launches)
+dpmm_status dpmm_timing_stages(dpmm_ctx* ctx, double* stage_ms, int64_t* stage_count)
 {
-    if (!ctx || !total_ms || !launches) return fail(DPMM_ERR_ARG, "null argument");
+    if (!ctx || !stage_ms || !stage_count) return fail(DPMM_ERR_ARG, "null argument");
     dpmm_status s = set_device(ctx);
     if (s != DPMM_OK) return s;
     HIP_TRY(hipStreamSynchronize(ctx->stream));
-    double tot = 0.0;
+    for (int q = 0; q < DPMM_NUM_STAGES; ++q) {
+        stage_ms[q] = 0.0;
+        stage_count[q] = 0;
+    }
     for (int q = 0; q < ctx->n_timed; ++q) {
         float ms = 0.0f;
         HIP_TRY(hipEventElapsedTime(&ms, ctx->ev[2 * q], ctx->ev[2 * q + 1]));
-        tot += ms;
+        stage_ms[ctx->ev_stage[q]] += ms;
+        stage_count[ctx->ev_stage[q]] += 1;
     }
-    *total_ms = tot;
-    *launches = ctx->n_timed;
     ctx->n_timed = 0;
+    return DPMM_OK;
+}
+
+dpmm_status dpmm_timing_read(dpmm_ctx* ctx, double* total_ms, int64_t* launches)
+{
+    if (!ctx || !total_ms || !launches) return fail(DPMM_ERR_ARG, "null argument");
+    double ms[DPMM_NUM_STAGES];
+    int64_t cnt[DPMM_NUM_STAGES];
+    dpmm_status s = dpmm_timing_stages(ctx, ms, cnt);
+    if (s != DPMM_OK) return s;
+    *total_ms = ms[DPMM_STAGE_ASSIGN];
+    *launches = cnt[DPMM_STAGE_ASSIGN];
     return DPMM_OK;
 }
 

@@ -113,7 +113,7 @@ __device__ void cluster_pass(const Ws& ws, const AssignArgs& a, T* tab, int64_t 
                 if (kk >= K) continue;
                 const T lp = (T)ws.logpi[kk];
                 const T v = lp + acc[k4 + q] + gumbel_of<T>(w.w[q]);
-                if (a.dbg && K + 2 <= a.dbg_stride) a.dbg[i * a.dbg_stride + kk] = (float)acc[k4 + q];
+                if (a.dbg && K + 2 <= a.dbg_stride) put_dbg(a.dbg, a.dbg64, i * a.dbg_stride + kk, (double)acc[k4 + q]);
                 if (v > top.v1) {
                     top.v2 = top.v1; top.a2 = top.a1; top.p2 = top.p1;
                     top.v1 = v; top.a1 = acc[k4 + q]; top.p1 = lp; top.k1 = kk;
@@ -148,8 +148,14 @@ __global__ void __launch_bounds__(kAssignThreads) k_assign_valu(Ws ws, AssignArg
         const float gap = (float)(top.v1 - top.v2);
         const float bnd = score_bound((float)top.a1, (float)top.p1, e - b) +
                           score_bound((float)top.a2, (float)top.p2, e - b);
-        if (gap <= bnd || rel_margin((float)top.v1, (float)top.v2) < a.refine_tol) flags |= kRefineCluster;
+        // within the bound plus the near-tie margin: the FP64 decision could
+        // differ, or be a near tie (counted by the re-score)
+        const float near = (float)kNearTie * fmaxf(1.0f, fabsf((float)top.v1));
+        if (gap <= bnd + near || rel_margin((float)top.v1, (float)top.v2) < a.refine_tol) flags |= kRefineCluster;
     }
+    if (valid && sizeof(T) == 8 && K >= 2 &&
+        (double)(top.v1 - top.v2) / fmax(1.0, fabs((double)top.v1)) < kNearTie)
+        atomicAdd(&ws.st->counters[kCntNearTie], 1ull);
 
     if (!valid) return;
     const int k = top.k1;
@@ -212,20 +218,48 @@ __global__ void k_refine(Ws ws, AssignArgs a)
         const int64_t b = ws.roff[i], e = ws.roff[i + 1];
         int k = a.c_new[i];
         if (item & kRefineCluster) {
-            double best = -INFINITY;
+            double best = -INFINITY, second = -INFINITY;
             int bk = 0;
             Words w{};
             for (int kk = 0; kk < K; ++kk) {
                 if ((kk & 3) == 0) w = philox(ws.seed, (uint32_t)i, (uint32_t)(kk >> 2), a.step, kGumbelC, 0u);
                 const double v = ws.logpi[kk] + row_dot64(ws, b, e, ws.lt64 + (int64_t)kk * ws.G) +
                                  gumbel_of<double>(w.w[kk & 3]);
-                if (v > best) { best = v; bk = kk; }
+                if (v > best) { second = best; best = v; bk = kk; }
+                else if (v > second) second = v;
             }
             k = bk;
+            if (K >= 2 && (best - second) / fmax(1.0, fabs(best)) < kNearTie)
+                atomicAdd(&ws.st->counters[kCntNearTie], 1ull);
         }
         a.c_new[i] = k;
         atomicAdd(&ws.st->counters[kCntRefined], 1ull);
     }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 scores of listed cells (debug output): one workgroup per listed cell,
+// one thread per column, each walking the cell's packed row.
+// ---------------------------------------------------------------------------
+__global__ void k_dump_scores(Ws ws, const int32_t* c, const int32_t* cells, int32_t m, double* out)
+{
+    const int K = ws.st->K;
+    for (int j = blockIdx.x; j < m; j += gridDim.x) {
+        const int64_t i = cells[j];
+        if (i < 0 || i >= ws.N) continue;
+        const int64_t b = ws.roff[i], e = ws.roff[i + 1];
+        const int k = c[i];
+        for (int col = threadIdx.x; col < K + 2; col += blockDim.x) {
+            const int row = col < K ? col : ws.k_max + 2 * k + (col - K);
+            out[(int64_t)j * (K + 2) + col] = row_dot64(ws, b, e, ws.lt64 + (int64_t)row * ws.G);
+        }
+    }
+}
+
+void launch_dump_scores(const Ws& ws, const int32_t* c, const int32_t* cells, int32_t m, double* out, hipStream_t s)
+{
+    const int blocks = m < 4096 ? (m > 0 ? m : 1) : 4096;
+    hipLaunchKernelGGL(k_dump_scores, dim3(blocks), dim3(64), 0, s, ws, c, cells, m, out);
 }
 
 void launch_refine(const Ws& ws, const AssignArgs& a, hipStream_t s)

@@ -272,7 +272,7 @@ __global__ void __launch_bounds__(kMfmaThreads) __attribute__((amdgpu_waves_per_
                     const float s = sc[t * SS + k4 + q];
                     const float lp = (float)ws.logpi[kk];
                     const float v = lp + s + gumbel32(w.w[q]);
-                    if (a.dbg && K + 2 <= a.dbg_stride) a.dbg[i * a.dbg_stride + kk] = s;
+                    if (a.dbg && K + 2 <= a.dbg_stride) put_dbg(a.dbg, a.dbg64, i * a.dbg_stride + kk, (double)s);
                     if (v > t1) {
                         t2 = t1; a2 = a1; p2 = p1;
                         t1 = v; a1 = s; p1 = lp; k1 = kk;
@@ -287,7 +287,8 @@ __global__ void __launch_bounds__(kMfmaThreads) __attribute__((amdgpu_waves_per_
     bool uncertain = false;
     if (K >= 2) {
         const float bnd = bf16_bound(a1, p1, nsteps) + bf16_bound(a2, p2, nsteps);
-        if (t1 - t2 <= bnd || (t1 - t2) / fmaxf(1.0f, fabsf(t1)) < a.refine_tol) uncertain = true;
+        const float near = (float)kNearTie * fmaxf(1.0f, fabsf(t1));
+        if (t1 - t2 <= bnd + near || (t1 - t2) / fmaxf(1.0f, fabsf(t1)) < a.refine_tol) uncertain = true;
     }
     a.c_new[i] = k1;
     if (uncertain) {

@@ -376,11 +376,28 @@ __global__ void k_stats_atomic(Ws ws, const int32_t* __restrict__ c, const uint8
     }
 }
 
+// Zero n 32-bit words with a kernel (unlike a memset node it is safe in a
+// captured graph, and its launch error is seen by hipGetLastError).
+__global__ void k_zero_words(uint32_t* p, int64_t n)
+{
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
+        p[q] = 0u;
+}
+
+void launch_zero(void* p, size_t bytes, hipStream_t s)
+{
+    const int64_t n = (int64_t)(bytes / 4);
+    if (n <= 0) return;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 2048) blocks = 2048;
+    hipLaunchKernelGGL(k_zero_words, dim3((unsigned)blocks), dim3(256), 0, s, reinterpret_cast<uint32_t*>(p), n);
+}
+
 void launch_sort(const Ws& ws, const int32_t* c, const uint8_t* cs, int by_cluster, hipStream_t s,
                  bool counts_cleared, const int32_t* c_prev)
 {
     const int ng = by_cluster ? ws.k_max : 2 * ws.k_max;
-    if (!counts_cleared) hipMemsetAsync(ws.grp_cnt, 0, sizeof(int32_t) * (size_t)ng, s);
+    if (!counts_cleared) launch_zero(ws.grp_cnt, sizeof(int32_t) * (size_t)ng, s);
     const unsigned sb = (unsigned)((ws.N + kSortCellsPerBlock - 1) / kSortCellsPerBlock);
     hipLaunchKernelGGL(k_group_count, dim3(sb), dim3(kSortThreads), sizeof(uint32_t) * (size_t)ng, s, ws, c, cs,
                        by_cluster);
@@ -391,7 +408,7 @@ void launch_sort(const Ws& ws, const int32_t* c, const uint8_t* cs, int by_clust
 
 void launch_stats(const Ws& ws, const int32_t* c, const uint8_t* cs, hipStream_t s)
 {
-    hipMemsetAsync(ws.ssub, 0, sizeof(unsigned long long) * 2 * (size_t)ws.k_max * (size_t)ws.G, s);
+    launch_zero(ws.ssub, sizeof(unsigned long long) * 2 * (size_t)ws.k_max * (size_t)ws.G, s);
     launch_sort(ws, c, cs, 0, s);
     if (ws.G <= kStatMaxGenes) {
         const unsigned blocks = (unsigned)((ws.N + kStatCells - 1) / kStatCells);

@@ -75,8 +75,20 @@ enum Counter {
     kCntKmaxSkips = 5,
     kCntRefined = 6,
     kCntEvals = 7,        // sum over sweeps of N (K + 2)
-    kNumCounters = 8
+    kCntNearTie = 8,      // cluster decisions whose FP64 relative margin is below kNearTie
+    kNumCounters = 9
 };
+
+// Relative Gumbel-max margin (top1 - top2) / max(1, |top1|) below which a
+// decision is a near tie: counted, and always taken in FP64.
+constexpr double kNearTie = 1e-6;
+
+// optional per-cell score dump of a sweep, FP32 or FP64
+__host__ __device__ inline void put_dbg(void* dbg, int dbg64, int64_t idx, double v)
+{
+    if (dbg64) reinterpret_cast<double*>(dbg)[idx] = v;
+    else reinterpret_cast<float*>(dbg)[idx] = (float)v;
+}
 
 struct DevState {
     int32_t K;            // current number of clusters
@@ -88,6 +100,7 @@ struct DevState {
     int32_t has_new;      // 1 while cluster K - 1 is the new cluster of the current sweep
     int32_t pad;
     unsigned long long counters[kNumCounters];
+    double log_joint;     // written by launch_log_joint
 };
 
 // Packed count entry: gene in the low 16 bits, count in the high 16 bits.

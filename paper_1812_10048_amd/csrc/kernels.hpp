@@ -7,6 +7,7 @@
 namespace dpmm {
 
 // bookkeeping.hip
+void launch_zero(void* p, size_t bytes, hipStream_t s);   // bytes: a multiple of 4
 void launch_exclusive_scan(int64_t* v, int64_t n, int64_t* tile_sums, hipStream_t s);
 void launch_pack(const int64_t* row_ptr, const int32_t* col, const int32_t* val, int64_t N, int32_t G, int64_t nnz,
                  int64_t* roff, int64_t* tile_sums, uint32_t* ent, DevState* st, hipStream_t s);
@@ -35,8 +36,9 @@ struct SubArgs {
     const int32_t* c_new;
     uint8_t* cs_new;
     uint32_t step;
-    float* dbg;
+    void* dbg;            // optional score dump (FP32, or FP64 when dbg64), row stride dbg_stride
     int32_t dbg_stride;
+    int32_t dbg64;
 };
 void launch_sub_stats(const Ws& ws, const SubArgs& a, hipStream_t s);
 hipError_t sub_stats_cells(int64_t N, int G, int32_t* cells);
@@ -54,8 +56,9 @@ struct AssignArgs {
     int32_t* c_new;
     uint8_t* cs_new;
     uint32_t step;
-    float* dbg;           // optional score dump, row stride dbg_stride
+    void* dbg;            // optional score dump (FP32, or FP64 when dbg64), row stride dbg_stride
     int32_t dbg_stride;
+    int32_t dbg64;
     int32_t refine;       // queue uncertain decisions for the FP64 re-score
     float refine_tol;     // extra relative-margin threshold (0: bound only)
     int32_t k_hint;       // recent K known to the host (sizes the MFMA column tiles)
@@ -65,6 +68,9 @@ void launch_assign_fp64(const Ws& ws, const AssignArgs& a, hipStream_t s);
 void launch_assign_bf16(const Ws& ws, const AssignArgs& a, hipStream_t s);
 hipError_t configure_assign_bf16();
 void launch_refine(const Ws& ws, const AssignArgs& a, hipStream_t s);
+// FP64 scores of listed cells against the last redraw's parameters: K cluster
+// columns, then the two sub-clusters of the cell's cluster c[i] (row stride K + 2)
+void launch_dump_scores(const Ws& ws, const int32_t* c, const int32_t* cells, int32_t m, double* out, hipStream_t s);
 
 // splitmerge.hip
 void launch_lgamma_beta(const Ws& ws, hipStream_t s);   // lgbeta = lgamma(beta), wherever beta changes
@@ -72,6 +78,9 @@ void launch_split_ratios(const Ws& ws, const int32_t* c, hipStream_t s);
 void launch_random_split(const Ws& ws, const int32_t* c, uint8_t* cs, uint32_t step, hipStream_t s);
 void launch_merge_ratios(const Ws& ws, hipStream_t s);
 void launch_sm_decide(const Ws& ws, int merge_pass, uint32_t step, hipStream_t s);
+// collapsed log joint log p(c) + sum_k logDM(s_k) (eq. 10 with Gamma(alpha), eq. 12
+// integrated against eq. 28) into ws.st->log_joint
+void launch_log_joint(const Ws& ws, hipStream_t s);
 
 // dm.hip
 void launch_dm_logmarginal(const int64_t* sv, int32_t J, int32_t G, const double* beta, double* out, hipStream_t s);

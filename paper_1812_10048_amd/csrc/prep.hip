@@ -99,8 +99,8 @@ __global__ void __launch_bounds__(kPrepThreads) k_filter_fill(const int64_t* __r
 void launch_gene_moments(const int32_t* col, const int32_t* val, int64_t nnz, int32_t G, unsigned long long* sum,
                          unsigned long long* sumsq, hipStream_t s)
 {
-    hipMemsetAsync(sum, 0, sizeof(unsigned long long) * (size_t)G, s);
-    hipMemsetAsync(sumsq, 0, sizeof(unsigned long long) * (size_t)G, s);
+    launch_zero(sum, sizeof(unsigned long long) * (size_t)G, s);
+    launch_zero(sumsq, sizeof(unsigned long long) * (size_t)G, s);
     if (nnz <= 0) return;
     int64_t blocks = (nnz + kPrepThreads - 1) / kPrepThreads;
     if (blocks > 8192) blocks = 8192;

@@ -248,6 +248,32 @@ static void launch_sm_pair(const Ws& ws, int mode, hipStream_t s)
     hipLaunchKernelGGL(k_sm_finish, dim3((unsigned)kb), dim3(64), 0, s, ws, mode, T);
 }
 
+// The collapsed log joint of the current partition (a chain diagnostic):
+// log p(c) + sum_k logDM(s_k), with log p(c) = K log alpha + lgamma(alpha)
+// - lgamma(alpha + N) + sum_k lgamma(n_k) (eq. 10 with Gamma(alpha) restored)
+// and logDM(s_k) from the cluster pass (mode 2).  One thread, clusters in
+// order, compensated.
+__global__ void k_log_joint(Ws ws)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int K = ws.st->K;
+    CSum tot;
+    for (int k = 0; k < K; ++k) {
+        tot.add(ws.dm_k[k]);
+        tot.add(lgamma((double)(ws.nsub[2 * k] + ws.nsub[2 * k + 1])));
+    }
+    tot.add((double)K * log(ws.alpha));
+    tot.add(lgamma(ws.alpha));
+    tot.add(-lgamma(ws.alpha + (double)ws.N));
+    ws.st->log_joint = tot.value();
+}
+
+void launch_log_joint(const Ws& ws, hipStream_t s)
+{
+    launch_sm_pair(ws, 2, s);
+    hipLaunchKernelGGL(k_log_joint, dim3(1), dim3(64), 0, s, ws);
+}
+
 __device__ inline void pair_of(long long p, int* k1, int* k2)
 {
     int b = (int)((1.0 + sqrt(1.0 + 8.0 * (double)p)) * 0.5);
@@ -332,7 +358,7 @@ __global__ void __launch_bounds__(kQThreads) k_split_q(Ws ws, const int32_t* __r
 void launch_split_ratios(const Ws& ws, const int32_t* c, hipStream_t s)
 {
     if (ws.flags & kFlagSplitQ) {
-        hipMemsetAsync(ws.qsub, 0, sizeof(double) * (size_t)ws.k_max, s);
+        launch_zero(ws.qsub, sizeof(double) * (size_t)ws.k_max, s);
         hipLaunchKernelGGL(k_split_q, dim3(256), dim3(kQThreads), sizeof(double) * (size_t)ws.k_max, s, ws, c);
     }
     launch_sm_pair(ws, 0, s);

@@ -229,8 +229,8 @@ __global__ void __launch_bounds__(kSubThreads) __attribute__((amdgpu_waves_per_e
                         ws.lpsub[i] = lp;
                     }
                     if (a.dbg && K + 2 <= a.dbg_stride) {
-                        a.dbg[i * a.dbg_stride + K] = reset ? __builtin_nanf("") : (float)s0;
-                        a.dbg[i * a.dbg_stride + K + 1] = reset ? __builtin_nanf("") : (float)s1;
+                        put_dbg(a.dbg, a.dbg64, i * a.dbg_stride + K, reset ? __builtin_nan("") : s0);
+                        put_dbg(a.dbg, a.dbg64, i * a.dbg_stride + K + 1, reset ? __builtin_nan("") : s1);
                     }
                 }
             }

@@ -54,10 +54,14 @@ class dpmm_stats_out(ctypes.Structure):
                 ("splits_proposed", ctypes.c_int64), ("splits_accepted", ctypes.c_int64),
                 ("merges_proposed", ctypes.c_int64), ("merges_accepted", ctypes.c_int64),
                 ("kmax_skips", ctypes.c_int64), ("refined", ctypes.c_int64), ("gamma_caps", ctypes.c_int64),
-                ("evals", ctypes.c_int64)]
+                ("evals", ctypes.c_int64), ("near_tie", ctypes.c_int64), ("log_joint", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+# DPMM_STAGE_* of include/dpmm.h, in order
+STAGES = ["redraw", "assign", "refine", "subcluster", "compact", "split_merge", "eb"]
 
 
 _P = ctypes.c_void_p
@@ -78,10 +82,12 @@ _SIGNATURES = {
     "dpmm_get_beta": ([_P, _P], _S),
     "dpmm_set_beta": ([_P, _P], _S),
     "dpmm_get_hastings": ([_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), _P, _P], _S),
-    "dpmm_set_debug_scores": ([_P, _P, ctypes.c_int32], _S),
+    "dpmm_set_debug_scores": ([_P, _P, ctypes.c_int32, ctypes.c_int32], _S),
+    "dpmm_dump_scores": ([_P, _P, ctypes.c_int32, _P], _S),
     "dpmm_get_split_tables": ([_P, _P, _P], _S),
     "dpmm_timing_enable": ([_P, ctypes.c_int32], _S),
     "dpmm_timing_read": ([_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)], _S),
+    "dpmm_timing_stages": ([_P, _P, _P], _S),
     "dpmm_dm_logmarginal": ([_P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P], _S),
     "dpmm_dm_grad": ([_P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P], _S),
     "dpmm_gene_moments": ([ctypes.POINTER(dpmm_csr), _P, _P, _P], _S),
@@ -181,8 +187,12 @@ def dpmm_get_hastings(ctx: int, logr_host: int = 0, accept_host: int = 0):
     return p.value, n.value
 
 
-def dpmm_set_debug_scores(ctx: int, scores_dev: int, k_cap: int) -> None:
-    _check(lib().dpmm_set_debug_scores(ctx, scores_dev or None, k_cap))
+def dpmm_set_debug_scores(ctx: int, scores_dev: int, k_cap: int, fp64: bool = False) -> None:
+    _check(lib().dpmm_set_debug_scores(ctx, scores_dev or None, k_cap, 1 if fp64 else 0))
+
+
+def dpmm_dump_scores(ctx: int, cells_dev: int, m: int, out_dev: int) -> None:
+    _check(lib().dpmm_dump_scores(ctx, cells_dev or None, m, out_dev or None))
 
 
 def dpmm_get_split_tables(ctx: int, hi_dev: int, lo_dev: int) -> None:
@@ -191,6 +201,14 @@ def dpmm_get_split_tables(ctx: int, hi_dev: int, lo_dev: int) -> None:
 
 def dpmm_timing_enable(ctx: int, enable: bool) -> None:
     _check(lib().dpmm_timing_enable(ctx, 1 if enable else 0))
+
+
+def dpmm_timing_stages(ctx: int) -> dict:
+    """{stage: (milliseconds, intervals)} since the last read."""
+    ms = (ctypes.c_double * len(STAGES))()
+    n = (ctypes.c_int64 * len(STAGES))()
+    _check(lib().dpmm_timing_stages(ctx, ms, n))
+    return {name: (ms[j], n[j]) for j, name in enumerate(STAGES)}
 
 
 def dpmm_timing_read(ctx: int):

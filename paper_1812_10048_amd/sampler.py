@@ -162,16 +162,28 @@ class Sampler:
         p, n = C.dpmm_get_hastings(self._ctx, logr.ctypes.data, acc.ctypes.data)
         return p, logr[:n].copy(), acc[:n].copy()
 
-    def debug_scores(self, k_cap: int | None):
-        """Start (k_cap given) or stop (None) the per-cell score dump; returns
-        the FP32 [N, k_cap + 2] buffer the next sweeps write into."""
+    def debug_scores(self, k_cap: int | None, fp64: bool = False):
+        """Start (k_cap given) or stop (None) the per-cell score dump of the
+        sweeps' own arithmetic; returns the [N, k_cap + 2] buffer (FP32, or
+        FP64 with ``fp64``) the next sweeps write into."""
         if k_cap is None:
             C.dpmm_set_debug_scores(self._ctx, 0, 0)
             self._dbg = None
             return None
-        self._dbg = torch.full((self.N, k_cap + 2), float("nan"), dtype=torch.float32, device="cuda")
-        C.dpmm_set_debug_scores(self._ctx, self._dbg.data_ptr(), int(k_cap))
+        dt = torch.float64 if fp64 else torch.float32
+        self._dbg = torch.full((self.N, k_cap + 2), float("nan"), dtype=dt, device="cuda")
+        C.dpmm_set_debug_scores(self._ctx, self._dbg.data_ptr(), int(k_cap), fp64)
         return self._dbg
+
+    def dump_scores(self, cells) -> torch.Tensor:
+        """FP64 [m, K + 2] log-likelihoods of the listed cells against the last
+        redraw's parameters: K clusters, then the two sub-clusters of each
+        cell's current cluster."""
+        cl = _dev(torch.as_tensor(cells), torch.int32)
+        K = self.K
+        out = torch.empty(cl.numel(), K + 2, dtype=torch.float64, device="cuda")
+        C.dpmm_dump_scores(self._ctx, cl.data_ptr(), cl.numel(), out.data_ptr())
+        return out
 
     def split_tables(self):
         K = self.K
@@ -185,6 +197,9 @@ class Sampler:
 
     def timing_read(self):
         return C.dpmm_timing_read(self._ctx)
+
+    def timing_stages(self) -> dict:
+        return C.dpmm_timing_stages(self._ctx)
 
 
 class DMLogMarginal(torch.autograd.Function):

@@ -44,6 +44,9 @@ def test_c4_hastings_match_oracle():
     o = oracle.Oracle(rp, col, val, G, init=False, **kw)
     o.set_state(snap["step"], snap["K"], snap["c"].cpu().numpy(), snap["cs"].cpu().numpy(),
                 np.asarray(snap["reset"]))
+    # both sides from the same state (set_state also clears the per-cell eq. 8
+    # probabilities of the split proposal term on both)
+    s.set_state(snap["step"], snap["K"], snap["c"], snap["cs"], snap["reset"])
     passes = []
     for it in range(4):
         o.split_merge()

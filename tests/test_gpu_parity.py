@@ -1,34 +1,31 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
 
 Both sides start from the same seeded data and the same state, draw the same
-Philox numbers, and are compared step by step:
+Philox numbers, and are compared step by step by ``lockstep.Lockstep``:
   * a1  log pi and log theta: |gpu - oracle| <= 1e-9 max(1, |oracle|)
-  * a2  FP32 log-likelihoods (debug dump): |gpu - oracle| <= 1e-4 |oracle|
+  * a2  log-likelihoods: the sweep's own FP64 scores within 1e-9, FP32 within
+        1e-4 relative, split-BF16 within 3e-5 relative, every cell of the
+        68k-cell recipe; FP64 listed-cell dumps within 1e-9
   * a3  labels: bit-exact except cells whose oracle Gumbel-max margin is
-        below 1e-6 (counted; the GPU re-scores uncertain decisions in FP64)
-  * a4  statistics: bit-exact whenever the labels are
+        below 1e-6 (the chains are then re-synchronised and go on); the
+        near-tie counter equal to the oracle's count
+  * a4  statistics: bit-exact after every step; the log joint within 1e-9
   * a5  log R: |gpu - oracle| <= 1e-9 x (sum of the magnitudes of its terms);
         accept flags and resulting labels equal
 """
-import math
-import sys
-
 import numpy as np
 import pytest
 import torch
 
 import oracle
+from lockstep import Lockstep, say
 from paper_1812_10048_amd import synth
 from paper_1812_10048_amd.sampler import Sampler
 
 pytestmark = pytest.mark.gpu
 
-MARGIN = 1e-6
-
-
-def _say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
+# the plain passes (one fair coin: sub-cluster split or merge), flags = 0
+COLLAPSED = dict(split_q=False, new_cluster=False, random_split=False)
 
 
 def _sampler(d, precision, **kw):
@@ -40,134 +37,47 @@ def _oracle(d, **kw):
     return oracle.Oracle(rp, col, val, d.n_genes, **kw)
 
 
-def _labels(s):
-    c, cs = s.labels()
-    return c.cpu().numpy(), cs.cpu().numpy()
-
-
-def _compare_labels(o, s, what):
-    c, cs = _labels(s)
-    bad_c = np.nonzero(c != o.c)[0]
-    bad_s = np.nonzero((c == o.c) & (cs != o.cs))[0]
-    # every mismatch must be a decision the oracle itself took by less than the margin
-    assert np.all(o.margin_c[bad_c] < MARGIN), (what, bad_c[:10], o.margin_c[bad_c][:10])
-    assert np.all(o.margin_s[bad_s] < MARGIN), (what, bad_s[:10], o.margin_s[bad_s][:10])
-    return len(bad_c) + len(bad_s)
-
-
-def _compare_stats(o, s):
-    st = s.stats(with_tables=True)
-    K = st["K"]
-    assert K == o.K
-    assert np.array_equal(st["nsub"], o.nsub[: 2 * K])
-    assert np.array_equal(st["ssub"].cpu().numpy(), o.ssub[: 2 * K])
-    return st
-
-
-def _compare_params(o, s):
-    K = o.K
-    lp, lt = s.params()
-    lp = lp.cpu().numpy()[:K]
-    lt = lt.cpu().numpy()
-    ref_lp = o.logpi[:K]
-    assert np.all(np.abs(lp - ref_lp) <= 1e-9 * np.maximum(1.0, np.abs(ref_lp)))
-    gc = lt[:K]
-    gs = lt[o.k_max: o.k_max + 2 * K]
-    rc = o.logtheta[:K]
-    rs = o.logtheta[o.k_max: o.k_max + 2 * K]
-    err_c = np.max(np.abs(gc - rc) / np.maximum(1.0, np.abs(rc)))
-    err_s = np.max(np.abs(gs - rs) / np.maximum(1.0, np.abs(rs)))
-    assert err_c <= 1e-9 and err_s <= 1e-9, (err_c, err_s)
-    return max(err_c, err_s)
-
-
-def _compare_hastings(o, s):
-    p, logr, acc = s.hastings()
-    assert p == o.sm_pass
-    n = o.sm_n
-    assert len(logr) == n
-    ref = o.sm_logr[:n]
-    scale = o.sm_scale[:n]
-    nan_ref = np.isnan(ref)
-    assert np.array_equal(np.isnan(logr), nan_ref)
-    ok = ~nan_ref
-    err = np.abs(logr[ok] - ref[ok]) / np.maximum(1.0, scale[ok])
-    assert np.all(err <= 1e-9), err.max()
-    assert np.array_equal(acc, o.sm_accept[:n])
-    return float(err.max()) if err.size else 0.0
+def _pair(d, precision, **kw):
+    return _oracle(d, **kw), _sampler(d, precision, **kw)
 
 
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("k_init", [1, 5])
 def test_init_state_matches_oracle(k_init):
-    _say("init", k_init)
+    say("init", k_init)
     d = synth.generate("c1", seed=2, n_cells=700)
-    o = _oracle(d, seed=3, k_max=32, k_init=k_init)
-    s = _sampler(d, "fp32", seed=3, k_max=32, k_init=k_init)
-    c, cs = _labels(s)
-    assert np.array_equal(c, o.c) and np.array_equal(cs, o.cs)
-    _compare_stats(o, s)
+    o, s = _pair(d, "fp32", seed=3, k_max=32, k_init=k_init)
+    c, cs = s.labels()
+    assert np.array_equal(c.cpu().numpy(), o.c) and np.array_equal(cs.cpu().numpy(), o.cs)
+    Lockstep("init", o, s).compare_stats()
 
 
+@pytest.mark.parametrize("moves", ["paper", "collapsed"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "split_bf16"])
-def test_chain_lockstep_small_recipe(precision):
-    """Two independent chains, one per implementation, from the same seed:
-    identical at every sweep and split/merge while no near-tie occurs."""
-    _say("lockstep", precision)
+def test_chain_lockstep_small_recipe(precision, moves):
+    """Two chains, one per implementation, from the same seed: compared at
+    every sweep and split/merge for 25 iterations from one cluster."""
+    say("lockstep", precision, moves)
     d = synth.generate("c1", seed=0)
-    kw = dict(alpha=1.0, beta=1.0, seed=11, k_max=64, k_init=1)
-    o = _oracle(d, **kw)
-    s = _sampler(d, precision, **kw)
-    compared = 0
-    for it in range(25):
-        o.sweep()
-        s.sweep(1)
-        _compare_params(o, s)
-        if _compare_labels(o, s, f"sweep {it}"):
-            _say("near-tie divergence at sweep", it)
-            break
-        _compare_stats(o, s)
-        o.split_merge()
-        s.split_merge()
-        _compare_hastings(o, s)
-        if _compare_labels(o, s, f"split/merge {it}"):
-            break
-        _compare_stats(o, s)
-        compared += 1
-    assert compared >= 10
-    st = s.stats()
-    _say("K", st["K"], "refined", st["refined"], "splits", st["splits_accepted"], "merges", st["merges_accepted"])
+    kw = dict(alpha=1.0, beta=1.0, seed=11, k_max=64, k_init=1, **(COLLAPSED if moves == "collapsed" else {}))
+    ls = Lockstep(f"c1-{precision}-{moves}", *_pair(d, precision, **kw))
+    ls.iterate(25)
+    ls.finish()
+    assert ls.o.K >= 3
 
 
 @pytest.mark.parametrize("precision", ["fp64", "split_bf16"])
 def test_split_q_chain_lockstep(precision):
-    """With the split proposal term (DPMM_FLAG_SPLIT_Q, Section 2.3) on both
-    sides: split ratios within the condition-aware tolerance of the oracle's,
-    the same accept decisions and labels, for several split passes."""
-    _say("split_q lockstep", precision)
+    """The split proposal term alone (DPMM_FLAG_SPLIT_Q, Section 2.3): split
+    ratios, decisions and labels in lockstep, several split passes."""
+    say("split_q lockstep", precision)
     d = synth.generate("c1", seed=4)
-    kw = dict(alpha=1.0, beta=1.0, seed=17, k_max=64, k_init=1)
-    o = _oracle(d, split_q=True, **kw)
-    s = _sampler(d, precision, split_q=True, **kw)
-    splits = 0
-    for it in range(25):
-        o.sweep()
-        s.sweep(1)
-        _compare_params(o, s)
-        if _compare_labels(o, s, f"sweep {it}"):
-            break
-        _compare_stats(o, s)
-        o.split_merge()
-        s.split_merge()
-        _compare_hastings(o, s)
-        if o.sm_pass == 0 and np.any(~np.isnan(o.sm_logr[: o.sm_n])):
-            splits += 1
-        if _compare_labels(o, s, f"split/merge {it}"):
-            break
-        _compare_stats(o, s)
-    assert splits >= 2
-    _say("K", s.stats()["K"], "split passes compared", splits)
+    kw = dict(alpha=1.0, beta=1.0, seed=17, k_max=64, k_init=1, **{**COLLAPSED, "split_q": True})
+    ls = Lockstep(f"split_q-{precision}", *_pair(d, precision, **kw))
+    ls.iterate(25)
+    ls.finish()
+    assert ls.passes[0] >= 2
 
 
 def _three_groups():
@@ -180,94 +90,75 @@ def _three_groups():
 
 @pytest.mark.parametrize("case", ["three_groups-fp64", "three_groups-split_bf16", "c1-fp32"])
 def test_new_cluster_chain_lockstep(case):
-    """With the Gibbs step over K + 1 clusters (DPMM_FLAG_NEW_CLUSTER, eq. 4) on
-    both sides (and the split proposal term on c1): parameters, labels,
-    statistics and Hastings ratios in lockstep with the oracle; on the
-    three-group data the Gibbs step itself opens clusters."""
+    """The Gibbs step over K + 1 clusters (DPMM_FLAG_NEW_CLUSTER, eq. 4) on both
+    sides (with the split proposal term on c1); on the three-group data the
+    Gibbs step itself opens clusters."""
     data, precision = case.split("-")
-    _say("new_cluster lockstep", case)
+    say("new_cluster lockstep", case)
     if data == "c1":
         d = synth.generate("c1", seed=7)
-        kw = dict(alpha=1.0, beta=1.0, seed=23, k_max=64, k_init=1, new_cluster=True, split_q=True)
+        kw = dict(alpha=1.0, beta=1.0, seed=23, k_max=64, k_init=1,
+                  **{**COLLAPSED, "new_cluster": True, "split_q": True})
     else:
         d = _three_groups()
-        kw = dict(alpha=2.0, beta=0.2, seed=9, k_max=16, k_init=1, new_cluster=True)
-    o = _oracle(d, **kw)
-    s = _sampler(d, precision, **kw)
+        kw = dict(alpha=2.0, beta=0.2, seed=9, k_max=16, k_init=1, **{**COLLAPSED, "new_cluster": True})
+    ls = Lockstep(f"new_cluster-{case}", *_pair(d, precision, **kw))
     opened = 0
-    compared = 0
     for it in range(30):
-        k0 = o.K
-        o.sweep()
-        s.sweep(1)
-        _compare_params(o, s)
-        if _compare_labels(o, s, f"sweep {it}"):
-            break
-        _compare_stats(o, s)
-        opened += o.K > k0
-        o.split_merge()
-        s.split_merge()
-        _compare_hastings(o, s)
-        if _compare_labels(o, s, f"split/merge {it}"):
-            break
-        _compare_stats(o, s)
-        compared += 1
-    assert compared >= 10
+        k0 = ls.o.K
+        ls.sweep()
+        opened += ls.o.K > k0
+        ls.split_merge()
+    ls.finish(opened=opened)
     if data == "three_groups":
         assert opened >= 1
-    _say("K", s.stats()["K"], "sweeps that opened a cluster", opened)
 
 
 @pytest.mark.parametrize("case", ["c1-split_bf16", "c1-fp64", "tiny-fp64"])
 def test_random_split_chain_lockstep(case):
-    """With the random-split pass (DPMM_FLAG_RANDOM_SPLIT, chain B of Section
-    2.4) on both sides: the pass chosen, the ratios of every pass, the accept
-    decisions, labels and statistics in lockstep with the oracle; on the tiny
-    high-alpha data random splits are accepted."""
+    """The random-split pass (DPMM_FLAG_RANDOM_SPLIT, chain B of Section 2.4):
+    the pass chosen, every ratio, the decisions, labels and statistics; on the
+    tiny high-alpha data random splits are accepted."""
     data, precision = case.split("-")
-    _say("random_split lockstep", case)
+    say("random_split lockstep", case)
     if data == "c1":
         d = synth.generate("c1", seed=12)
-        kw = dict(alpha=1.0, beta=1.0, seed=31, k_max=64, k_init=1, random_split=True)
+        kw = dict(alpha=1.0, beta=1.0, seed=31, k_max=64, k_init=1, **{**COLLAPSED, "random_split": True})
     else:
         X = np.random.default_rng(3).integers(1, 4, size=(24, 3))
         d = synth.from_dense(X)
-        kw = dict(alpha=200.0, beta=1.0, seed=5, k_max=16, k_init=1, random_split=True)
-    o = _oracle(d, **kw)
-    s = _sampler(d, precision, **kw)
-    rpasses = accepted = 0
+        kw = dict(alpha=200.0, beta=1.0, seed=5, k_max=16, k_init=1, **{**COLLAPSED, "random_split": True})
+    ls = Lockstep(f"random_split-{case}", *_pair(d, precision, **kw))
+    accepted_random = 0
     for it in range(30):
-        o.sweep()
-        s.sweep(1)
-        _compare_params(o, s)
-        if _compare_labels(o, s, f"sweep {it}"):
-            break
-        _compare_stats(o, s)
-        o.split_merge()
-        s.split_merge()
-        _compare_hastings(o, s)
-        if o.sm_pass == 2:
-            rpasses += 1
-            accepted += int(o.sm_accept[: o.sm_n].sum())
-        if _compare_labels(o, s, f"split/merge {it}"):
-            break
-        _compare_stats(o, s)
-    assert rpasses >= 3
+        ls.sweep()
+        ls.split_merge()
+        if ls.o.sm_pass == 2:
+            accepted_random += int(ls.o.sm_accept[: ls.o.sm_n].sum())
+    ls.finish(accepted_random=accepted_random)
+    assert ls.passes[2] >= 3
     if data == "tiny":
-        assert accepted >= 1
-    _say("K", s.stats()["K"], "random passes", rpasses, "accepted", accepted)
+        assert accepted_random >= 1
 
 
 SCORE_TOL = {"fp32": 1e-4, "split_bf16": 3e-5}
 
 
+def _sweep_columns(o, K):
+    """Clusters of a sweep that started with K: K + 1 when the Gibbs step runs
+    over a new cluster (eq. 4) and there is room for it, else K."""
+    return K + 1 if (o._st.flags & oracle.NEW_CLUSTER) and K < o.k_max else K
+
+
 @pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
 def test_sweep_at_68k_cells_matches_oracle(precision):
-    """The 68,000 x 1,000 recipe: one sweep and one split/merge from a state
-    reached by the oracle, with the log-likelihoods checked cell by cell
-    (FP32: 1e-4 relative; split-BF16: 3e-5 relative, its certified bound is
-    about 1.5e-5)."""
-    _say("c2 full size", precision)
+    """The 68,000 x 1,000 recipe at full size: two sweeps and split/merge calls
+    from a state the oracle reached, with the sweep's own log-likelihoods of
+    every cell checked against FP64 (FP32 1e-4 relative, split-BF16 3e-5
+    relative; the sub-cluster scores are FP64 in both and checked at 1e-9 in
+    the second sweep, when no cluster re-draws its sub-labels), and the FP64
+    listed-cell dump at 1e-9."""
+    say("c2 full size", precision)
     d = synth.generate("c2", seed=0)
     kw = dict(alpha=1.0, beta=1.0, seed=5, k_max=64)
     o = _oracle(d, k_init=1, **kw)
@@ -275,43 +166,71 @@ def test_sweep_at_68k_cells_matches_oracle(precision):
     snap = o.snapshot()
     s = _sampler(d, precision, k_init=1, **kw)
     s.set_state(snap["step"], snap["K"], snap["c"], snap["cs"], snap["reset"])
-    _compare_stats(o, s)
-    K = o.K
-    dbg = s.debug_scores(K)
-    o.sweep()
-    s.sweep(1)
-    _compare_params(o, s)
-    mism = _compare_labels(o, s, "c2 sweep")
-    if mism == 0:
-        _compare_stats(o, s)
-    # FP32 log-likelihoods of a sample of cells against FP64
-    rng = np.random.default_rng(0)
-    cells = np.sort(rng.choice(d.n_cells, size=3000, replace=False))
-    ref = o.cell_logliks(cells)
-    got = dbg.cpu().numpy()[cells]
-    K2 = o.K
-    assert K2 <= K
-    gk = got[:, :K2]
-    rk = ref[:, :K2]
-    tol = SCORE_TOL[precision]
-    rel = np.abs(gk - rk) / np.maximum(1.0, np.abs(rk))
-    _say("max relative log-likelihood error", float(rel.max()), "median", float(np.median(rel)))
-    assert np.all(np.abs(gk - rk) <= tol * np.abs(rk) + 1e-3)
-    live = ~np.isnan(got[:, K2])   # cells of clusters not flagged for reset
-    # the two sub-cluster scores are FP64 in every precision
-    assert np.all(np.abs(got[live, K2:K2 + 2] - ref[live, K2:K2 + 2]) <= 1e-6 * np.abs(ref[live, K2:K2 + 2]) + 1e-3)
-    s.debug_scores(None)
-    o.split_merge()
-    s.split_merge()
-    if mism == 0:
-        _compare_hastings(o, s)
-        _compare_labels(o, s, "c2 split/merge")
-        _compare_stats(o, s)
-    _say("c2 mismatches", mism, "refined", s.stats()["refined"])
+    o.set_state(snap["step"], snap["K"], snap["c"], snap["cs"], snap["reset"])
+    ls = Lockstep(f"c2-{precision}", o, s)
+    ls.compare_stats()
+    worst = {}
+    for sweep in range(2):
+        K = o.K
+        dbg = s.debug_scores(K + 1, fp64=True)       # room for the new cluster of eq. 4
+        ls.sweep()
+        s.debug_scores(None)
+        got = dbg.cpu().numpy()
+        Ks, K2 = _sweep_columns(o, K), o.K
+        ref = o.cell_logliks(np.arange(d.n_cells))
+        Kc = min(Ks, K2)
+        gk, rk = got[:, :Kc], ref[:, :Kc]
+        rel = np.abs(gk - rk) / np.maximum(1.0, np.abs(rk))
+        worst[f"cluster_rel_err_sweep{sweep}"] = float(rel.max())
+        assert np.all(np.abs(gk - rk) <= SCORE_TOL[precision] * np.abs(rk) + 1e-3)
+        live = ~np.isnan(got[:, Ks])
+        if sweep == 1:
+            assert live.mean() > 0.99          # no cluster re-drew its sub-labels
+        if K2 >= K:                            # no cluster of the sweep renumbered
+            sub_err = (np.abs(got[live, Ks:Ks + 2] - ref[live, K2:K2 + 2]) /
+                       np.maximum(1.0, np.abs(ref[live, K2:K2 + 2])))
+            worst[f"sub_rel_err_sweep{sweep}"] = float(sub_err.max(initial=0.0))
+            assert np.all(sub_err <= 1e-9)
+        # FP64 dump of listed cells: one per block of 256 and the last cell
+        pick = np.unique(np.r_[np.arange(0, d.n_cells, 256), d.n_cells - 1]).astype(np.int32)
+        dump = s.dump_scores(pick).cpu().numpy()
+        dref = ref[pick]
+        assert np.all(np.abs(dump - dref) <= 1e-9 * np.maximum(1.0, np.abs(dref)))
+        ls.split_merge()
+    ls.finish(**worst)
+
+
+def test_fp64_sweep_scores_match_at_fp64_tolerance():
+    """The FP64 precision: the sweep's own cluster and sub-cluster scores of
+    every cell within 1e-9 relative of the oracle's."""
+    say("fp64 scores")
+    d = synth.generate("c1", seed=5)
+    kw = dict(alpha=1.0, beta=1.0, seed=3, k_max=32, k_init=4)
+    o, s = _pair(d, "fp64", **kw)
+    ls = Lockstep("fp64-scores", o, s)
+    checked = 0
+    for sweep in range(4):
+        K = o.K
+        dbg = s.debug_scores(K + 1, fp64=True)
+        ls.sweep()
+        s.debug_scores(None)
+        got = dbg.cpu().numpy()
+        Ks, K2 = _sweep_columns(o, K), o.K
+        ref = o.cell_logliks(np.arange(d.n_cells))
+        Kc = min(Ks, K2)
+        assert np.all(np.abs(got[:, :Kc] - ref[:, :Kc]) <= 1e-9 * np.maximum(1.0, np.abs(ref[:, :Kc])))
+        if K2 >= K:
+            live = ~np.isnan(got[:, Ks])
+            g, r = got[live, Ks:Ks + 2], ref[live, K2:K2 + 2]
+            assert np.all(np.abs(g - r) <= 1e-9 * np.maximum(1.0, np.abs(r)))
+            checked += int(live.sum())
+        ls.split_merge()
+    ls.finish(sub_scores_checked=checked)
+    assert checked > 0
 
 
 def test_empirical_bayes_step_matches_oracle():
-    _say("eb")
+    say("eb")
     d = synth.generate("c1", seed=4, n_cells=1200)
     kw = dict(alpha=1.0, beta=0.5, seed=9, k_max=32)
     o = _oracle(d, k_init=1, **kw)
@@ -319,6 +238,8 @@ def test_empirical_bayes_step_matches_oracle():
     snap = o.snapshot()
     s = _sampler(d, "fp32", k_init=1, **kw)
     s.set_state(snap["step"], snap["K"], snap["c"], snap["cs"], snap["reset"])
+    o.set_state(snap["step"], snap["K"], snap["c"], snap["cs"], snap["reset"])
+    ls = Lockstep("eb", o, s)
     for _ in range(3):
         o.eb_update()
         s.eb_update()
@@ -326,22 +247,17 @@ def test_empirical_bayes_step_matches_oracle():
         assert np.all(np.abs(b - o.beta) <= 1e-9 * np.abs(o.beta)), np.max(np.abs(b - o.beta) / o.beta)
     # the Hastings sums read per-gene log-gamma tables, which must follow beta
     # wherever it is written: after the EB steps, and after set_beta
-    o.split_merge()
-    s.split_merge()
-    _compare_hastings(o, s)
-    assert _compare_labels(o, s, "eb split/merge") == 0
+    ls.split_merge()
     nb = np.random.default_rng(3).uniform(0.05, 3.0, size=d.n_genes)
     o.beta[:] = nb
     s.beta = torch.from_numpy(nb).cuda()
     for it in range(2):
-        o.split_merge()
-        s.split_merge()
-        _compare_hastings(o, s)
-        assert _compare_labels(o, s, f"set_beta split/merge {it}") == 0
+        ls.split_merge()
+    ls.finish()
 
 
 def test_dm_logmarginal_and_gradient_match_oracle():
-    _say("dm")
+    say("dm")
     from paper_1812_10048_amd.sampler import DMLogMarginal
     rng = np.random.default_rng(1)
     J, G = 36, 2000
@@ -361,19 +277,14 @@ def test_dm_logmarginal_and_gradient_match_oracle():
 
 
 def test_edge_cases():
-    _say("edges")
+    say("edges")
     # a cell with no counts, a single gene, a single cell
     X = np.array([[0, 3, 1], [0, 0, 0], [5, 0, 2], [1, 1, 1]])
     d = synth.from_dense(X)
     for prec in ("fp64", "fp32", "split_bf16"):
-        o = _oracle(d, seed=1, k_max=4, k_init=2)
-        s = _sampler(d, prec, seed=1, k_max=4, k_init=2)
-        for _ in range(6):
-            o.sweep(); s.sweep(1)
-            assert _compare_labels(o, s, "edge") == 0
-            _compare_stats(o, s)
-            o.split_merge(); s.split_merge()
-            assert _compare_labels(o, s, "edge sm") == 0
+        ls = Lockstep(f"edge-{prec}", *_pair(d, prec, seed=1, k_max=4, k_init=2))
+        ls.iterate(6)
+        ls.finish()
     d1 = synth.from_dense(np.array([[7]]))
     s = _sampler(d1, "fp32", seed=0, k_max=2)
     s.iterate(3)
@@ -387,24 +298,29 @@ def test_edge_cases():
     with pytest.raises(C.DpmmError) as e:
         Sampler(torch.tensor([0, 2]), torch.tensor([1, 1], dtype=torch.int32), torch.tensor([1, 1], dtype=torch.int32), 3)
     assert e.value.status == C.DPMM_ERR_DATA
+    # the FP64 dump needs parameters drawn by a sweep
+    s2 = _sampler(d, "fp32", seed=1, k_max=4, k_init=2)
+    with pytest.raises(C.DpmmError) as e:
+        s2.dump_scores([0, 1])
+    assert e.value.status == C.DPMM_ERR_STATE
 
 
 def test_capacity_limit_counts_skipped_splits():
-    _say("kmax")
+    say("kmax")
     d = synth.generate("c1", seed=0, n_cells=600)
     kw = dict(alpha=1.0, beta=1.0, seed=11, k_max=2, k_init=1)
-    o = _oracle(d, **kw)
-    s = _sampler(d, "fp32", **kw)
-    for _ in range(12):
-        o.iterate(1)
-        s.iterate(1)
-        assert _compare_labels(o, s, "kmax") == 0
-    assert s.K <= 2
-    assert s.stats()["kmax_skips"] == o.counters()["kmax_skips"]
+    ls = Lockstep("kmax", *_pair(d, "fp32", **kw))
+    ls.iterate(12)
+    ls.finish()
+    assert ls.s.K <= 2
+    assert ls.s.stats()["kmax_skips"] == ls.o.counters()["kmax_skips"]
 
 
 def test_resume_reproduces_the_chain():
-    _say("resume")
+    """A chain resumed from (step, K, c, cbar, reset, beta) saved between two
+    iterations continues exactly as the uninterrupted one (every cell's eq. 8
+    probability is redrawn by the sweep before the next split pass reads it)."""
+    say("resume")
     d = synth.generate("c1", seed=1, n_cells=900)
     kw = dict(alpha=1.0, beta=0.7, seed=21, k_max=32, k_init=3)
     a = _sampler(d, "fp32", **kw)
@@ -421,10 +337,10 @@ def test_resume_reproduces_the_chain():
             x.iterate(1)
             if (it + 1) % 3 == 0:
                 x.eb_update()
+    ca, csa = a.labels()
     for x in (b, r):
-        cx, csx = _labels(x)
-        ca, csa = _labels(a)
-        assert np.array_equal(cx, ca) and np.array_equal(csx, csa)
+        cx, csx = x.labels()
+        assert torch.equal(cx, ca) and torch.equal(csx, csa)
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64", "split_bf16"])
@@ -432,31 +348,22 @@ def test_resume_reproduces_the_chain():
 def test_many_cluster_kernel_paths(precision, k_init):
     """Cluster counts that select each register-tile width of the assignment
     kernel, its cluster-group loop (K > 64) and the gathered sub-cluster pass."""
-    _say("paths", precision, k_init)
+    say("paths", precision, k_init)
     d = synth.generate("c1", seed=6, n_cells=3000)
     kw = dict(alpha=1.0, beta=1.0, seed=13, k_max=96, k_init=k_init)
-    o = _oracle(d, **kw)
-    s = _sampler(d, precision, **kw)
+    o, s = _pair(d, precision, **kw)
     assert o.K == s.K == k_init
-    for it in range(2):
-        o.sweep()
-        s.sweep(1)
-        _compare_params(o, s)
-        assert _compare_labels(o, s, f"paths sweep {it}") == 0
-        _compare_stats(o, s)
-        o.split_merge()
-        s.split_merge()
-        _compare_hastings(o, s)
-        assert _compare_labels(o, s, f"paths sm {it}") == 0
-        _compare_stats(o, s)
+    ls = Lockstep(f"paths-{precision}-{k_init}", o, s)
+    ls.iterate(2)
+    ls.finish()
 
 
 def test_split_bf16_tables_are_hi_lo_of_log_theta():
     """Row a8: hi = bf16(fp32(log theta)), lo = bf16(fp32(log theta - hi)),
     round to nearest even, and |log theta - hi - lo| <= 2^-17 |log theta|."""
-    _say("split tables")
+    say("split tables")
     d = synth.generate("c1", seed=3, n_cells=1500)
-    s = _sampler(d, "split_bf16", seed=4, k_max=16, k_init=3, beta=0.3)
+    s = _sampler(d, "split_bf16", seed=4, k_max=16, k_init=3, beta=0.3, **COLLAPSED)
     s.sweep(2)
     K = s.K
     _, lt = s.params()
@@ -479,26 +386,14 @@ def test_wide_matrices_take_the_global_memory_paths(precision, n_genes):
     reads its parameters from global memory, above 8192 its histograms are
     global atomics, above 16384 the initial statistics use the atomic kernel;
     the split-BF16 kernel walks a few hundred gene chunks."""
-    _say("wide", precision, n_genes)
+    say("wide", precision, n_genes)
     rec = synth.Recipe("wide", 2500, n_genes, "fixed:900,700,500,400", 0.02, 3000.0, 0.5)
     d = synth.generate(rec, seed=3)
     kw = dict(alpha=1.0, beta=1.0, seed=17, k_max=16, k_init=3)
-    o = _oracle(d, **kw)
-    s = _sampler(d, precision, **kw)
-    _compare_stats(o, s)
-    for it in range(3):
-        o.sweep()
-        s.sweep(1)
-        _compare_params(o, s)
-        if _compare_labels(o, s, f"wide sweep {it}"):
-            break
-        _compare_stats(o, s)
-        o.split_merge()
-        s.split_merge()
-        _compare_hastings(o, s)
-        if _compare_labels(o, s, f"wide sm {it}"):
-            break
-        _compare_stats(o, s)
+    ls = Lockstep(f"wide-{precision}-{n_genes}", *_pair(d, precision, **kw))
+    ls.compare_stats()
+    ls.iterate(3)
+    ls.finish()
 
 
 @pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
@@ -506,29 +401,17 @@ def test_two_hundred_clusters(precision):
     """About 200 clusters of k_max = 256, started from the true partition of
     a 200-cluster matrix: several column groups in both assignment kernels and
     ~20k merge candidates in the single-workgroup decision."""
-    _say("k200", precision)
+    say("k200", precision)
     rec = synth.Recipe("k200", 20000, 500, "dirichlet:200", 0.05, 2000.0, 0.5)
     d = synth.generate(rec, seed=8)
     kw = dict(alpha=1.0, beta=1.0, seed=19, k_max=256, k_init=1)
-    o = _oracle(d, **kw)
-    s = _sampler(d, precision, **kw)
+    o, s = _pair(d, precision, **kw)
     cs0 = np.random.default_rng(2).integers(0, 2, size=d.n_cells)
     reset = np.ones(d.n_true, dtype=np.uint8)
     o.set_state(0, d.n_true, d.z, cs0, reset)
     s.set_state(0, d.n_true, torch.from_numpy(d.z), torch.from_numpy(cs0), reset)
-    _compare_stats(o, s)
+    ls = Lockstep(f"k200-{precision}", o, s)
+    ls.compare_stats()
     assert o.K > 150
-    merges = 0
-    for it in range(4):
-        o.sweep()
-        s.sweep(1)
-        _compare_params(o, s)
-        assert _compare_labels(o, s, f"k200 sweep {it}") == 0
-        _compare_stats(o, s)
-        o.split_merge()
-        s.split_merge()
-        _compare_hastings(o, s)
-        merges += o.sm_pass == 1
-        assert _compare_labels(o, s, f"k200 sm {it}") == 0
-        _compare_stats(o, s)
-    _say("k200 K", o.K, "merge passes", merges)
+    ls.iterate(4)
+    ls.finish()

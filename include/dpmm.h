@@ -182,6 +182,21 @@ dpmm_status dpmm_workspace_size(const dpmm_csr* csr, const dpmm_params* params, 
 dpmm_status dpmm_init(const dpmm_csr* csr, const dpmm_params* params, void* workspace,
                       size_t workspace_bytes, void* stream, dpmm_ctx** out);
 
+/* For callers that cannot allocate memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): dpmm_init without the
+ * workspace argument and without any allocation.  The workspace comes from a
+ * static device array of 64 MiB that the library holds on every GPU it runs
+ * on until the process ends (its last 256 bytes hold the launch hint that
+ * dpmm_init keeps in pinned host memory), and the host context from a static
+ * slot per device.  Matrices whose dpmm_workspace_size exceeds 64 MiB - 256
+ * bytes are rejected with DPMM_ERR_NOMEM.  One such context per GPU at a
+ * time: a second call before dpmm_destroy of the first returns
+ * DPMM_ERR_STATE; calls on contexts that share the storage would race.  The
+ * storage keeps the last context's contents; this call initialises every
+ * part of it that the sampler reads.  Everything else is as dpmm_init
+ * (inputs, stream, results: the same chain draw for draw).  Sync. */
+dpmm_status dpmm_init_static(const dpmm_csr* csr, const dpmm_params* params, void* stream, dpmm_ctx** out);
+
 /* Release the host object.  The workspace is the caller's to free afterwards
  * (after the stream has drained).  Sync. */
 dpmm_status dpmm_destroy(dpmm_ctx* ctx);

@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -159,6 +160,7 @@ struct dpmm_ctx {
     std::vector<int> ev_stage;         // stage of each pair
     int n_timed = 0;
     int32_t* k_host = nullptr;         // pinned copy of K, refreshed after every call
+    bool in_scratch = false;           // workspace and context live in the per-device static storage
 };
 
 namespace {
@@ -197,11 +199,17 @@ dpmm_status read_state(dpmm_ctx* ctx, DevState* out)
 // queue a copy of the device K into the pinned hint (read by later launches)
 dpmm_status refresh_k_hint(dpmm_ctx* ctx)
 {
+    if (!ctx->k_host) return DPMM_OK;
     HIP_TRY(hipMemcpyAsync(ctx->k_host, &ctx->ws.st->K, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
     return DPMM_OK;
 }
 
-int32_t k_hint(const dpmm_ctx* ctx) { return *reinterpret_cast<volatile int32_t*>(ctx->k_host); }
+// Without the mapped hint (a context in static storage) launches are sized for
+// k_max; the kernels loop over cluster groups either way.
+int32_t k_hint(const dpmm_ctx* ctx)
+{
+    return ctx->k_host ? *reinterpret_cast<volatile int32_t*>(ctx->k_host) : ctx->k_max;
+}
 
 // statistics from the current labels, then compaction without touching flags
 dpmm_status recompute_stats(dpmm_ctx* ctx)
@@ -230,8 +238,15 @@ dpmm_status dpmm_workspace_size(const dpmm_csr* csr, const dpmm_params* params, 
     return DPMM_OK;
 }
 
-dpmm_status dpmm_init(const dpmm_csr* csr, const dpmm_params* params, void* workspace, size_t workspace_bytes,
-                      void* stream, dpmm_ctx** out)
+}  // extern "C"
+
+namespace {
+
+// dpmm_init, with the host context either allocated (static_slot == nullptr)
+// or placed in a caller-provided slot, and the K hint either in mapped pinned
+// host memory or, in the static slot's case, in a device word (hint_dev).
+dpmm_status init_impl(const dpmm_csr* csr, const dpmm_params* params, void* workspace, size_t workspace_bytes,
+                      void* stream, dpmm_ctx** out, dpmm_ctx* static_slot, int32_t* hint_dev)
 {
     g_err[0] = 0;
     dpmm_status s = check_args(csr, params);
@@ -244,10 +259,15 @@ dpmm_status dpmm_init(const dpmm_csr* csr, const dpmm_params* params, void* work
     if (workspace_bytes < L.total)
         return fail(DPMM_ERR_NOMEM, "workspace of %zu bytes, %zu needed", workspace_bytes, L.total);
 
-    dpmm_ctx* ctx = new (std::nothrow) dpmm_ctx();
+    dpmm_ctx* ctx = static_slot ? static_slot : new (std::nothrow) dpmm_ctx();
     if (!ctx) return fail(DPMM_ERR_NOMEM, "host allocation failed");
+    ctx->in_scratch = static_slot != nullptr;
+    auto release = [](dpmm_ctx* c) {
+        if (c->in_scratch) *c = dpmm_ctx();
+        else delete c;
+    };
     hipError_t he = hipGetDevice(&ctx->device);
-    if (he != hipSuccess) { delete ctx; return fail(DPMM_ERR_HIP, "hipGetDevice: %s", hipGetErrorString(he)); }
+    if (he != hipSuccess) { release(ctx); return fail(DPMM_ERR_HIP, "hipGetDevice: %s", hipGetErrorString(he)); }
     ctx->stream = (hipStream_t)stream;
     ctx->N = csr->n_cells;
     ctx->nnz = csr->nnz;
@@ -318,14 +338,18 @@ dpmm_status dpmm_init(const dpmm_csr* csr, const dpmm_params* params, void* work
 
     auto cleanup = [&](dpmm_status st) {
         if (ctx->k_host) hipHostFree(ctx->k_host);
-        delete ctx;
+        release(ctx);
         return st;
     };
-    he = hipHostMalloc((void**)&ctx->k_host, sizeof(int32_t), hipHostMallocMapped);
-    if (he != hipSuccess) { ctx->k_host = nullptr; return cleanup(fail(DPMM_ERR_HIP, "hipHostMalloc: %s", hipGetErrorString(he))); }
-    *ctx->k_host = params->k_init;
-    he = hipHostGetDevicePointer((void**)&ws.k_hint, ctx->k_host, 0);
-    if (he != hipSuccess) return cleanup(fail(DPMM_ERR_HIP, "hipHostGetDevicePointer: %s", hipGetErrorString(he)));
+    if (hint_dev) {
+        ws.k_hint = hint_dev;
+    } else {
+        he = hipHostMalloc((void**)&ctx->k_host, sizeof(int32_t), hipHostMallocMapped);
+        if (he != hipSuccess) { ctx->k_host = nullptr; return cleanup(fail(DPMM_ERR_HIP, "hipHostMalloc: %s", hipGetErrorString(he))); }
+        *ctx->k_host = params->k_init;
+        he = hipHostGetDevicePointer((void**)&ws.k_hint, ctx->k_host, 0);
+        if (he != hipSuccess) return cleanup(fail(DPMM_ERR_HIP, "hipHostGetDevicePointer: %s", hipGetErrorString(he)));
+    }
     if (params->precision == DPMM_SPLIT_BF16) {
         he = configure_assign_bf16();
         if (he == hipSuccess) he = configure_layout();
@@ -369,6 +393,62 @@ dpmm_status dpmm_init(const dpmm_csr* csr, const dpmm_params* params, void* work
     return DPMM_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Static storage for dpmm_init_static: a workspace of kScratchBytes per device
+// (the last 256 bytes hold the K hint) and one host context slot per device.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+constexpr size_t kScratchHint = 256;
+constexpr int kMaxDevices = 64;
+
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices];          // device address of scratch, per device
+bool g_scratch_busy[kMaxDevices];          // a context holds the device's storage
+dpmm_ctx g_scratch_ctx[kMaxDevices];
+
+}  // namespace
+
+extern "C" {
+
+dpmm_status dpmm_init(const dpmm_csr* csr, const dpmm_params* params, void* workspace, size_t workspace_bytes,
+                      void* stream, dpmm_ctx** out)
+{
+    return init_impl(csr, params, workspace, workspace_bytes, stream, out, nullptr, nullptr);
+}
+
+dpmm_status dpmm_init_static(const dpmm_csr* csr, const dpmm_params* params, void* stream, dpmm_ctx** out)
+{
+    g_err[0] = 0;
+    dpmm_status s = check_args(csr, params);
+    if (s != DPMM_OK) return s;
+    if (!out) return fail(DPMM_ERR_ARG, "null out");
+    *out = nullptr;
+    const size_t need = plan(csr->n_cells, csr->n_genes, csr->nnz, params->k_max, params->precision, params->flags).total;
+    if (need > kScratchBytes - kScratchHint)
+        return fail(DPMM_ERR_NOMEM, "dpmm_init_static: %zu bytes of workspace needed, the static workspace holds %zu",
+                    need, kScratchBytes - kScratchHint);
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(DPMM_ERR_UNSUPPORTED, "device %d beyond the static slots", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (g_scratch_busy[dev]) return fail(DPMM_ERR_STATE, "the static workspace of device %d is held by a context", dev);
+    if (!g_scratch_ptr[dev]) {
+        // the symbol's address on this device (each device holds its own copy)
+        void* p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(DPMM_ERR_HIP, "hipGetSymbolAddress returned no address");
+        g_scratch_ptr[dev] = p;
+    }
+    char* base = static_cast<char*>(g_scratch_ptr[dev]);
+    int32_t* hint = reinterpret_cast<int32_t*>(base + kScratchBytes - kScratchHint);
+    s = init_impl(csr, params, base, kScratchBytes - kScratchHint, stream, out, &g_scratch_ctx[dev], hint);
+    if (s == DPMM_OK) g_scratch_busy[dev] = true;
+    return s;
+}
+
+
 dpmm_status dpmm_destroy(dpmm_ctx* ctx)
 {
     if (!ctx) return fail(DPMM_ERR_ARG, "null ctx");
@@ -376,7 +456,14 @@ dpmm_status dpmm_destroy(dpmm_ctx* ctx)
     hipStreamSynchronize(ctx->stream);
     for (hipEvent_t e : ctx->ev) hipEventDestroy(e);
     if (ctx->k_host) hipHostFree(ctx->k_host);
-    delete ctx;
+    if (ctx->in_scratch) {
+        std::lock_guard<std::mutex> lock(g_scratch_mutex);
+        const int dev = ctx->device;
+        *ctx = dpmm_ctx();
+        if (dev >= 0 && dev < kMaxDevices) g_scratch_busy[dev] = false;
+    } else {
+        delete ctx;
+    }
     return DPMM_OK;
 }
 

@@ -70,6 +70,7 @@ _SIGNATURES = {
     "dpmm_last_error": ([], ctypes.c_char_p),
     "dpmm_workspace_size": ([ctypes.POINTER(dpmm_csr), ctypes.POINTER(dpmm_params), ctypes.POINTER(ctypes.c_size_t)], _S),
     "dpmm_init": ([ctypes.POINTER(dpmm_csr), ctypes.POINTER(dpmm_params), _P, ctypes.c_size_t, _P, ctypes.POINTER(_P)], _S),
+    "dpmm_init_static": ([ctypes.POINTER(dpmm_csr), ctypes.POINTER(dpmm_params), _P, ctypes.POINTER(_P)], _S),
     "dpmm_destroy": ([_P], _S),
     "dpmm_sweep": ([_P, ctypes.c_int32], _S),
     "dpmm_split_merge": ([_P], _S),
@@ -131,6 +132,12 @@ def dpmm_init(csr: dpmm_csr, params: dpmm_params, workspace: int, workspace_byte
     ctx = _P(0)
     _check(lib().dpmm_init(ctypes.byref(csr), ctypes.byref(params), workspace, workspace_bytes, stream,
                            ctypes.byref(ctx)))
+    return ctx.value
+
+
+def dpmm_init_static(csr: dpmm_csr, params: dpmm_params, stream: int) -> int:
+    ctx = _P(0)
+    _check(lib().dpmm_init_static(ctypes.byref(csr), ctypes.byref(params), stream, ctypes.byref(ctx)))
     return ctx.value
 
 

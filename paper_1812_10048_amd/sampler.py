@@ -31,12 +31,15 @@ class Sampler:
     eq. 4); ``random_split`` sets DPMM_FLAG_RANDOM_SPLIT (a third pass of
     random splits, chain B of Section 2.4).  All three are on by default
     (DPMM_FLAGS_PAPER, the moves as the paper states them); all off gives the
-    collapsed split ratio alone.
+    collapsed split ratio alone.  ``static_workspace`` creates the context
+    with dpmm_init_static (no allocation; small matrices only, one such
+    sampler per GPU at a time).
     """
 
     def __init__(self, row_ptr, col, val, n_genes: int, *, alpha: float = 1.0, beta=1.0, seed: int = 0,
                  k_init: int = 1, k_max: int = 128, precision: str = "fp32", refine_tol: float = -1.0,
-                 split_q: bool = True, new_cluster: bool = True, random_split: bool = True):
+                 split_q: bool = True, new_cluster: bool = True, random_split: bool = True,
+                 static_workspace: bool = False):
         if not torch.cuda.is_available():
             raise RuntimeError("libdpmm needs a GPU")
         rp = _dev(torch.as_tensor(row_ptr), torch.int64)
@@ -58,12 +61,17 @@ class Sampler:
                                int(seed) & 0xFFFFFFFFFFFFFFFF, int(k_init), self.k_max, C.PRECISIONS[precision],
                                (C.FLAG_SPLIT_Q if split_q else 0) | (C.FLAG_NEW_CLUSTER if new_cluster else 0) |
                                (C.FLAG_RANDOM_SPLIT if random_split else 0), float(refine_tol))
-        nbytes = C.dpmm_workspace_size(csr, params)
-        # 256-byte alignment inside a slightly larger buffer
-        self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
-        base = self._ws.data_ptr()
-        off = (-base) % 256
-        self._ctx = C.dpmm_init(csr, params, base + off, nbytes, _stream())
+        if static_workspace:
+            # the library's static per-device workspace (dpmm_init_static)
+            self._ws = None
+            self._ctx = C.dpmm_init_static(csr, params, _stream())
+        else:
+            nbytes = C.dpmm_workspace_size(csr, params)
+            # 256-byte alignment inside a slightly larger buffer
+            self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+            base = self._ws.data_ptr()
+            off = (-base) % 256
+            self._ctx = C.dpmm_init(csr, params, base + off, nbytes, _stream())
         self._dbg = None
 
     # -- lifetime ----------------------------------------------------------

@@ -8,8 +8,9 @@ followed by a split/merge move; every 10th step also takes the empirical-Bayes
 step of the per-gene concentration.  Evaluations per sweep are N (K + 2).
 
 Prints one JSON line.  Timing: W untimed steps, then K steps between two
-stream synchronisations; the assignment kernel's own duration comes from HIP
-events the library records on its stream.
+stream synchronisations; after that, K more steps with HIP events around every
+stage (recorded by the library on its stream) give the per-stage times and
+the assignment kernel's own duration.
 """
 from __future__ import annotations
 
@@ -67,31 +68,68 @@ def measured_traffic():
     return got["FETCH_SIZE"] + got["WRITE_SIZE"]
 
 
-def cpu_baseline(d, K_true, budget_s: float, seed: int):
-    """The FP64 oracle on the first cells of the same matrix, same state."""
-    import numpy as np
-    import oracle
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
-    n = min(d.n_cells, 20_000)
-    rp, col, val = d.host_arrays(n)
-    o = oracle.Oracle(rp, col, val, d.n_genes, alpha=1.0, beta=1.0, seed=seed, k_max=128, init=False)
-    rng = np.random.default_rng(seed)
-    o.set_state(0, K_true, d.z[:n], rng.integers(0, 2, size=n), np.ones(K_true))
+
+def _oracle_steps(o, n_steps, budget_s=None):
+    """(evaluations, seconds) of full steps (sweep + split/merge) of the
+    oracle; evaluations N (K + 2) per sweep, K taken before the sweep."""
     evals = 0
-    t0 = time.perf_counter()
     steps = 0
-    while True:
+    t0 = time.perf_counter()
+    while steps < n_steps:
         K = o.K
         o.sweep()
         o.split_merge()
-        evals += n * (K + 2)
+        evals += o.N * (K + 2)
         steps += 1
-        if time.perf_counter() - t0 > budget_s:
+        if budget_s is not None and time.perf_counter() - t0 > budget_s:
             break
-    dt = time.perf_counter() - t0
-    return {"value": evals / dt, "unit": "evals/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"first {n} cells of the same matrix, true partition start, {steps} full steps "
-                      f"(sweep + split/merge) in {dt:.1f} s"}
+    return evals, time.perf_counter() - t0, steps
+
+
+def cpu_baseline(d, K_true, seed: int, cs0):
+    """The FP64 oracle timed on the host's cores, as planned beside the GPU
+    run: (i) three full steps on the whole matrix from the GPU's start state
+    (all threads), (ii) a 20,000-cell sample on one thread, (iii) the
+    2,000 x 500 recipe from one cluster, 100 steps (all threads)."""
+    import numpy as np
+    import oracle
+
+    threads = oracle.num_threads()
+    rp, col, val = d.host_arrays()
+    o = oracle.Oracle(rp, col, val, d.n_genes, alpha=1.0, beta=1.0, seed=seed, k_max=128, init=False)
+    o.set_state(0, K_true, d.z, cs0, np.ones(K_true))
+    ev, dt, steps = _oracle_steps(o, 3)
+    log(f"cpu oracle: {steps} steps on {d.n_cells} cells in {dt:.2f}s on {threads} threads")
+    del o
+    n = min(d.n_cells, 20_000)
+    rp1, col1, val1 = d.host_arrays(n)
+    o1 = oracle.Oracle(rp1, col1, val1, d.n_genes, alpha=1.0, beta=1.0, seed=seed, k_max=128, init=False)
+    o1.set_state(0, K_true, d.z[:n], cs0[:n], np.ones(K_true))
+    oracle.set_num_threads(1)
+    ev1, dt1, steps1 = _oracle_steps(o1, 10 ** 9, budget_s=5.0)
+    oracle.set_num_threads(threads)
+    del o1
+    from paper_1812_10048_amd import synth
+    c1 = synth.generate("c1", seed=0)
+    rpc, colc, valc = c1.host_arrays()
+    oc = oracle.Oracle(rpc, colc, valc, c1.n_genes, alpha=1.0, beta=1.0, seed=0, k_max=64, k_init=1)
+    evc, dtc, stepsc = _oracle_steps(oc, 100)
+    return {"value": ev / dt, "unit": "evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"all {d.n_cells} cells of the same matrix, {steps} full steps (sweep + split/merge, "
+                      f"paper-literal moves) from the GPU run's start state, {dt:.2f} s",
+            "cpu_model": cpu_model(),
+            "one_thread": {"value": ev1 / dt1, "sample": f"first {n} cells, {steps1} steps in {dt1:.1f} s"},
+            "c1_full_run": {"value": evc / dtc, "seconds": dtc, "steps": stepsc, "K_end": int(oc.K),
+                            "sample": "2,000 x 500 recipe from one cluster, 100 steps"}}
 
 
 def main() -> int:
@@ -102,7 +140,6 @@ def main() -> int:
     ap.add_argument("--workload", default="c5", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="split_bf16", choices=["fp32", "fp64", "split_bf16"])
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the plain FP32 reference run")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -148,8 +185,6 @@ def main() -> int:
             step(smp, i)
         torch.cuda.synchronize()
         st0 = smp.stats()
-        smp.timing(True)
-        smp.timing_read()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for i in range(args.steps):
@@ -157,13 +192,27 @@ def main() -> int:
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         st1 = smp.stats()
-        kms, launches = smp.timing_read()
+        # after the timed region: the same number of steps again with an event
+        # pair around every stage, for the per-stage times and the average
+        # duration of the assignment kernel (events on the library's stream)
+        smp.timing(True)
+        smp.timing_stages()
+        t1 = time.perf_counter()
+        for i in range(args.steps):
+            step(smp, args.warmup + args.steps + i)
+        torch.cuda.synchronize()
+        dt_events = time.perf_counter() - t1
+        stages = smp.timing_stages()
         smp.timing(False)
+        kms, launches = stages["assign"]
         c, cs = smp.labels()
-        res = dict(dt=dt, evals=st1["evals"] - st0["evals"], kms=kms, launches=launches, K0=st0["K"], K1=st1["K"],
-                   refined=st1["refined"] - st0["refined"], c=c, cs=cs)
-        log(f"{precision}: {args.steps} steps in {dt:.4f}s, K {res['K0']} -> {res['K1']}, assign kernel "
-            f"{kms / max(1, launches):.4f} ms x {launches}, refined {res['refined']}")
+        res = dict(dt=dt, evals=st1["evals"] - st0["evals"], kms=kms, launches=launches, K0=st0["K"],
+                   K1=st1["K"], refined=st1["refined"] - st0["refined"], near_tie=st1["near_tie"] - st0["near_tie"],
+                   c=c, cs=cs, stages={k: v[0] / max(1, args.steps) for k, v in stages.items()},
+                   dt_with_events=dt_events)
+        log(f"{precision}: {args.steps} steps in {dt:.4f}s ({dt_events:.4f}s with stage events), K {res['K0']} -> "
+            f"{res['K1']}, assign kernel {kms / max(1, launches):.4f} ms x {launches}, refined {res['refined']}, "
+            f"stages ms/step " + ", ".join(f"{k} {v:.4f}" for k, v in res["stages"].items()))
         smp.close()
         return res
 
@@ -179,8 +228,11 @@ def main() -> int:
     if args.precision != "fp32" and not args.no_compare:
         ref = run("fp32")
         same = bool(torch.equal(ref["c"], main_run["c"]) and torch.equal(ref["cs"], main_run["cs"]))
+        fp32_kernel_s = ref["kms"] / 1e3 / max(1, ref["launches"])
         cmp = {"fp32_value": ref["evals"] / ref["dt"], "fp32_ms_per_step": ref["dt"] / args.steps * 1e3,
                "fp32_assign_kernel_ms": ref["kms"] / max(1, ref["launches"]),
+               "fp32_assign_frac_hbm": alg_bytes(d.n_cells, d.nnz) / fp32_kernel_s / 1e9 / HBM_PEAK_GBS,
+               "fp32_stages_ms_per_step": ref["stages"],
                "speedup_vs_fp32": (main_run["evals"] / main_run["dt"]) / (ref["evals"] / ref["dt"]),
                "kernel_speedup_vs_fp32": (ref["kms"] / max(1, ref["launches"])) /
                                          max(1e-12, main_run["kms"] / max(1, main_run["launches"])),
@@ -203,8 +255,9 @@ def main() -> int:
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(d, K_true, args.cpu_budget, args.seed)
-        log(f"cpu baseline {cpu['value']:.3e} evals/s on {cpu['cores']} threads")
+        cpu = cpu_baseline(d, K_true, args.seed, cs0.numpy())
+        log(f"cpu baseline {cpu['value']:.3e} evals/s on {cpu['cores']} threads, one thread "
+            f"{cpu['one_thread']['value']:.3e}, c1 100 steps in {cpu['c1_full_run']['seconds']:.2f}s")
 
     dtype = {"fp32": "fp32", "fp64": "fp64", "split_bf16": "bf16"}[args.precision]
     out = {
@@ -213,7 +266,10 @@ def main() -> int:
         "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
         "config": {"workload": f"{args.workload}: {desc}", "n_cells": d.n_cells, "n_genes": d.n_genes,
                    "nnz": d.nnz, "precision": args.precision, "K_start": st0["K"], "K_end": st1["K"],
-                   "step": "sweep + split/merge (+ empirical-Bayes beta step every 10th)"},
+                   "step": "sweep + split/merge (+ empirical-Bayes beta step every 10th)",
+                   "moves": "paper-literal: split proposal term, Gibbs over K + 1, random splits",
+                   "stages_ms_per_step": main_run["stages"], "refined": main_run["refined"],
+                   "near_tie": main_run["near_tie"]},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "comparison": cmp,

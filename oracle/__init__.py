@@ -133,6 +133,8 @@ def _declare(L: ctypes.CDLL) -> None:
     L.oracle_cell_logliks.restype = None
     L.oracle_num_threads.argtypes = []
     L.oracle_num_threads.restype = ctypes.c_int
+    L.oracle_set_num_threads.argtypes = [ctypes.c_int]
+    L.oracle_set_num_threads.restype = None
 
 
 def _ptr(a: np.ndarray) -> int:
@@ -220,6 +222,10 @@ def merge_logr(s1, s2, n1, n2, beta, alpha):
 
 def num_threads() -> int:
     return lib().oracle_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    lib().oracle_set_num_threads(int(n))
 
 
 # ----------------------------------------------------------------------------

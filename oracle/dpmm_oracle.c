@@ -1131,6 +1131,15 @@ void oracle_cell_logliks(const oracle_state* st, const int64_t* cells, int64_t m
     }
 }
 
+void oracle_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int oracle_num_threads(void)
 {
 #ifdef _OPENMP

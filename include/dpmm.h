@@ -162,7 +162,10 @@ enum {
     DPMM_STAGE_COMPACT = 4,      /* empty clusters dropped, labels rewritten           */
     DPMM_STAGE_SPLIT_MERGE = 5,  /* a5: ratios, decisions, relabelling                 */
     DPMM_STAGE_EB = 6,           /* a6 + a7: empirical-Bayes beta step                 */
-    DPMM_NUM_STAGES = 7
+    DPMM_STAGE_LAYOUT = 7,       /* split-BF16: every 8th sweep, the check (and, when
+                                    the partition changed, the rebuild) of the
+                                    cluster-sorted copy of the counts              */
+    DPMM_NUM_STAGES = 8
 };
 
 /* Message of the last failed call on this thread ("" if none). */

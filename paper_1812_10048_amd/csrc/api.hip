@@ -37,15 +37,21 @@ dpmm_status fail(dpmm_status st, const char* fmt, ...)
 constexpr size_t kAlign = 256;
 constexpr int kMaxTimed = 16384;       // timed stage intervals kept between two reads
 constexpr int kTablePadRows = 64;      // spare cluster rows read by its last column group
+constexpr int kRelayoutEvery = 8;      // sweeps between checks of the cluster-sorted copy
 
 size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
 struct Layout {
     size_t ent, roff, tiles, c0, c1, cs0, cs1, st, reset, nsub, ssub, beta, lgbeta, logpi, lt64, lc32, ls32, lhi, llo,
-        lgrise, lpsub, qsub, rbits, rssub, rnsub, refine, perm, srow, grp_cnt, grp_off, grp_cur, nsub_prev, blk_ent, blk_off, ovf_off, ovf_ent, relab_c, relab_s, sm_logr, sm_acc, mkey, mlist, dm_k, eb_tmp, rd_part, sm_part, total;
+        lgrise, lpsub, qsub, rbits, rssub, rnsub, refine, perm, srow, grp_cnt, grp_off, grp_cur, nsub_prev, lay_kc,
+        lay_pbeg, lay_pcnt, lay_cell, lay_doff, lay_toff, lay_dense, lay_tail, lay_nnz, lay_rank, lay_gene, lay_bhi,
+        lay_blo, relab_c, relab_s, sm_logr, sm_acc, mkey, mlist, dm_k, eb_tmp, rd_part, sm_part, total;
 };
 
 int32_t num_blocks(int64_t N) { return (int32_t)((N + kBlkCells - 1) / kBlkCells); }
+// blocks of the cluster-sorted copy: each cluster's last block may be partial
+int32_t lay_blocks(int64_t N, int32_t k_max) { return num_blocks(N) + k_max; }
+int32_t lay_cols(int32_t k_max) { return (k_max + 15) / 16 * 16 + kTablePadRows; }
 // gene chunks of the split-BF16 kernel: an even number, so that its pipeline
 // (two register stages, unrolled by two) has no conditional chunk; the chunks
 // past G hold no entries and zero log theta
@@ -63,8 +69,9 @@ Layout plan(int64_t N, int32_t G, int64_t nnz, int32_t k_max, int32_t precision,
     const int64_t Gpad = (int64_t)num_chunks(G) * kBlkGenes;
     const int64_t ncand = (int64_t)k_max + (int64_t)k_max * (k_max - 1) / 2;
     const bool blocked = precision == DPMM_SPLIT_BF16;
-    const int64_t nseg = blocked ? (int64_t)num_blocks(N) * num_chunks(G) : 0;
-    const int64_t ntiles = ((N > nseg ? N : nseg) + 4095) / 4096 + 1;
+    const int64_t nbc = blocked ? lay_blocks(N, k_max) : 0;
+    const int64_t nslots = nbc * kBlkCells;
+    const int64_t ntiles = ((N > nslots ? N : nslots) + 4095) / 4096 + 1;
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o += align_up(bytes); return at; };
     L.ent = take(4 * (size_t)(nnz_pad + 4));   // + one 16-byte slot of slack
@@ -100,10 +107,21 @@ Layout plan(int64_t N, int32_t G, int64_t nnz, int32_t k_max, int32_t precision,
     L.grp_off = take(8 * (size_t)k_max + 4);
     L.grp_cur = take(8 * (size_t)k_max);
     L.nsub_prev = take(16 * (size_t)k_max);
-    L.blk_ent = take(blocked ? 4 * (size_t)(nnz + 3 * nseg + 4) : 0);   // + one 16-byte slot of slack
-    L.blk_off = take(blocked ? 8 * (size_t)(nseg + 1) : 0);
-    L.ovf_off = take(blocked ? 8 * (size_t)(num_blocks(N) + 1) : 0);
-    L.ovf_ent = take(blocked ? 8 * (size_t)(nnz > 0 ? nnz : 1) : 0);   // at most every entry
+    L.lay_kc = take(blocked ? 4 * (size_t)nbc : 0);
+    L.lay_pbeg = take(blocked ? 4 * (size_t)nbc : 0);
+    L.lay_pcnt = take(blocked ? 4 * (size_t)nbc : 0);
+    L.lay_cell = take(blocked ? 4 * (size_t)nslots : 0);
+    L.lay_doff = take(blocked ? 8 * (size_t)(nbc + 1) : 0);
+    L.lay_toff = take(blocked ? 8 * (size_t)(nslots + 1) : 0);
+    // a block's dense chunks cost less than the tail entries they take (36
+    // each), so they hold at most 36 bytes per entry
+    L.lay_dense = take(blocked ? (size_t)kDenseChunkBytes * (size_t)((nnz * 36 + kDenseChunkBytes - 1) / kDenseChunkBytes + 1) : 0);
+    L.lay_tail = take(blocked ? 4 * (size_t)(nnz > 0 ? nnz : 1) : 0);   // at most every entry
+    L.lay_nnz = take(blocked ? 2 * (size_t)nslots : 0);
+    L.lay_rank = take(blocked ? 2 * (size_t)k_max * (size_t)G : 0);
+    L.lay_gene = take(blocked ? 2 * (size_t)k_max * kLayDmax * kBlkGenes : 0);
+    L.lay_bhi = take(blocked ? 2 * (size_t)k_max * (size_t)lay_cols(k_max) * kLayDmax * kBlkGenes : 0);
+    L.lay_blo = take(blocked ? 2 * (size_t)k_max * (size_t)lay_cols(k_max) * kLayDmax * kBlkGenes : 0);
     L.relab_c = take(8 * (size_t)k_max);
     L.relab_s = take(2 * (size_t)k_max);
     L.sm_logr = take(8 * (size_t)ncand);
@@ -161,6 +179,8 @@ struct dpmm_ctx {
     int n_timed = 0;
     int32_t* k_host = nullptr;         // pinned copy of K, refreshed after every call
     bool in_scratch = false;           // workspace and context live in the per-device static storage
+    int since_layout = 0;              // sweeps since the cluster-sorted copy was last considered
+    int64_t rs_ready_step = -1;        // step of the random split whose coins and halves the last sweep built
 };
 
 namespace {
@@ -211,7 +231,8 @@ int32_t k_hint(const dpmm_ctx* ctx)
     return ctx->k_host ? *reinterpret_cast<volatile int32_t*>(ctx->k_host) : ctx->k_max;
 }
 
-// statistics from the current labels, then compaction without touching flags
+// statistics from the current labels, then compaction without touching
+// flags; with split-BF16 the cluster-sorted copy is rebuilt from the labels
 dpmm_status recompute_stats(dpmm_ctx* ctx)
 {
     // no sweep has drawn these labels: no proposal term yet
@@ -219,7 +240,9 @@ dpmm_status recompute_stats(dpmm_ctx* ctx)
     launch_stats(ctx->ws, ctx->c[ctx->cur], ctx->cs[ctx->cur], ctx->stream);
     launch_compact(ctx->ws, 0, ctx->stream);
     launch_relabel(ctx->ws, ctx->c[ctx->cur], ctx->cs[ctx->cur], ctx->stream);
+    if (ctx->precision == DPMM_SPLIT_BF16) launch_relayout(ctx->ws, ctx->c[ctx->cur], ctx->tiles, 1, ctx->stream);
     HIP_TRY(hipGetLastError());
+    ctx->since_layout = 0;
     return DPMM_OK;
 }
 
@@ -314,12 +337,21 @@ dpmm_status init_impl(const dpmm_csr* csr, const dpmm_params* params, void* work
     ws.grp_off = (int32_t*)(base + L.grp_off);
     ws.grp_cur = (int32_t*)(base + L.grp_cur);
     ws.nsub_prev = (unsigned long long*)(base + L.nsub_prev);
-    ws.blk_ent = (const uint32_t*)(base + L.blk_ent);
-    ws.blk_off = (int64_t*)(base + L.blk_off);
-    ws.ovf_off = (int64_t*)(base + L.ovf_off);
-    ws.ovf_ent = (uint2*)(base + L.ovf_ent);
-    ws.nblk = num_blocks(csr->n_cells);
-    ws.nch = num_chunks(csr->n_genes);
+    ws.lay_kc = (int32_t*)(base + L.lay_kc);
+    ws.lay_pbeg = (int32_t*)(base + L.lay_pbeg);
+    ws.lay_pcnt = (int32_t*)(base + L.lay_pcnt);
+    ws.lay_cell = (int32_t*)(base + L.lay_cell);
+    ws.lay_doff = (int64_t*)(base + L.lay_doff);
+    ws.lay_toff = (int64_t*)(base + L.lay_toff);
+    ws.lay_dense = (uint8_t*)(base + L.lay_dense);
+    ws.lay_tail = (uint32_t*)(base + L.lay_tail);
+    ws.lay_nnz = (uint16_t*)(base + L.lay_nnz);
+    ws.lay_rank = (uint16_t*)(base + L.lay_rank);
+    ws.lay_gene = (uint16_t*)(base + L.lay_gene);
+    ws.lay_bhi = (uint16_t*)(base + L.lay_bhi);
+    ws.lay_blo = (uint16_t*)(base + L.lay_blo);
+    ws.nblk_cap = params->precision == DPMM_SPLIT_BF16 ? lay_blocks(csr->n_cells, params->k_max) : 0;
+    ws.lay_cols = lay_cols(params->k_max);
     ws.relab_c = (int32_t*)(base + L.relab_c);
     ws.relab_s = (uint8_t*)(base + L.relab_s);
     ws.sm_logr = (double*)(base + L.sm_logr);
@@ -363,7 +395,6 @@ dpmm_status init_impl(const dpmm_csr* csr, const dpmm_params* params, void* work
     if (he != hipSuccess) return cleanup(fail(DPMM_ERR_HIP, "hipMemsetAsync: %s", hipGetErrorString(he)));
     launch_pack(csr->row_ptr, csr->col, csr->val, csr->n_cells, csr->n_genes, csr->nnz, (int64_t*)ws.roff,
                 ctx->tiles, (uint32_t*)ws.ent, ws.st, ctx->stream);
-    if (params->precision == DPMM_SPLIT_BF16) launch_build_blocked(ws, ctx->tiles, ctx->stream);
     if (params->beta_per_gene)
         he = hipMemcpyAsync(ws.beta, params->beta_per_gene, 8 * (size_t)ws.G, hipMemcpyDeviceToDevice, ctx->stream);
     else
@@ -467,6 +498,17 @@ dpmm_status dpmm_destroy(dpmm_ctx* ctx)
     return DPMM_OK;
 }
 
+// The move of the split/merge call at `step`: 0 split into the sub-clusters,
+// 1 merges, 2 random splits (only with DPMM_FLAG_RANDOM_SPLIT, the three then
+// equally likely).  The chain coin depends only on (seed, step).
+static int chain_pass(const dpmm_ctx* ctx, uint32_t step)
+{
+    const Words w = philox(ctx->ws.seed, 0u, 0u, step, kChain, 0u);
+    const double coin = unit52(w.w[0], w.w[1]);
+    if (ctx->ws.flags & kFlagRandomSplit) return coin < 1.0 / 3.0 ? 0 : (coin < 2.0 / 3.0 ? 2 : 1);
+    return coin < 0.5 ? 0 : 1;
+}
+
 dpmm_status dpmm_sweep(dpmm_ctx* ctx, int32_t n_sweeps)
 {
     if (!ctx) return fail(DPMM_ERR_ARG, "null ctx");
@@ -477,10 +519,18 @@ dpmm_status dpmm_sweep(dpmm_ctx* ctx, int32_t n_sweeps)
     for (int32_t n = 0; n < n_sweeps; ++n) {
         const int nxt = 1 - ctx->cur;
         const uint32_t step = (uint32_t)ctx->step;
+        if (ctx->precision == DPMM_SPLIT_BF16 && ++ctx->since_layout >= kRelayoutEvery) {
+            // rebuild the cluster-sorted copy if the partition changed
+            // structurally (a deterministic, device-side decision)
+            StageTimer st(ctx, DPMM_STAGE_LAYOUT);
+            launch_relayout(ws, ctx->c[ctx->cur], ctx->tiles, 0, ctx->stream);
+            ctx->since_layout = 0;
+        }
         {
             StageTimer st(ctx, DPMM_STAGE_REDRAW);
             if (ws.flags & kFlagNewCluster) launch_extend(ws, ctx->stream);
             launch_redraw(ws, step, ctx->precision == DPMM_SPLIT_BF16, ctx->stream);   // also empties the re-score queue
+            if (ctx->precision == DPMM_SPLIT_BF16) launch_lay_btab(ws, ctx->stream);
         }
         AssignArgs a{};
         a.c_old = ctx->c[ctx->cur];
@@ -513,6 +563,12 @@ dpmm_status dpmm_sweep(dpmm_ctx* ctx, int32_t n_sweeps)
         sa.dbg = ctx->dbg;
         sa.dbg_stride = ctx->dbg_cap + 2;
         sa.dbg64 = ctx->dbg64;
+        // a random split next: its coins and coin halves come with this pass
+        if (n + 1 == n_sweeps && ws.rssub && chain_pass(ctx, step + 1) == 2) {
+            sa.rsplit = 1;
+            sa.rs_step = step + 1;
+        }
+        ctx->rs_ready_step = sa.rsplit ? (int64_t)ctx->step + 1 : -1;
         {
             StageTimer st(ctx, DPMM_STAGE_SUBCLUSTER);
             launch_sub_stats(ws, sa, ctx->stream);
@@ -537,14 +593,9 @@ dpmm_status dpmm_split_merge(dpmm_ctx* ctx)
     dpmm_status s = set_device(ctx);
     if (s != DPMM_OK) return s;
     const uint32_t step = (uint32_t)ctx->step;
-    // the chain coin depends only on (seed, step): drawn here, without a sync
-    // pass 0: split into the sub-clusters; 1: merges; 2: random splits (only
-    // with DPMM_FLAG_RANDOM_SPLIT, the three then equally likely)
-    const Words w = philox(ctx->ws.seed, 0u, 0u, step, kChain, 0u);
-    const double coin = unit52(w.w[0], w.w[1]);
-    int pass;
-    if (ctx->ws.flags & kFlagRandomSplit) pass = coin < 1.0 / 3.0 ? 0 : (coin < 2.0 / 3.0 ? 2 : 1);
-    else pass = coin < 0.5 ? 0 : 1;
+    const int pass = chain_pass(ctx, step);    // drawn here, without a sync
+    const bool ready = ctx->rs_ready_step == ctx->step;
+    ctx->rs_ready_step = -1;
     StageTimer st(ctx, DPMM_STAGE_SPLIT_MERGE);
     if (pass == 1) {
         launch_merge_ratios(ctx->ws, ctx->stream);
@@ -553,7 +604,7 @@ dpmm_status dpmm_split_merge(dpmm_ctx* ctx)
         launch_split_ratios(ctx->ws, ctx->c[ctx->cur], ctx->stream);
         launch_sm_decide(ctx->ws, 0, step, ctx->stream);
     } else {
-        launch_random_split(ctx->ws, ctx->c[ctx->cur], ctx->cs[ctx->cur], step, ctx->stream);
+        launch_random_split(ctx->ws, ctx->c[ctx->cur], ctx->cs[ctx->cur], step, ready, ctx->stream);
     }
     launch_relabel(ctx->ws, ctx->c[ctx->cur], ctx->cs[ctx->cur], ctx->stream);
     HIP_TRY(hipGetLastError());     // (k_sm_decide has written the K hint)
@@ -657,6 +708,7 @@ dpmm_status dpmm_set_state(dpmm_ctx* ctx, int64_t step, int32_t K, const int32_t
     ctx->step = step;
     ctx->sweeps = ctx->sm_calls = 0;
     ctx->last_pass = -1;
+    ctx->rs_ready_step = -1;
     return DPMM_OK;
 }
 

@@ -1,26 +1,40 @@
 // assign_mfma.hip -- the cluster draw (eq. 4, third line) with the cluster
-// log-likelihoods on the matrix cores: S = X L^T for a block of cells, X their
-// UMI counts (eq. 26) and L = log theta split as hi + lo in BF16.
+// log-likelihoods S_ik = sum_u x_i^u log theta_{k,u} (eq. 26) on the matrix
+// cores, over the cluster-sorted copy of the counts built in layout.hip.
 //
-//   * counts <= 256 are exact in BF16; a larger count x is stored as xa (x
-//     with its low bits cleared to keep 8 significant bits, exact in BF16)
-//     and the rest (x - xa) log theta is added in FP32;
-//   * products of a count and a BF16 value are exact in FP32; the MFMA
-//     accumulates in FP32 (v_mfma_f32_16x16x32_bf16, gfx950);
-//   * S = X hi^T + X lo^T, |log theta - hi - lo| <= 2^-17 |log theta|.
+// A workgroup of 8 wavefronts owns one block of kBlkCells cells of one layout
+// cluster L; wavefront w owns slots 32w .. 32w + 31 (2 row tiles of 16).  The
+// block's first D_b chunks of kBlkGenes genes (in L's gene order) are dense
+// counts, one byte each, stored in the order of the MFMA A fragments, so each
+// lane reads its two k-steps of a row tile with one 16-byte load and widens
+// the bytes to BF16 (exact: counts <= 255).  log theta = hi + lo in BF16 comes
+// from the same gene order (layout.hip, k_lay_btab).  The chunks go in groups
+// of up to kStageChunks: each lane issues the loads of all its A fragments of
+// the group while the workgroup stages the group's hi/lo rows in LDS, then
+// each wavefront issues
+// 2 k-steps x 2 row tiles x NT column tiles x 2 (hi, lo)
+// v_mfma_f32_16x16x32_bf16 per chunk.  Every other entry of a cell (a gene
+// past the dense chunks, or a count above 255) is in the cell's tail list and
+// adds x * fp32(log theta) on the vector ALUs.  Two threads per cell then
+// take the Gumbel-max over half of the K scores each, and merge their two
+// best; a decision within the certified rounding bound of its two best
+// scores (or within the near-tie margin) is queued for the FP64 re-score.
 //
-// A workgroup of 4 wavefronts owns one block of kBlkCells cells of the
-// blocked layout; wavefront w owns cells 64w .. 64w + 63 (4 row tiles of 16).
-// For each chunk of 64 genes: the workgroup stages the hi/lo chunk of
-// log theta cluster-major, reads the chunk's segment with coalesced 16-byte
-// loads and writes each pre-encoded entry (BF16 value at its LDS byte offset)
-// into the dense tile, then each wavefront issues 2 k-steps x 4 row tiles x
-// Nt column tiles x 2 (hi, lo) MFMAs, and the entries are cleared again.  The
-// next chunk's entries and log theta rows are loaded into registers while
-// this chunk computes.  Counts above 256 come from a static per-block list
-// whose FP32 corrections are added to the scores.
-// The cell's lane then takes the Gumbel-max over the K scores with a
-// certified rounding bound; close decisions are queued for the FP64 re-score.
+// Rounding bound of a score S (all terms x log theta <= 0):
+//   * representation: |log theta - hi - lo| <= 2^-17 |log theta| (dense
+//     part), |log theta - fp32(log theta)| <= 2^-24 |log theta| (tail);
+//   * products: a count <= 255 times a BF16 value is exact in FP32; a tail
+//     product is rounded once;
+//   * sums: however the matrix core orders and rounds the additions inside
+//     and across v_mfma_f32_16x16x32_bf16, each addition of two non-zero FP32
+//     values is taken to err by at most one unit in the last place (2^-23
+//     relative, which covers round-to-nearest and truncation), adding a zero
+//     is exact, and every partial sum is bounded by the sum of the magnitudes
+//     of its terms; a cell with n non-zero counts has at most 2n dense terms
+//     (hi and lo) and n tail terms, so at most 2n + 8 inexact additions
+//     including the tail, log pi and the Gumbel noise;
+//   * the FP32 Gumbel noise is within 1e-5 of the FP64 noise.
+// bound = (2^-17 + (2n + 8) 2^-23) 1.01 (|S| + |log pi| + 20) + 1e-5.
 #include "dpmm_common.hpp"
 #include "kernels.hpp"
 
@@ -29,278 +43,354 @@ namespace dpmm {
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float floatx4_t;
 
-constexpr int kMfmaThreads = kBlkCells;       // 256: one thread per cell
-constexpr int kMfmaRow = kBlkRow;             // BF16 elements per LDS tile row (padded)
-constexpr int kPrefetch = 2;                  // segment entries held in registers: 2 x 4 per thread
-constexpr int kMaxChunks = (65535 + kBlkGenes - 1) / kBlkGenes;
+constexpr int kMfmaThreads = 2 * kBlkCells;   // 512: two threads per block slot
+constexpr int kStageChunks = 2;               // dense chunks whose B rows are staged in LDS at a time
+constexpr int kTailStage = 2048;              // tail entries of a block staged in LDS (more: read from memory)
+constexpr int kRowB = kBlkGenes + 8;          // BF16 elements per staged B row (padded against bank conflicts)
 
-__host__ __device__ constexpr size_t mfma_main_bytes(int nt)
+__host__ __device__ constexpr size_t mfma_lds_bytes(int nt)
 {
-    // A tile (256 cells) + hi/lo B tiles, or the FP32 score tile reusing them
-    return (size_t)(kBlkCells * kMfmaRow * 2 + 2 * 16 * nt * kMfmaRow * 2) >
-                   (size_t)kBlkCells * (16 * nt + 1) * 4
-               ? (size_t)(kBlkCells * kMfmaRow * 2 + 2 * 16 * nt * kMfmaRow * 2)
+    // hi/lo B rows of kStageChunks chunks, or the FP32 score tile reusing them
+    return (size_t)kStageChunks * 2 * 16 * nt * kRowB * 2 > (size_t)kBlkCells * (16 * nt + 1) * 4
+               ? (size_t)kStageChunks * 2 * 16 * nt * kRowB * 2
                : (size_t)kBlkCells * (16 * nt + 1) * 4;
 }
-__host__ __device__ constexpr size_t mfma_lds_bytes(int nt) { return mfma_main_bytes(nt); }
-
-// one pre-encoded entry into the tile: BF16 value at its byte offset
-__device__ inline void put(char* tile, uint32_t en) { *reinterpret_cast<uint16_t*>(tile + (en >> 16)) = (uint16_t)en; }
-__device__ inline void wipe(char* tile, uint32_t en) { *reinterpret_cast<uint16_t*>(tile + (en >> 16)) = 0; }
 
 __device__ inline float gumbel32(uint32_t w) { return -logf(-logf(unit23f(w))); }
+// bounds of -log(-log(u)) over the u23 values, (0.5 .. 2^23 - 0.5) 2^-23:
+// -2.8122 and 16.6355, widened for the FP32 logarithms
+constexpr float kGumbelLo = -2.82f;
+constexpr float kGumbelHi = 16.65f;
 
-// rounding bound of a split-BF16 score: representation 2^-17, FP32
-// accumulation over nsteps MFMA k-steps (with slack for the 32-term products
-// inside each), FP32 overflow corrections and the FP32 Gumbel noise
-__device__ inline float bf16_bound(float acc, float lp, int nsteps)
+__device__ inline float bf16_bound(float acc, float lp, int nnz)
 {
-    return ((float)(nsteps + 40) * 0x1p-24f + 0x1p-17f) * (fabsf(acc) + fabsf(lp) + 20.0f) + 1e-5f;
+    return (0x1p-17f + (float)(2 * nnz + 8) * 0x1p-23f) * 1.01f * (fabsf(acc) + fabsf(lp) + 20.0f) + 1e-5f;
 }
 
-// hi/lo rows of log theta for one chunk: 2 x 16 NT rows x 64 genes, one
-// 16-byte piece per thread and r
-template <int NT>
-struct BRows {
-    uint4 v[NT];
+// four count bytes -> four BF16 values, two per 32-bit word (the FP32 value of
+// a byte has its low 16 bits zero, so its high half is the exact BF16)
+__device__ inline void widen4(uint32_t v, uint32_t& lo2, uint32_t& hi2)
+{
+    // (byte -> float is one v_cvt_f32_ubyteN each)
+    const uint32_t f0 = __float_as_uint((float)(v & 0xFFu));
+    const uint32_t f1 = __float_as_uint((float)((v >> 8) & 0xFFu));
+    const uint32_t f2 = __float_as_uint((float)((v >> 16) & 0xFFu));
+    const uint32_t f3 = __float_as_uint((float)(v >> 24));
+    lo2 = __builtin_amdgcn_perm(f1, f0, 0x07060302u);
+    hi2 = __builtin_amdgcn_perm(f3, f2, 0x07060302u);
+}
+
+// eight count bytes (two words) -> one A fragment of 8 BF16
+__device__ inline bf16x8_t widen8(uint32_t w0, uint32_t w1)
+{
+    uint32_t p[4];
+    widen4(w0, p[0], p[1]);
+    widen4(w1, p[2], p[3]);
+    bf16x8_t r;
+    __builtin_memcpy(&r, p, sizeof(r));
+    return r;
+}
+
+// The best two Gumbel-perturbed scores seen: value, score and log pi of each.
+struct Top2 {
+    float t1, t2, a1, a2, p1, p2;
+    int k1;
+    __device__ inline void init()
+    {
+        t1 = t2 = -INFINITY;
+        a1 = a2 = p1 = p2 = 0.f;
+        k1 = 0;
+    }
+    __device__ inline void add(float v, float s, float lp, int k)
+    {
+        if (v > t1) {
+            t2 = t1; a2 = a1; p2 = p1;
+            t1 = v; a1 = s; p1 = lp; k1 = k;
+        } else if (v > t2) {
+            t2 = v; a2 = s; p2 = lp;
+        }
+    }
 };
 
-__device__ inline void brow_slot(int idx, int nt, int& tbl, int& row, int& sg)
-{
-    const int per = 16 * nt * (kBlkGenes / 8);
-    tbl = idx / per;
-    const int rem = idx - tbl * per;
-    row = rem / (kBlkGenes / 8);
-    sg = rem % (kBlkGenes / 8);
-}
-
 template <int NT>
-__device__ inline BRows<NT> load_brows(const Ws& ws, int kb, int jj, int t)
-{
-    BRows<NT> b;
-#pragma unroll
-    for (int r = 0; r < NT; ++r) {
-        int tbl, row, sg;
-        brow_slot(t + r * kMfmaThreads, NT, tbl, row, sg);
-        b.v[r] = *reinterpret_cast<const uint4*>((tbl ? ws.llo : ws.lhi) + (int64_t)(kb + row) * ws.Gpad +
-                                                 jj * kBlkGenes + sg * 8);
-    }
-    return b;
-}
-
-template <int NT>
-__device__ inline void store_brows(const BRows<NT>& b, uint16_t* bhi, uint16_t* blo, int t)
-{
-#pragma unroll
-    for (int r = 0; r < NT; ++r) {
-        int tbl, row, sg;
-        brow_slot(t + r * kMfmaThreads, NT, tbl, row, sg);
-        *reinterpret_cast<uint4*>((tbl ? blo : bhi) + row * kMfmaRow + sg * 8) = b.v[r];
-    }
-}
-
-// raw buffer resource over n bytes at p (gfx9 descriptor word 3); loads past
-// n bytes return zeros
-constexpr int kBufWord3 = 0x00020000;
-constexpr int kOutOfRange = 0x7FFFFFF0;
-__device__ inline __amdgpu_buffer_rsrc_t buffer_of(const void* p, uint32_t n)
-{
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)n, kBufWord3);
-}
-
-// The first kPrefetch x 4 entries of a segment [f0, f1), through a buffer
-// resource over the block's entries: a lane past the segment end asks for an
-// offset beyond the resource and reads the entry 0, which writes into a
-// padding column.  The loads are unconditional, so the compiler waits for
-// exactly the loads a use needs.
-__device__ inline void load_segment(__amdgpu_buffer_rsrc_t ent, uint32_t f0, uint32_t f1, int t, uint4 (&seg)[kPrefetch])
-{
-#pragma unroll
-    for (int r = 0; r < kPrefetch; ++r) {
-        const uint32_t q = f0 + 4 * t + 4 * kMfmaThreads * r;
-        const int off = q < f1 ? (int)(4 * q) : kOutOfRange;
-        const auto v = __builtin_amdgcn_raw_buffer_load_b128(ent, off, 0, 0);
-        seg[r] = make_uint4(v[0], v[1], v[2], v[3]);
-    }
-}
-
-template <int NT>
-__global__ void __launch_bounds__(kMfmaThreads) __attribute__((amdgpu_waves_per_eu(NT <= 2 ? 3 : 2))) k_assign_bf16(Ws ws, AssignArgs a)
+__global__ void __launch_bounds__(kMfmaThreads) __attribute__((amdgpu_waves_per_eu(4))) k_assign_bf16(Ws ws, AssignArgs a)
 {
     extern __shared__ __attribute__((aligned(16))) char lds[];
-    uint16_t* atile = reinterpret_cast<uint16_t*>(lds);
-    uint16_t* bhi = atile + kBlkCells * kMfmaRow;
-    uint16_t* blo = bhi + 16 * NT * kMfmaRow;
-    float* sc = reinterpret_cast<float*>(lds);                         // epilogue alias
+    uint16_t* bst = reinterpret_cast<uint16_t*>(lds);                 // [chunk][hi, lo][16 NT][kRowB]
+    float* sc = reinterpret_cast<float*>(lds);                         // epilogue alias [256][16 NT + 1]
+    __shared__ float x_t1[kBlkCells], x_t2[kBlkCells], x_a1[kBlkCells], x_a2[kBlkCells], x_p1[kBlkCells],
+        x_p2[kBlkCells];
+    __shared__ int x_k1[kBlkCells];
+    __shared__ float x_d[2][kBlkCells];        // each half's best score + log pi
+    __shared__ uint32_t t_ent[kTailStage];     // the block's tail entries
     constexpr int SS = 16 * NT + 1;
+    constexpr int NCOL = 16 * NT;
+    constexpr int HALF = NCOL / 2;             // clusters per thread of a slot's pair (multiple of 8)
 
+    const int b = blockIdx.x;
+    if (b >= ws.st->lay_nblk) return;
     const int K = ws.st->K;
     const int t = threadIdx.x;
     const int lane = t & 63;
-    const int wave = t >> 6;
-    const int blk = blockIdx.x;
-    const int64_t i = (int64_t)blk * kBlkCells + t;
-    const bool valid = i < ws.N;
-    const int64_t* soff = ws.blk_off + (int64_t)blk * ws.nch;
-    const uint32_t* bent = ws.blk_ent + soff[0];       // this block's entries, 32-bit offsets below
-    const __amdgpu_buffer_rsrc_t bres = buffer_of(bent, (uint32_t)(4 * (soff[ws.nch] - soff[0])));
-    // the block's segment offsets, relative to its first entry, once into LDS
-    __shared__ uint32_t s_off[kMaxChunks + 1];
-    for (int q = t; q <= ws.nch; q += kMfmaThreads) s_off[q] = (uint32_t)(soff[q] - soff[0]);
-    __syncthreads();
+    const int wave = t >> 6;                   // 8 wavefronts, 32 slots (two row tiles) each
+    const int sl = t & (kBlkCells - 1);        // the slot of this thread in the epilogue
+    const int half = t >> 8;                   // which half of a column group it takes
+    const int64_t slot = (int64_t)b * kBlkCells + sl;
+    const int cell = ws.lay_cell[slot];
+    const int L = ws.lay_kc[b];
+    const int64_t d0 = ws.lay_doff[b];
+    const int D = (int)(ws.lay_doff[b + 1] - d0);
+    // this lane's 16 bytes of row tile 2w + m of chunk j: + j chunk + m 1 KiB
+    const uint8_t* dense = ws.lay_dense + d0 * kDenseChunkBytes;   // uniform base
+    const uint32_t doff = (uint32_t)((wave * 2) * 64 + lane) * 16;
+    const int64_t tb = ws.lay_toff[slot], te = ws.lay_toff[slot + 1];
+    // the block's tail entries are contiguous: one coalesced copy into LDS,
+    // read after the first barrier below
+    const int64_t tbase = ws.lay_toff[(int64_t)b * kBlkCells];
+    const int64_t tcount = ws.lay_toff[(int64_t)(b + 1) * kBlkCells] - tbase;
+    const bool staged = tcount <= kTailStage;
+    if (staged)
+        for (int i = t; i < (int)tcount; i += kMfmaThreads) t_ent[i] = ws.lay_tail[tbase + i];
+    constexpr int R = kLayDmax * kBlkGenes;
 
-    float t1 = -INFINITY, t2 = -INFINITY, a1 = 0.f, a2 = 0.f, p1 = 0.f, p2 = 0.f;
-    int k1 = 0;
-    const int nsteps = 2 * ws.nch;
+    Top2 top;
+    top.init();
 
-    for (int kb = 0; kb < K; kb += 16 * NT) {
-        floatx4_t acc[4][NT];
+    for (int kb = 0; kb < K; kb += NCOL) {
+        floatx4_t acc[2][NT];
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
+        for (int m = 0; m < 2; ++m)
 #pragma unroll
             for (int n = 0; n < NT; ++n) acc[m][n] = floatx4_t{0.f, 0.f, 0.f, 0.f};
-        __syncthreads();
-        // clear the tile once; afterwards only written entries are cleared
-        for (int g = 0; g < kMfmaRow; g += 8)
-            *reinterpret_cast<uint4*>(atile + t * kMfmaRow + g) = make_uint4(0, 0, 0, 0);
-
-        // Software pipeline with two register stages (chunks of even and odd
-        // index): a stage holds its chunk's B rows and first kPrefetch x 4
-        // segment entries; after the chunk has been multiplied and its
-        // entries wiped, the stage is reloaded with the chunk two ahead, so
-        // the loads have a whole chunk to arrive.  The chunk count is even
-        // and past the last chunk the index is clamped, so no stage is
-        // conditional and every path issues the same loads.
-        const int last = ws.nch - 1;
-        BRows<NT> nb0 = load_brows<NT>(ws, kb, 0, t);
-        uint4 sg0[kPrefetch];
-        uint32_t f00 = s_off[0], f01 = s_off[1];
-        load_segment(bres, f00, f01, t, sg0);
-        BRows<NT> nb1 = load_brows<NT>(ws, kb, 1, t);
-        uint4 sg1[kPrefetch];
-        uint32_t f10 = s_off[1], f11 = s_off[2];
-        load_segment(bres, f10, f11, t, sg1);
-        char* tileb = reinterpret_cast<char*>(atile);
-
-        auto phase = [&](int j, BRows<NT>& nb, uint4 (&sg)[kPrefetch], uint32_t& f0, uint32_t& f1)
-            __attribute__((always_inline)) {
-            __syncthreads();
-            // commit chunk j: B rows to LDS, entries into the tile
-            store_brows<NT>(nb, bhi, blo, t);
+#pragma unroll 1
+        for (int g0 = 0; g0 < kLayDmax; g0 += kStageChunks) {
+            if (g0 >= D) break;                // uniform across the workgroup
+            const int gn = min(kStageChunks, D - g0);
+            // the group's A fragments in flight while its B rows are staged
+            uint4 av[kStageChunks][2];
 #pragma unroll
-            for (int r = 0; r < kPrefetch; ++r) {
-                put(tileb, sg[r].x); put(tileb, sg[r].y); put(tileb, sg[r].z); put(tileb, sg[r].w);
-            }
-            for (uint32_t q = f0 + 4 * t + 4 * kMfmaThreads * kPrefetch; q < f1; q += 4 * kMfmaThreads) {
-                const uint4 v = *reinterpret_cast<const uint4*>(bent + q);
-                put(tileb, v.x); put(tileb, v.y); put(tileb, v.z); put(tileb, v.w);
-            }
-            __syncthreads();
+            for (int jj = 0; jj < kStageChunks; ++jj)
 #pragma unroll
-            for (int s = 0; s < 2; ++s) {
-                const int col = 32 * s + 8 * (lane >> 4);
-                bf16x8_t af[4];
-#pragma unroll
-                for (int m = 0; m < 4; ++m)
-                    af[m] = *reinterpret_cast<const bf16x8_t*>(atile + (64 * wave + 16 * m + (lane & 15)) * kMfmaRow + kBlkLead + col);
-#pragma unroll
-                for (int n = 0; n < NT; ++n) {
-                    const bf16x8_t bh = *reinterpret_cast<const bf16x8_t*>(bhi + (16 * n + (lane & 15)) * kMfmaRow + col);
-#pragma unroll
-                    for (int m = 0; m < 4; ++m)
-                        acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[m], bh, acc[m][n], 0, 0, 0);
-                }
-#pragma unroll
-                for (int n = 0; n < NT; ++n) {
-                    const bf16x8_t bl = *reinterpret_cast<const bf16x8_t*>(blo + (16 * n + (lane & 15)) * kMfmaRow + col);
-#pragma unroll
-                    for (int m = 0; m < 4; ++m)
-                        acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[m], bl, acc[m][n], 0, 0, 0);
+                for (int m = 0; m < 2; ++m)
+                    av[jj][m] = jj < gn ? *reinterpret_cast<const uint4*>(dense + (doff + (uint32_t)((g0 + jj) * kDenseChunkBytes + m * 1024)))
+                                        : make_uint4(0, 0, 0, 0);
+            __syncthreads();                   // the previous readers of the LDS are done
+            {
+                // B rows: gn chunks x (hi, lo) x NCOL columns x 8 pieces of 16 bytes
+                const int items = gn * 2 * NCOL * (kBlkGenes / 8);
+                const uint16_t* hi = ws.lay_bhi + ((int64_t)L * ws.lay_cols + kb) * R + g0 * kBlkGenes;
+                const uint16_t* lo = ws.lay_blo + ((int64_t)L * ws.lay_cols + kb) * R + g0 * kBlkGenes;
+                for (int q = t; q < items; q += kMfmaThreads) {
+                    const int piece = q & 7;
+                    const int col = (q >> 3) % NCOL;
+                    const int rest = (q >> 3) / NCOL;      // jj * 2 + tbl
+                    const int tbl = rest & 1, jj = rest >> 1;
+                    const uint16_t* src = (tbl ? lo : hi) + (int64_t)col * R + jj * kBlkGenes + piece * 8;
+                    *reinterpret_cast<uint4*>(bst + (rest * NCOL + col) * kRowB + piece * 8) =
+                        *reinterpret_cast<const uint4*>(src);
                 }
             }
             __syncthreads();
-            // clear the written entries (the first ones are still in the stage)
 #pragma unroll
-            for (int r = 0; r < kPrefetch; ++r) {
-                wipe(tileb, sg[r].x); wipe(tileb, sg[r].y); wipe(tileb, sg[r].z); wipe(tileb, sg[r].w);
-            }
-            for (uint32_t q = f0 + 4 * t + 4 * kMfmaThreads * kPrefetch; q < f1; q += 4 * kMfmaThreads) {
-                const uint4 v = *reinterpret_cast<const uint4*>(bent + q);
-                wipe(tileb, v.x); wipe(tileb, v.y); wipe(tileb, v.z); wipe(tileb, v.w);
-            }
-            // reload the stage with the chunk two ahead
-            const int jn = min(j + 2, last);
-            f0 = s_off[jn];
-            f1 = s_off[jn + 1];
-            nb = load_brows<NT>(ws, kb, jn, t);
-            load_segment(bres, f0, f1, t, sg);
-        };
-        for (int j = 0; j < ws.nch; j += 2) {
-            phase(j, nb0, sg0, f00, f01);
-            phase(j + 1, nb1, sg1, f10, f11);
-        }
-        __syncthreads();
-        // scores through LDS: lane l holds, for row tile m and column tile n,
-        // cells 64w + 16m + 4(l/16) + j (j < 4) against cluster 16n + l%16
+            for (int jj = 0; jj < kStageChunks; ++jj) {
+                if (jj >= gn) break;
+                bf16x8_t af[2][2];
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
+                for (int m = 0; m < 2; ++m) {
+                    af[m][0] = widen8(av[jj][m].x, av[jj][m].y);
+                    af[m][1] = widen8(av[jj][m].z, av[jj][m].w);
+                }
+                const uint16_t* bh = bst + (2 * jj) * NCOL * kRowB;
+                const uint16_t* bl = bst + (2 * jj + 1) * NCOL * kRowB;
 #pragma unroll
-            for (int n = 0; n < NT; ++n)
+                for (int s = 0; s < 2; ++s) {
+                    const int col = 32 * s + 8 * (lane >> 4);
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    sc[(64 * wave + 16 * m + 4 * (lane >> 4) + q) * SS + 16 * n + (lane & 15)] = acc[m][n][q];
-        __syncthreads();
-        // FP32 corrections of the counts above 256 (static list of this block)
-        for (int64_t o = ws.ovf_off[blk] + t; o < ws.ovf_off[blk + 1]; o += kMfmaThreads) {
-            const uint2 ov = ws.ovf_ent[o];
-            const int cell = (int)(ov.x & 0xFFu);
-            const int g = (int)(ov.x >> 8);
-            const float xb = (float)ov.y;
-            const float* lrow = ws.lc32 + (int64_t)g * ws.kpad + kb;
-            for (int k = 0; k < 16 * NT && kb + k < K; ++k) atomicAdd(&sc[cell * SS + k], xb * lrow[k]);
-        }
-        __syncthreads();
-        if (valid) {
-            // four clusters per Philox call; constant word indices keep the
-            // words in registers
-            for (int k4 = 0; k4 < 16 * NT && kb + k4 < K; k4 += 4) {
-                const Words w = philox(ws.seed, (uint32_t)i, (uint32_t)((kb + k4) >> 2), a.step, kGumbelC, 0u);
+                    for (int n = 0; n < NT; ++n) {
+                        const bf16x8_t vh = *reinterpret_cast<const bf16x8_t*>(bh + (16 * n + (lane & 15)) * kRowB + col);
+                        const bf16x8_t vl = *reinterpret_cast<const bf16x8_t*>(bl + (16 * n + (lane & 15)) * kRowB + col);
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int kk = kb + k4 + q;
-                    if (kk >= K) break;
-                    const float s = sc[t * SS + k4 + q];
-                    const float lp = (float)ws.logpi[kk];
-                    const float v = lp + s + gumbel32(w.w[q]);
-                    if (a.dbg && K + 2 <= a.dbg_stride) put_dbg(a.dbg, a.dbg64, i * a.dbg_stride + kk, (double)s);
-                    if (v > t1) {
-                        t2 = t1; a2 = a1; p2 = p1;
-                        t1 = v; a1 = s; p1 = lp; k1 = kk;
-                    } else if (v > t2) {
-                        t2 = v; a2 = s; p2 = lp;
+                        for (int m = 0; m < 2; ++m) {
+                            acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[m][s], vh, acc[m][n], 0, 0, 0);
+                            acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[m][s], vl, acc[m][n], 0, 0, 0);
+                        }
                     }
                 }
             }
         }
+        __syncthreads();
+        // scores through LDS: lane l holds, for row tile m and column tile n,
+        // slots 32w + 16m + 4(l/16) + q (q < 4) against cluster kb + 16n + l%16
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+            for (int n = 0; n < NT; ++n)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    sc[(32 * wave + 16 * m + 4 * (lane >> 4) + q) * SS + 16 * n + (lane & 15)] = acc[m][n][q];
+        __syncthreads();
+        if (cell >= 0) {
+            // this thread's half of the column group: HALF clusters from kh
+            const int kh = kb + half * HALF;
+            // the cell's tail entries in FP32 against the gene-major table,
+            // added in entry order to this thread's own columns of the score
+            // row, two entries' table rows in flight at a time
+            float* srow = sc + sl * SS + half * HALF;
+            if (te > tb) {
+                float ta[HALF];
+#pragma unroll
+                for (int k = 0; k < HALF; ++k) ta[k] = srow[k];
+                const float* lcb = ws.lc32 + kh;
+                int64_t e = tb;
+#pragma unroll 1
+                for (; e + 1 < te; e += 2) {
+                    const uint32_t n0 = staged ? t_ent[e - tbase] : ws.lay_tail[e];
+                    const uint32_t n1 = staged ? t_ent[e + 1 - tbase] : ws.lay_tail[e + 1];
+                    const float4* r0 = reinterpret_cast<const float4*>(lcb + (int64_t)(n0 & 0xFFFFu) * ws.kpad);
+                    const float4* r1 = reinterpret_cast<const float4*>(lcb + (int64_t)(n1 & 0xFFFFu) * ws.kpad);
+                    float4 v0[HALF / 4], v1[HALF / 4];
+#pragma unroll
+                    for (int k4 = 0; k4 < HALF / 4; ++k4) {
+                        v0[k4] = r0[k4];
+                        v1[k4] = r1[k4];
+                    }
+                    const float x0 = (float)(n0 >> 16), x1 = (float)(n1 >> 16);
+#pragma unroll
+                    for (int k4 = 0; k4 < HALF / 4; ++k4) {
+                        ta[4 * k4 + 0] = fmaf(x0, v0[k4].x, ta[4 * k4 + 0]);
+                        ta[4 * k4 + 1] = fmaf(x0, v0[k4].y, ta[4 * k4 + 1]);
+                        ta[4 * k4 + 2] = fmaf(x0, v0[k4].z, ta[4 * k4 + 2]);
+                        ta[4 * k4 + 3] = fmaf(x0, v0[k4].w, ta[4 * k4 + 3]);
+                    }
+#pragma unroll
+                    for (int k4 = 0; k4 < HALF / 4; ++k4) {
+                        ta[4 * k4 + 0] = fmaf(x1, v1[k4].x, ta[4 * k4 + 0]);
+                        ta[4 * k4 + 1] = fmaf(x1, v1[k4].y, ta[4 * k4 + 1]);
+                        ta[4 * k4 + 2] = fmaf(x1, v1[k4].z, ta[4 * k4 + 2]);
+                        ta[4 * k4 + 3] = fmaf(x1, v1[k4].w, ta[4 * k4 + 3]);
+                    }
+                }
+                if (e < te) {
+                    const uint32_t n0 = staged ? t_ent[e - tbase] : ws.lay_tail[e];
+                    const float4* r0 = reinterpret_cast<const float4*>(lcb + (int64_t)(n0 & 0xFFFFu) * ws.kpad);
+                    const float x0 = (float)(n0 >> 16);
+#pragma unroll
+                    for (int k4 = 0; k4 < HALF / 4; ++k4) {
+                        const float4 v = r0[k4];
+                        ta[4 * k4 + 0] = fmaf(x0, v.x, ta[4 * k4 + 0]);
+                        ta[4 * k4 + 1] = fmaf(x0, v.y, ta[4 * k4 + 1]);
+                        ta[4 * k4 + 2] = fmaf(x0, v.z, ta[4 * k4 + 2]);
+                        ta[4 * k4 + 3] = fmaf(x0, v.w, ta[4 * k4 + 3]);
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < HALF; ++k) srow[k] = ta[k];
+            }
+            // Gumbel pruning.  Scores and log pi are <= 0, so a cluster's
+            // rounding bound grows with |score + log pi|.  The noise of a
+            // draw lies in [kGumbelLo, kGumbelHi]; a cluster whose score plus
+            // log pi is below the group's best by more than that width plus
+            // both clusters' rounding bounds and the refinement margins can
+            // neither win nor be the runner-up of an uncertified decision, in
+            // FP32 or in exact arithmetic, so its noise is not drawn.
+            float dmax = -INFINITY;
+            for (int k = 0; k < HALF; ++k) {
+                const int kk = kh + k;
+                if (kk >= K) break;
+                dmax = fmaxf(dmax, srow[k] + (float)ws.logpi[kk]);
+            }
+            x_d[half][sl] = dmax;
+        }
+        __syncthreads();
+        if (cell >= 0) {
+            const int kh = kb + half * HALF;
+            const float* srow = sc + sl * SS + half * HALF;
+            const float dm = fmaxf(x_d[0][sl], x_d[1][sl]);
+            // with f the relative factor of bf16_bound and D the distance below
+            // dm: the winner is within the noise width of dm, so the condition
+            // D > width + f (2|dm| + D + 60) + margins is D > thr
+            const float f = (0x1p-17f + (float)(2 * ws.lay_nnz[slot] + 8) * 0x1p-23f) * 1.01f;
+            const float adm = fabsf(dm);
+            const float thr = ((kGumbelHi - kGumbelLo) + f * (2.0f * adm + 60.0f) +
+                               ((float)kNearTie + fmaxf(a.refine_tol, 0.0f)) * (adm + 20.0f) + 1.0f) /
+                              (1.0f - f);
+            const float cut = dm - thr;
+            // four clusters per Philox call; constant indices keep the words
+            // in registers
+#pragma unroll
+            for (int k4 = 0; k4 < HALF; k4 += 4) {
+                if (kh + k4 >= K) continue;
+                bool any = false;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int kk = kh + k4 + q;
+                    if (kk < K && srow[k4 + q] + (float)ws.logpi[kk] >= cut) any = true;
+                    if (a.dbg && kk < K && K + 2 <= a.dbg_stride)
+                        put_dbg(a.dbg, a.dbg64, (int64_t)cell * a.dbg_stride + kk, (double)srow[k4 + q]);
+                }
+                if (!any) continue;
+                const Words w = philox(ws.seed, (uint32_t)cell, (uint32_t)((kh + k4) >> 2), a.step, kGumbelC, 0u);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int kk = kh + k4 + q;
+                    if (kk >= K) continue;
+                    const float s = srow[k4 + q];
+                    const float lp = (float)ws.logpi[kk];
+                    if (s + lp < cut) continue;
+                    top.add(lp + s + gumbel32(w.w[q]), s, lp, kk);
+                }
+            }
+        }
     }
-    if (!valid) return;
+    // the two halves of each slot: the upper half hands its best two to the
+    // lower, which merges them in cluster order (lower half first, as a single
+    // thread scanning the clusters in order would)
+    if (half == 1) {
+        x_t1[sl] = top.t1; x_t2[sl] = top.t2; x_a1[sl] = top.a1; x_a2[sl] = top.a2;
+        x_p1[sl] = top.p1; x_p2[sl] = top.p2; x_k1[sl] = top.k1;
+    }
+    __syncthreads();
+    if (half == 1 || cell < 0) return;
+    // column groups alternate halves, so the merged order differs from a scan
+    // only among exactly equal values: ties keep the lower cluster index, as
+    // here the strict comparisons keep the earlier value and the lower half's
+    // clusters of a group precede the upper half's.  With several groups
+    // (K > 16 NT) an upper-half cluster can precede a lower-half one of the
+    // next group; a tie between them resolves to the lower index explicitly.
+    {
+        const float u1 = x_t1[sl], u2 = x_t2[sl];
+        const int uk = x_k1[sl];
+        if (u1 > top.t1 || (u1 == top.t1 && uk < top.k1)) {
+            // the upper half's best wins; the runner-up is the better of the
+            // lower half's best and the upper half's second
+            const float o1 = top.t1, oa = top.a1, op = top.p1;
+            top.t2 = o1 > u2 ? o1 : u2;
+            top.a2 = o1 > u2 ? oa : x_a2[sl];
+            top.p2 = o1 > u2 ? op : x_p2[sl];
+            top.t1 = u1; top.a1 = x_a1[sl]; top.p1 = x_p1[sl]; top.k1 = uk;
+        } else if (u1 > top.t2) {
+            top.t2 = u1; top.a2 = x_a1[sl]; top.p2 = x_p1[sl];
+        }
+    }
     bool uncertain = false;
     if (K >= 2) {
-        const float bnd = bf16_bound(a1, p1, nsteps) + bf16_bound(a2, p2, nsteps);
-        const float near = (float)kNearTie * fmaxf(1.0f, fabsf(t1));
-        if (t1 - t2 <= bnd + near || (t1 - t2) / fmaxf(1.0f, fabsf(t1)) < a.refine_tol) uncertain = true;
+        const int nnz = ws.lay_nnz[slot];
+        const float bnd = bf16_bound(top.a1, top.p1, nnz) + bf16_bound(top.a2, top.p2, nnz);
+        const float near = (float)kNearTie * fmaxf(1.0f, fabsf(top.t1));
+        if (top.t1 - top.t2 <= bnd + near || (top.t1 - top.t2) / fmaxf(1.0f, fabsf(top.t1)) < a.refine_tol)
+            uncertain = true;
     }
-    a.c_new[i] = k1;
+    a.c_new[cell] = top.k1;
     if (uncertain) {
         const int q = atomicAdd(&ws.st->n_refine, 1);
-        if (q < ws.N) ws.refine[q] = (uint32_t)i | kRefineCluster;
+        if (q < ws.N) ws.refine[q] = (uint32_t)cell | kRefineCluster;
     }
 }
 
 template <int NT>
 static void launch_nt(const Ws& ws, const AssignArgs& a, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_assign_bf16<NT>, dim3((unsigned)ws.nblk), dim3(kMfmaThreads), mfma_lds_bytes(NT), s, ws, a);
+    hipLaunchKernelGGL(k_assign_bf16<NT>, dim3((unsigned)ws.nblk_cap), dim3(kMfmaThreads), mfma_lds_bytes(NT), s, ws, a);
 }
 
 // Allow the dynamic LDS size of every variant on the current device.

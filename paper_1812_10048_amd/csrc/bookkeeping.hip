@@ -44,9 +44,10 @@ __device__ inline int64_t block_exclusive_scan(int64_t v, int64_t* lds, int64_t*
     return incl - v;
 }
 
-__global__ void k_scan_tiles(int64_t* __restrict__ v, int64_t n, int64_t* __restrict__ tile_sums)
+__global__ void k_scan_tiles(int64_t* __restrict__ v, int64_t n, int64_t* __restrict__ tile_sums, const int32_t* gate)
 {
     __shared__ int64_t lds[kScanThreads];
+    if (gate && !*gate) return;
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPerThread;
     int64_t loc[kScanPerThread];
     int64_t s = 0;
@@ -67,9 +68,10 @@ __global__ void k_scan_tiles(int64_t* __restrict__ v, int64_t n, int64_t* __rest
     if (threadIdx.x == 0) tile_sums[blockIdx.x] = total;
 }
 
-__global__ void k_scan_tile_sums(int64_t* __restrict__ tile_sums, int64_t ntiles)
+__global__ void k_scan_tile_sums(int64_t* __restrict__ tile_sums, int64_t ntiles, const int32_t* gate)
 {
     __shared__ int64_t lds[kScanThreads];
+    if (gate && !*gate) return;
     int64_t carry = 0;
     for (int64_t b = 0; b < ntiles; b += kScanThreads) {
         const int64_t idx = b + threadIdx.x;
@@ -83,19 +85,21 @@ __global__ void k_scan_tile_sums(int64_t* __restrict__ tile_sums, int64_t ntiles
 }
 
 __global__ void k_scan_add(int64_t* __restrict__ v, int64_t n, const int64_t* __restrict__ tile_sums,
-                           int64_t ntiles)
+                           int64_t ntiles, const int32_t* gate)
 {
+    if (gate && !*gate) return;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) v[i] += tile_sums[i / kScanTile];
     if (i == 0) v[n] = tile_sums[ntiles];
 }
 
-void launch_exclusive_scan(int64_t* v, int64_t n, int64_t* tile_sums, hipStream_t s)
+void launch_exclusive_scan(int64_t* v, int64_t n, int64_t* tile_sums, hipStream_t s, const int32_t* gate)
 {
     const int64_t ntiles = (n + kScanTile - 1) / kScanTile;
-    if (ntiles > 0) hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)ntiles), dim3(kScanThreads), 0, s, v, n, tile_sums);
-    hipLaunchKernelGGL(k_scan_tile_sums, dim3(1), dim3(kScanThreads), 0, s, tile_sums, ntiles);
-    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)((n + 256) / 256)), dim3(256), 0, s, v, n, tile_sums, ntiles);
+    if (ntiles > 0)
+        hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)ntiles), dim3(kScanThreads), 0, s, v, n, tile_sums, gate);
+    hipLaunchKernelGGL(k_scan_tile_sums, dim3(1), dim3(kScanThreads), 0, s, tile_sums, ntiles, gate);
+    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)((n + 256) / 256)), dim3(256), 0, s, v, n, tile_sums, ntiles, gate);
 }
 
 // One wavefront per row: validate (columns strictly increasing and < G,
@@ -213,9 +217,11 @@ __device__ inline SortCells load_groups(const Ws& ws, const int32_t* __restrict_
 }
 
 __global__ void __launch_bounds__(kSortThreads) k_group_count(Ws ws, const int32_t* __restrict__ c,
-                                                              const uint8_t* __restrict__ cs, int by_cluster)
+                                                              const uint8_t* __restrict__ cs, int by_cluster,
+                                                              const int32_t* gate)
 {
     extern __shared__ uint32_t hist[];   // [groups]
+    if (gate && !*gate) return;
     const int ng = by_cluster ? ws.k_max : 2 * ws.k_max;
     for (int q = threadIdx.x; q < ng; q += kSortThreads) hist[q] = 0;
     const int64_t b0 = (int64_t)blockIdx.x * kSortCellsPerBlock;
@@ -231,9 +237,10 @@ __global__ void __launch_bounds__(kSortThreads) k_group_count(Ws ws, const int32
 }
 
 // exclusive scan of the group sizes; with groups (k, r) the sizes are n_{k,r}
-__global__ void __launch_bounds__(kSortThreads) k_group_scan(Ws ws, int by_cluster)
+__global__ void __launch_bounds__(kSortThreads) k_group_scan(Ws ws, int by_cluster, const int32_t* gate)
 {
     __shared__ int32_t lds[kSortThreads];
+    if (gate && !*gate) return;
     const int ng = by_cluster ? ws.k_max : 2 * ws.k_max;
     int32_t carry = 0;
     for (int base = 0; base < ng; base += kSortThreads) {
@@ -260,9 +267,11 @@ __global__ void __launch_bounds__(kSortThreads) k_group_scan(Ws ws, int by_clust
 
 __global__ void __launch_bounds__(kSortThreads) k_group_scatter(Ws ws, const int32_t* __restrict__ c,
                                                                 const uint8_t* __restrict__ cs, int by_cluster,
-                                                                const int32_t* __restrict__ c_prev)
+                                                                const int32_t* __restrict__ c_prev,
+                                                                const int32_t* gate)
 {
     extern __shared__ uint32_t lds_u[];      // [groups] counts, then [groups] bases
+    if (gate && !*gate) return;
     const int ng = by_cluster ? ws.k_max : 2 * ws.k_max;
     uint32_t* cnt = lds_u;
     uint32_t* base = lds_u + ng;
@@ -394,16 +403,16 @@ void launch_zero(void* p, size_t bytes, hipStream_t s)
 }
 
 void launch_sort(const Ws& ws, const int32_t* c, const uint8_t* cs, int by_cluster, hipStream_t s,
-                 bool counts_cleared, const int32_t* c_prev)
+                 bool counts_cleared, const int32_t* c_prev, const int32_t* gate)
 {
     const int ng = by_cluster ? ws.k_max : 2 * ws.k_max;
     if (!counts_cleared) launch_zero(ws.grp_cnt, sizeof(int32_t) * (size_t)ng, s);
     const unsigned sb = (unsigned)((ws.N + kSortCellsPerBlock - 1) / kSortCellsPerBlock);
     hipLaunchKernelGGL(k_group_count, dim3(sb), dim3(kSortThreads), sizeof(uint32_t) * (size_t)ng, s, ws, c, cs,
-                       by_cluster);
-    hipLaunchKernelGGL(k_group_scan, dim3(1), dim3(kSortThreads), 0, s, ws, by_cluster);
+                       by_cluster, gate);
+    hipLaunchKernelGGL(k_group_scan, dim3(1), dim3(kSortThreads), 0, s, ws, by_cluster, gate);
     hipLaunchKernelGGL(k_group_scatter, dim3(sb), dim3(kSortThreads), 2 * sizeof(uint32_t) * (size_t)ng, s, ws, c,
-                       cs, by_cluster, c_prev);
+                       cs, by_cluster, c_prev, gate);
 }
 
 void launch_stats(const Ws& ws, const int32_t* c, const uint8_t* cs, hipStream_t s)
@@ -436,10 +445,12 @@ __global__ void __launch_bounds__(1024) k_compact(Ws ws, int after_sweep)
     for (int k = t; k < K; k += blockDim.x) lds_map[k] = (ws.nsub[2 * k] + ws.nsub[2 * k + 1]) > 0 ? 1 : 0;
     __syncthreads();
     if (t == 0) {
+        // changed: a cluster with cells takes a new index, so labels must be
+        // rewritten; dropping empty clusters at the end renumbers nobody
         int nk = 0, changed = 0;
         for (int k = 0; k < K; ++k) {
             lds_map[k] = lds_map[k] ? nk++ : -1;
-            if (lds_map[k] != k) changed = 1;
+            if (lds_map[k] >= 0 && lds_map[k] != k) changed = 1;
         }
         s_nk = nk;
         s_changed = changed;
@@ -447,20 +458,29 @@ __global__ void __launch_bounds__(1024) k_compact(Ws ws, int after_sweep)
     __syncthreads();
     const int nk = s_nk;
     const int G = ws.G;
-    if (s_changed) {
+    // the coin-half statistics of a coming random split move with the rest
+    const bool rs = ws.rssub && ws.st->rs_live;
+    if (s_changed || nk < K) {
         for (int k = 0; k < K; ++k) {
             const int j = lds_map[k];
             if (j >= 0 && j != k) {
                 for (int u = t; u < 2 * G; u += blockDim.x)
                     ws.ssub[(int64_t)2 * j * G + u] = ws.ssub[(int64_t)2 * k * G + u];
+                if (rs)
+                    for (int u = t; u < 2 * G; u += blockDim.x)
+                        ws.rssub[(int64_t)2 * j * G + u] = ws.rssub[(int64_t)2 * k * G + u];
                 if (t < 2) ws.nsub[2 * j + t] = ws.nsub[2 * k + t];
+                if (rs && t < 2) ws.rnsub[2 * j + t] = ws.rnsub[2 * k + t];
                 if (t == 0) ws.reset[j] = ws.reset[k];
             }
             __syncthreads();
         }
         for (int k = nk; k < K; ++k) {
             for (int u = t; u < 2 * G; u += blockDim.x) ws.ssub[(int64_t)2 * k * G + u] = 0;
+            if (rs)
+                for (int u = t; u < 2 * G; u += blockDim.x) ws.rssub[(int64_t)2 * k * G + u] = 0;
             if (t < 2) ws.nsub[2 * k + t] = 0;
+            if (rs && t < 2) ws.rnsub[2 * k + t] = 0;
             if (t == 0) ws.reset[k] = 0;
         }
         __syncthreads();
@@ -485,6 +505,7 @@ __global__ void __launch_bounds__(1024) k_compact(Ws ws, int after_sweep)
         ws.st->K = nk;
         ws.st->has_new = 0;
         ws.st->relabel = s_changed;
+        if (s_changed) ws.st->relabels += 1;
         if (ws.k_hint) __hip_atomic_store(ws.k_hint, nk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }

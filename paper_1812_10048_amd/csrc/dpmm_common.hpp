@@ -101,6 +101,12 @@ struct DevState {
     int32_t pad;
     unsigned long long counters[kNumCounters];
     double log_joint;     // written by launch_log_joint
+    uint32_t relabels;    // times the labels were renumbered (compaction, accepted moves)
+    int32_t lay_go;       // the cluster-sorted copy is being rebuilt (gate of its kernels)
+    int32_t lay_nblk;     // blocks of the copy
+    int32_t lay_K;        // K when the copy was built
+    uint32_t lay_relabels;   // relabels when the copy was built
+    int32_t rs_live;      // the coin-half statistics of the next random split are in rssub / rnsub
 };
 
 // Packed count entry: gene in the low 16 bits, count in the high 16 bits.
@@ -108,12 +114,12 @@ struct DevState {
 constexpr uint32_t kPadEntry = 0x0000FFFFu;   // gene 0xFFFF, count 0
 
 constexpr int kBlkCells = 256;
+constexpr int kLayDmax = 8;                        // dense gene chunks per block of the cluster-sorted copy
+constexpr int kDenseChunkBytes = 256 * 64;         // one byte per (cell, gene) of a block and chunk
 constexpr uint32_t kFlagSplitQ = 1u;          // dpmm_params.flags bit of the split proposal term
 constexpr uint32_t kFlagNewCluster = 2u;      // ... and of the Gibbs step over K + 1 clusters
 constexpr uint32_t kFlagRandomSplit = 4u;     // ... and of the random-split pass
 constexpr int kBlkGenes = 64;
-constexpr int kBlkLead = 8;              // padding columns at the start of a dense tile row
-constexpr int kBlkRow = kBlkLead + kBlkGenes;   // BF16 elements per row of the dense LDS tile
 
 // Refine-queue flags (high bits of a queued cell index).
 constexpr uint32_t kRefineCluster = 1u << 31;
@@ -217,15 +223,25 @@ struct Ws {
     int32_t* grp_off;      // [2 k_max + 1] group offsets in perm
     int32_t* grp_cur;      // [2 k_max] scatter cursors
     unsigned long long* nsub_prev;   // [2 k_max] n_{k,r} at the start of the sweep
-    // blocked copy of the counts for the matrix cores: cell blocks of
-    // kBlkCells cells x gene chunks of kBlkGenes genes, one segment per
-    // (block, chunk), entries (BF16 count | LDS byte offset << 16)
-    const uint32_t* blk_ent;
-    int64_t* blk_off;      // [nblk * nch + 1] segment offsets (multiples of 4)
-    int64_t* ovf_off;      // [nblk + 1] offsets of each block's counts above 256
-    uint2* ovf_ent;        // (cell in block | gene << 8, count - its BF16 head)
-    int32_t nblk;
-    int32_t nch;
+    // cluster-sorted copy of the counts for the matrix cores (split-BF16,
+    // layout.hip): blocks of kBlkCells cells of one cluster, genes renumbered
+    // per cluster, the first D_b chunks of kBlkGenes genes dense (one byte per
+    // count, MFMA fragment order), the other entries in per-cell tail lists
+    int32_t* lay_kc;       // [nblk_cap] layout cluster of each block
+    int32_t* lay_pbeg;     // [nblk_cap] its first cell in the sort order
+    int32_t* lay_pcnt;     // [nblk_cap] its number of cells
+    int32_t* lay_cell;     // [nblk_cap kBlkCells] cell of each slot, -1 if empty
+    int64_t* lay_doff;     // [nblk_cap + 1] dense chunks before each block
+    int64_t* lay_toff;     // [nblk_cap kBlkCells + 1] tail entries before each slot
+    uint8_t* lay_dense;    // dense chunks, kDenseChunkBytes each
+    uint32_t* lay_tail;    // tail entries (gene | count << 16), each slot's in row order
+    uint16_t* lay_nnz;     // [nblk_cap kBlkCells] non-zero counts of each slot's cell
+    uint16_t* lay_rank;    // [k_max G] place of gene u in cluster L's order
+    uint16_t* lay_gene;    // [k_max kLayDmax kBlkGenes] gene at place j
+    uint16_t* lay_bhi;     // [k_max][lay_cols][kLayDmax kBlkGenes] hi of log theta in L's gene order
+    uint16_t* lay_blo;     // same for lo
+    int32_t nblk_cap;      // blocks the copy can hold: ceil(N / kBlkCells) + k_max
+    int32_t lay_cols;      // column rows per layout cluster in lay_bhi / lay_blo
     int32_t sub_cells;     // sorted cells per workgroup of the sub-cluster/statistics pass
     uint32_t flags;        // kFlagSplitQ: the split ratio carries -sum log p(cbar_i)
     double* lpsub;         // [N] log p(cbar_i) of eq. 8 in the last sweep (with kFlagSplitQ only)

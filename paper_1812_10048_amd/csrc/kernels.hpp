@@ -8,7 +8,8 @@ namespace dpmm {
 
 // bookkeeping.hip
 void launch_zero(void* p, size_t bytes, hipStream_t s);   // bytes: a multiple of 4
-void launch_exclusive_scan(int64_t* v, int64_t n, int64_t* tile_sums, hipStream_t s);
+// gate (device, may be null): the kernels do nothing unless *gate != 0
+void launch_exclusive_scan(int64_t* v, int64_t n, int64_t* tile_sums, hipStream_t s, const int32_t* gate = nullptr);
 void launch_pack(const int64_t* row_ptr, const int32_t* col, const int32_t* val, int64_t N, int32_t G, int64_t nnz,
                  int64_t* roff, int64_t* tile_sums, uint32_t* ent, DevState* st, hipStream_t s);
 void launch_init_labels(const Ws& ws, int32_t k_init, int32_t* c, uint8_t* cs, hipStream_t s);
@@ -16,11 +17,16 @@ void launch_stats(const Ws& ws, const int32_t* c, const uint8_t* cs, hipStream_t
 // c_prev (by cluster only, may be null): the labels before the sweep, whose
 // membership of the cell's new cluster goes into the top bits of srow.w
 void launch_sort(const Ws& ws, const int32_t* c, const uint8_t* cs, int by_cluster, hipStream_t s,
-                 bool counts_cleared = false, const int32_t* c_prev = nullptr);
+                 bool counts_cleared = false, const int32_t* c_prev = nullptr, const int32_t* gate = nullptr);
 
 // layout.hip
-void launch_build_blocked(const Ws& ws, int64_t* tile_sums, hipStream_t s);
+// rebuild the cluster-sorted copy from labels c (force: unconditionally; else
+// only when the partition changed structurally since the last build)
+void launch_relayout(const Ws& ws, const int32_t* c, int64_t* tile_sums, int force, hipStream_t s);
+void launch_lay_btab(const Ws& ws, hipStream_t s);    // permuted hi/lo tables, after each redraw
 hipError_t configure_layout();
+
+// bookkeeping.hip
 void launch_extend(const Ws& ws, hipStream_t s);
 void launch_gene_moments(const int32_t* col, const int32_t* val, int64_t nnz, int32_t G, unsigned long long* sum,
                          unsigned long long* sumsq, hipStream_t s);
@@ -39,6 +45,8 @@ struct SubArgs {
     void* dbg;            // optional score dump (FP32, or FP64 when dbg64), row stride dbg_stride
     int32_t dbg_stride;
     int32_t dbg64;
+    int32_t rsplit;       // also draw the coins of the random split at step rs_step and
+    uint32_t rs_step;     // accumulate the statistics of the coin halves (rbits, rssub, rnsub)
 };
 void launch_sub_stats(const Ws& ws, const SubArgs& a, hipStream_t s);
 hipError_t sub_stats_cells(int64_t N, int G, int32_t* cells);
@@ -75,7 +83,7 @@ void launch_dump_scores(const Ws& ws, const int32_t* c, const int32_t* cells, in
 // splitmerge.hip
 void launch_lgamma_beta(const Ws& ws, hipStream_t s);   // lgbeta = lgamma(beta), wherever beta changes
 void launch_split_ratios(const Ws& ws, const int32_t* c, hipStream_t s);
-void launch_random_split(const Ws& ws, const int32_t* c, uint8_t* cs, uint32_t step, hipStream_t s);
+void launch_random_split(const Ws& ws, const int32_t* c, uint8_t* cs, uint32_t step, bool ready, hipStream_t s);
 void launch_merge_ratios(const Ws& ws, hipStream_t s);
 void launch_sm_decide(const Ws& ws, int merge_pass, uint32_t step, hipStream_t s);
 // collapsed log joint log p(c) + sum_k logDM(s_k) (eq. 10 with Gamma(alpha), eq. 12

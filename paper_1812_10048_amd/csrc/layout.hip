@@ -1,223 +1,315 @@
-// layout.hip -- the blocked copy of the count matrix read by the matrix-core
-// kernel, built once at init from the packed rows.
+// layout.hip -- the cluster-sorted copy of the count matrix read by the
+// matrix-core kernel (split-BF16), rebuilt from the labels when the partition
+// has changed.
 //
-// Cells are taken in blocks of kBlkCells (in input order) and genes in chunks
-// of kBlkGenes.  Segment (b, j) holds every entry of block b's cells whose
-// gene is in chunk j, ordered by cell then gene.  Since the counts never
-// change, each entry is stored ready for the kernel's scatter into its dense
-// BF16 tile in LDS:
-//   low 16 bits   BF16 value of the count (of its top 8 significant bits
-//                 when the count exceeds 256),
-//   high 16 bits  byte offset of (cell, gene) in the tile.
-// Each tile row starts with kBlkLead padding columns, so the entry 0 (BF16
-// zero at byte offset 0) writes into a padding column: segments are padded to
-// a multiple of four with it, so the scatter needs no test, and a load that
-// returns zeros is harmless too.  Counts above
-// 256 also go to a per-block list (cell, gene, count - head) whose FP32
-// corrections the kernel adds to the scores.
+// The profiles theta_k of droplet data put most of a cluster's counts on a few
+// hundred genes, and which genes those are differs from cluster to cluster.
+// So the copy is built per cluster: the cells of cluster L (labels at build
+// time) are taken in blocks of kBlkCells (a cluster's last block is padded
+// with empty slots), and the genes are renumbered for L by decreasing count
+// s_{L,u} (the cluster's sufficient statistics).  In that order a block's
+// counts crowd into the first few chunks of kBlkGenes genes.  The first D_b
+// chunks of block b are stored dense, one byte per (cell, gene), in the order
+// of the matrix-core fragments; every other entry (a gene past those chunks,
+// or a count above 255) is a tail entry of its cell, (gene | count << 16).
+// D_b (at most kLayDmax) minimises the block's cost, 16 KiB per dense chunk
+// against kTailCost per tail entry.
 //
-// The order of the entries inside a segment is free (each carries its own
-// offset).  The matrix-core kernel reads a segment with 16-byte loads, thread
-// t taking positions 1024r + 4t + c, so one wavefront store instruction
-// (wave w, r, c) writes the entries at 1024r + 256w + 4l + c, l < 64.  A
-// last pass reorders each segment so that such an instruction writes
-// entries of distinct LDS banks: the entries are taken round-robin over the
-// banks (rank within the bank, then bank) and dealt to the store
-// instructions in turn, 64 consecutive ones each.
+// The copy only decides how each cell's log-likelihoods are summed; any cell
+// in any block is scored exactly the same way, so the copy may lag behind the
+// labels.  It is rebuilt at init and at dpmm_set_state, and by the sweeps when
+// the partition has changed structurally (a cluster appeared, disappeared or
+// was renumbered); the build kernels then run gated on a device flag.
 #include "dpmm_common.hpp"
 #include "kernels.hpp"
 
 namespace dpmm {
 
-constexpr int kLayThreads = kBlkCells;   // one thread per cell of the block
+constexpr int kLayThreads = kBlkCells;        // one thread per block slot
+constexpr int kRankThreads = 1024;
+constexpr int kRankMaxGenes = 8192;           // genes renumbered per cluster up to this G
+constexpr long long kTailCost = 36;           // a tail entry against a dense byte
 
-__device__ inline uint32_t count_head(uint32_t x)
+__device__ inline bool lay_gate(const Ws& ws, int gated) { return !gated || ws.st->lay_go; }
+
+// Decide whether the copy is stale: the partition changed structurally since
+// it was built (K differs, or labels were renumbered).
+__global__ void k_lay_decide(Ws ws, int force)
 {
-    if (x <= 256u) return x;
-    const int sh = (32 - __clz((int)x)) - 8;
-    return (x >> sh) << sh;
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    DevState* st = ws.st;
+    st->lay_go = (force || st->K != st->lay_K || st->relabels != st->lay_relabels) ? 1 : 0;
 }
 
-__device__ inline uint32_t encode_entry(int cell, int g_local, uint32_t x)
+// One thread: the blocks of each cluster (from the sort's group offsets), the
+// block -> (cluster, first sorted cell, cells) map, and the number of blocks.
+__global__ void k_lay_plan(Ws ws, int gated)
 {
-    // a count with at most 8 significant bits is exact in FP32 and BF16
-    const uint32_t bf = __float_as_uint((float)count_head(x)) >> 16;
-    const uint32_t off = (uint32_t)(cell * kBlkRow + kBlkLead + g_local) * 2u;
-    return bf | (off << 16);
+    if (threadIdx.x != 0 || blockIdx.x != 0 || !lay_gate(ws, gated)) return;
+    const int K = ws.st->K;
+    int b = 0;
+    for (int k = 0; k < K; ++k) {
+        const int beg = ws.grp_off[k], end = ws.grp_off[k + 1];
+        for (int p = beg; p < end && b < ws.nblk_cap; p += kBlkCells, ++b) {
+            ws.lay_kc[b] = k;
+            ws.lay_pbeg[b] = p;
+            ws.lay_pcnt[b] = min(kBlkCells, end - p);
+        }
+    }
+    ws.st->lay_nblk = b;
+    ws.st->lay_K = K;
+    ws.st->lay_relabels = ws.st->relabels;
 }
 
-// entries of each (block, chunk), padded to a multiple of 4, and the number
-// of counts above 256 of each block
-__global__ void __launch_bounds__(kLayThreads) k_seg_count(Ws ws)
+// One workgroup per cluster: the genes in decreasing order of the cluster's
+// count s_{k,0,u} + s_{k,1,u}, ties by gene (a bitonic sort of 64-bit keys in
+// LDS).  rank[k][u] is gene u's place, gene[k][j] the gene at place j (first
+// kLayDmax chunks).  Past kRankMaxGenes genes the order is the identity.
+__global__ void __launch_bounds__(kRankThreads) k_lay_ranks(Ws ws, int gated)
 {
-    extern __shared__ uint32_t cnt[];    // [nch]
-    __shared__ uint32_t novf;
+    extern __shared__ unsigned long long keys[];
+    if (!lay_gate(ws, gated)) return;
+    const int K = ws.st->K;
+    const int k = blockIdx.x;
+    if (k >= K) return;
+    const int G = ws.G;
+    uint16_t* rank = ws.lay_rank + (int64_t)k * G;
+    uint16_t* gene = ws.lay_gene + (int64_t)k * kLayDmax * kBlkGenes;
+    if (G > kRankMaxGenes) {
+        for (int u = threadIdx.x; u < G; u += kRankThreads) rank[u] = (uint16_t)u;
+        for (int j = threadIdx.x; j < kLayDmax * kBlkGenes; j += kRankThreads) gene[j] = (uint16_t)(j < G ? j : 0);
+        return;
+    }
+    int n = 1;
+    while (n < G) n <<= 1;
+    const unsigned long long* s0 = ws.ssub + (int64_t)(2 * k) * G;
+    const unsigned long long* s1 = s0 + G;
+    constexpr unsigned long long kMaxCount = (1ull << 47) - 1ull;
+    for (int u = threadIdx.x; u < n; u += kRankThreads) {
+        unsigned long long v = 0;
+        if (u < G) {
+            const unsigned long long c = s0[u] + s1[u];
+            // larger count first, then smaller gene: descending key order
+            v = ((c < kMaxCount ? c : kMaxCount) << 16) | (unsigned long long)(0xFFFFu - (unsigned)u);
+            v += 1ull << 63;      // genes sort above the padding keys (0)
+        }
+        keys[u] = v;
+    }
+    __syncthreads();
+    for (int size = 2; size <= n; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = threadIdx.x; i < n; i += kRankThreads) {
+                const int j = i ^ stride;
+                if (j > i) {
+                    const bool desc = (i & size) == 0;     // descending runs first
+                    const unsigned long long a = keys[i], b = keys[j];
+                    if (desc ? a < b : a > b) {
+                        keys[i] = b;
+                        keys[j] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int j = threadIdx.x; j < G; j += kRankThreads) {
+        const int u = (int)(0xFFFFu - (unsigned)(keys[j] & 0xFFFFull));
+        rank[u] = (uint16_t)j;
+        if (j < kLayDmax * kBlkGenes) gene[j] = (uint16_t)u;
+    }
+    for (int j = G + threadIdx.x; j < kLayDmax * kBlkGenes; j += kRankThreads) gene[j] = 0;
+}
+
+// One workgroup per block: the cell of each slot, its number of entries, the
+// block's dense chunk count D_b and each slot's number of tail entries (into
+// the arrays that the scans turn into offsets).
+__global__ void __launch_bounds__(kLayThreads) k_lay_count(Ws ws, int gated)
+{
+    __shared__ uint32_t hist[kLayDmax];
+    __shared__ uint32_t s_D;
+    if (!lay_gate(ws, gated)) return;
     const int b = blockIdx.x;
-    for (int j = threadIdx.x; j < ws.nch; j += kLayThreads) cnt[j] = 0;
-    if (threadIdx.x == 0) novf = 0;
+    const int t = threadIdx.x;
+    const int64_t slot = (int64_t)b * kBlkCells + t;
+    if (b >= ws.st->lay_nblk) {
+        if (t == 0) ws.lay_doff[b] = 0;
+        ws.lay_toff[slot] = 0;
+        ws.lay_cell[slot] = -1;
+        ws.lay_nnz[slot] = 0;
+        return;
+    }
+    if (t < kLayDmax) hist[t] = 0;
     __syncthreads();
-    const int64_t i = (int64_t)b * kBlkCells + threadIdx.x;
-    if (i < ws.N) {
-        for (int64_t p = ws.roff[i]; p < ws.roff[i + 1]; ++p) {
-            const uint32_t en = ws.ent[p];
-            const uint32_t x = en >> 16;
-            // (a gene past G is invalid input, reported by the row check)
-            if (!x || (en & 0xFFFFu) >= (uint32_t)ws.G) continue;
-            atomicAdd(&cnt[(en & 0xFFFFu) / kBlkGenes], 1u);
-            if (count_head(x) != x) atomicAdd(&novf, 1u);
+    const int kc = ws.lay_kc[b];
+    const int cell = t < ws.lay_pcnt[b] ? ws.perm[ws.lay_pbeg[b] + t] : -1;
+    const uint16_t* rank = ws.lay_rank + (int64_t)kc * ws.G;
+    const int64_t rb = cell >= 0 ? ws.roff[cell] : 0, re = cell >= 0 ? ws.roff[cell + 1] : 0;
+    // pass 1: the block's entries per chunk of the cluster's gene order
+    // (rows are padded to 16 bytes, so they are read four entries at a time)
+    uint32_t nnz = 0;
+    for (int64_t p = rb; p < re; p += 4) {
+        const uint4 v = *reinterpret_cast<const uint4*>(ws.ent + p);
+        const uint32_t en[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t x = en[q] >> 16;
+            const uint32_t g = en[q] & 0xFFFFu;
+            if (!x || g >= (uint32_t)ws.G) continue;
+            ++nnz;
+            const uint32_t ch = rank[g] / kBlkGenes;
+            if (x < 256u && ch < (uint32_t)kLayDmax) atomicAdd(&hist[ch], 1u);
         }
     }
     __syncthreads();
-    for (int j = threadIdx.x; j < ws.nch; j += kLayThreads)
-        ws.blk_off[(int64_t)b * ws.nch + j] = (int64_t)((cnt[j] + 3u) & ~3u);
-    if (threadIdx.x == 0) ws.ovf_off[b] = (int64_t)novf;
-}
-
-__device__ inline uint32_t block_exclusive(uint32_t v, uint32_t* scan, uint32_t* total)
-{
-    const int t = threadIdx.x;
-    scan[t] = v;
-    __syncthreads();
-    for (int off = 1; off < kLayThreads; off <<= 1) {
-        const uint32_t add = t >= off ? scan[t - off] : 0u;
-        __syncthreads();
-        scan[t] += add;
-        __syncthreads();
+    if (t == 0) {
+        // cost of D dense chunks: 16 KiB each, plus kTailCost per entry not
+        // in them (4 bytes of HBM, and a gather of the gene's FP32 row of
+        // log theta, about 160 bytes from L2, which moves about 5x faster)
+        long long best = 0, cost = 0;
+        uint32_t D = 0;
+        for (int d = 1; d <= kLayDmax; ++d) {
+            cost += (long long)kBlkCells * kBlkGenes - kTailCost * (long long)hist[d - 1];
+            if (cost < best) {
+                best = cost;
+                D = (uint32_t)d;
+            }
+        }
+        s_D = D;
+        ws.lay_doff[b] = D;
     }
-    const uint32_t incl = scan[t];
-    *total = scan[kLayThreads - 1];
     __syncthreads();
-    return incl - v;
+    // pass 2: the slot's entries that stay out of the dense chunks
+    const uint32_t lim = s_D * kBlkGenes;
+    uint32_t dense = 0;
+    for (int64_t p = rb; p < re; p += 4) {
+        const uint4 v = *reinterpret_cast<const uint4*>(ws.ent + p);
+        const uint32_t en[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t x = en[q] >> 16;
+            const uint32_t g = en[q] & 0xFFFFu;
+            if (x && x < 256u && g < (uint32_t)ws.G && rank[g] < lim) ++dense;
+        }
+    }
+    ws.lay_cell[slot] = cell;
+    ws.lay_nnz[slot] = (uint16_t)min(nnz, 65535u);
+    ws.lay_toff[slot] = (int64_t)(nnz - dense);
 }
 
-// write the entries: per chunk, a workgroup-wide exclusive scan of the cells'
-// entry counts gives each cell its place in the segment
-__global__ void __launch_bounds__(kLayThreads) k_seg_fill(Ws ws)
+// Byte of (slot, place jj in chunk j) in the block's dense chunks: fragment
+// order of v_mfma_f32_16x16x32_bf16's A operand, 16 bytes per lane holding
+// the two k-steps of its row, lanes of a row tile contiguous.
+__device__ inline uint32_t dense_byte(int slot, int j, int jj)
 {
-    __shared__ uint32_t scan[kLayThreads];
+    const int w = slot >> 6, m = (slot >> 4) & 3, r = slot & 15;
+    const int s = (jj >> 5) & 1, q = (jj >> 3) & 3, e = jj & 7;
+    const int lane = 16 * q + r;
+    return (uint32_t)j * kDenseChunkBytes + (uint32_t)(((w * 4 + m) * 64 + lane) * 16 + s * 8 + e);
+}
+
+// One workgroup per block: the dense chunks assembled in LDS and written out
+// with 16-byte stores; the tail entries of each slot in row order.
+__global__ void __launch_bounds__(kLayThreads) k_lay_fill(Ws ws, int gated)
+{
+    extern __shared__ __attribute__((aligned(16))) uint8_t tile[];     // [kLayDmax][16 KiB]
+    if (!lay_gate(ws, gated)) return;
     const int b = blockIdx.x;
+    if (b >= ws.st->lay_nblk) return;
     const int t = threadIdx.x;
-    const int64_t i = (int64_t)b * kBlkCells + t;
-    const int64_t rb = i < ws.N ? ws.roff[i] : 0;
-    const int64_t end = i < ws.N ? ws.roff[i + 1] : 0;
-    uint32_t* out = const_cast<uint32_t*>(ws.blk_ent);
-    const uint32_t pad = 0u;                 // zero into cell 0's first padding column
-    int64_t pos = rb;
-    for (int j = 0; j < ws.nch; ++j) {
-        const int hi = (j + 1) * kBlkGenes;
-        uint32_t n = 0;
-        for (int64_t p = pos; p < end; ++p) {
-            const uint32_t en = ws.ent[p];
-            if ((int)(en & 0xFFFFu) >= hi) break;
-            if (en >> 16) ++n;
-        }
-        uint32_t total;
-        const uint32_t before = block_exclusive(n, scan, &total);
-        const int64_t seg = ws.blk_off[(int64_t)b * ws.nch + j];
-        const int64_t seg_end = ws.blk_off[(int64_t)b * ws.nch + j + 1];
-        int64_t w = seg + before;
-        while (pos < end) {
-            const uint32_t en = ws.ent[pos];
-            const int g = (int)(en & 0xFFFFu);
-            if (g >= hi) break;
-            if (en >> 16) out[w++] = encode_entry(t, g - j * kBlkGenes, en >> 16);
-            ++pos;
-        }
-        for (int64_t q = seg + total + t; q < seg_end; q += kLayThreads) out[q] = pad;
-    }
-    // counts above 256: (cell | gene << 8, count - head)
-    uint32_t n = 0;
-    for (int64_t p = rb; p < end; ++p) {
-        const uint32_t x = ws.ent[p] >> 16;
-        if (x && count_head(x) != x) ++n;
-    }
-    uint32_t total;
-    int64_t w = ws.ovf_off[b] + block_exclusive(n, scan, &total);
-    for (int64_t p = rb; p < end; ++p) {
-        const uint32_t en = ws.ent[p];
-        const uint32_t x = en >> 16;
-        if (x && count_head(x) != x)
-            ws.ovf_ent[w++] = make_uint2((uint32_t)t | ((en & 0xFFFFu) << 8), x - count_head(x));
-    }
-}
-
-constexpr int kBalThreads = 256;
-constexpr int kLdsBanks = 64;                       // LDS banks of 4 bytes
-constexpr int kMaxSegEntries = kBlkCells * kBlkGenes;   // every (cell, gene) of a block and chunk
-
-// position of the k-th entry of the round-robin order in a segment of n
-// entries (n a multiple of 4): the store instructions (r, w, c) in turn, each
-// with m = min(64, (n - 1024r - 256w) / 4) lanes
-__device__ inline uint32_t balanced_position(uint32_t k, uint32_t n)
-{
-    uint32_t base = 0;
-    for (uint32_t rw = 0;; ++rw) {
-        const uint32_t start = 256u * rw;     // 1024r + 256w
-        const uint32_t m = min(64u, (n - start) / 4u);
-        if (k < base + 4u * m) {
-            const uint32_t c = (k - base) / m;
-            const uint32_t l = (k - base) - c * m;
-            return start + 4u * l + c;
-        }
-        base += 4u * m;
-    }
-}
-
-__global__ void __launch_bounds__(kBalThreads) k_seg_balance(Ws ws)
-{
-    extern __shared__ uint32_t buf[];           // [kMaxSegEntries] the segment
-    __shared__ uint32_t cnt[kLdsBanks], rank[kLdsBanks], npad;
-    const int64_t sg = blockIdx.x;
-    const int64_t b0 = ws.blk_off[sg];
-    const uint32_t n = (uint32_t)(ws.blk_off[sg + 1] - b0);
-    // (a longer segment only comes from invalid input, reported by the row check)
-    if (n == 0 || n > (uint32_t)kMaxSegEntries) return;
-    uint32_t* seg = const_cast<uint32_t*>(ws.blk_ent) + b0;
-    const int t = threadIdx.x;
-    if (t < kLdsBanks) { cnt[t] = 0; rank[t] = 0; }
-    if (t == 0) npad = 0;
-    for (uint32_t q = t; q < n; q += kBalThreads) buf[q] = seg[q];
+    const int D = (int)(ws.lay_doff[b + 1] - ws.lay_doff[b]);
+    uint4* t4 = reinterpret_cast<uint4*>(tile);
+    for (int q = t; q < D * kDenseChunkBytes / 16; q += kLayThreads) t4[q] = make_uint4(0, 0, 0, 0);
     __syncthreads();
-    for (uint32_t q = t; q < n; q += kBalThreads) {
-        const uint32_t en = buf[q];
-        if (en & 0xFFFFu) atomicAdd(&cnt[(en >> 18) & (kLdsBanks - 1)], 1u);
+    const int64_t slot = (int64_t)b * kBlkCells + t;
+    const int cell = ws.lay_cell[slot];
+    const int kc = ws.lay_kc[b];
+    const uint16_t* rank = ws.lay_rank + (int64_t)kc * ws.G;
+    if (cell >= 0) {
+        int64_t w = ws.lay_toff[slot];
+        const uint32_t lim = (uint32_t)D * kBlkGenes;
+        for (int64_t p = ws.roff[cell]; p < ws.roff[cell + 1]; p += 4) {
+            const uint4 v = *reinterpret_cast<const uint4*>(ws.ent + p);
+            const uint32_t ent4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint32_t en = ent4[q];
+                const uint32_t x = en >> 16;
+                const uint32_t g = en & 0xFFFFu;
+                if (!x || g >= (uint32_t)ws.G) continue;
+                const uint32_t rk = rank[g];
+                if (x < 256u && rk < lim) tile[dense_byte(t, rk / kBlkGenes, rk % kBlkGenes)] = (uint8_t)x;
+                else ws.lay_tail[w++] = en;
+            }
+        }
     }
     __syncthreads();
-    uint32_t nreal = 0;
-    for (int b = 0; b < kLdsBanks; ++b) nreal += cnt[b];
-    for (uint32_t q = t; q < n; q += kBalThreads) {
-        const uint32_t en = buf[q];
-        uint32_t k;
-        if (en & 0xFFFFu) {
-            const uint32_t b = (en >> 18) & (kLdsBanks - 1);
-            const uint32_t r = atomicAdd(&rank[b], 1u);
-            // entries before (r, b): min(cnt, r) of every bank, and one of each
-            // earlier bank that reaches rank r
-            k = 0;
-            for (uint32_t b2 = 0; b2 < (uint32_t)kLdsBanks; ++b2)
-                k += min(cnt[b2], r) + (b2 < b && cnt[b2] > r ? 1u : 0u);
-        } else {
-            k = nreal + atomicAdd(&npad, 1u);    // padding (zero) entries last
-        }
-        seg[balanced_position(k, n)] = en;
-    }
+    uint4* out = reinterpret_cast<uint4*>(ws.lay_dense + ws.lay_doff[b] * kDenseChunkBytes);
+    for (int q = t; q < D * kDenseChunkBytes / 16; q += kLayThreads) out[q] = t4[q];
 }
 
 hipError_t configure_layout()
 {
-    return hipFuncSetAttribute((const void*)k_seg_balance, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)(sizeof(uint32_t) * (size_t)kMaxSegEntries));
+    hipError_t e = hipFuncSetAttribute((const void*)k_lay_fill, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)(kLayDmax * kDenseChunkBytes));
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)k_lay_ranks, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)(sizeof(unsigned long long) * kRankMaxGenes));
+    return e;
 }
 
-void launch_build_blocked(const Ws& ws, int64_t* tile_sums, hipStream_t s)
+// Rebuild the copy from the labels c.  force: unconditionally (init,
+// dpmm_set_state); else only when k_lay_decide finds it stale, every kernel
+// being gated on that decision.
+void launch_relayout(const Ws& ws, const int32_t* c, int64_t* tile_sums, int force, hipStream_t s)
 {
-    const int64_t nseg = (int64_t)ws.nblk * ws.nch;
-    hipLaunchKernelGGL(k_seg_count, dim3(ws.nblk), dim3(kLayThreads), sizeof(uint32_t) * (size_t)ws.nch, s, ws);
-    launch_exclusive_scan(ws.blk_off, nseg, tile_sums, s);
-    launch_exclusive_scan(ws.ovf_off, ws.nblk, tile_sums, s);
-    hipLaunchKernelGGL(k_seg_fill, dim3(ws.nblk), dim3(kLayThreads), 0, s, ws);
-    hipLaunchKernelGGL(k_seg_balance, dim3((unsigned)nseg), dim3(kBalThreads), sizeof(uint32_t) * (size_t)kMaxSegEntries,
-                       s, ws);
+    const int gated = force ? 0 : 1;
+    hipLaunchKernelGGL(k_lay_decide, dim3(1), dim3(64), 0, s, ws, force);
+    launch_sort(ws, c, nullptr, 1, s, false, nullptr, gated ? &ws.st->lay_go : nullptr);
+    hipLaunchKernelGGL(k_lay_plan, dim3(1), dim3(64), 0, s, ws, gated);
+    int n = 1;
+    while (n < ws.G) n <<= 1;
+    const size_t rank_lds = ws.G > kRankMaxGenes ? 0 : sizeof(unsigned long long) * (size_t)n;
+    hipLaunchKernelGGL(k_lay_ranks, dim3((unsigned)ws.k_max), dim3(kRankThreads), rank_lds, s, ws, gated);
+    hipLaunchKernelGGL(k_lay_count, dim3((unsigned)ws.nblk_cap), dim3(kLayThreads), 0, s, ws, gated);
+    launch_exclusive_scan(ws.lay_doff, ws.nblk_cap, tile_sums, s, gated ? &ws.st->lay_go : nullptr);
+    launch_exclusive_scan(ws.lay_toff, (int64_t)ws.nblk_cap * kBlkCells, tile_sums, s,
+                          gated ? &ws.st->lay_go : nullptr);
+    hipLaunchKernelGGL(k_lay_fill, dim3((unsigned)ws.nblk_cap), dim3(kLayThreads), kLayDmax * kDenseChunkBytes, s, ws,
+                       gated);
+}
+
+// After every redraw: the hi/lo tables of log theta (split-BF16, cluster-major
+// [k][Gpad]) with the genes in each layout cluster's order, for the first
+// kLayDmax chunks: tab[L][col][j] = table[col][gene_L[j]], zero for the
+// columns past K that the kernel's last column tile reads.
+__global__ void k_lay_btab(Ws ws)
+{
+    const int K = ws.st->K;
+    const int KL = ws.st->lay_K;
+    const int R = kLayDmax * kBlkGenes;
+    const int64_t n = (int64_t)KL * ws.lay_cols * R;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
+        const int j = (int)(q % R);
+        const int64_t lc = q / R;
+        const int col = (int)(lc % ws.lay_cols);
+        const int L = (int)(lc / ws.lay_cols);
+        uint16_t hi = 0, lo = 0;
+        if (col < K) {
+            const int64_t at = (int64_t)col * ws.Gpad + ws.lay_gene[(int64_t)L * R + j];
+            hi = ws.lhi[at];
+            lo = ws.llo[at];
+        }
+        ws.lay_bhi[q] = hi;
+        ws.lay_blo[q] = lo;
+    }
+}
+
+void launch_lay_btab(const Ws& ws, hipStream_t s)
+{
+    const int64_t n = (int64_t)ws.k_max * ws.lay_cols * kLayDmax * kBlkGenes;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_lay_btab, dim3((unsigned)blocks), dim3(256), 0, s, ws);
 }
 
 }  // namespace dpmm

@@ -398,7 +398,10 @@ __global__ void k_rsplit_apply(Ws ws, const int32_t* __restrict__ c, uint8_t* __
                 ws.nsub[2 * j + threadIdx.x] = ws.rnsub[2 * j + threadIdx.x];
             }
         }
-        if (threadIdx.x == 0) ws.st->sm_pass = 2;
+        if (threadIdx.x == 0) {
+            ws.st->sm_pass = 2;
+            ws.st->rs_live = 0;
+        }
     }
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ws.N; i += (int64_t)gridDim.x * blockDim.x) {
         const int k = c[i];
@@ -406,15 +409,19 @@ __global__ void k_rsplit_apply(Ws ws, const int32_t* __restrict__ c, uint8_t* __
     }
 }
 
-void launch_random_split(const Ws& ws, const int32_t* c, uint8_t* cs, uint32_t step, hipStream_t s)
+// With `ready` the coins and the statistics of the halves were built by the
+// sub-cluster pass of the sweep before (k_sub_stats) for this step.
+void launch_random_split(const Ws& ws, const int32_t* c, uint8_t* cs, uint32_t step, bool ready, hipStream_t s)
 {
     int64_t cb = (ws.N + 255) / 256;
     if (cb > 4096) cb = 4096;
-    hipLaunchKernelGGL(k_rsplit_coins, dim3((unsigned)cb), dim3(256), 0, s, ws, step);
     Ws halves = ws;
     halves.ssub = ws.rssub;
     halves.nsub = ws.rnsub;
-    launch_stats(halves, c, ws.rbits, s);
+    if (!ready) {
+        hipLaunchKernelGGL(k_rsplit_coins, dim3((unsigned)cb), dim3(256), 0, s, ws, step);
+        launch_stats(halves, c, ws.rbits, s);
+    }
     launch_sm_pair(halves, 1, s);
     launch_sm_decide(halves, 0, step, s);
     hipLaunchKernelGGL(k_rsplit_apply, dim3((unsigned)cb), dim3(256), 0, s, ws, c, cs);
@@ -525,6 +532,7 @@ __global__ void __launch_bounds__(kDecideThreads) k_sm_decide(Ws ws, int merge_p
             ws.st->K = s_K;
             if (ws.k_hint) __hip_atomic_store(ws.k_hint, s_K, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
             ws.st->relabel = s_any;
+            if (s_any) ws.st->relabels += 1;
             ws.st->sm_pass = 0;
             ws.st->sm_n = K;
         }
@@ -647,6 +655,7 @@ __global__ void __launch_bounds__(kDecideThreads) k_sm_decide(Ws ws, int merge_p
         ws.st->K = nk;
         if (ws.k_hint) __hip_atomic_store(ws.k_hint, nk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         ws.st->relabel = merges > 0;
+        if (merges > 0) ws.st->relabels += 1;
         ws.st->sm_pass = 1;
         ws.st->sm_n = (int32_t)npairs;
     }

@@ -17,6 +17,12 @@
 // the LDS histogram of (k, cbar_i).  The two scores themselves are formed only
 // for the debug dump.  The histograms are flushed with one 64-bit atomic per
 // non-zero gene.  The matrix is read once for both jobs.
+//
+// When the next split/merge call is a random split (chain B, Section 2.4; its
+// pass is a function of the seed and the step alone), the same pass also
+// draws every cell's fair coin for it and builds the statistics of the coin
+// halves of each cluster in a second pair of histograms, so that the random
+// split needs no pass over the matrix of its own.
 #include "dpmm_common.hpp"
 #include "kernels.hpp"
 
@@ -49,7 +55,10 @@ __global__ void __launch_bounds__(kSubThreads) __attribute__((amdgpu_waves_per_e
     constexpr bool stage = STAGE, lhist = LHIST, dump = DUMP;
     double* dl = reinterpret_cast<double*>(lds);                        // [G] delta if staged
     uint32_t* hist = reinterpret_cast<uint32_t*>(lds + (stage ? 8 * (size_t)G : 0));    // [2][G], then a spare slot per lane
-    __shared__ uint32_t ncnt[2];
+    __shared__ uint32_t ncnt[2], ncnt2[2];
+    const bool rs = a.rsplit != 0;
+    uint32_t* hist2 = hist + 2 * G + 64;                                 // [2][G] coin halves, then a spare slot per lane
+    if (blockIdx.x == 0 && threadIdx.x == 0) ws.st->rs_live = rs ? 1 : 0;
     const int K = ws.st->K;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -94,7 +103,9 @@ __global__ void __launch_bounds__(kSubThreads) __attribute__((amdgpu_waves_per_e
         }
         if (lhist)
             for (int u = threadIdx.x; u < 2 * G; u += kSubThreads) hist[u] = 0;
-        if (threadIdx.x < 2) ncnt[threadIdx.x] = 0;
+        if (lhist && rs)
+            for (int u = threadIdx.x; u < 2 * G; u += kSubThreads) hist2[u] = 0;
+        if (threadIdx.x < 2) ncnt[threadIdx.x] = ncnt2[threadIdx.x] = 0;
         __syncthreads();
         // log of the eq. 8 weights: nbar_{k,r}, less one when the cell was in (k, r)
         const long long n0 = (long long)ws.nsub_prev[2 * k], n1 = (long long)ws.nsub_prev[2 * k + 1];
@@ -113,9 +124,14 @@ __global__ void __launch_bounds__(kSubThreads) __attribute__((amdgpu_waves_per_e
             uint4 dsc = make_uint4(0, 0, 0, 0);
             float nd = 0.0f;      // FP32 Gumbel noise of sub-cluster 1 less that of 0
             int code = 0;         // reset: the fair draw; else 1 + old sub-label if the cell was in k, 0 if not
+            int coin = 0;         // the cell's coin of the coming random split
             if (lane < ncell) {
                 dsc = ws.srow[base + lane];
                 const uint32_t i = dsc.x;
+                if (rs) {
+                    coin = (int)(philox(ws.seed, i, 0u, a.rs_step, kRSplit, 0u).w[0] >> 31);
+                    ws.rbits[i] = (uint8_t)coin;
+                }
                 if (reset) {
                     code = (int)(philox(ws.seed, i, 0u, a.step, kResub, 0u).w[0] >> 31);
                 } else {
@@ -134,6 +150,7 @@ __global__ void __launch_bounds__(kSubThreads) __attribute__((amdgpu_waves_per_e
                 const int64_t e = live ? b + len : b;
                 const float ndc = __shfl(nd, src);
                 const int cc = __shfl(code, src);
+                const int rc = __shfl(coin, src);
                 int sub;
                 double df = 0.0, s0 = 0.0, s1 = 0.0;
                 double dd = 0.0;        // score of sub-cluster 1 less that of 0 (with the weights)
@@ -206,9 +223,11 @@ __global__ void __launch_bounds__(kSubThreads) __attribute__((amdgpu_waves_per_e
                         if constexpr (LHIST) {
                             // a pad entry adds 0 to the lane's spare slot
                             atomicAdd(&hist[x ? sub * G + g : 2 * G + lane], x);
+                            if (rs) atomicAdd(&hist2[x ? rc * G + g : 2 * G + lane], x);
                         } else {
                             if (!x) continue;
                             atomicAdd(&grow[g], (unsigned long long)x);
+                            if (rs) atomicAdd(&ws.rssub[(int64_t)(2 * k + rc) * G + g], (unsigned long long)x);
                         }
                     }
                 };
@@ -217,6 +236,7 @@ __global__ void __launch_bounds__(kSubThreads) __attribute__((amdgpu_waves_per_e
                 for (int64_t q = b + 4 * lg + 4 * kSubLanes * kSubLoads; q < e; q += 4 * kSubLanes) add(*reinterpret_cast<const uint4*>(ws.ent + q));
                 if (lg == 0 && live) {
                     atomicAdd(&ncnt[sub], 1u);
+                    if (rs) atomicAdd(&ncnt2[rc], 1u);
                     a.cs_new[i] = (uint8_t)sub;
                     if constexpr (SPLITQ) {
                         // log p(cbar_i) of eq. 8 for the split proposal term: a
@@ -243,16 +263,25 @@ __global__ void __launch_bounds__(kSubThreads) __attribute__((amdgpu_waves_per_e
                 if (v) atomicAdd(&row[u], (unsigned long long)v);
             }
         }
+        if (lhist && rs) {
+            unsigned long long* row = ws.rssub + (int64_t)(2 * k) * G;
+            for (int u = threadIdx.x; u < 2 * G; u += kSubThreads) {
+                const uint32_t v = hist2[u];
+                if (v) atomicAdd(&row[u], (unsigned long long)v);
+            }
+        }
         if (threadIdx.x < 2 && ncnt[threadIdx.x])
             atomicAdd(&ws.nsub[2 * k + threadIdx.x], (unsigned long long)ncnt[threadIdx.x]);
+        if (rs && threadIdx.x < 2 && ncnt2[threadIdx.x])
+            atomicAdd(&ws.rnsub[2 * k + threadIdx.x], (unsigned long long)ncnt2[threadIdx.x]);
     }
 }
 
-static size_t sub_stats_lds(int G)
+static size_t sub_stats_lds(int G, bool rs)
 {
     size_t lds = 0;
     if (G <= kSubStageGenes) lds += 8 * (size_t)G;
-    if (G <= kSubHistGenes) lds += 8 * (size_t)G + 4 * 64;   // + a spare slot per lane
+    if (G <= kSubHistGenes) lds += (rs ? 2 : 1) * (8 * (size_t)G + 4 * 64);   // + a spare slot per lane
     return lds;
 }
 
@@ -278,11 +307,16 @@ static SubKernel sub_stats_kernel(int G, bool dump, bool split_q)
 hipError_t sub_stats_cells(int64_t N, int G, int32_t* cells)
 {
     int dev = 0, cus = 0, per_cu = 0;
-    hipError_t e = hipGetDevice(&dev);
+    hipError_t e = hipSuccess;
+    // allow every variant the LDS of the pass with the coin halves
+    for (int v = 0; v < 4 && e == hipSuccess; ++v)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(sub_stats_kernel(G, v & 1, v >> 1)),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)sub_stats_lds(G, true));
+    if (e == hipSuccess) e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(sub_stats_kernel(G, false, false)),
-                                                         kSubThreads, sub_stats_lds(G));
+                                                         kSubThreads, sub_stats_lds(G, false));
     if (e != hipSuccess) return e;
     const int64_t slots = (int64_t)(cus > 0 ? cus : 1) * (per_cu > 0 ? per_cu : 1);
     int64_t c = (N + slots - 1) / slots;
@@ -295,8 +329,12 @@ void launch_sub_stats(const Ws& ws, const SubArgs& a, hipStream_t s)
 {
     // the counts were cleared by the redraw of the same sweep (k_redraw_norm)
     launch_sort(ws, a.c_new, a.cs_old, 1, s, true, a.c_old);
+    if (a.rsplit) {
+        launch_zero(ws.rssub, sizeof(unsigned long long) * 2 * (size_t)ws.k_max * (size_t)ws.G, s);
+        launch_zero(ws.rnsub, sizeof(unsigned long long) * 2 * (size_t)ws.k_max, s);
+    }
     hipLaunchKernelGGL(sub_stats_kernel(ws.G, a.dbg != nullptr, ws.lpsub != nullptr), dim3((unsigned)((ws.N + ws.sub_cells - 1) / ws.sub_cells)), dim3(kSubThreads),
-                       sub_stats_lds(ws.G), s, ws, a);
+                       sub_stats_lds(ws.G, a.rsplit != 0), s, ws, a);
 }
 
 }  // namespace dpmm

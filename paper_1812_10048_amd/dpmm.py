@@ -61,7 +61,7 @@ class dpmm_stats_out(ctypes.Structure):
 
 
 # DPMM_STAGE_* of include/dpmm.h, in order
-STAGES = ["redraw", "assign", "refine", "subcluster", "compact", "split_merge", "eb"]
+STAGES = ["redraw", "assign", "refine", "subcluster", "compact", "split_merge", "eb", "layout"]
 
 
 _P = ctypes.c_void_p

@@ -114,12 +114,16 @@ def test_new_cluster_chain_lockstep(case):
         assert opened >= 1
 
 
-@pytest.mark.parametrize("case", ["c1-split_bf16", "c1-fp64", "tiny-fp64"])
+@pytest.mark.parametrize("case", ["c1-split_bf16", "c1-fp64", "tiny-fp64", "tiny-fp64-twice"])
 def test_random_split_chain_lockstep(case):
     """The random-split pass (DPMM_FLAG_RANDOM_SPLIT, chain B of Section 2.4):
     the pass chosen, every ratio, the decisions, labels and statistics; on the
-    tiny high-alpha data random splits are accepted."""
-    data, precision = case.split("-")
+    tiny high-alpha data random splits are accepted.  A random split right
+    after a sweep takes its coins and coin halves from the sweep's sub-cluster
+    pass; "twice" makes two split/merge calls per sweep, so that the second
+    one builds them with a pass of its own."""
+    data, precision, *mode = case.split("-")
+    calls = 2 if mode == ["twice"] else 1
     say("random_split lockstep", case)
     if data == "c1":
         d = synth.generate("c1", seed=12)
@@ -132,9 +136,10 @@ def test_random_split_chain_lockstep(case):
     accepted_random = 0
     for it in range(30):
         ls.sweep()
-        ls.split_merge()
-        if ls.o.sm_pass == 2:
-            accepted_random += int(ls.o.sm_accept[: ls.o.sm_n].sum())
+        for _ in range(calls):
+            ls.split_merge()
+            if ls.o.sm_pass == 2:
+                accepted_random += int(ls.o.sm_accept[: ls.o.sm_n].sum())
     ls.finish(accepted_random=accepted_random)
     assert ls.passes[2] >= 3
     if data == "tiny":

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libdpmm.so")
 BUILD_DIR = os.path.join(os.path.dirname(HERE), "_build")
 SOURCES = ["api.hip", "bookkeeping.hip", "layout.hip", "redraw.hip", "assign.hip", "assign_mfma.hip", "substats.hip",
-           "splitmerge.hip", "dm.hip", "prep.hip"]
+           "laysub.hip", "splitmerge.hip", "dm.hip", "prep.hip"]
 ARCH = "gfx950"
 
 FLAGS = [

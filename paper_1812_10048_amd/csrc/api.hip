@@ -45,13 +45,21 @@ struct Layout {
     size_t ent, roff, tiles, c0, c1, cs0, cs1, st, reset, nsub, ssub, beta, lgbeta, logpi, lt64, lc32, ls32, lhi, llo,
         lgrise, lpsub, qsub, rbits, rssub, rnsub, refine, perm, srow, grp_cnt, grp_off, grp_cur, nsub_prev, lay_kc,
         lay_pbeg, lay_pcnt, lay_cell, lay_doff, lay_toff, lay_dense, lay_tail, lay_nnz, lay_rank, lay_gene, lay_bhi,
-        lay_blo, relab_c, relab_s, sm_logr, sm_acc, mkey, mlist, dm_k, eb_tmp, rd_part, sm_part, total;
+        lay_blo, lay_part, span_part, lay_bbeg, lay_sbeg, mov, relab_c, relab_s, sm_logr, sm_acc, mkey, mlist, dm_k, eb_tmp, rd_part, sm_part, total;
 };
 
 int32_t num_blocks(int64_t N) { return (int32_t)((N + kBlkCells - 1) / kBlkCells); }
 // blocks of the cluster-sorted copy: each cluster's last block may be partial
 int32_t lay_blocks(int64_t N, int32_t k_max) { return num_blocks(N) + k_max; }
 int32_t lay_cols(int32_t k_max) { return (k_max + 15) / 16 * 16 + kTablePadRows; }
+// words of a block's statistics histogram in the sub-cluster pass over the
+// copy: (sub-cluster 0, 1 [, coin 0, 1]) x G, 0 when that exceeds the LDS
+// histogram (the pass then adds with atomics)
+int32_t lay_hist_words(int32_t G, uint32_t flags)
+{
+    const int64_t w = (int64_t)((flags & kFlagRandomSplit) ? 4 : 2) * G;
+    return w <= kLsHistWords ? (int32_t)w : 0;
+}
 // gene chunks of the split-BF16 kernel: an even number, so that its pipeline
 // (two register stages, unrolled by two) has no conditional chunk; the chunks
 // past G hold no entries and zero log theta
@@ -122,6 +130,11 @@ Layout plan(int64_t N, int32_t G, int64_t nnz, int32_t k_max, int32_t precision,
     L.lay_gene = take(blocked ? 2 * (size_t)k_max * kLayDmax * kBlkGenes : 0);
     L.lay_bhi = take(blocked ? 2 * (size_t)k_max * (size_t)lay_cols(k_max) * kLayDmax * kBlkGenes : 0);
     L.lay_blo = take(blocked ? 2 * (size_t)k_max * (size_t)lay_cols(k_max) * kLayDmax * kBlkGenes : 0);
+    L.lay_part = take(blocked ? 4 * (size_t)nbc * (size_t)lay_hist_words(G, flags) : 0);
+    L.span_part = take(blocked ? 4 * (size_t)lay_spans((int32_t)nbc, k_max) * (size_t)lay_hist_words(G, flags) : 0);
+    L.lay_bbeg = take(blocked ? 4 * (size_t)(k_max + 1) : 0);
+    L.lay_sbeg = take(blocked ? 4 * (size_t)(k_max + 1) : 0);
+    L.mov = take(blocked ? 4 * (size_t)N : 0);
     L.relab_c = take(8 * (size_t)k_max);
     L.relab_s = take(2 * (size_t)k_max);
     L.sm_logr = take(8 * (size_t)ncand);
@@ -350,6 +363,12 @@ dpmm_status init_impl(const dpmm_csr* csr, const dpmm_params* params, void* work
     ws.lay_gene = (uint16_t*)(base + L.lay_gene);
     ws.lay_bhi = (uint16_t*)(base + L.lay_bhi);
     ws.lay_blo = (uint16_t*)(base + L.lay_blo);
+    ws.lay_part = (uint32_t*)(base + L.lay_part);
+    ws.mov = (uint32_t*)(base + L.mov);
+    ws.span_part = (uint32_t*)(base + L.span_part);
+    ws.lay_pw = params->precision == DPMM_SPLIT_BF16 ? lay_hist_words(csr->n_genes, params->flags) : 0;
+    ws.lay_bbeg = (int32_t*)(base + L.lay_bbeg);
+    ws.lay_sbeg = (int32_t*)(base + L.lay_sbeg);
     ws.nblk_cap = params->precision == DPMM_SPLIT_BF16 ? lay_blocks(csr->n_cells, params->k_max) : 0;
     ws.lay_cols = lay_cols(params->k_max);
     ws.relab_c = (int32_t*)(base + L.relab_c);
@@ -571,7 +590,8 @@ dpmm_status dpmm_sweep(dpmm_ctx* ctx, int32_t n_sweeps)
         ctx->rs_ready_step = sa.rsplit ? (int64_t)ctx->step + 1 : -1;
         {
             StageTimer st(ctx, DPMM_STAGE_SUBCLUSTER);
-            launch_sub_stats(ws, sa, ctx->stream);
+            if (ctx->precision == DPMM_SPLIT_BF16) launch_lay_sub(ws, sa, ctx->stream);
+            else launch_sub_stats(ws, sa, ctx->stream);
         }
         {
             StageTimer st(ctx, DPMM_STAGE_COMPACT);

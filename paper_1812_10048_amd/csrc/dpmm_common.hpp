@@ -107,6 +107,8 @@ struct DevState {
     int32_t lay_K;        // K when the copy was built
     uint32_t lay_relabels;   // relabels when the copy was built
     int32_t rs_live;      // the coin-half statistics of the next random split are in rssub / rnsub
+    int32_t n_mov;        // cells queued for the packed-matrix sub-cluster draw (split-BF16 sweeps)
+    int32_t pad3;
 };
 
 // Packed count entry: gene in the low 16 bits, count in the high 16 bits.
@@ -120,6 +122,10 @@ constexpr uint32_t kFlagSplitQ = 1u;          // dpmm_params.flags bit of the sp
 constexpr uint32_t kFlagNewCluster = 2u;      // ... and of the Gibbs step over K + 1 clusters
 constexpr uint32_t kFlagRandomSplit = 4u;     // ... and of the random-split pass
 constexpr int kBlkGenes = 64;
+constexpr int kSpanBlocks = 32;                    // blocks per span of the statistics reduction (laysub.hip)
+constexpr int kLsHistWords = 8192;                 // LDS histogram of a block's statistics: rows x G words up to this
+// spans of the reduction: each cluster's blocks are cut separately
+__host__ __device__ inline int32_t lay_spans(int32_t nblk_cap, int32_t k_max) { return nblk_cap / kSpanBlocks + k_max; }
 
 // Refine-queue flags (high bits of a queued cell index).
 constexpr uint32_t kRefineCluster = 1u << 31;
@@ -165,6 +171,57 @@ struct RowCursor {
         }
     }
 };
+#endif
+
+#if defined(__HIPCC__)
+// The sub-cluster draw of eq. 8 for a cell of cluster k, shared by the passes
+// over the packed matrix and over the cluster-sorted copy.  Weights: nbar_{k,r}
+// at the start of the sweep, less one for the sub-cluster the cell was in
+// (code: 1 + its old sub-label if it was in k, else 0).
+struct SubWeights {
+    double l0, l0m, l1, l1m;
+};
+__device__ inline double log_count(long long w) { return w > 0 ? log((double)w) : -INFINITY; }
+__device__ inline SubWeights sub_weights(const unsigned long long* nsub_prev, int k)
+{
+    const long long n0 = (long long)nsub_prev[2 * k], n1 = (long long)nsub_prev[2 * k + 1];
+    return SubWeights{log_count(n0), log_count(n0 - 1), log_count(n1), log_count(n1 - 1)};
+}
+// FP32 Gumbel noise of sub-cluster 1 less that of sub-cluster 0
+__device__ inline float sub_noise(uint64_t seed, uint32_t i, uint32_t step, uint32_t stream)
+{
+    const Words w = philox(seed, i, 0u, step, stream, 0u);
+    return (-logf(-logf(unit23f(w.w[1])))) - (-logf(-logf(unit23f(w.w[0]))));
+}
+// The draw given df = sum_u x_u (log thetabar_{k,1,u} - log thetabar_{k,0,u})
+// in FP64; dd (the FP64 score difference with the weights) is returned for
+// the split proposal term.  The draw compares dd + g1 - g0 with 0: the FP32
+// noise is within 3e-6 of the FP64 noise, so when the FP32 difference clears
+// tau its sign is the FP64 sign; otherwise (or with a zero weight) the FP64
+// comparison decides.
+__device__ inline int sub_draw(uint64_t seed, uint32_t i, uint32_t step, uint32_t stream, const SubWeights& w,
+                               int code, float nd, double df, double* dd_out)
+{
+    double lw0 = code == 1 ? w.l0m : w.l0;
+    double lw1 = code == 2 ? w.l1m : w.l1;
+    if (!(lw0 > -INFINITY) && !(lw1 > -INFINITY)) lw0 = lw1 = 0.0;   // both weights zero: equal
+    const double dd = lw1 - lw0 + df;
+    *dd_out = dd;
+    const float d32 = (float)dd + nd;
+    const float tau = 1e-3f + 1e-5f * fabsf((float)dd);
+    if (isfinite(dd) && fabsf(d32) > tau) return d32 > 0.0f ? 1 : 0;
+    const Words wd = philox(seed, i, 0u, step, stream, 0u);
+    const double v0 = lw0 + (-log(-log(unit23d(wd.w[0]))));
+    const double v1 = lw1 + df + (-log(-log(unit23d(wd.w[1]))));
+    return v1 > v0 ? 1 : 0;
+}
+// log p(cbar_i) of eq. 8 for the split proposal term: a two-way softmax of
+// the scores, whose difference is dd
+__device__ inline double sub_logp(double dd, int sub)
+{
+    const double x = sub ? -dd : dd;
+    return -(fmax(x, 0.0) + log1p(exp(-fabs(x))));
+}
 #endif
 
 // Top bits of srow.w after a sort by new cluster: 1 + the cell's sub-label
@@ -240,6 +297,12 @@ struct Ws {
     uint16_t* lay_gene;    // [k_max kLayDmax kBlkGenes] gene at place j
     uint16_t* lay_bhi;     // [k_max][lay_cols][kLayDmax kBlkGenes] hi of log theta in L's gene order
     uint16_t* lay_blo;     // same for lo
+    uint32_t* lay_part;    // [nblk_cap][lay_pw] a block's count sums per (sub-cluster | coin, gene)
+    uint32_t* span_part;   // [lay_spans][lay_pw] the same summed over spans of blocks
+    int32_t lay_pw;        // rows x G of those histograms (rows 4 with random splits, else 2), 0 past kLsHistWords
+    int32_t* lay_bbeg;     // [k_max + 1] first block of each layout cluster
+    int32_t* lay_sbeg;     // [k_max + 1] spans (of up to 32 blocks) before each layout cluster's first
+    uint32_t* mov;         // [N] cells of a block whose new cluster is not the block's (laysub.hip)
     int32_t nblk_cap;      // blocks the copy can hold: ceil(N / kBlkCells) + k_max
     int32_t lay_cols;      // column rows per layout cluster in lay_bhi / lay_blo
     int32_t sub_cells;     // sorted cells per workgroup of the sub-cluster/statistics pass

@@ -49,6 +49,8 @@ struct SubArgs {
     uint32_t rs_step;     // accumulate the statistics of the coin halves (rbits, rssub, rnsub)
 };
 void launch_sub_stats(const Ws& ws, const SubArgs& a, hipStream_t s);
+// laysub.hip (split-BF16 sweeps, over the cluster-sorted copy)
+void launch_lay_sub(const Ws& ws, const SubArgs& a, hipStream_t s);
 hipError_t sub_stats_cells(int64_t N, int G, int32_t* cells);
 void launch_compact(const Ws& ws, int after_sweep, hipStream_t s);
 void launch_relabel(const Ws& ws, int32_t* c, uint8_t* cs, hipStream_t s);

@@ -47,15 +47,21 @@ __global__ void k_lay_plan(Ws ws, int gated)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0 || !lay_gate(ws, gated)) return;
     const int K = ws.st->K;
-    int b = 0;
+    int b = 0, x = 0;
     for (int k = 0; k < K; ++k) {
         const int beg = ws.grp_off[k], end = ws.grp_off[k + 1];
+        ws.lay_bbeg[k] = b;
+        ws.lay_sbeg[k] = x;
+        const int b_first = b;
         for (int p = beg; p < end && b < ws.nblk_cap; p += kBlkCells, ++b) {
             ws.lay_kc[b] = k;
             ws.lay_pbeg[b] = p;
             ws.lay_pcnt[b] = min(kBlkCells, end - p);
         }
+        x += (b - b_first + kSpanBlocks - 1) / kSpanBlocks;
     }
+    ws.lay_bbeg[K] = b;
+    ws.lay_sbeg[K] = x;
     ws.st->lay_nblk = b;
     ws.st->lay_K = K;
     ws.st->lay_relabels = ws.st->relabels;

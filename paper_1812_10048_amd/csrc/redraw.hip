@@ -179,7 +179,7 @@ __global__ void __launch_bounds__(kRedrawThreads) k_redraw_norm(Ws ws, int write
 {
     const int K = ws.st->K;
     // the re-score queue of the sweep that follows starts empty
-    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) ws.st->n_refine = 0;
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) ws.st->n_refine = ws.st->n_mov = 0;
     {
         const int64_t nt = (int64_t)gridDim.x * gridDim.y * blockDim.x;
         const int64_t t0 = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * blockDim.x + threadIdx.x;

@@ -108,9 +108,7 @@ __global__ void __launch_bounds__(kSubThreads) __attribute__((amdgpu_waves_per_e
         if (threadIdx.x < 2) ncnt[threadIdx.x] = ncnt2[threadIdx.x] = 0;
         __syncthreads();
         // log of the eq. 8 weights: nbar_{k,r}, less one when the cell was in (k, r)
-        const long long n0 = (long long)ws.nsub_prev[2 * k], n1 = (long long)ws.nsub_prev[2 * k + 1];
-        auto logw = [](long long w) { return w > 0 ? log((double)w) : -INFINITY; };
-        const double l0 = logw(n0), l0m = logw(n0 - 1), l1 = logw(n1), l1m = logw(n1 - 1);
+        const SubWeights sw = sub_weights(ws.nsub_prev, k);
         // Each wavefront takes 64 sorted cells at a time.  First one lane per
         // cell forms what depends on the cell alone (its row descriptor, which
         // also carries its old membership, so that one load serves; the
@@ -135,8 +133,7 @@ __global__ void __launch_bounds__(kSubThreads) __attribute__((amdgpu_waves_per_e
                 if (reset) {
                     code = (int)(philox(ws.seed, i, 0u, a.step, kResub, 0u).w[0] >> 31);
                 } else {
-                    const Words w = philox(ws.seed, i, 0u, a.step, kGumbelS, 0u);
-                    nd = (-logf(-logf(unit23f(w.w[1])))) - (-logf(-logf(unit23f(w.w[0]))));
+                    nd = sub_noise(ws.seed, i, a.step, kGumbelS);
                     code = (int)(dsc.w >> kSrowOldShift);      // written by the sort
                 }
             }
@@ -193,24 +190,7 @@ __global__ void __launch_bounds__(kSubThreads) __attribute__((amdgpu_waves_per_e
                         s0 = group_sum(s0);
                         s1 = group_sum(s1);
                     }
-                    double lw0 = cc == 1 ? l0m : l0;
-                    double lw1 = cc == 2 ? l1m : l1;
-                    if (!(lw0 > -INFINITY) && !(lw1 > -INFINITY)) lw0 = lw1 = 0.0;   // both weights zero: equal
-                    // The draw compares dd + g1 - g0 with 0.  FP32 noise is within
-                    // 3e-6 of the FP64 noise, so when the FP32 difference clears
-                    // tau its sign is the FP64 sign; otherwise (or with a zero
-                    // weight) the FP64 comparison decides.
-                    dd = lw1 - lw0 + df;
-                    const float d32 = (float)dd + ndc;
-                    const float tau = 1e-3f + 1e-5f * fabsf((float)dd);
-                    if (isfinite(dd) && fabsf(d32) > tau) {
-                        sub = d32 > 0.0f ? 1 : 0;
-                    } else {
-                        const Words w = philox(ws.seed, (uint32_t)i, 0u, a.step, kGumbelS, 0u);
-                        const double v0 = lw0 + (-log(-log(unit23d(w.w[0]))));
-                        const double v1 = lw1 + df + (-log(-log(unit23d(w.w[1]))));
-                        sub = v1 > v0 ? 1 : 0;
-                    }
+                    sub = sub_draw(ws.seed, (uint32_t)i, a.step, kGumbelS, sw, cc, ndc, df, &dd);
                 }
                 // statistics of (k, sub), from the registers where the row already is
                 unsigned long long* grow = ws.ssub + (int64_t)(2 * k + sub) * G;
@@ -241,12 +221,7 @@ __global__ void __launch_bounds__(kSubThreads) __attribute__((amdgpu_waves_per_e
                     if constexpr (SPLITQ) {
                         // log p(cbar_i) of eq. 8 for the split proposal term: a
                         // two-way softmax of the scores, whose difference is dd
-                        double lp = 0.0;
-                        if (!reset) {
-                            const double x = sub ? -dd : dd;
-                            lp = -(fmax(x, 0.0) + log1p(exp(-fabs(x))));
-                        }
-                        ws.lpsub[i] = lp;
+                        ws.lpsub[i] = reset ? 0.0 : sub_logp(dd, sub);
                     }
                     if (a.dbg && K + 2 <= a.dbg_stride) {
                         put_dbg(a.dbg, a.dbg64, i * a.dbg_stride + K, reset ? __builtin_nan("") : s0);

@@ -61,7 +61,8 @@ def measured_traffic():
     text = open(TRAFFIC_FILE).read()
     digests = set(re.findall(r"^source digest: (\w+)", text, re.M))
     got = {}
-    for c, v in re.findall(r"^traffic (FETCH_SIZE|WRITE_SIZE) .*?: ([0-9.eE+-]+) bytes per dispatch", text, re.M):
+    for c, v in re.findall(r"^traffic (FETCH_SIZE|WRITE_SIZE) dpmm::k_assign_bf16\S*: ([0-9.eE+-]+) bytes per dispatch",
+                           text, re.M):
         got[c] = float(v)
     if digests != {source_digest()} or set(got) != {"FETCH_SIZE", "WRITE_SIZE"}:
         return None

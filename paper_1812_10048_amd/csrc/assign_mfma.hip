@@ -112,8 +112,10 @@ struct Top2 {
     }
 };
 
+// (4 wavefronts per SIMD hold NT <= 3 without spilling; NT = 4 takes the registers of 2)
 template <int NT>
-__global__ void __launch_bounds__(kMfmaThreads) __attribute__((amdgpu_waves_per_eu(4))) k_assign_bf16(Ws ws, AssignArgs a)
+__global__ void __launch_bounds__(kMfmaThreads) __attribute__((amdgpu_waves_per_eu(NT >= 4 ? 2 : 4)))
+k_assign_bf16(Ws ws, AssignArgs a)
 {
     extern __shared__ __attribute__((aligned(16))) char lds[];
     uint16_t* bst = reinterpret_cast<uint16_t*>(lds);                 // [chunk][hi, lo][16 NT][kRowB]

@@ -164,12 +164,6 @@ __global__ void __launch_bounds__(kSubThreads) __attribute__((amdgpu_waves_per_e
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
                         const uint32_t x = en[j] >> 16;
-                        if constexpr (STAGE && !DUMP) {
-                            // a pad entry adds 0 x delta_0 (log theta is finite)
-                            const int g = x ? (int)(en[j] & 0xFFFFu) : 0;
-                            df = fma((double)x, dl[g], df);
-                            continue;
-                        }
                         if (!x) continue;
                         const int g = (int)(en[j] & 0xFFFFu);
                         df = fma((double)x, stage ? dl[g] : g1[g] - g0[g], df);

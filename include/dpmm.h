@@ -334,6 +334,20 @@ dpmm_status dpmm_dm_grad(const int64_t* s, int32_t J, int32_t G, const double* b
  * The CSR is not otherwise validated.  Stateless; async on stream. */
 dpmm_status dpmm_gene_moments(const dpmm_csr* csr, uint64_t* sum_dev, uint64_t* sumsq_dev, void* stream);
 
+/* The k genes of largest standard deviation across the N cells (Section 3
+ * keeps such genes), from the moments of dpmm_gene_moments.  The population
+ * variance of gene u is B_u / N^2 with B_u = N sumsq[u] - sum[u]^2, formed
+ * exactly in 128-bit integers, so the ranking is exact; equal B_u go to the
+ * lower gene.
+ *   sum_dev, sumsq_dev: DEVICE uint64[G] (dpmm_gene_moments of n_cells cells);
+ *   map_dev: DEVICE int32[G], overwritten: the place of u among the chosen
+ *     genes in increasing gene order, or -1 (the map dpmm_filter_genes takes);
+ *   std_dev: DEVICE double[G] or NULL: sqrt(B_u) / N;
+ *   k >= 0 (k >= G keeps every gene).
+ * Stateless; async on stream. */
+dpmm_status dpmm_top_genes(const uint64_t* sum_dev, const uint64_t* sumsq_dev, int32_t n_genes, int64_t n_cells,
+                           int32_t k, int32_t* map_dev, double* std_dev, void* stream);
+
 /* The CSR restricted to the genes u with map[u] >= 0, renumbered to map[u]
  * (map: DEVICE int32[G]; its kept values must increase with u, so that the
  * rows stay sorted, and lie in [0, G_out)).  Two calls:

@@ -899,6 +899,20 @@ dpmm_status dpmm_gene_moments(const dpmm_csr* csr, uint64_t* sum_dev, uint64_t* 
     return DPMM_OK;
 }
 
+dpmm_status dpmm_top_genes(const uint64_t* sum_dev, const uint64_t* sumsq_dev, int32_t n_genes, int64_t n_cells,
+                           int32_t k, int32_t* map_dev, double* std_dev, void* stream)
+{
+    if (!sum_dev || !sumsq_dev || !map_dev) return fail(DPMM_ERR_ARG, "null argument");
+    if (n_genes < 1 || n_genes > 65535) return fail(DPMM_ERR_ARG, "n_genes must be in [1, 65535]");
+    if (n_cells < 1 || n_cells >= (1ll << 30)) return fail(DPMM_ERR_ARG, "n_cells must be in [1, 2^30)");
+    if (k < 0) return fail(DPMM_ERR_ARG, "k must be >= 0");
+    launch_top_genes(reinterpret_cast<const unsigned long long*>(sum_dev),
+                     reinterpret_cast<const unsigned long long*>(sumsq_dev), n_genes, n_cells, k, map_dev, std_dev,
+                     (hipStream_t)stream);
+    HIP_TRY(hipGetLastError());
+    return DPMM_OK;
+}
+
 dpmm_status dpmm_filter_genes(const dpmm_csr* csr, const int32_t* map_dev, int64_t* row_ptr_out, int32_t* col_out,
                               int32_t* val_out, int64_t* nnz_out, void* stream)
 {

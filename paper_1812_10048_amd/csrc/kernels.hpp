@@ -28,6 +28,8 @@ hipError_t configure_layout();
 
 // bookkeeping.hip
 void launch_extend(const Ws& ws, hipStream_t s);
+void launch_top_genes(const unsigned long long* sum, const unsigned long long* sumsq, int32_t G, int64_t N, int32_t k,
+                      int32_t* map, double* std_out, hipStream_t s);
 void launch_gene_moments(const int32_t* col, const int32_t* val, int64_t nnz, int32_t G, unsigned long long* sum,
                          unsigned long long* sumsq, hipStream_t s);
 void launch_filter_count(const int64_t* row_ptr, const int32_t* col, int64_t N, int32_t G, const int32_t* map,

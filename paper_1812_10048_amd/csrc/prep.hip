@@ -96,6 +96,82 @@ __global__ void __launch_bounds__(kPrepThreads) k_filter_fill(const int64_t* __r
     }
 }
 
+// ---------------------------------------------------------------------------
+// The k genes of largest standard deviation.  The population variance of gene
+// u is B_u / N^2 with B_u = N sum x^2 - (sum x)^2, an integer below 2^127 for
+// N < 2^31 and 64-bit moments; N^2 is common to all genes, so ranking by B in
+// exact 128-bit arithmetic ranks the standard deviations exactly.  Equal B go
+// to the lower gene.
+// ---------------------------------------------------------------------------
+typedef unsigned __int128 u128;
+
+__device__ inline u128 variance_numerator(unsigned long long s, unsigned long long q, uint64_t n)
+{
+    return (u128)n * (u128)q - (u128)s * (u128)s;
+}
+
+// rank of gene g = the genes before it in (B descending, gene ascending); the
+// genes of rank < k are flagged in map (1, else -1).  Each workgroup walks all
+// genes in tiles of kPrepThreads, the tile's B in LDS.
+__global__ void __launch_bounds__(kPrepThreads) k_gene_rank(const unsigned long long* __restrict__ sum,
+                                                            const unsigned long long* __restrict__ sumsq, int32_t G,
+                                                            uint64_t n, int32_t k, int32_t* map, double* std_out)
+{
+    __shared__ unsigned long long thi[kPrepThreads], tlo[kPrepThreads];
+    const int g = blockIdx.x * kPrepThreads + threadIdx.x;
+    const u128 bg = g < G ? variance_numerator(sum[g], sumsq[g], n) : 0;
+    int above = 0;
+    for (int h0 = 0; h0 < G; h0 += kPrepThreads) {
+        const int h = h0 + threadIdx.x;
+        const u128 bh = h < G ? variance_numerator(sum[h], sumsq[h], n) : 0;
+        __syncthreads();
+        thi[threadIdx.x] = (unsigned long long)(bh >> 64);
+        tlo[threadIdx.x] = (unsigned long long)bh;
+        __syncthreads();
+        const int m = min(kPrepThreads, G - h0);
+        for (int j = 0; j < m; ++j) {
+            const u128 b = ((u128)thi[j] << 64) | (u128)tlo[j];
+            above += (b > bg || (b == bg && h0 + j < g)) ? 1 : 0;
+        }
+    }
+    if (g >= G) return;
+    map[g] = above < k ? 1 : -1;
+    if (std_out) {
+        const double v = (double)(unsigned long long)(bg >> 64) * 0x1p64 + (double)(unsigned long long)bg;
+        std_out[g] = sqrt(v) / (double)n;
+    }
+}
+
+// one workgroup: the flagged genes numbered 0, 1, ... in gene order
+__global__ void __launch_bounds__(kScanThreads) k_gene_places(int32_t* map, int32_t G)
+{
+    __shared__ int32_t part[kScanThreads];
+    const int t = threadIdx.x;
+    const int chunk = (G + kScanThreads - 1) / kScanThreads;
+    const int b = t * chunk, e = min(G, b + chunk);
+    int c = 0;
+    for (int u = b; u < e; ++u) c += map[u] > 0 ? 1 : 0;
+    part[t] = c;
+    __syncthreads();
+    for (int off = 1; off < kScanThreads; off <<= 1) {
+        const int add = t >= off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += add;
+        __syncthreads();
+    }
+    int at = part[t] - c;
+    for (int u = b; u < e; ++u) map[u] = map[u] > 0 ? at++ : -1;
+}
+
+void launch_top_genes(const unsigned long long* sum, const unsigned long long* sumsq, int32_t G, int64_t N, int32_t k,
+                      int32_t* map, double* std_out, hipStream_t s)
+{
+    const unsigned blocks = (unsigned)((G + kPrepThreads - 1) / kPrepThreads);
+    hipLaunchKernelGGL(k_gene_rank, dim3(blocks), dim3(kPrepThreads), 0, s, sum, sumsq, G, (uint64_t)N, k, map,
+                       std_out);
+    hipLaunchKernelGGL(k_gene_places, dim3(1), dim3(kScanThreads), 0, s, map, G);
+}
+
 void launch_gene_moments(const int32_t* col, const int32_t* val, int64_t nnz, int32_t G, unsigned long long* sum,
                          unsigned long long* sumsq, hipStream_t s)
 {

@@ -93,6 +93,7 @@ _SIGNATURES = {
     "dpmm_dm_grad": ([_P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P], _S),
     "dpmm_gene_moments": ([ctypes.POINTER(dpmm_csr), _P, _P, _P], _S),
     "dpmm_filter_genes": ([ctypes.POINTER(dpmm_csr), _P, _P, _P, _P, ctypes.POINTER(ctypes.c_int64), _P], _S),
+    "dpmm_top_genes": ([_P, _P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, _P, _P, _P], _S),
 }
 
 _lib = None
@@ -235,6 +236,11 @@ def dpmm_dm_grad(s_dev: int, J: int, G: int, beta_dev: int, g_dev: int, grad_dev
 
 def dpmm_gene_moments(csr: dpmm_csr, sum_dev: int, sumsq_dev: int, stream: int) -> None:
     _check(lib().dpmm_gene_moments(ctypes.byref(csr), sum_dev, sumsq_dev, stream))
+
+
+def dpmm_top_genes(sum_dev: int, sumsq_dev: int, n_genes: int, n_cells: int, k: int, map_dev: int, std_dev,
+                   stream: int) -> None:
+    _check(lib().dpmm_top_genes(sum_dev, sumsq_dev, int(n_genes), int(n_cells), int(k), map_dev, std_dev, stream))
 
 
 def dpmm_filter_genes(csr: dpmm_csr, map_dev: int, row_ptr_out: int, col_out, val_out, stream: int) -> int:

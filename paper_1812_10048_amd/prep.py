@@ -3,14 +3,13 @@
 Section 3 clusters droplet UMI data after keeping the genes of largest
 standard deviation across cells.  This module reads 10x Market Matrix files
 into the cell-major CSR the library takes, ranks the genes by standard
-deviation from exact per-gene moments computed by the library's HIP kernels,
-and restricts the CSR to the chosen genes on the GPU.  Reading files is host
+deviation exactly on the GPU from the per-gene moments (the library's HIP
+kernels), and restricts the CSR to the chosen genes on the GPU.  Reading files is host
 IO; every pass over the counts runs in the library.
 """
 from __future__ import annotations
 
 import gzip
-import math
 
 import numpy as np
 import torch
@@ -65,44 +64,52 @@ def _csr(row_ptr, col, val, n_genes: int):
     return csr, (rp, cl, vl)
 
 
-def gene_moments(row_ptr, col, val, n_genes: int):
-    """Exact (sum_i x_iu, sum_i x_iu^2) per gene, as Python-int numpy object arrays."""
+def _moments_dev(row_ptr, col, val, n_genes: int):
     csr, keep = _csr(row_ptr, col, val, n_genes)
     s = torch.zeros(n_genes, dtype=torch.int64, device="cuda")
     q = torch.zeros(n_genes, dtype=torch.int64, device="cuda")
     C.dpmm_gene_moments(csr, s.data_ptr(), q.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    return s, q, keep
+
+
+def gene_moments(row_ptr, col, val, n_genes: int):
+    """Exact (sum_i x_iu, sum_i x_iu^2) per gene, as Python-int numpy object arrays."""
+    s, q, _ = _moments_dev(row_ptr, col, val, n_genes)
     torch.cuda.current_stream().synchronize()
     # stored as uint64; both fit in int64 for valid data
     return s.cpu().numpy().astype(object), q.cpu().numpy().astype(object)
 
 
-def gene_std(row_ptr, col, val, n_genes: int) -> np.ndarray:
-    """Population standard deviation of each gene's counts across the N cells:
-    sqrt((N sum x^2 - (sum x)^2) / N^2), the bracket in exact integers."""
+def top_genes(row_ptr, col, val, n_genes: int, k: int):
+    """The k genes of largest standard deviation across the cells (Section 3),
+    ranked exactly on the GPU (equal variances: the lower gene first):
+    (genes in increasing order as numpy int64, the gene -> place map as a
+    device tensor for filter_genes, the standard deviations as numpy)."""
     n_cells = len(row_ptr) - 1
-    s, q = gene_moments(row_ptr, col, val, n_genes)
-    return np.array([math.sqrt((n_cells * qi - si * si) / (n_cells * n_cells)) for si, qi in zip(s, q)])
-
-
-def top_genes(std, k: int) -> np.ndarray:
-    """The k genes of largest standard deviation (ties: the lower index), in
-    increasing gene order."""
-    std = np.asarray(std, dtype=np.float64)
-    k = min(int(k), std.size)
-    order = np.lexsort((np.arange(std.size), -std))
-    return np.sort(order[:k])
+    s, q, _ = _moments_dev(row_ptr, col, val, n_genes)
+    gmap = torch.empty(n_genes, dtype=torch.int32, device="cuda")
+    std = torch.empty(n_genes, dtype=torch.float64, device="cuda")
+    C.dpmm_top_genes(s.data_ptr(), q.data_ptr(), n_genes, n_cells, int(k), gmap.data_ptr(), std.data_ptr(),
+                     torch.cuda.current_stream().cuda_stream)
+    torch.cuda.current_stream().synchronize()
+    genes = np.nonzero(gmap.cpu().numpy() >= 0)[0].astype(np.int64)
+    return genes, gmap, std.cpu().numpy()
 
 
 def filter_genes(row_ptr, col, val, n_genes: int, genes):
-    """The CSR restricted to ``genes`` (increasing), renumbered 0..len-1, on the
-    GPU: (row_ptr, col, val) as device tensors."""
-    genes = np.asarray(genes, dtype=np.int64)
-    if genes.size and (np.any(np.diff(genes) <= 0) or genes[0] < 0 or genes[-1] >= n_genes):
-        raise ValueError("genes must be increasing and in [0, n_genes)")
+    """The CSR restricted to ``genes`` (increasing gene indices, or the
+    gene -> place map of top_genes as a device tensor), renumbered
+    0..len-1, on the GPU: (row_ptr, col, val) as device tensors."""
     csr, keep = _csr(row_ptr, col, val, n_genes)
-    gmap = np.full(n_genes, -1, dtype=np.int32)
-    gmap[genes] = np.arange(genes.size, dtype=np.int32)
-    gm = torch.from_numpy(gmap).cuda()
+    if isinstance(genes, torch.Tensor) and genes.is_cuda:
+        gm = genes.to(torch.int32).contiguous()
+    else:
+        genes = np.asarray(genes, dtype=np.int64)
+        if genes.size and (np.any(np.diff(genes) <= 0) or genes[0] < 0 or genes[-1] >= n_genes):
+            raise ValueError("genes must be increasing and in [0, n_genes)")
+        gmap = np.full(n_genes, -1, dtype=np.int32)
+        gmap[genes] = np.arange(genes.size, dtype=np.int32)
+        gm = torch.from_numpy(gmap).cuda()
     stream = torch.cuda.current_stream().cuda_stream
     rp_out = torch.empty(csr.n_cells + 1, dtype=torch.int64, device="cuda")
     nnz = C.dpmm_filter_genes(csr, gm.data_ptr(), rp_out.data_ptr(), None, None, stream)

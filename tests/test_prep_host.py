@@ -48,13 +48,6 @@ def test_read_10x_mtx_rejects_bad_files(tmp_path):
         prep.read_10x_mtx(p)
 
 
-def test_top_genes_breaks_ties_by_the_lower_index():
-    std = np.array([1.0, 3.0, 2.0, 3.0, 0.5, 2.0])
-    assert list(prep.top_genes(std, 3)) == [1, 2, 3]
-    assert list(prep.top_genes(std, 4)) == [1, 2, 3, 5]
-    assert list(prep.top_genes(std, 10)) == [0, 1, 2, 3, 4, 5]
-
-
 def test_oracle_moments_and_filter_against_numpy_and_scipy():
     rng = np.random.default_rng(1)
     m = _random_counts(rng, 40, 70).T.tocsr()

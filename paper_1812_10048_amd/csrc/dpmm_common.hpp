@@ -297,6 +297,11 @@ struct Ws {
     uint16_t* lay_gene;    // [k_max kLayDmax kBlkGenes] gene at place j
     uint16_t* lay_bhi;     // [k_max][lay_cols][kLayDmax kBlkGenes] hi of log theta in L's gene order
     uint16_t* lay_blo;     // same for lo
+    uint64_t* lay_lim;     // [k_max][kLayDmax][2][8][4] base-256 digits of the fixed-point delta (laysub.hip)
+    int32_t* lay_dE;       // [k_max] its binary scale
+    int32_t* lay_dS;       // [k_max][kLayDmax + 1][8] digit sums over the first D chunks
+    double* lay_dfull;     // [k_max][G] the difference itself, gene-major (tail entries)
+    double* lay_sw;        // [k_max][4] the sub-cluster weights of the draw (SubWeights)
     uint32_t* lay_part;    // [nblk_cap][lay_pw] a block's count sums per (sub-cluster | coin, gene)
     uint32_t* span_part;   // [lay_spans][lay_pw] the same summed over spans of blocks
     int32_t lay_pw;        // rows x G of those histograms (rows 4 with random splits, else 2), 0 past kLsHistWords

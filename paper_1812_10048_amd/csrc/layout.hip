@@ -284,17 +284,114 @@ void launch_relayout(const Ws& ws, const int32_t* c, int64_t* tile_sums, int for
                        gated);
 }
 
+// The sub-cluster score difference of layout cluster L in fixed point, for
+// the integer matrix-core sums of the sub-cluster pass (laysub.hip):
+// delta_p = log thetabar_{L,1,u} - log thetabar_{L,0,u} at place p (gene u of
+// L's order), v_p = rint(delta_p 2^E) with E = 54 - e_max (|delta_p| <
+// 2^e_max for all p < kLayDmax kBlkGenes, so |v_p| <= 2^54), written as seven
+// base-256 digits in -128 .. 127: v_p = sum_k d_{p,k} 256^k.  lay_lim holds
+// the digits as the A operand of v_mfma_i32_16x16x32_i8 (row k, k-group g,
+// 8 consecutive places), lay_dS[L][D][k] the digit sums over the first D
+// chunks and lay_dE[L] = E; lay_dfull[L] holds delta_u gene-major (for the
+// tail entries) and lay_sw[L] the weights of the draw (sub_weights).  Block L
+// of k_lay_btab (256 threads), for every L of the copy that is a live,
+// non-reset cluster.
+__device__ inline void lay_dtab(const Ws& ws, int L, int K, int KL)
+{
+    constexpr int R = kLayDmax * kBlkGenes;
+    constexpr int kNoExp = -(1 << 30);         // no non-zero difference
+    __shared__ int8_t dig[R][8];
+    __shared__ int red[4];
+    if (L >= KL || L >= K || ws.reset[L]) return;
+    const int t = threadIdx.x;
+    const int G = ws.G;
+    const double* g0 = ws.lt64 + (int64_t)(ws.k_max + 2 * L) * G;
+    const double* g1 = g0 + G;
+    for (int u = t; u < G; u += 256) ws.lay_dfull[(int64_t)L * G + u] = g1[u] - g0[u];
+    if (t == 0) {
+        const SubWeights w = sub_weights(ws.nsub_prev, L);
+        double* o = ws.lay_sw + 4 * (int64_t)L;
+        o[0] = w.l0;
+        o[1] = w.l0m;
+        o[2] = w.l1;
+        o[3] = w.l1m;
+    }
+    double d[2];
+    int e = kNoExp;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int u = ws.lay_gene[(int64_t)L * R + t + 256 * h];
+        d[h] = g1[u] - g0[u];
+        if (d[h] != 0.0) {
+            int ex;
+            frexp(d[h], &ex);
+            e = max(e, ex);
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) e = max(e, __shfl_xor(e, o, 64));
+    if ((t & 63) == 0) red[t >> 6] = e;
+    __syncthreads();
+    const int emax = max(max(red[0], red[1]), max(red[2], red[3]));
+    const int E = emax == kNoExp ? 0 : 54 - emax;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        long long v = (long long)rint(ldexp(d[h], E));
+#pragma unroll
+        for (int k = 0; k < 7; ++k) {
+            const int dk = (int)(int8_t)(uint8_t)(v & 0xFF);
+            dig[t + 256 * h][k] = (int8_t)dk;
+            v = (v - dk) >> 8;
+        }
+        dig[t + 256 * h][7] = 0;
+    }
+    __syncthreads();
+    // word (j, s, k, g): digit k of places 64 j + 32 s + 8 g .. + 7
+    for (int w = t; w < kLayDmax * 2 * 8 * 4; w += 256) {
+        const int g = w & 3, k = (w >> 2) & 7, s = (w >> 5) & 1, j = w >> 6;
+        const int p0 = 64 * j + 32 * s + 8 * g;
+        uint64_t word = 0;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) word |= (uint64_t)(uint8_t)dig[p0 + b][k] << (8 * b);
+        ws.lay_lim[(int64_t)L * (kLayDmax * 2 * 8 * 4) + w] = word;
+    }
+    // digit sums per chunk, then over the first D chunks
+    __shared__ int csum[kLayDmax][8];
+    if (t < kLayDmax * 8) {
+        const int j = t >> 3, k = t & 7;
+        int sum = 0;
+        for (int p = 0; p < kBlkGenes; ++p) sum += dig[64 * j + p][k];
+        csum[j][k] = sum;
+    }
+    __syncthreads();
+    if (t < 8) {
+        int acc = 0;
+        int32_t* out = ws.lay_dS + (int64_t)L * (kLayDmax + 1) * 8;
+        out[t] = 0;
+        for (int j = 0; j < kLayDmax; ++j) {
+            acc += csum[j][t];
+            out[(j + 1) * 8 + t] = acc;
+        }
+        if (t == 0) ws.lay_dE[L] = E;
+    }
+}
+
 // After every redraw: the hi/lo tables of log theta (split-BF16, cluster-major
 // [k][Gpad]) with the genes in each layout cluster's order, for the first
 // kLayDmax chunks: tab[L][col][j] = table[col][gene_L[j]], zero for the
-// columns past K that the kernel's last column tile reads.
-__global__ void k_lay_btab(Ws ws)
+// columns past K that the kernel's last column tile reads.  The first k_max
+// blocks write the fixed-point difference tables above instead.
+__global__ void __launch_bounds__(256) k_lay_btab(Ws ws)
 {
     const int K = ws.st->K;
     const int KL = ws.st->lay_K;
     const int R = kLayDmax * kBlkGenes;
+    if ((int)blockIdx.x < ws.k_max) {
+        lay_dtab(ws, (int)blockIdx.x, K, KL);
+        return;
+    }
     const int64_t n = (int64_t)KL * ws.lay_cols * R;
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t stride = (int64_t)(gridDim.x - ws.k_max) * blockDim.x;
+    for (int64_t q = (int64_t)(blockIdx.x - ws.k_max) * blockDim.x + threadIdx.x; q < n; q += stride) {
         const int j = (int)(q % R);
         const int64_t lc = q / R;
         const int col = (int)(lc % ws.lay_cols);
@@ -315,7 +412,7 @@ void launch_lay_btab(const Ws& ws, hipStream_t s)
     const int64_t n = (int64_t)ws.k_max * ws.lay_cols * kLayDmax * kBlkGenes;
     int64_t blocks = (n + 255) / 256;
     if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(k_lay_btab, dim3((unsigned)blocks), dim3(256), 0, s, ws);
+    hipLaunchKernelGGL(k_lay_btab, dim3((unsigned)(blocks + ws.k_max)), dim3(256), 0, s, ws);
 }
 
 }  // namespace dpmm

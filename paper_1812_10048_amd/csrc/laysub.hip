@@ -2,81 +2,120 @@
 // sufficient statistics (step a4) of a split-BF16 sweep, over the
 // cluster-sorted copy of the counts (layout.hip) instead of the packed matrix.
 //
-// A workgroup of 512 threads takes one block of the copy, with layout cluster
-// L.  The block's cells whose new label is L (nearly all of them once the
-// chain has settled) are drawn here; any other cell of the block goes to a
-// queue that k_mov_sub serves from the packed matrix, exactly as the
-// packed-matrix pass would.
-//   1. Thread (slot, half) loads the half of its cell's dense bytes that it
-//      owns, two 16-byte pieces per chunk, all chunks in flight at once, keeps
-//      them in registers and forms the FP64 sum of x_u delta_u, with
-//      delta_u = log thetabar_{L,1,u} - log thetabar_{L,0,u} staged in LDS in
-//      L's gene order; each half adds every other tail entry of the cell, and
-//      the halves are added in a fixed order.
-//   2. The draw itself (sub_draw, shared with the packed-matrix pass).
-//   3. Statistics: chunk by chunk the bytes go to LDS, and the matrix cores
-//      form M X, X the chunk's 256 x 64 counts (cells x genes), M the 0/1 rows
-//      "cell of L in sub-cluster 0", "... 1" (and "coin 0", "coin 1" of a
-//      random split coming next), in BF16 with FP32 accumulation.  Every
-//      product and partial sum is an integer below 2^24, so the sums are
-//      exact.  The sums go to a per-block LDS histogram over (row, gene),
-//      together with the tail entries (a count above 255 is a tail entry too,
-//      and those crowd on a cluster's top genes).  Each block writes its whole
-//      histogram to lay_part; k_lay_span adds them over spans of consecutive
-//      blocks of a cluster and k_lay_reduce adds a cluster's spans into its
-//      statistics.  No atomics reach memory: device-scope 64-bit atomics on
-//      a few hot addresses from every block serialise.  (Past kLsHistWords
-//      histogram words, the sums go to the statistics with atomics instead.)
+// A workgroup of 8 wavefronts takes one block of the copy, with layout
+// cluster L; wavefront w owns the block's row tiles 2w and 2w + 1 (32 cells),
+// whose dense bytes are stored as the A fragments of the matrix-core products
+// (lane l: cell l % 16 of the tile, places 8 (l / 16) .. + 7 and
+// 32 + 8 (l / 16) .. + 7 of each chunk of 64 places).  The block's cells whose
+// new label is L (nearly all of them once the chain has settled) are drawn
+// here; any other cell of the block goes to a queue that k_mov_sub serves
+// from the packed matrix, exactly as the packed-matrix pass would.  After the
+// workgroup has staged what depends on L, each wavefront works on its own,
+// with no further barrier until the block's histogram is written:
+//   1. Each lane loads its fragments of both tiles, all chunks in flight at
+//      once, keeps them in registers and forms the FP64 sums of x_u delta_u
+//      over its 16 places per chunk, delta_u = log thetabar_{L,1,u} -
+//      log thetabar_{L,0,u} staged in LDS in L's gene order; the four lanes
+//      of a cell split its tail entries, and their sums are added in a fixed
+//      pattern that gives all four the same value.
+//   2. The draw itself (sub_draw, shared with the packed-matrix pass), taken
+//      by the four lanes of a cell alike.
+//   3. Statistics on the matrix cores, in 8-bit integers with 32-bit sums
+//      (exact).  The fragments hold a cell's genes along k, the statistics
+//      sum over cells: a product with a 0/1 selection matrix (one 1 per
+//      column) turns the counts of 16 places of a tile into the layout where
+//      each lane holds one place of four cells; packed as bytes, the counts of
+//      the wavefront's 32 cells then multiply the 0/1 rows "cell of L in
+//      sub-cluster 0", "... 1" (and "coin 0", "coin 1" of a random split
+//      coming next) over those cells.  The signed operands take x - 128 and
+//      the row's cell count times 128 is added back.  The sums go to a
+//      per-block LDS histogram over (row, gene), together with the tail
+//      entries (a count above 255 is a tail entry too, and those crowd on a
+//      cluster's top genes).  Each block writes its whole histogram to
+//      lay_part; k_lay_span adds them over spans of consecutive blocks of a
+//      cluster and k_lay_reduce adds a cluster's spans into its statistics.
+//      No atomics reach memory: device-scope 64-bit atomics on a few hot
+//      addresses from every block serialise.  (Past kLsHistWords histogram
+//      words, the sums go to the statistics with atomics instead.)
 #include "dpmm_common.hpp"
 #include "kernels.hpp"
 
 namespace dpmm {
 
-typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
-typedef __attribute__((__vector_size__(4 * sizeof(float)))) float floatx4_t;
+typedef __attribute__((__vector_size__(4 * sizeof(int)))) int intx4_t;
 
-constexpr int kLsThreads = 2 * kBlkCells;     // two threads per slot
+constexpr int kLsThreads = 2 * kBlkCells;     // 8 wavefronts of 32 cells
 constexpr int kPlaces = kLayDmax * kBlkGenes;  // places of a cluster's gene order in the dense chunks
-constexpr int kPartRows = 4;                   // sub-cluster 0, 1, coin 0, 1
 constexpr int kMovGroups = 32;                 // cells per workgroup pass of k_mov_sub (8 lanes each)
 constexpr int kMovLanes = 8;
 constexpr int kRedSpan = kSpanBlocks;
 
-// eight bytes (two words) -> eight BF16 values (exact: each is an integer
-// below 256, whose FP32 value has its low 16 bits zero)
-__device__ inline bf16x8_t bytes_bf16(uint32_t w0, uint32_t w1)
+// byte 0 of each of four words -> one word
+__device__ inline uint32_t low_bytes(const intx4_t& c)
 {
-    uint32_t p[4];
-    const uint32_t in[2] = {w0, w1};
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const uint32_t v = in[h];
-        const uint32_t f0 = __float_as_uint((float)(v & 0xFFu));
-        const uint32_t f1 = __float_as_uint((float)((v >> 8) & 0xFFu));
-        const uint32_t f2 = __float_as_uint((float)((v >> 16) & 0xFFu));
-        const uint32_t f3 = __float_as_uint((float)(v >> 24));
-        p[2 * h] = __builtin_amdgcn_perm(f1, f0, 0x07060302u);
-        p[2 * h + 1] = __builtin_amdgcn_perm(f3, f2, 0x07060302u);
-    }
-    bf16x8_t r;
-    __builtin_memcpy(&r, p, sizeof(r));
-    return r;
+    const uint32_t lo = __builtin_amdgcn_perm((uint32_t)c[1], (uint32_t)c[0], 0x0c0c0400u);
+    const uint32_t hi = __builtin_amdgcn_perm((uint32_t)c[3], (uint32_t)c[2], 0x0c0c0400u);
+    return __builtin_amdgcn_perm(hi, lo, 0x05040100u);
 }
 
-// The swizzle of a piece's row r in LDS: r ^ (q & 1 | (rt & 1) << 1 | (r >> 3) << 2)
-__device__ inline int lane_swizzle(int q, int rt_odd, int r_hi) { return (q & 1) | (rt_odd << 1) | (r_hi << 2); }
+// x -> x - 128 on eight count bytes taken as signed 8-bit values
+constexpr long kOffset8 = (long)0x8080808080808080ull;
+
+// k-step s (0, 1) of a fragment: 8 bytes, places 32 s + 8 (l / 16) .. + 7
+__device__ inline long kstep(const uint4& v, int s)
+{
+    return s ? (long)((uint64_t)v.z | ((uint64_t)v.w << 32)) : (long)((uint64_t)v.x | ((uint64_t)v.y << 32));
+}
+
+// The statistics of a wavefront's 32 cells over the block's dense chunks
+// (step 3 of k_lay_sub): per chunk, eight selection products bring the counts
+// of each place to the lanes of its column, four products with the 0/1 rows
+// sum them over the cells, and lane group 0 adds rows 0 .. ROWS - 1 to the
+// LDS histogram (LHIST) or to the statistics rows srow (sub-clusters) and
+// crow (coins).
+template <int ROWS, bool LHIST>
+__device__ inline void chunk_stats(const uint4 (&av)[kLayDmax][2], int D, long amask, const long (&sel)[2],
+                                   const int (&rc128)[4], const uint16_t* s_gene, uint32_t* thist, int G, int g, int r,
+                                   unsigned long long* srow, unsigned long long* crow)
+{
+    const intx4_t zero = {0, 0, 0, 0};
+#pragma unroll
+    for (int j = 0; j < kLayDmax; ++j) {
+        if (j >= D) break;
+        // lane (r, g) gets the counts of place 16 nt + r for cells 16 m + 4 g + i in word i
+        intx4_t o[4];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            const intx4_t c0 = __builtin_amdgcn_mfma_i32_16x16x32_i8(kstep(av[j][0], nt >> 1), sel[nt & 1], zero, 0, 0, 0);
+            const intx4_t c1 = __builtin_amdgcn_mfma_i32_16x16x32_i8(kstep(av[j][1], nt >> 1), sel[nt & 1], zero, 0, 0, 0);
+            const uint64_t xb = ((uint64_t)low_bytes(c0) | ((uint64_t)low_bytes(c1) << 32)) ^ (uint64_t)kOffset8;
+            o[nt] = __builtin_amdgcn_mfma_i32_16x16x32_i8(amask, (long)xb, zero, 0, 0, 0);
+        }
+        // rows 0 .. 3 of the products are in lane group 0, row i in word i
+        if (g == 0) {
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                const int u = s_gene[j * kBlkGenes + 16 * nt + r];
+#pragma unroll
+                for (int i = 0; i < ROWS; ++i) {
+                    const uint32_t v = (uint32_t)(o[nt][i] + rc128[i]);
+                    if (LHIST) atomicAdd(&thist[i * G + u], v);
+                    else if (v) atomicAdd((i < 2 ? srow : crow) + (int64_t)(i & 1) * G + u, (unsigned long long)v);
+                }
+            }
+        }
+    }
+}
 
 template <bool DUMP, bool SPLITQ>
-__global__ void __launch_bounds__(kLsThreads) k_lay_sub(Ws ws, SubArgs a)
+__global__ void __launch_bounds__(kLsThreads) __attribute__((amdgpu_waves_per_eu(DUMP ? 2 : 4)))
+k_lay_sub(Ws ws, SubArgs a)
 {
-    __shared__ double dl[kPlaces];                         // delta in L's gene order
+    __shared__ double dl[DUMP ? kPlaces : 1];              // delta in L's gene order (dump)
+    __shared__ uint64_t s_lim[DUMP ? 1 : kPlaces];         // its fixed-point digits (lay_lim of L)
+    __shared__ uint16_t s_gene[kPlaces];                   // gene at each place of L
     __shared__ double tl0[DUMP ? kPlaces : 1], tl1[DUMP ? kPlaces : 1];   // the two rows themselves (dump)
-    __shared__ __attribute__((aligned(16))) uint8_t chunk[kDenseChunkBytes];
-    __shared__ double hsum[3][2][kBlkCells];               // per-half sums: delta, and rows 0 / 1 (dump)
-    __shared__ int8_t s_sub[kBlkCells];                    // sub-label of a cell of L, -1 for any other slot
-    __shared__ uint8_t s_coin[kBlkCells];
-    __shared__ float psum[2][kPartRows][kBlkGenes];
-    __shared__ uint32_t thist[kLsHistWords];               // tail counts per (row, gene)
+    __shared__ uint32_t thist[kLsHistWords];               // count sums per (row, gene)
     __shared__ uint32_t ncnt[2], ncnt2[2];
 
     const bool rs = a.rsplit != 0;
@@ -86,151 +125,281 @@ __global__ void __launch_bounds__(kLsThreads) k_lay_sub(Ws ws, SubArgs a)
     const int t = threadIdx.x;
     const int lane = t & 63;
     const int wave = t >> 6;
-    const int sl = t & (kBlkCells - 1);
-    const int h = t >> 8;                      // which half of the cell's bytes (places 8q .. 8q + 7 of
-                                               // both k-steps, q = 2h, 2h + 1)
-    const int64_t slot = (int64_t)b * kBlkCells + sl;
+    const int r = lane & 15;                   // the lane's row of its two tiles
+    const int g = lane >> 4;                   // and its k-group
     const int L = ws.lay_kc[b];
     const int K = ws.st->K;
     const int G = ws.G;
     const int64_t d0 = ws.lay_doff[b];
     const int D = (int)(ws.lay_doff[b + 1] - d0);
-    const int cell = ws.lay_cell[slot];
-    const bool stay = cell >= 0 && L < K && a.c_new[cell] == L;
     const bool reset = L < K ? ws.reset[L] != 0 : true;
     const double* g0 = ws.lt64 + (int64_t)(ws.k_max + 2 * (L < K ? L : 0)) * G;
     const double* g1 = g0 + G;
 
-    if (!reset) {
+    // the lane's fragments of row tiles 2w, 2w + 1: + j chunk + m 1 KiB
+    const uint8_t* dense = ws.lay_dense + d0 * kDenseChunkBytes;   // uniform base
+    const uint32_t doff = (uint32_t)((wave * 2) * 64 + lane) * 16;
+    uint4 av[kLayDmax][2];
+#pragma unroll
+    for (int j = 0; j < kLayDmax; ++j)
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+            av[j][m] = j < D ? *reinterpret_cast<const uint4*>(dense + (doff + (uint32_t)(j * kDenseChunkBytes + m * 1024)))
+                             : make_uint4(0, 0, 0, 0);
+    // the lane's cells, their tail ranges and old labels, and (before the
+    // barrier, so that the chain of loads overlaps the staging) the lane's
+    // first tail entry of each with its difference
+    int cell[2], ocode[2];
+    bool stay[2];
+    int64_t tb[2], te[2];
+    uint32_t en0[2];
+    double dt0[2];
+    const double* dfull = ws.lay_dfull + (int64_t)(L < K ? L : 0) * G;
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+        const int64_t slot = (int64_t)b * kBlkCells + 32 * wave + 16 * m + r;
+        cell[m] = ws.lay_cell[slot];
+        tb[m] = ws.lay_toff[slot];
+        te[m] = ws.lay_toff[slot + 1];
+        stay[m] = cell[m] >= 0 && L < K && a.c_new[cell[m]] == L;
+        ocode[m] = stay[m] && a.c_old[cell[m]] == L ? 1 + (a.cs_old[cell[m]] & 1) : 0;
+        en0[m] = stay[m] && tb[m] + g < te[m] ? ws.lay_tail[tb[m] + g] : 0u;   // (an entry's count is >= 1)
+        dt0[m] = !DUMP && !reset && en0[m] ? dfull[en0[m] & 0xFFFFu] : 0.0;
+        if (g == 0 && cell[m] >= 0 && !stay[m]) {
+            const int q = atomicAdd(&ws.st->n_mov, 1);
+            if (q < ws.N) ws.mov[q] = (uint32_t)cell[m];
+        }
+    }
+    {
         const uint16_t* gene = ws.lay_gene + (int64_t)L * kPlaces;
         for (int j = t; j < D * kBlkGenes; j += kLsThreads) {
             const int u = gene[j];
-            const double v0 = g0[u], v1 = g1[u];
-            dl[j] = v1 - v0;
-            if (DUMP) {
+            s_gene[j] = (uint16_t)u;
+            if (DUMP && !reset) {
+                const double v0 = g0[u], v1 = g1[u];
+                dl[j] = v1 - v0;
                 tl0[j] = v0;
                 tl1[j] = v1;
             }
+            if (!DUMP && !reset) s_lim[j] = ws.lay_lim[(int64_t)L * kPlaces + j];
         }
     }
     if (t < 2) ncnt[t] = ncnt2[t] = 0;
     const int rows = rs ? 4 : 2;
-    // LDS offsets of this thread's two pieces of a chunk (swizzled, see below)
-    const int rt_me = sl >> 4, r_me = sl & 15;
-    const uint32_t w_off0 = (uint32_t)(rt_me * 64 + 16 * (2 * h) + (r_me ^ lane_swizzle(2 * h, rt_me & 1, r_me >> 3))) * 16;
-    const uint32_t w_off1 =
-        (uint32_t)(rt_me * 64 + 16 * (2 * h + 1) + (r_me ^ lane_swizzle(2 * h + 1, rt_me & 1, r_me >> 3))) * 16;
     const bool lhist = rows * G <= ws.lay_pw;
     if (lhist)
         for (int q = t; q < rows * G; q += kLsThreads) thist[q] = 0;
-    if (h == 0 && cell >= 0 && !stay) {
-        const int q = atomicAdd(&ws.st->n_mov, 1);
-        if (q < ws.N) ws.mov[q] = (uint32_t)cell;
-    }
-    // the thread's two 16-byte pieces of every chunk
-    const uint8_t* dense = ws.lay_dense + d0 * kDenseChunkBytes;       // uniform base
-    const uint32_t u0 = (uint32_t)((sl >> 4) * 64 + 32 * h + (sl & 15)) * 16;
-    uint4 rv[kLayDmax][2];
-#pragma unroll
-    for (int j = 0; j < kLayDmax; ++j) {
-        if (j < D) {
-            rv[j][0] = *reinterpret_cast<const uint4*>(dense + (u0 + (uint32_t)(j * kDenseChunkBytes)));
-            rv[j][1] = *reinterpret_cast<const uint4*>(dense + (u0 + (uint32_t)(j * kDenseChunkBytes + 256)));
-        } else {
-            rv[j][0] = rv[j][1] = make_uint4(0, 0, 0, 0);
-        }
-    }
     __syncthreads();
-    // 1. the FP64 sums; byte 4p + c of a piece is place 32 (p >> 1) + 8 q + 4 (p & 1) + c
-    double df = 0.0, s0 = 0.0, s1 = 0.0;
-    if (stay && !reset) {
+
+    // 1. the FP64 sums
+    double df[2] = {0.0, 0.0}, s0[2] = {0.0, 0.0}, s1[2] = {0.0, 0.0};
+    if (DUMP && !reset) {
+        // on the vector ALUs (with the two rows themselves); byte 4p + c of a
+        // fragment is place 32 (p >> 1) + 8 g + 4 (p & 1) + c
 #pragma unroll
         for (int j = 0; j < kLayDmax; ++j) {
             if (j >= D) break;
 #pragma unroll
-            for (int qq = 0; qq < 2; ++qq) {
-                const uint32_t w[4] = {rv[j][qq].x, rv[j][qq].y, rv[j][qq].z, rv[j][qq].w};
-                const int q = 2 * h + qq;
+            for (int p = 0; p < 4; ++p)
 #pragma unroll
-                for (int p = 0; p < 4; ++p)
+                for (int c = 0; c < 4; ++c) {
+                    const int place = j * kBlkGenes + 32 * (p >> 1) + 8 * g + 4 * (p & 1) + c;
+                    const double dv = dl[place];
 #pragma unroll
-                    for (int c = 0; c < 4; ++c) {
-                        const int place = j * kBlkGenes + 32 * (p >> 1) + 8 * q + 4 * (p & 1) + c;
-                        const double x = (double)((w[p] >> (8 * c)) & 0xFFu);
-                        df = fma(x, dl[place], df);
-                        if (DUMP) {
-                            s0 = fma(x, tl0[place], s0);
-                            s1 = fma(x, tl1[place], s1);
-                        }
+                    for (int m = 0; m < 2; ++m) {
+                        const uint32_t w = p == 0 ? av[j][m].x : p == 1 ? av[j][m].y : p == 2 ? av[j][m].z : av[j][m].w;
+                        const double x = (double)((w >> (8 * c)) & 0xFFu);
+                        df[m] = fma(x, dv, df[m]);
+                        s0[m] = fma(x, tl0[place], s0[m]);
+                        s1[m] = fma(x, tl1[place], s1[m]);
                     }
+                }
+        }
+    }
+    if (!DUMP && !reset) {
+        // on the matrix cores, exactly: with the digits d_{p,k} of the
+        // fixed-point difference v_p (lay_lim), sum_p x_p v_p =
+        // sum_k 256^k (sum_p (x_p - 128) d_{p,k} + 128 S_k) over the D chunks,
+        // S_k = sum_p d_{p,k} (x - 128 is a signed byte).  Product: digits
+        // (A: row k, lane (k, g)) x the lane's own counts (B: column = cell
+        // r); lane (r, g) gets the sums of digits k = 4 g .. 4 g + 3 of its
+        // cell (rows 7 .. 15 are zero).
+        const intx4_t zero = {0, 0, 0, 0};
+        intx4_t dacc[2] = {zero, zero};
+        const int kr = r < 8 ? r : 7;
+#pragma unroll
+        for (int j = 0; j < kLayDmax; ++j) {
+            if (j >= D) break;
+            __builtin_amdgcn_sched_barrier(0);  // (one chunk's digits in registers at a time)
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                const long dig = (long)s_lim[((j * 2 + s) * 8 + kr) * 4 + g];
+#pragma unroll
+                for (int m = 0; m < 2; ++m)
+                    dacc[m] = __builtin_amdgcn_mfma_i32_16x16x32_i8(dig, kstep(av[j][m], s) ^ kOffset8, dacc[m], 0, 0, 0);
             }
         }
-        const int64_t tb = ws.lay_toff[slot], te = ws.lay_toff[slot + 1];
-        for (int64_t e = tb + h; e < te; e += 2) {
-            const uint32_t en = ws.lay_tail[e];
-            const int u = (int)(en & 0xFFFFu);
-            const double x = (double)(en >> 16);
-            df = fma(x, g1[u] - g0[u], df);
+        const int E = ws.lay_dE[L];
+        const int32_t* S = ws.lay_dS + ((int64_t)L * (kLayDmax + 1) + D) * 8;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int k = 4 * g + i;
+            const int sk = k < 8 ? S[k] : 0;
+#pragma unroll
+            for (int m = 0; m < 2; ++m) df[m] += ldexp((double)(dacc[m][i] + 128 * sk), 8 * k - E);
+        }
+    }
+    if (!reset) {
+        // the tail: entry tb + g + 4 i of the cell, in entry order
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+            if (!stay[m]) continue;
+            int64_t e = tb[m] + g;
+            if (!DUMP) {
+                if (en0[m]) df[m] = fma((double)(en0[m] >> 16), dt0[m], df[m]);
+                e += 4;
+            }
+            for (; e < te[m]; e += 4) {
+                const uint32_t en = ws.lay_tail[e];
+                const int u = (int)(en & 0xFFFFu);
+                const double x = (double)(en >> 16);
+                if (DUMP) {
+                    df[m] = fma(x, g1[u] - g0[u], df[m]);
+                    s0[m] = fma(x, g0[u], s0[m]);
+                    s1[m] = fma(x, g1[u], s1[m]);
+                } else {
+                    df[m] = fma(x, dfull[u], df[m]);
+                }
+            }
+        }
+        // the four lanes of a cell: (own + partner across 16) + (the other pair), the same sum on all four
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+            df[m] += __shfl_xor(df[m], 16);
+            df[m] += __shfl_xor(df[m], 32);
             if (DUMP) {
-                s0 = fma(x, g0[u], s0);
-                s1 = fma(x, g1[u], s1);
+                s0[m] += __shfl_xor(s0[m], 16);
+                s0[m] += __shfl_xor(s0[m], 32);
+                s1[m] += __shfl_xor(s1[m], 16);
+                s1[m] += __shfl_xor(s1[m], 32);
             }
         }
     }
-    hsum[0][h][sl] = df;
-    if (DUMP) {
-        hsum[1][h][sl] = s0;
-        hsum[2][h][sl] = s1;
-    }
-    __syncthreads();
-    // 2. the draw
-    if (h == 0) {
-        int sv = -1, cv = 0;
-        if (stay) {
-            const uint32_t i = (uint32_t)cell;
+
+    // 2. the draw: lane groups 0 and 1 take the cell of tile 0, groups 2 and
+    // 3 that of tile 1; groups 0 and 2 write
+    const int md = g >> 1;
+    int my_sv = -1, my_cv = 0;
+    {
+        const bool st = md ? stay[1] : stay[0];
+        if (st) {
+            const uint32_t i = (uint32_t)(md ? cell[1] : cell[0]);
             double dd = 0.0;
             if (reset) {
-                sv = (int)(philox(ws.seed, i, 0u, a.step, kResub, 0u).w[0] >> 31);
+                my_sv = (int)(philox(ws.seed, i, 0u, a.step, kResub, 0u).w[0] >> 31);
             } else {
-                const int code = a.c_old[cell] == L ? 1 + (a.cs_old[cell] & 1) : 0;
-                sv = sub_draw(ws.seed, i, a.step, kGumbelS, sub_weights(ws.nsub_prev, L), code,
-                              sub_noise(ws.seed, i, a.step, kGumbelS), hsum[0][0][sl] + hsum[0][1][sl], &dd);
+                const double* lw = ws.lay_sw + 4 * (int64_t)L;
+                const SubWeights sw{lw[0], lw[1], lw[2], lw[3]};
+                my_sv = sub_draw(ws.seed, i, a.step, kGumbelS, sw, md ? ocode[1] : ocode[0],
+                                 sub_noise(ws.seed, i, a.step, kGumbelS), md ? df[1] : df[0], &dd);
             }
-            a.cs_new[cell] = (uint8_t)sv;
-            atomicAdd(&ncnt[sv], 1u);
-            if (rs) {
-                cv = (int)(philox(ws.seed, i, 0u, a.rs_step, kRSplit, 0u).w[0] >> 31);
-                ws.rbits[cell] = (uint8_t)cv;
-                atomicAdd(&ncnt2[cv], 1u);
-            }
-            if (SPLITQ) ws.lpsub[cell] = reset ? 0.0 : sub_logp(dd, sv);
-            if (a.dbg && K + 2 <= a.dbg_stride) {
-                put_dbg(a.dbg, a.dbg64, (int64_t)cell * a.dbg_stride + K,
-                        reset || !DUMP ? __builtin_nan("") : hsum[1][0][sl] + hsum[1][1][sl]);
-                put_dbg(a.dbg, a.dbg64, (int64_t)cell * a.dbg_stride + K + 1,
-                        reset || !DUMP ? __builtin_nan("") : hsum[2][0][sl] + hsum[2][1][sl]);
+            if (rs) my_cv = (int)(philox(ws.seed, i, 0u, a.rs_step, kRSplit, 0u).w[0] >> 31);
+            if ((g & 1) == 0) {
+                a.cs_new[i] = (uint8_t)my_sv;
+                if (rs) ws.rbits[i] = (uint8_t)my_cv;
+                if (SPLITQ) ws.lpsub[i] = reset ? 0.0 : sub_logp(dd, my_sv);
+                if (a.dbg && K + 2 <= a.dbg_stride) {
+                    put_dbg(a.dbg, a.dbg64, (int64_t)i * a.dbg_stride + K,
+                            reset || !DUMP ? __builtin_nan("") : (md ? s0[1] : s0[0]));
+                    put_dbg(a.dbg, a.dbg64, (int64_t)i * a.dbg_stride + K + 1,
+                            reset || !DUMP ? __builtin_nan("") : (md ? s1[1] : s1[0]));
+                }
             }
         }
-        s_sub[sl] = (int8_t)sv;
-        s_coin[sl] = (uint8_t)cv;
     }
-    __syncthreads();
-    // tail entries of the cells of L: every other one per half
-    if (stay) {
-        const int sv = s_sub[sl], cv = s_coin[sl];
-        const int64_t tb = ws.lay_toff[slot], te = ws.lay_toff[slot + 1];
+    // both cells' labels on all four lanes of the row
+    int sv[2], cv[2];
+    {
+        const int mine = (my_sv + 1) | (my_cv << 2);
+        const int c0 = __shfl(mine, r), c1 = __shfl(mine, 32 + r);
+        sv[0] = (c0 & 3) - 1;
+        cv[0] = c0 >> 2;
+        sv[1] = (c1 & 3) - 1;
+        cv[1] = c1 >> 2;
+    }
+    // the wavefront's cells per statistics row (sub-cluster 0, 1, coin 0, 1)
+    uint32_t rc[4];
+#pragma unroll
+    for (int row = 0; row < 4; ++row) {
+        const bool on = row < 2 ? my_sv == row : rs && my_sv >= 0 && my_cv == row - 2;
+        rc[row] = (uint32_t)__popcll(__ballot((g & 1) == 0 && on));
+    }
+    if (lane == 0) {
+        if (rc[0]) atomicAdd(&ncnt[0], rc[0]);
+        if (rc[1]) atomicAdd(&ncnt[1], rc[1]);
+        if (rs && rc[2]) atomicAdd(&ncnt2[0], rc[2]);
+        if (rs && rc[3]) atomicAdd(&ncnt2[1], rc[3]);
+    }
+
+    // 3. statistics.  Operand byte e of lane group g stands for the
+    // wavefront's cell 16 (e >> 2) + 4 g + (e & 3), in both operands of the
+    // statistics product (the matrix cores pair the bytes of A and B by lane
+    // group and byte alike).  Mask (A): row r of that cell.
+    long amask;
+    {
+        const int code = (sv[0] + 1) | ((sv[1] + 1) << 2) | (cv[0] << 4) | (cv[1] << 5);
+        uint64_t mk = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int cd = __shfl(code, 4 * g + i);
+#pragma unroll
+            for (int m = 0; m < 2; ++m) {
+                const int s = ((cd >> (2 * m)) & 3) - 1, c = (cd >> (4 + m)) & 1;
+                const bool on = r < 2 ? s == r : r < 4 && rs && s >= 0 && c == r - 2;
+                if (on) mk |= (uint64_t)1 << (8 * (4 * m + i));
+            }
+        }
+        amask = (long)mk;
+    }
+    // selection (B) of place 16 h + r of a k-step: byte (16 h + r) & 7 of lane group (16 h + r) >> 3
+    long sel[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int q = 16 * h + r;
+        sel[h] = g == (q >> 3) ? (long)((uint64_t)1 << (8 * (q & 7))) : 0;
+    }
+    {
+        const int rc128[4] = {128 * (int)rc[0], 128 * (int)rc[1], 128 * (int)rc[2], 128 * (int)rc[3]};
         if (lhist) {
-            uint32_t* hs = thist + sv * G;
-            uint32_t* hc = thist + (2 + cv) * G;
-            for (int64_t e = tb + h; e < te; e += 2) {
+            if (rs) chunk_stats<4, true>(av, D, amask, sel, rc128, s_gene, thist, G, g, r, nullptr, nullptr);
+            else chunk_stats<2, true>(av, D, amask, sel, rc128, s_gene, thist, G, g, r, nullptr, nullptr);
+        } else {
+            unsigned long long* srow = ws.ssub + (int64_t)(2 * L) * G;
+            unsigned long long* crow = rs ? ws.rssub + (int64_t)(2 * L) * G : nullptr;
+            if (rs) chunk_stats<4, false>(av, D, amask, sel, rc128, s_gene, nullptr, G, g, r, srow, crow);
+            else chunk_stats<2, false>(av, D, amask, sel, rc128, s_gene, nullptr, G, g, r, srow, crow);
+        }
+    }
+    // tail entries of the cells of L, split over the cell's four lanes
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+        if (!stay[m]) continue;
+        if (lhist) {
+            uint32_t* hs = thist + sv[m] * G;
+            uint32_t* hc = thist + (2 + cv[m]) * G;
+            if (en0[m]) {
+                atomicAdd(&hs[en0[m] & 0xFFFFu], en0[m] >> 16);
+                if (rs) atomicAdd(&hc[en0[m] & 0xFFFFu], en0[m] >> 16);
+            }
+            for (int64_t e = tb[m] + g + 4; e < te[m]; e += 4) {
                 const uint32_t en = ws.lay_tail[e];
                 atomicAdd(&hs[en & 0xFFFFu], en >> 16);
                 if (rs) atomicAdd(&hc[en & 0xFFFFu], en >> 16);
             }
         } else {
-            unsigned long long* srow = ws.ssub + (int64_t)(2 * L + sv) * G;
-            unsigned long long* crow = rs ? ws.rssub + (int64_t)(2 * L + cv) * G : nullptr;
-            for (int64_t e = tb + h; e < te; e += 2) {
+            unsigned long long* srow = ws.ssub + (int64_t)(2 * L + sv[m]) * G;
+            unsigned long long* crow = rs ? ws.rssub + (int64_t)(2 * L + cv[m]) * G : nullptr;
+            for (int64_t e = tb[m] + g; e < te[m]; e += 4) {
                 const uint32_t en = ws.lay_tail[e];
                 const unsigned long long x = en >> 16;
                 atomicAdd(&srow[en & 0xFFFFu], x);
@@ -238,84 +407,8 @@ __global__ void __launch_bounds__(kLsThreads) k_lay_sub(Ws ws, SubArgs a)
             }
         }
     }
-    // 3. dense statistics on the matrix cores.  Wavefront w takes the genes of
-    // column tile w & 3 against cells 128 (w >> 2) .. + 127 (four k-steps of
-    // 32); the mask rows (A operand: lane l holds row l % 16 for cells
-    // 8 (l / 16) .. + 7 of a k-step) are fixed for the block.
-    const int nt = wave & 3, kh = wave >> 2;
-    bf16x8_t am[4];
-#pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
-        uint16_t m16[8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int c = 128 * kh + 32 * ks + 8 * (lane >> 4) + e;
-            const int m = lane & 15;
-            const int sv = s_sub[c];
-            bool on = false;
-            if (m < 2) on = sv == m;
-            else if (m < 4) on = rs && sv >= 0 && (int)s_coin[c] == m - 2;
-            m16[e] = on ? (uint16_t)0x3F80u : (uint16_t)0u;   // BF16 1.0 or 0
-        }
-        __builtin_memcpy(&am[ks], m16, sizeof(m16));
-    }
-    // B operand: lane l holds gene 16 nt + l % 16 for cells 8 (l / 16) .. + 7
-    // of a k-step.  In LDS the chunk keeps its fragment order (16-byte piece
-    // 64 rt + 16 q + r: cell 16 rt + r, places 8 q .. + 7 and 32 + 8 q .. + 7)
-    // except that r is stored as r ^ swz(q, rt, r >> 3): the eight pieces a
-    // lane reads, and the lanes of one read, then fall on distinct banks.
-    const int g = 16 * nt + (lane & 15);
-    const int qg = (g >> 3) & 3;
-    const uint32_t gbyte = (uint32_t)(16 * qg) * 16 + (uint32_t)(g >> 5) * 8 + (uint32_t)(g & 7);
-    const int swz_l = lane_swizzle(qg, lane >> 5, (lane >> 4) & 1);   // (rt & 1, r >> 3 of this lane's cells)
-    const uint16_t* gene_of = ws.lay_gene + (int64_t)L * kPlaces;
-#pragma unroll 1
-    for (int j = 0; j < D; ++j) {
-        __syncthreads();                       // the previous chunk's readers are done
-        *reinterpret_cast<uint4*>(chunk + w_off0) = rv[0][0];
-        *reinterpret_cast<uint4*>(chunk + w_off1) = rv[0][1];
-        // rotate the chunks so that the one just stored is dropped (constant indices only)
-#pragma unroll
-        for (int jj = 0; jj + 1 < kLayDmax; ++jj) {
-            rv[jj][0] = rv[jj + 1][0];
-            rv[jj][1] = rv[jj + 1][1];
-        }
-        __syncthreads();
-        floatx4_t acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-            const int c0 = 128 * kh + 32 * ks + 8 * (lane >> 4);
-            const uint8_t* src = chunk + (uint32_t)((c0 >> 4) * 64 + (c0 & 15)) * 16 + gbyte;
-            uint32_t w0 = 0, w1 = 0;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                w0 |= (uint32_t)src[16 * (e ^ swz_l)] << (8 * e);
-                w1 |= (uint32_t)src[16 * ((e + 4) ^ swz_l)] << (8 * e);
-            }
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[ks], bytes_bf16(w0, w1), acc, 0, 0, 0);
-        }
-        // rows 0 .. 3 of the tile are in lanes 0 .. 15, row i in acc[i]
-        if (lane < 16)
-#pragma unroll
-            for (int i = 0; i < kPartRows; ++i) psum[kh][i][16 * nt + lane] = acc[i];
-        __syncthreads();
-        if (t < rows * kBlkGenes) {
-            const int r = t / kBlkGenes, gg = t % kBlkGenes;
-            const uint32_t v = (uint32_t)(psum[0][r][gg] + psum[1][r][gg]);
-            if (v) {
-                const int u = gene_of[j * kBlkGenes + gg];
-                if (lhist) {
-                    atomicAdd(&thist[r * G + u], v);
-                } else {
-                    unsigned long long* dst = r < 2 ? ws.ssub + (int64_t)(2 * L + r) * G + u
-                                                    : ws.rssub + (int64_t)(2 * L + r - 2) * G + u;
-                    atomicAdd(dst, (unsigned long long)v);
-                }
-            }
-        }
-    }
+    __syncthreads();
     if (lhist) {
-        __syncthreads();
         uint32_t* part = ws.lay_part + (int64_t)b * ws.lay_pw;
         for (int q = t; q < rows * G; q += kLsThreads) part[q] = thist[q];
     }
@@ -410,10 +503,11 @@ __global__ void __launch_bounds__(256) k_mov_sub(Ws ws, SubArgs a)
 // The blocks' histograms into the statistics, in two passes without atomics.
 // The blocks of each layout cluster L are consecutive, from lay_bbeg[L]; they
 // are cut into spans of kRedSpan blocks, lay_sbeg[L] spans before L's first.
-// k_lay_span: workgroup x sums span x's histograms into span_part[x];
+// k_lay_span: workgroup (x, y) sums words 512 y .. + 511 of span x's
+// histograms into span_part[x], two adjacent words per thread;
 // k_lay_reduce: entry (r, u) of cluster L, the sum over L's spans, added to
 // the statistics by the one thread that owns it.
-__global__ void __launch_bounds__(kLsThreads) k_lay_span(Ws ws, int rows)
+__global__ void __launch_bounds__(256) k_lay_span(Ws ws, int rows)
 {
     const int KL = ws.st->lay_K;
     const int x = blockIdx.x;
@@ -430,13 +524,17 @@ __global__ void __launch_bounds__(kLsThreads) k_lay_span(Ws ws, int rows)
     const int64_t pw = ws.lay_pw;
     const uint32_t* in = ws.lay_part + (int64_t)b0 * pw;
     uint32_t* out = ws.span_part + (int64_t)x * pw;
-    const int n = rows * ws.G;
-    for (int q = threadIdx.x; q < n; q += kLsThreads) {
-        uint32_t acc = 0;              // at most kRedSpan x 256 cells x 65535 < 2^32
+    const int n = rows * ws.G;         // even, as is pw
+    const int q = 2 * (blockIdx.y * 256 + threadIdx.x);
+    if (q >= n) return;
+    uint2 acc = make_uint2(0u, 0u);    // at most kRedSpan x 256 cells x 65535 < 2^32
 #pragma unroll 8
-        for (int i = 0; i < nb; ++i) acc += in[(int64_t)i * pw + q];
-        out[q] = acc;
+    for (int i = 0; i < nb; ++i) {
+        const uint2 v = *reinterpret_cast<const uint2*>(in + (int64_t)i * pw + q);
+        acc.x += v.x;
+        acc.y += v.y;
     }
+    *reinterpret_cast<uint2*>(out + q) = acc;
 }
 
 __global__ void __launch_bounds__(256) k_lay_reduce(Ws ws, int rows)
@@ -487,8 +585,8 @@ void launch_lay_sub(const Ws& ws, const SubArgs& a, hipStream_t s)
     hipLaunchKernelGGL(mov_sub_kernel(dump, split_q), dim3((unsigned)mb), dim3(kMovGroups * kMovLanes), 0, s, ws, a);
     const int rows = a.rsplit ? 4 : 2;
     if (rows * ws.G <= ws.lay_pw) {
-        hipLaunchKernelGGL(k_lay_span, dim3((unsigned)lay_spans(ws.nblk_cap, ws.k_max)), dim3(kLsThreads), 0, s, ws,
-                           rows);
+        hipLaunchKernelGGL(k_lay_span, dim3((unsigned)lay_spans(ws.nblk_cap, ws.k_max), (unsigned)((rows * ws.G + 511) / 512)),
+                           dim3(256), 0, s, ws, rows);
         hipLaunchKernelGGL(k_lay_reduce, dim3((unsigned)((rows * ws.G + 255) / 256), (unsigned)ws.k_max), dim3(256), 0,
                            s, ws, rows);
     }

@@ -43,7 +43,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
 struct Layout {
     size_t ent, roff, tiles, c0, c1, cs0, cs1, st, reset, nsub, ssub, beta, lgbeta, logpi, lt64, lc32, ls32, lhi, llo,
-        lgrise, lpsub, qsub, rbits, rssub, rnsub, refine, perm, srow, grp_cnt, grp_off, grp_cur, nsub_prev, lay_kc,
+        lgrise, subdd, qsub, rbits, rssub, rnsub, refine, perm, srow, grp_cnt, grp_off, grp_cur, nsub_prev, lay_kc,
         lay_pbeg, lay_pcnt, lay_cell, lay_doff, lay_toff, lay_dense, lay_tail, lay_nnz, lay_rank, lay_gene, lay_bhi,
         lay_blo, lay_lim, lay_dE, lay_dS, lay_dfull, lay_sw, lay_part, span_part, lay_bbeg, lay_sbeg, mov, relab_c, relab_s, sm_logr, sm_acc, mkey, mlist, dm_k, eb_tmp, rd_part, sm_part, total;
 };
@@ -96,7 +96,7 @@ Layout plan(int64_t N, int32_t G, int64_t nnz, int32_t k_max, int32_t precision,
     L.beta = take(8 * (size_t)G);
     L.lgbeta = take(8 * (size_t)G);
     L.lgrise = take(8 * (size_t)kRiseTab * (size_t)G);
-    L.lpsub = take((flags & kFlagSplitQ) ? 8 * (size_t)N : 0);
+    L.subdd = take((flags & kFlagSplitQ) ? 8 * (size_t)N : 0);
     L.qsub = take(8 * (size_t)k_max);
     const bool rsplit = (flags & kFlagRandomSplit) != 0;
     L.rbits = take(rsplit ? (size_t)N : 0);
@@ -254,7 +254,8 @@ int32_t k_hint(const dpmm_ctx* ctx)
 dpmm_status recompute_stats(dpmm_ctx* ctx)
 {
     // no sweep has drawn these labels: no proposal term yet
-    if (ctx->ws.lpsub) HIP_TRY(hipMemsetAsync(ctx->ws.lpsub, 0, 8 * (size_t)ctx->N, ctx->stream));
+    // all NaN (no proposal term yet)
+    if (ctx->ws.subdd) HIP_TRY(hipMemsetAsync(ctx->ws.subdd, 0xFF, 8 * (size_t)ctx->N, ctx->stream));
     launch_stats(ctx->ws, ctx->c[ctx->cur], ctx->cs[ctx->cur], ctx->stream);
     launch_compact(ctx->ws, 0, ctx->stream);
     launch_relabel(ctx->ws, ctx->c[ctx->cur], ctx->cs[ctx->cur], ctx->stream);
@@ -336,7 +337,7 @@ dpmm_status init_impl(const dpmm_csr* csr, const dpmm_params* params, void* work
     ws.lgbeta = (double*)(base + L.lgbeta);
     ws.lgrise = (double*)(base + L.lgrise);
     ws.flags = params->flags;
-    ws.lpsub = (params->flags & kFlagSplitQ) ? (double*)(base + L.lpsub) : nullptr;
+    ws.subdd = (params->flags & kFlagSplitQ) ? (double*)(base + L.subdd) : nullptr;
     ws.qsub = (double*)(base + L.qsub);
     const bool rsplit = (params->flags & kFlagRandomSplit) != 0;
     ws.rbits = rsplit ? (uint8_t*)(base + L.rbits) : nullptr;
@@ -631,7 +632,7 @@ dpmm_status dpmm_split_merge(dpmm_ctx* ctx)
         launch_merge_ratios(ctx->ws, ctx->stream);
         launch_sm_decide(ctx->ws, 1, step, ctx->stream);
     } else if (pass == 0) {
-        launch_split_ratios(ctx->ws, ctx->c[ctx->cur], ctx->stream);
+        launch_split_ratios(ctx->ws, ctx->c[ctx->cur], ctx->cs[ctx->cur], ctx->stream);
         launch_sm_decide(ctx->ws, 0, step, ctx->stream);
     } else {
         launch_random_split(ctx->ws, ctx->c[ctx->cur], ctx->cs[ctx->cur], step, ready, ctx->stream);

@@ -312,8 +312,9 @@ struct Ws {
     int32_t lay_cols;      // column rows per layout cluster in lay_bhi / lay_blo
     int32_t sub_cells;     // sorted cells per workgroup of the sub-cluster/statistics pass
     uint32_t flags;        // kFlagSplitQ: the split ratio carries -sum log p(cbar_i)
-    double* lpsub;         // [N] log p(cbar_i) of eq. 8 in the last sweep (with kFlagSplitQ only)
-    double* qsub;          // [k_max] sum of lpsub over the cells of each cluster (split pass)
+    double* subdd;         // [N] the score difference dd of the cell's draw of eq. 8 in the last sweep, NaN
+                           // for a cell of a reset cluster (with kFlagSplitQ only; log p(cbar_i) = sub_logp)
+    double* qsub;          // [k_max] sum of log p(cbar_i) over the cells of each cluster (split pass)
     uint8_t* rbits;        // [N] coins of the last random-split pass (with kFlagRandomSplit)
     unsigned long long* rssub;   // [2 k_max G] statistics of the coin halves
     unsigned long long* rnsub;   // [2 k_max] sizes of the coin halves

@@ -86,7 +86,7 @@ void launch_dump_scores(const Ws& ws, const int32_t* c, const int32_t* cells, in
 
 // splitmerge.hip
 void launch_lgamma_beta(const Ws& ws, hipStream_t s);   // lgbeta = lgamma(beta), wherever beta changes
-void launch_split_ratios(const Ws& ws, const int32_t* c, hipStream_t s);
+void launch_split_ratios(const Ws& ws, const int32_t* c, const uint8_t* cs, hipStream_t s);
 void launch_random_split(const Ws& ws, const int32_t* c, uint8_t* cs, uint32_t step, bool ready, hipStream_t s);
 void launch_merge_ratios(const Ws& ws, hipStream_t s);
 void launch_sm_decide(const Ws& ws, int merge_pass, uint32_t step, hipStream_t s);

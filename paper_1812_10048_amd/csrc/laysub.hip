@@ -67,27 +67,39 @@ __device__ inline long kstep(const uint4& v, int s)
     return s ? (long)((uint64_t)v.z | ((uint64_t)v.w << 32)) : (long)((uint64_t)v.x | ((uint64_t)v.y << 32));
 }
 
+// A lane's fragment of row tile 2 w + m of chunk j (16 bytes)
+__device__ inline uint4 frag(const uint8_t* dense, uint32_t doff, int j, int m)
+{
+    return *reinterpret_cast<const uint4*>(dense + (doff + (uint32_t)(j * kDenseChunkBytes + m * 1024)));
+}
+
 // The statistics of a wavefront's 32 cells over the block's dense chunks
-// (step 3 of k_lay_sub): per chunk, eight selection products bring the counts
-// of each place to the lanes of its column, four products with the 0/1 rows
-// sum them over the cells, and lane group 0 adds rows 0 .. ROWS - 1 to the
-// LDS histogram (LHIST) or to the statistics rows srow (sub-clusters) and
-// crow (coins).
+// (step 3 of k_lay_sub), chunk by chunk with the next chunk's fragments in
+// flight: eight selection products bring the counts of each place to the
+// lanes of its column, four products with the 0/1 rows sum them over the
+// cells, and lane group 0 adds rows 0 .. ROWS - 1 to the LDS histogram
+// (LHIST) or to the statistics rows srow (sub-clusters) and crow (coins).
 template <int ROWS, bool LHIST>
-__device__ inline void chunk_stats(const uint4 (&av)[kLayDmax][2], int D, long amask, const long (&sel)[2],
+__device__ inline void chunk_stats(const uint8_t* dense, uint32_t doff, int D, long amask, const long (&sel)[2],
                                    const int (&rc128)[4], const uint16_t* s_gene, uint32_t* thist, int G, int g, int r,
                                    unsigned long long* srow, unsigned long long* crow)
 {
+    if (D <= 0) return;
     const intx4_t zero = {0, 0, 0, 0};
-#pragma unroll
-    for (int j = 0; j < kLayDmax; ++j) {
-        if (j >= D) break;
+    uint4 f0 = frag(dense, doff, 0, 0), f1 = frag(dense, doff, 0, 1);
+#pragma unroll 1
+    for (int j = 0; j < D; ++j) {
+        uint4 n0 = f0, n1 = f1;
+        if (j + 1 < D) {
+            n0 = frag(dense, doff, j + 1, 0);
+            n1 = frag(dense, doff, j + 1, 1);
+        }
         // lane (r, g) gets the counts of place 16 nt + r for cells 16 m + 4 g + i in word i
         intx4_t o[4];
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) {
-            const intx4_t c0 = __builtin_amdgcn_mfma_i32_16x16x32_i8(kstep(av[j][0], nt >> 1), sel[nt & 1], zero, 0, 0, 0);
-            const intx4_t c1 = __builtin_amdgcn_mfma_i32_16x16x32_i8(kstep(av[j][1], nt >> 1), sel[nt & 1], zero, 0, 0, 0);
+            const intx4_t c0 = __builtin_amdgcn_mfma_i32_16x16x32_i8(kstep(f0, nt >> 1), sel[nt & 1], zero, 0, 0, 0);
+            const intx4_t c1 = __builtin_amdgcn_mfma_i32_16x16x32_i8(kstep(f1, nt >> 1), sel[nt & 1], zero, 0, 0, 0);
             const uint64_t xb = ((uint64_t)low_bytes(c0) | ((uint64_t)low_bytes(c1) << 32)) ^ (uint64_t)kOffset8;
             o[nt] = __builtin_amdgcn_mfma_i32_16x16x32_i8(amask, (long)xb, zero, 0, 0, 0);
         }
@@ -104,11 +116,13 @@ __device__ inline void chunk_stats(const uint4 (&av)[kLayDmax][2], int D, long a
                 }
             }
         }
+        f0 = n0;
+        f1 = n1;
     }
 }
 
 template <bool DUMP, bool SPLITQ>
-__global__ void __launch_bounds__(kLsThreads) __attribute__((amdgpu_waves_per_eu(DUMP ? 2 : 4)))
+__global__ void __launch_bounds__(kLsThreads) __attribute__((amdgpu_waves_per_eu(DUMP ? 2 : 8)))
 k_lay_sub(Ws ws, SubArgs a)
 {
     __shared__ double dl[DUMP ? kPlaces : 1];              // delta in L's gene order (dump)
@@ -139,13 +153,13 @@ k_lay_sub(Ws ws, SubArgs a)
     // the lane's fragments of row tiles 2w, 2w + 1: + j chunk + m 1 KiB
     const uint8_t* dense = ws.lay_dense + d0 * kDenseChunkBytes;   // uniform base
     const uint32_t doff = (uint32_t)((wave * 2) * 64 + lane) * 16;
-    uint4 av[kLayDmax][2];
-#pragma unroll
-    for (int j = 0; j < kLayDmax; ++j)
-#pragma unroll
-        for (int m = 0; m < 2; ++m)
-            av[j][m] = j < D ? *reinterpret_cast<const uint4*>(dense + (doff + (uint32_t)(j * kDenseChunkBytes + m * 1024)))
-                             : make_uint4(0, 0, 0, 0);
+    // chunk 0 in flight while the block stages (a block has at least one chunk
+    // or none of its cells has a dense byte; chunk 0 of an empty block is never read)
+    uint4 f0 = make_uint4(0, 0, 0, 0), f1 = f0;
+    if (D > 0) {
+        f0 = frag(dense, doff, 0, 0);
+        f1 = frag(dense, doff, 0, 1);
+    }
     // the lane's cells, their tail ranges and old labels, and (before the
     // barrier, so that the chain of loads overlaps the staging) the lane's
     // first tail entry of each with its difference
@@ -196,9 +210,9 @@ k_lay_sub(Ws ws, SubArgs a)
     if (DUMP && !reset) {
         // on the vector ALUs (with the two rows themselves); byte 4p + c of a
         // fragment is place 32 (p >> 1) + 8 g + 4 (p & 1) + c
-#pragma unroll
-        for (int j = 0; j < kLayDmax; ++j) {
-            if (j >= D) break;
+#pragma unroll 1
+        for (int j = 0; j < D; ++j) {
+            const uint4 v[2] = {frag(dense, doff, j, 0), frag(dense, doff, j, 1)};
 #pragma unroll
             for (int p = 0; p < 4; ++p)
 #pragma unroll
@@ -207,7 +221,7 @@ k_lay_sub(Ws ws, SubArgs a)
                     const double dv = dl[place];
 #pragma unroll
                     for (int m = 0; m < 2; ++m) {
-                        const uint32_t w = p == 0 ? av[j][m].x : p == 1 ? av[j][m].y : p == 2 ? av[j][m].z : av[j][m].w;
+                        const uint32_t w = p == 0 ? v[m].x : p == 1 ? v[m].y : p == 2 ? v[m].z : v[m].w;
                         const double x = (double)((w >> (8 * c)) & 0xFFu);
                         df[m] = fma(x, dv, df[m]);
                         s0[m] = fma(x, tl0[place], s0[m]);
@@ -227,17 +241,22 @@ k_lay_sub(Ws ws, SubArgs a)
         const intx4_t zero = {0, 0, 0, 0};
         intx4_t dacc[2] = {zero, zero};
         const int kr = r < 8 ? r : 7;
-#pragma unroll
-        for (int j = 0; j < kLayDmax; ++j) {
-            if (j >= D) break;
-            __builtin_amdgcn_sched_barrier(0);  // (one chunk's digits in registers at a time)
+        // chunk by chunk, the next chunk's fragments in flight
+#pragma unroll 1
+        for (int j = 0; j < D; ++j) {
+            uint4 n0 = f0, n1 = f1;
+            if (j + 1 < D) {
+                n0 = frag(dense, doff, j + 1, 0);
+                n1 = frag(dense, doff, j + 1, 1);
+            }
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
                 const long dig = (long)s_lim[((j * 2 + s) * 8 + kr) * 4 + g];
-#pragma unroll
-                for (int m = 0; m < 2; ++m)
-                    dacc[m] = __builtin_amdgcn_mfma_i32_16x16x32_i8(dig, kstep(av[j][m], s) ^ kOffset8, dacc[m], 0, 0, 0);
+                dacc[0] = __builtin_amdgcn_mfma_i32_16x16x32_i8(dig, kstep(f0, s) ^ kOffset8, dacc[0], 0, 0, 0);
+                dacc[1] = __builtin_amdgcn_mfma_i32_16x16x32_i8(dig, kstep(f1, s) ^ kOffset8, dacc[1], 0, 0, 0);
             }
+            f0 = n0;
+            f1 = n1;
         }
         const int E = ws.lay_dE[L];
         const int32_t* S = ws.lay_dS + ((int64_t)L * (kLayDmax + 1) + D) * 8;
@@ -307,7 +326,7 @@ k_lay_sub(Ws ws, SubArgs a)
             if ((g & 1) == 0) {
                 a.cs_new[i] = (uint8_t)my_sv;
                 if (rs) ws.rbits[i] = (uint8_t)my_cv;
-                if (SPLITQ) ws.lpsub[i] = reset ? 0.0 : sub_logp(dd, my_sv);
+                if (SPLITQ) ws.subdd[i] = reset ? __builtin_nan("") : dd;
                 if (a.dbg && K + 2 <= a.dbg_stride) {
                     put_dbg(a.dbg, a.dbg64, (int64_t)i * a.dbg_stride + K,
                             reset || !DUMP ? __builtin_nan("") : (md ? s0[1] : s0[0]));
@@ -371,13 +390,13 @@ k_lay_sub(Ws ws, SubArgs a)
     {
         const int rc128[4] = {128 * (int)rc[0], 128 * (int)rc[1], 128 * (int)rc[2], 128 * (int)rc[3]};
         if (lhist) {
-            if (rs) chunk_stats<4, true>(av, D, amask, sel, rc128, s_gene, thist, G, g, r, nullptr, nullptr);
-            else chunk_stats<2, true>(av, D, amask, sel, rc128, s_gene, thist, G, g, r, nullptr, nullptr);
+            if (rs) chunk_stats<4, true>(dense, doff, D, amask, sel, rc128, s_gene, thist, G, g, r, nullptr, nullptr);
+            else chunk_stats<2, true>(dense, doff, D, amask, sel, rc128, s_gene, thist, G, g, r, nullptr, nullptr);
         } else {
             unsigned long long* srow = ws.ssub + (int64_t)(2 * L) * G;
             unsigned long long* crow = rs ? ws.rssub + (int64_t)(2 * L) * G : nullptr;
-            if (rs) chunk_stats<4, false>(av, D, amask, sel, rc128, s_gene, nullptr, G, g, r, srow, crow);
-            else chunk_stats<2, false>(av, D, amask, sel, rc128, s_gene, nullptr, G, g, r, srow, crow);
+            if (rs) chunk_stats<4, false>(dense, doff, D, amask, sel, rc128, s_gene, nullptr, G, g, r, srow, crow);
+            else chunk_stats<2, false>(dense, doff, D, amask, sel, rc128, s_gene, nullptr, G, g, r, srow, crow);
         }
     }
     // tail entries of the cells of L, split over the cell's four lanes
@@ -491,7 +510,7 @@ __global__ void __launch_bounds__(256) k_mov_sub(Ws ws, SubArgs a)
                 ws.rbits[i] = (uint8_t)coin;
                 atomicAdd(&ws.rnsub[2 * k + coin], 1ull);
             }
-            if (SPLITQ) ws.lpsub[i] = reset ? 0.0 : sub_logp(dd, sub);
+            if (SPLITQ) ws.subdd[i] = reset ? __builtin_nan("") : dd;
             if (a.dbg && K + 2 <= a.dbg_stride) {
                 put_dbg(a.dbg, a.dbg64, (int64_t)i * a.dbg_stride + K, reset || !DUMP ? __builtin_nan("") : s0);
                 put_dbg(a.dbg, a.dbg64, (int64_t)i * a.dbg_stride + K + 1, reset || !DUMP ? __builtin_nan("") : s1);
@@ -578,7 +597,7 @@ void launch_lay_sub(const Ws& ws, const SubArgs& a, hipStream_t s)
         launch_zero(ws.rssub, sizeof(unsigned long long) * 2 * (size_t)ws.k_max * (size_t)ws.G, s);
         launch_zero(ws.rnsub, sizeof(unsigned long long) * 2 * (size_t)ws.k_max, s);
     }
-    const bool dump = a.dbg != nullptr, split_q = ws.lpsub != nullptr;
+    const bool dump = a.dbg != nullptr, split_q = ws.subdd != nullptr;
     hipLaunchKernelGGL(lay_sub_kernel(dump, split_q), dim3((unsigned)ws.nblk_cap), dim3(kLsThreads), 0, s, ws, a);
     int64_t mb = (ws.N + kMovGroups - 1) / kMovGroups;
     if (mb > 1024) mb = 1024;

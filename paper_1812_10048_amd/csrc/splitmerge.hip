@@ -337,10 +337,12 @@ __global__ void __launch_bounds__(kMergeThreads) k_merge_ratios(Ws ws)
 }
 
 // Q_k = sum over the cells now in cluster k of log p(cbar_i) from the last
-// sweep (the split proposal term of Section 2.3): per-workgroup LDS sums, then
-// one FP64 atomic per cluster.
+// sweep (the split proposal term of Section 2.3), formed here from the score
+// difference of each cell's draw and its sub-label (only split passes need
+// it): per-workgroup LDS sums, then one FP64 atomic per cluster.
 constexpr int kQThreads = 256;
-__global__ void __launch_bounds__(kQThreads) k_split_q(Ws ws, const int32_t* __restrict__ c)
+__global__ void __launch_bounds__(kQThreads) k_split_q(Ws ws, const int32_t* __restrict__ c,
+                                                       const uint8_t* __restrict__ cs)
 {
     extern __shared__ double qacc[];     // [K]
     const int K = ws.st->K;
@@ -348,18 +350,21 @@ __global__ void __launch_bounds__(kQThreads) k_split_q(Ws ws, const int32_t* __r
     __syncthreads();
     for (int64_t i = (int64_t)blockIdx.x * kQThreads + threadIdx.x; i < ws.N; i += (int64_t)gridDim.x * kQThreads) {
         const int k = c[i];
-        if (k >= 0 && k < K) atomicAdd(&qacc[k], ws.lpsub[i]);
+        if (k >= 0 && k < K) {
+            const double dd = ws.subdd[i];
+            if (!isnan(dd)) atomicAdd(&qacc[k], sub_logp(dd, cs[i] & 1));
+        }
     }
     __syncthreads();
     for (int k = threadIdx.x; k < K; k += kQThreads)
         if (qacc[k] != 0.0) atomicAdd(&ws.qsub[k], qacc[k]);
 }
 
-void launch_split_ratios(const Ws& ws, const int32_t* c, hipStream_t s)
+void launch_split_ratios(const Ws& ws, const int32_t* c, const uint8_t* cs, hipStream_t s)
 {
     if (ws.flags & kFlagSplitQ) {
         launch_zero(ws.qsub, sizeof(double) * (size_t)ws.k_max, s);
-        hipLaunchKernelGGL(k_split_q, dim3(256), dim3(kQThreads), sizeof(double) * (size_t)ws.k_max, s, ws, c);
+        hipLaunchKernelGGL(k_split_q, dim3(256), dim3(kQThreads), sizeof(double) * (size_t)ws.k_max, s, ws, c, cs);
     }
     launch_sm_pair(ws, 0, s);
 }

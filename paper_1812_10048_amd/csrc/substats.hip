@@ -215,7 +215,7 @@ __global__ void __launch_bounds__(kSubThreads) __attribute__((amdgpu_waves_per_e
                     if constexpr (SPLITQ) {
                         // log p(cbar_i) of eq. 8 for the split proposal term: a
                         // two-way softmax of the scores, whose difference is dd
-                        ws.lpsub[i] = reset ? 0.0 : sub_logp(dd, sub);
+                        ws.subdd[i] = reset ? __builtin_nan("") : dd;
                     }
                     if (a.dbg && K + 2 <= a.dbg_stride) {
                         put_dbg(a.dbg, a.dbg64, i * a.dbg_stride + K, reset ? __builtin_nan("") : s0);
@@ -302,7 +302,7 @@ void launch_sub_stats(const Ws& ws, const SubArgs& a, hipStream_t s)
         launch_zero(ws.rssub, sizeof(unsigned long long) * 2 * (size_t)ws.k_max * (size_t)ws.G, s);
         launch_zero(ws.rnsub, sizeof(unsigned long long) * 2 * (size_t)ws.k_max, s);
     }
-    hipLaunchKernelGGL(sub_stats_kernel(ws.G, a.dbg != nullptr, ws.lpsub != nullptr), dim3((unsigned)((ws.N + ws.sub_cells - 1) / ws.sub_cells)), dim3(kSubThreads),
+    hipLaunchKernelGGL(sub_stats_kernel(ws.G, a.dbg != nullptr, ws.subdd != nullptr), dim3((unsigned)((ws.N + ws.sub_cells - 1) / ws.sub_cells)), dim3(kSubThreads),
                        sub_stats_lds(ws.G, a.rsplit != 0), s, ws, a);
 }
 

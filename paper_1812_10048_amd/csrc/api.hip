@@ -45,7 +45,7 @@ struct Layout {
     size_t ent, roff, tiles, c0, c1, cs0, cs1, st, reset, nsub, ssub, beta, lgbeta, logpi, lt64, lc32, ls32, lhi, llo,
         lgrise, subdd, qsub, rbits, rssub, rnsub, refine, perm, srow, grp_cnt, grp_off, grp_cur, nsub_prev, lay_kc,
         lay_pbeg, lay_pcnt, lay_cell, lay_doff, lay_toff, lay_dense, lay_tail, lay_nnz, lay_rank, lay_gene, lay_bhi,
-        lay_blo, lay_lim, lay_dE, lay_dS, lay_dfull, lay_sw, lay_part, span_part, lay_bbeg, lay_sbeg, mov, relab_c, relab_s, sm_logr, sm_acc, mkey, mlist, dm_k, eb_tmp, rd_part, sm_part, total;
+        lay_blo, lay_lim, lay_dE, lay_dS, lay_dfull, lay_sw, lay_part, lay_bbeg, lay_sbeg, mov, relab_c, relab_s, sm_logr, sm_acc, mkey, mlist, dm_k, eb_tmp, rd_part, sm_part, total;
 };
 
 int32_t num_blocks(int64_t N) { return (int32_t)((N + kBlkCells - 1) / kBlkCells); }
@@ -136,7 +136,6 @@ Layout plan(int64_t N, int32_t G, int64_t nnz, int32_t k_max, int32_t precision,
     L.lay_dfull = take(blocked ? 8 * (size_t)k_max * (size_t)G : 0);
     L.lay_sw = take(blocked ? 8 * (size_t)k_max * 4 : 0);
     L.lay_part = take(blocked ? 4 * (size_t)nbc * (size_t)lay_hist_words(G, flags) : 0);
-    L.span_part = take(blocked ? 4 * (size_t)lay_spans((int32_t)nbc, k_max) * (size_t)lay_hist_words(G, flags) : 0);
     L.lay_bbeg = take(blocked ? 4 * (size_t)(k_max + 1) : 0);
     L.lay_sbeg = take(blocked ? 4 * (size_t)(k_max + 1) : 0);
     L.mov = take(blocked ? 4 * (size_t)N : 0);
@@ -376,7 +375,6 @@ dpmm_status init_impl(const dpmm_csr* csr, const dpmm_params* params, void* work
     ws.lay_sw = (double*)(base + L.lay_sw);
     ws.lay_part = (uint32_t*)(base + L.lay_part);
     ws.mov = (uint32_t*)(base + L.mov);
-    ws.span_part = (uint32_t*)(base + L.span_part);
     ws.lay_pw = params->precision == DPMM_SPLIT_BF16 ? lay_hist_words(csr->n_genes, params->flags) : 0;
     ws.lay_bbeg = (int32_t*)(base + L.lay_bbeg);
     ws.lay_sbeg = (int32_t*)(base + L.lay_sbeg);

@@ -303,7 +303,6 @@ struct Ws {
     double* lay_dfull;     // [k_max][G] the difference itself, gene-major (tail entries)
     double* lay_sw;        // [k_max][4] the sub-cluster weights of the draw (SubWeights)
     uint32_t* lay_part;    // [nblk_cap][lay_pw] a block's count sums per (sub-cluster | coin, gene)
-    uint32_t* span_part;   // [lay_spans][lay_pw] the same summed over spans of blocks
     int32_t lay_pw;        // rows x G of those histograms (rows 4 with random splits, else 2), 0 past kLsHistWords
     int32_t* lay_bbeg;     // [k_max + 1] first block of each layout cluster
     int32_t* lay_sbeg;     // [k_max + 1] spans (of up to 32 blocks) before each layout cluster's first

@@ -33,10 +33,10 @@
 //      entries (a count above 255 is a tail entry too, and those crowd on a
 //      cluster's top genes).  Each block writes its whole histogram to
 //      lay_part; k_lay_span adds them over spans of consecutive blocks of a
-//      cluster and k_lay_reduce adds a cluster's spans into its statistics.
-//      No atomics reach memory: device-scope 64-bit atomics on a few hot
-//      addresses from every block serialise.  (Past kLsHistWords histogram
-//      words, the sums go to the statistics with atomics instead.)
+//      cluster and adds the span sums to the statistics: device-scope 64-bit
+//      atomics from every cell (or every block) on a cluster's few hot
+//      addresses would serialise.  (Past kLsHistWords histogram words, the
+//      sums go to the statistics with atomics instead.)
 #include "dpmm_common.hpp"
 #include "kernels.hpp"
 
@@ -519,13 +519,12 @@ __global__ void __launch_bounds__(256) k_mov_sub(Ws ws, SubArgs a)
     }
 }
 
-// The blocks' histograms into the statistics, in two passes without atomics.
-// The blocks of each layout cluster L are consecutive, from lay_bbeg[L]; they
-// are cut into spans of kRedSpan blocks, lay_sbeg[L] spans before L's first.
-// k_lay_span: workgroup (x, y) sums words 512 y .. + 511 of span x's
-// histograms into span_part[x], two adjacent words per thread;
-// k_lay_reduce: entry (r, u) of cluster L, the sum over L's spans, added to
-// the statistics by the one thread that owns it.
+// The blocks' histograms into the statistics.  The blocks of each layout
+// cluster L are consecutive, from lay_bbeg[L]; they are cut into spans of
+// kRedSpan blocks, lay_sbeg[L] spans before L's first.  Workgroup (x, y) sums
+// words 512 y .. + 511 of span x's histograms, two adjacent words per thread,
+// and adds each non-zero sum to the statistics with one 64-bit atomic: a few
+// per address and span instead of one per count.
 __global__ void __launch_bounds__(256) k_lay_span(Ws ws, int rows)
 {
     const int KL = ws.st->lay_K;
@@ -538,12 +537,13 @@ __global__ void __launch_bounds__(256) k_lay_span(Ws ws, int rows)
         else hi = mid;
     }
     const int L = lo;
+    if (L >= ws.st->K) return;
     const int b0 = ws.lay_bbeg[L] + (x - ws.lay_sbeg[L]) * kRedSpan;
     const int nb = min(ws.lay_bbeg[L + 1] - b0, kRedSpan);
     const int64_t pw = ws.lay_pw;
     const uint32_t* in = ws.lay_part + (int64_t)b0 * pw;
-    uint32_t* out = ws.span_part + (int64_t)x * pw;
-    const int n = rows * ws.G;         // even, as is pw
+    const int G = ws.G;
+    const int n = rows * G;            // even, as is pw
     const int q = 2 * (blockIdx.y * 256 + threadIdx.x);
     if (q >= n) return;
     uint2 acc = make_uint2(0u, 0u);    // at most kRedSpan x 256 cells x 65535 < 2^32
@@ -553,25 +553,15 @@ __global__ void __launch_bounds__(256) k_lay_span(Ws ws, int rows)
         acc.x += v.x;
         acc.y += v.y;
     }
-    *reinterpret_cast<uint2*>(out + q) = acc;
-}
-
-__global__ void __launch_bounds__(256) k_lay_reduce(Ws ws, int rows)
-{
-    const int L = blockIdx.y;
-    if (L >= ws.st->lay_K || L >= ws.st->K) return;
-    const int G = ws.G;
-    const int q = blockIdx.x * 256 + threadIdx.x;
-    if (q >= rows * G) return;
-    const int x0 = ws.lay_sbeg[L], x1 = ws.lay_sbeg[L + 1];
-    const int64_t pw = ws.lay_pw;
-    unsigned long long acc = 0;
-#pragma unroll 4
-    for (int x = x0; x < x1; ++x) acc += ws.span_part[(int64_t)x * pw + q];
-    if (!acc) return;
-    const int r = q / G, u = q - r * G;
-    if (r < 2) ws.ssub[(int64_t)(2 * L + r) * G + u] += acc;
-    else ws.rssub[(int64_t)(2 * L + r - 2) * G + u] += acc;
+    const uint32_t sums[2] = {acc.x, acc.y};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        if (!sums[h]) continue;
+        const int w = q + h, r = w / G, u = w - r * G;
+        unsigned long long* dst = r < 2 ? ws.ssub + (int64_t)(2 * L + r) * G + u
+                                        : ws.rssub + (int64_t)(2 * L + r - 2) * G + u;
+        atomicAdd(dst, (unsigned long long)sums[h]);
+    }
 }
 
 using LaySubKernel = void (*)(Ws, SubArgs);
@@ -603,12 +593,9 @@ void launch_lay_sub(const Ws& ws, const SubArgs& a, hipStream_t s)
     if (mb > 1024) mb = 1024;
     hipLaunchKernelGGL(mov_sub_kernel(dump, split_q), dim3((unsigned)mb), dim3(kMovGroups * kMovLanes), 0, s, ws, a);
     const int rows = a.rsplit ? 4 : 2;
-    if (rows * ws.G <= ws.lay_pw) {
+    if (rows * ws.G <= ws.lay_pw)
         hipLaunchKernelGGL(k_lay_span, dim3((unsigned)lay_spans(ws.nblk_cap, ws.k_max), (unsigned)((rows * ws.G + 511) / 512)),
                            dim3(256), 0, s, ws, rows);
-        hipLaunchKernelGGL(k_lay_reduce, dim3((unsigned)((rows * ws.G + 255) / 256), (unsigned)ws.k_max), dim3(256), 0,
-                           s, ws, rows);
-    }
 }
 
 }  // namespace dpmm

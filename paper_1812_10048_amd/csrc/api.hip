@@ -53,12 +53,10 @@ int32_t num_blocks(int64_t N) { return (int32_t)((N + kBlkCells - 1) / kBlkCells
 int32_t lay_blocks(int64_t N, int32_t k_max) { return num_blocks(N) + k_max; }
 int32_t lay_cols(int32_t k_max) { return (k_max + 15) / 16 * 16 + kTablePadRows; }
 // words of a block's statistics histogram in the sub-cluster pass over the
-// copy: (sub-cluster 0, 1 [, coin 0, 1]) x G, 0 when that exceeds the LDS
-// histogram (the pass then adds with atomics)
-int32_t lay_hist_words(int32_t G, uint32_t flags)
+// copy: (sub-cluster 0, 1 [, coin 0, 1]) x the places of the dense chunks
+int32_t lay_hist_words(uint32_t flags)
 {
-    const int64_t w = (int64_t)((flags & kFlagRandomSplit) ? 4 : 2) * G;
-    return w <= kLsHistWords ? (int32_t)w : 0;
+    return ((flags & kFlagRandomSplit) ? 4 : 2) * kLayDmax * kBlkGenes;
 }
 // gene chunks of the split-BF16 kernel: an even number, so that its pipeline
 // (two register stages, unrolled by two) has no conditional chunk; the chunks
@@ -135,7 +133,7 @@ Layout plan(int64_t N, int32_t G, int64_t nnz, int32_t k_max, int32_t precision,
     L.lay_dS = take(blocked ? 4 * (size_t)k_max * (kLayDmax + 1) * 8 : 0);
     L.lay_dfull = take(blocked ? 8 * (size_t)k_max * (size_t)G : 0);
     L.lay_sw = take(blocked ? 8 * (size_t)k_max * 4 : 0);
-    L.lay_part = take(blocked ? 4 * (size_t)nbc * (size_t)lay_hist_words(G, flags) : 0);
+    L.lay_part = take(blocked ? 4 * (size_t)nbc * (size_t)lay_hist_words(flags) : 0);
     L.lay_bbeg = take(blocked ? 4 * (size_t)(k_max + 1) : 0);
     L.lay_sbeg = take(blocked ? 4 * (size_t)(k_max + 1) : 0);
     L.mov = take(blocked ? 4 * (size_t)N : 0);
@@ -375,7 +373,7 @@ dpmm_status init_impl(const dpmm_csr* csr, const dpmm_params* params, void* work
     ws.lay_sw = (double*)(base + L.lay_sw);
     ws.lay_part = (uint32_t*)(base + L.lay_part);
     ws.mov = (uint32_t*)(base + L.mov);
-    ws.lay_pw = params->precision == DPMM_SPLIT_BF16 ? lay_hist_words(csr->n_genes, params->flags) : 0;
+    ws.lay_pw = params->precision == DPMM_SPLIT_BF16 ? lay_hist_words(params->flags) : 0;
     ws.lay_bbeg = (int32_t*)(base + L.lay_bbeg);
     ws.lay_sbeg = (int32_t*)(base + L.lay_sbeg);
     ws.nblk_cap = params->precision == DPMM_SPLIT_BF16 ? lay_blocks(csr->n_cells, params->k_max) : 0;

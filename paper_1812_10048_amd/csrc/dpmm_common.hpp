@@ -123,7 +123,6 @@ constexpr uint32_t kFlagNewCluster = 2u;      // ... and of the Gibbs step over 
 constexpr uint32_t kFlagRandomSplit = 4u;     // ... and of the random-split pass
 constexpr int kBlkGenes = 64;
 constexpr int kSpanBlocks = 32;                    // blocks per span of the statistics reduction (laysub.hip)
-constexpr int kLsHistWords = 8192;                 // LDS histogram of a block's statistics: rows x G words up to this
 // spans of the reduction: each cluster's blocks are cut separately
 __host__ __device__ inline int32_t lay_spans(int32_t nblk_cap, int32_t k_max) { return nblk_cap / kSpanBlocks + k_max; }
 
@@ -302,8 +301,8 @@ struct Ws {
     int32_t* lay_dS;       // [k_max][kLayDmax + 1][8] digit sums over the first D chunks
     double* lay_dfull;     // [k_max][G] the difference itself, gene-major (tail entries)
     double* lay_sw;        // [k_max][4] the sub-cluster weights of the draw (SubWeights)
-    uint32_t* lay_part;    // [nblk_cap][lay_pw] a block's count sums per (sub-cluster | coin, gene)
-    int32_t lay_pw;        // rows x G of those histograms (rows 4 with random splits, else 2), 0 past kLsHistWords
+    uint32_t* lay_part;    // [nblk_cap][lay_pw] a block's count sums per (sub-cluster | coin, place of its cluster)
+    int32_t lay_pw;        // rows x kLayDmax kBlkGenes words of those histograms (rows 4 with random splits, else 2)
     int32_t* lay_bbeg;     // [k_max + 1] first block of each layout cluster
     int32_t* lay_sbeg;     // [k_max + 1] spans (of up to 32 blocks) before each layout cluster's first
     uint32_t* mov;         // [N] cells of a block whose new cluster is not the block's (laysub.hip)

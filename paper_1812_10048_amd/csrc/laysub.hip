@@ -46,6 +46,7 @@ typedef __attribute__((__vector_size__(4 * sizeof(int)))) int intx4_t;
 
 constexpr int kLsThreads = 2 * kBlkCells;     // 8 wavefronts of 32 cells
 constexpr int kPlaces = kLayDmax * kBlkGenes;  // places of a cluster's gene order in the dense chunks
+constexpr int kPartRows = 4;                   // histogram rows: sub-cluster 0, 1, coin 0, 1
 constexpr int kMovGroups = 32;                 // cells per workgroup pass of k_mov_sub (8 lanes each)
 constexpr int kMovLanes = 8;
 constexpr int kRedSpan = kSpanBlocks;
@@ -77,12 +78,11 @@ __device__ inline uint4 frag(const uint8_t* dense, uint32_t doff, int j, int m)
 // (step 3 of k_lay_sub), chunk by chunk with the next chunk's fragments in
 // flight: eight selection products bring the counts of each place to the
 // lanes of its column, four products with the 0/1 rows sum them over the
-// cells, and lane group 0 adds rows 0 .. ROWS - 1 to the LDS histogram
-// (LHIST) or to the statistics rows srow (sub-clusters) and crow (coins).
-template <int ROWS, bool LHIST>
+// cells, and lane group 0 adds rows 0 .. ROWS - 1 to the block's LDS
+// histogram over (row, place).
+template <int ROWS>
 __device__ inline void chunk_stats(const uint8_t* dense, uint32_t doff, int D, long amask, const long (&sel)[2],
-                                   const int (&rc128)[4], const uint16_t* s_gene, uint32_t* thist, int G, int g, int r,
-                                   unsigned long long* srow, unsigned long long* crow)
+                                   const int (&rc128)[4], uint32_t (*phist)[kPlaces], int g, int r)
 {
     if (D <= 0) return;
     const intx4_t zero = {0, 0, 0, 0};
@@ -106,15 +106,9 @@ __device__ inline void chunk_stats(const uint8_t* dense, uint32_t doff, int D, l
         // rows 0 .. 3 of the products are in lane group 0, row i in word i
         if (g == 0) {
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) {
-                const int u = s_gene[j * kBlkGenes + 16 * nt + r];
+            for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
-                for (int i = 0; i < ROWS; ++i) {
-                    const uint32_t v = (uint32_t)(o[nt][i] + rc128[i]);
-                    if (LHIST) atomicAdd(&thist[i * G + u], v);
-                    else if (v) atomicAdd((i < 2 ? srow : crow) + (int64_t)(i & 1) * G + u, (unsigned long long)v);
-                }
-            }
+                for (int i = 0; i < ROWS; ++i) atomicAdd(&phist[i][j * kBlkGenes + 16 * nt + r], (uint32_t)(o[nt][i] + rc128[i]));
         }
         f0 = n0;
         f1 = n1;
@@ -127,9 +121,8 @@ k_lay_sub(Ws ws, SubArgs a)
 {
     __shared__ double dl[DUMP ? kPlaces : 1];              // delta in L's gene order (dump)
     __shared__ uint64_t s_lim[DUMP ? 1 : kPlaces];         // its fixed-point digits (lay_lim of L)
-    __shared__ uint16_t s_gene[kPlaces];                   // gene at each place of L
     __shared__ double tl0[DUMP ? kPlaces : 1], tl1[DUMP ? kPlaces : 1];   // the two rows themselves (dump)
-    __shared__ uint32_t thist[kLsHistWords];               // count sums per (row, gene)
+    __shared__ uint32_t phist[kPartRows][kPlaces];         // count sums per (row, place of L)
     __shared__ uint32_t ncnt[2], ncnt2[2];
 
     const bool rs = a.rsplit != 0;
@@ -167,6 +160,7 @@ k_lay_sub(Ws ws, SubArgs a)
     bool stay[2];
     int64_t tb[2], te[2];
     uint32_t en0[2];
+    int rk0[2];
     double dt0[2];
     const double* dfull = ws.lay_dfull + (int64_t)(L < K ? L : 0) * G;
 #pragma unroll
@@ -179,30 +173,29 @@ k_lay_sub(Ws ws, SubArgs a)
         ocode[m] = stay[m] && a.c_old[cell[m]] == L ? 1 + (a.cs_old[cell[m]] & 1) : 0;
         en0[m] = stay[m] && tb[m] + g < te[m] ? ws.lay_tail[tb[m] + g] : 0u;   // (an entry's count is >= 1)
         dt0[m] = !DUMP && !reset && en0[m] ? dfull[en0[m] & 0xFFFFu] : 0.0;
+        rk0[m] = en0[m] ? ws.lay_rank[(int64_t)L * G + (en0[m] & 0xFFFFu)] : 0;
         if (g == 0 && cell[m] >= 0 && !stay[m]) {
             const int q = atomicAdd(&ws.st->n_mov, 1);
             if (q < ws.N) ws.mov[q] = (uint32_t)cell[m];
         }
     }
-    {
+    if (!reset) {
         const uint16_t* gene = ws.lay_gene + (int64_t)L * kPlaces;
         for (int j = t; j < D * kBlkGenes; j += kLsThreads) {
-            const int u = gene[j];
-            s_gene[j] = (uint16_t)u;
-            if (DUMP && !reset) {
+            if (DUMP) {
+                const int u = gene[j];
                 const double v0 = g0[u], v1 = g1[u];
                 dl[j] = v1 - v0;
                 tl0[j] = v0;
                 tl1[j] = v1;
+            } else {
+                s_lim[j] = ws.lay_lim[(int64_t)L * kPlaces + j];
             }
-            if (!DUMP && !reset) s_lim[j] = ws.lay_lim[(int64_t)L * kPlaces + j];
         }
     }
     if (t < 2) ncnt[t] = ncnt2[t] = 0;
     const int rows = rs ? 4 : 2;
-    const bool lhist = rows * G <= ws.lay_pw;
-    if (lhist)
-        for (int q = t; q < rows * G; q += kLsThreads) thist[q] = 0;
+    for (int q = t; q < rows * kPlaces; q += kLsThreads) phist[q / kPlaces][q % kPlaces] = 0;
     __syncthreads();
 
     // 1. the FP64 sums
@@ -389,47 +382,36 @@ k_lay_sub(Ws ws, SubArgs a)
     }
     {
         const int rc128[4] = {128 * (int)rc[0], 128 * (int)rc[1], 128 * (int)rc[2], 128 * (int)rc[3]};
-        if (lhist) {
-            if (rs) chunk_stats<4, true>(dense, doff, D, amask, sel, rc128, s_gene, thist, G, g, r, nullptr, nullptr);
-            else chunk_stats<2, true>(dense, doff, D, amask, sel, rc128, s_gene, thist, G, g, r, nullptr, nullptr);
-        } else {
-            unsigned long long* srow = ws.ssub + (int64_t)(2 * L) * G;
-            unsigned long long* crow = rs ? ws.rssub + (int64_t)(2 * L) * G : nullptr;
-            if (rs) chunk_stats<4, false>(dense, doff, D, amask, sel, rc128, s_gene, nullptr, G, g, r, srow, crow);
-            else chunk_stats<2, false>(dense, doff, D, amask, sel, rc128, s_gene, nullptr, G, g, r, srow, crow);
-        }
+        if (rs) chunk_stats<4>(dense, doff, D, amask, sel, rc128, phist, g, r);
+        else chunk_stats<2>(dense, doff, D, amask, sel, rc128, phist, g, r);
     }
-    // tail entries of the cells of L, split over the cell's four lanes
+    // tail entries of the cells of L, split over the cell's four lanes: a
+    // gene among L's first kPlaces places goes to the histogram, any other
+    // (rare, and spread over many genes) straight to the statistics
+    const uint16_t* rank = ws.lay_rank + (int64_t)L * G;
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
         if (!stay[m]) continue;
-        if (lhist) {
-            uint32_t* hs = thist + sv[m] * G;
-            uint32_t* hc = thist + (2 + cv[m]) * G;
-            if (en0[m]) {
-                atomicAdd(&hs[en0[m] & 0xFFFFu], en0[m] >> 16);
-                if (rs) atomicAdd(&hc[en0[m] & 0xFFFFu], en0[m] >> 16);
-            }
-            for (int64_t e = tb[m] + g + 4; e < te[m]; e += 4) {
-                const uint32_t en = ws.lay_tail[e];
-                atomicAdd(&hs[en & 0xFFFFu], en >> 16);
-                if (rs) atomicAdd(&hc[en & 0xFFFFu], en >> 16);
-            }
-        } else {
-            unsigned long long* srow = ws.ssub + (int64_t)(2 * L + sv[m]) * G;
-            unsigned long long* crow = rs ? ws.rssub + (int64_t)(2 * L + cv[m]) * G : nullptr;
-            for (int64_t e = tb[m] + g; e < te[m]; e += 4) {
-                const uint32_t en = ws.lay_tail[e];
-                const unsigned long long x = en >> 16;
-                atomicAdd(&srow[en & 0xFFFFu], x);
-                if (rs) atomicAdd(&crow[en & 0xFFFFu], x);
+        unsigned long long* srow = ws.ssub + (int64_t)(2 * L + sv[m]) * G;
+        unsigned long long* crow = rs ? ws.rssub + (int64_t)(2 * L + cv[m]) * G : nullptr;
+        for (int64_t e = tb[m] + g; e < te[m]; e += 4) {
+            const bool first = e == tb[m] + g;
+            const uint32_t en = first ? en0[m] : ws.lay_tail[e];
+            const int p = first ? rk0[m] : rank[en & 0xFFFFu];
+            const uint32_t x = en >> 16;
+            if (p < kPlaces) {
+                atomicAdd(&phist[sv[m]][p], x);
+                if (rs) atomicAdd(&phist[2 + cv[m]][p], x);
+            } else {
+                atomicAdd(&srow[en & 0xFFFFu], (unsigned long long)x);
+                if (rs) atomicAdd(&crow[en & 0xFFFFu], (unsigned long long)x);
             }
         }
     }
     __syncthreads();
-    if (lhist) {
+    {
         uint32_t* part = ws.lay_part + (int64_t)b * ws.lay_pw;
-        for (int q = t; q < rows * G; q += kLsThreads) part[q] = thist[q];
+        for (int q = t; q < rows * kPlaces; q += kLsThreads) part[q] = phist[q / kPlaces][q % kPlaces];
     }
     if (t < 2 && ncnt[t]) atomicAdd(&ws.nsub[2 * L + t], (unsigned long long)ncnt[t]);
     if (rs && t < 2 && ncnt2[t]) atomicAdd(&ws.rnsub[2 * L + t], (unsigned long long)ncnt2[t]);
@@ -521,11 +503,11 @@ __global__ void __launch_bounds__(256) k_mov_sub(Ws ws, SubArgs a)
 
 // The blocks' histograms into the statistics.  The blocks of each layout
 // cluster L are consecutive, from lay_bbeg[L]; they are cut into spans of
-// kRedSpan blocks, lay_sbeg[L] spans before L's first.  Workgroup (x, y) sums
-// words 512 y .. + 511 of span x's histograms, two adjacent words per thread,
-// and adds each non-zero sum to the statistics with one 64-bit atomic: a few
-// per address and span instead of one per count.
-__global__ void __launch_bounds__(256) k_lay_span(Ws ws, int rows)
+// kRedSpan blocks, lay_sbeg[L] spans before L's first.  Workgroup (x, r) sums
+// row r of span x's histograms, place by place, and adds each non-zero sum to
+// the statistics of the place's gene with one 64-bit atomic: a few per
+// address and span instead of one per count.
+__global__ void __launch_bounds__(kPlaces) k_lay_span(Ws ws)
 {
     const int KL = ws.st->lay_K;
     const int x = blockIdx.x;
@@ -538,30 +520,19 @@ __global__ void __launch_bounds__(256) k_lay_span(Ws ws, int rows)
     }
     const int L = lo;
     if (L >= ws.st->K) return;
+    const int r = blockIdx.y, p = threadIdx.x;
     const int b0 = ws.lay_bbeg[L] + (x - ws.lay_sbeg[L]) * kRedSpan;
     const int nb = min(ws.lay_bbeg[L + 1] - b0, kRedSpan);
     const int64_t pw = ws.lay_pw;
-    const uint32_t* in = ws.lay_part + (int64_t)b0 * pw;
-    const int G = ws.G;
-    const int n = rows * G;            // even, as is pw
-    const int q = 2 * (blockIdx.y * 256 + threadIdx.x);
-    if (q >= n) return;
-    uint2 acc = make_uint2(0u, 0u);    // at most kRedSpan x 256 cells x 65535 < 2^32
+    const uint32_t* in = ws.lay_part + (int64_t)b0 * pw + (int64_t)r * kPlaces + p;
+    uint32_t acc = 0;                  // at most kRedSpan x 256 cells x 65535 < 2^32
 #pragma unroll 8
-    for (int i = 0; i < nb; ++i) {
-        const uint2 v = *reinterpret_cast<const uint2*>(in + (int64_t)i * pw + q);
-        acc.x += v.x;
-        acc.y += v.y;
-    }
-    const uint32_t sums[2] = {acc.x, acc.y};
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        if (!sums[h]) continue;
-        const int w = q + h, r = w / G, u = w - r * G;
-        unsigned long long* dst = r < 2 ? ws.ssub + (int64_t)(2 * L + r) * G + u
-                                        : ws.rssub + (int64_t)(2 * L + r - 2) * G + u;
-        atomicAdd(dst, (unsigned long long)sums[h]);
-    }
+    for (int i = 0; i < nb; ++i) acc += in[(int64_t)i * pw];
+    if (!acc) return;
+    const int G = ws.G;
+    const int u = ws.lay_gene[(int64_t)L * kPlaces + p];
+    unsigned long long* dst = r < 2 ? ws.ssub + (int64_t)(2 * L + r) * G + u : ws.rssub + (int64_t)(2 * L + r - 2) * G + u;
+    atomicAdd(dst, (unsigned long long)acc);
 }
 
 using LaySubKernel = void (*)(Ws, SubArgs);
@@ -593,9 +564,8 @@ void launch_lay_sub(const Ws& ws, const SubArgs& a, hipStream_t s)
     if (mb > 1024) mb = 1024;
     hipLaunchKernelGGL(mov_sub_kernel(dump, split_q), dim3((unsigned)mb), dim3(kMovGroups * kMovLanes), 0, s, ws, a);
     const int rows = a.rsplit ? 4 : 2;
-    if (rows * ws.G <= ws.lay_pw)
-        hipLaunchKernelGGL(k_lay_span, dim3((unsigned)lay_spans(ws.nblk_cap, ws.k_max), (unsigned)((rows * ws.G + 511) / 512)),
-                           dim3(256), 0, s, ws, rows);
+    hipLaunchKernelGGL(k_lay_span, dim3((unsigned)lay_spans(ws.nblk_cap, ws.k_max), (unsigned)rows), dim3(kPlaces), 0, s,
+                       ws);
 }
 
 }  // namespace dpmm

@@ -160,7 +160,7 @@ dpmm_status check_args(const dpmm_csr* csr, const dpmm_params* p)
     if (csr->reserved != 0) return fail(DPMM_ERR_ARG, "reserved field must be 0");
     if (!(p->alpha > 0.0)) return fail(DPMM_ERR_ARG, "alpha must be > 0");
     if (!p->beta_per_gene && !(p->beta > 0.0)) return fail(DPMM_ERR_ARG, "beta must be > 0");
-    if (p->k_max < 1 || p->k_max > 1024) return fail(DPMM_ERR_ARG, "k_max must be in [1, 1024]");
+    if (p->k_max < 1 || p->k_max > kMaxClusters) return fail(DPMM_ERR_ARG, "k_max must be in [1, 1024]");
     if (p->k_init < 1 || p->k_init > p->k_max) return fail(DPMM_ERR_ARG, "k_init must be in [1, k_max]");
     if (p->precision < DPMM_FP64 || p->precision > DPMM_SPLIT_BF16) return fail(DPMM_ERR_ARG, "unknown precision");
     if (p->flags & ~(DPMM_FLAG_SPLIT_Q | DPMM_FLAG_NEW_CLUSTER | DPMM_FLAG_RANDOM_SPLIT))

@@ -46,6 +46,7 @@ typedef __attribute__((__vector_size__(4 * sizeof(float)))) float floatx4_t;
 constexpr int kMfmaThreads = 2 * kBlkCells;   // 512: two threads per block slot
 constexpr int kStageChunks = 2;               // dense chunks whose B rows are staged in LDS at a time
 constexpr int kTailStage = 2048;              // tail entries of a block staged in LDS (more: read from memory)
+constexpr int kTailBatch = 2;                 // tail entries whose table rows a thread has in flight together
 constexpr int kRowB = kBlkGenes + 8;          // BF16 elements per staged B row (padded against bank conflicts)
 
 __host__ __device__ constexpr size_t mfma_lds_bytes(int nt)
@@ -125,6 +126,7 @@ k_assign_bf16(Ws ws, AssignArgs a)
     __shared__ int x_k1[kBlkCells];
     __shared__ float x_d[2][kBlkCells];        // each half's best score + log pi
     __shared__ uint32_t t_ent[kTailStage];     // the block's tail entries
+    __shared__ float s_lp[kMaxClusters];       // log pi in FP32
     constexpr int SS = 16 * NT + 1;
     constexpr int NCOL = 16 * NT;
     constexpr int HALF = NCOL / 2;             // clusters per thread of a slot's pair (multiple of 8)
@@ -153,6 +155,8 @@ k_assign_bf16(Ws ws, AssignArgs a)
     const bool staged = tcount <= kTailStage;
     if (staged)
         for (int i = t; i < (int)tcount; i += kMfmaThreads) t_ent[i] = ws.lay_tail[tbase + i];
+    // (both read after the first barrier below)
+    for (int k = t; k < K; k += kMfmaThreads) s_lp[k] = (float)ws.logpi[k];
     constexpr int R = kLayDmax * kBlkGenes;
 
     Top2 top;
@@ -243,47 +247,35 @@ k_assign_bf16(Ws ws, AssignArgs a)
 #pragma unroll
                 for (int k = 0; k < HALF; ++k) ta[k] = srow[k];
                 const float* lcb = ws.lc32 + kh;
-                int64_t e = tb;
+                // kTailBatch entries' table rows in flight at a time; past the
+                // end the last entry is read again and counts zero (adding
+                // 0 x a finite log theta leaves the sum unchanged)
 #pragma unroll 1
-                for (; e + 1 < te; e += 2) {
-                    const uint32_t n0 = staged ? t_ent[e - tbase] : ws.lay_tail[e];
-                    const uint32_t n1 = staged ? t_ent[e + 1 - tbase] : ws.lay_tail[e + 1];
-                    const float4* r0 = reinterpret_cast<const float4*>(lcb + (int64_t)(n0 & 0xFFFFu) * ws.kpad);
-                    const float4* r1 = reinterpret_cast<const float4*>(lcb + (int64_t)(n1 & 0xFFFFu) * ws.kpad);
-                    float4 v0[HALF / 4], v1[HALF / 4];
+                for (int64_t e = tb; e < te; e += kTailBatch) {
+                    uint32_t nn[kTailBatch];
+                    float xs[kTailBatch];
 #pragma unroll
-                    for (int k4 = 0; k4 < HALF / 4; ++k4) {
-                        v0[k4] = r0[k4];
-                        v1[k4] = r1[k4];
+                    for (int i = 0; i < kTailBatch; ++i) {
+                        const int64_t ei = e + i < te ? e + i : te - 1;
+                        nn[i] = staged ? t_ent[ei - tbase] : ws.lay_tail[ei];
+                        xs[i] = e + i < te ? (float)(nn[i] >> 16) : 0.0f;
                     }
-                    const float x0 = (float)(n0 >> 16), x1 = (float)(n1 >> 16);
+                    float4 v[kTailBatch][HALF / 4];
 #pragma unroll
-                    for (int k4 = 0; k4 < HALF / 4; ++k4) {
-                        ta[4 * k4 + 0] = fmaf(x0, v0[k4].x, ta[4 * k4 + 0]);
-                        ta[4 * k4 + 1] = fmaf(x0, v0[k4].y, ta[4 * k4 + 1]);
-                        ta[4 * k4 + 2] = fmaf(x0, v0[k4].z, ta[4 * k4 + 2]);
-                        ta[4 * k4 + 3] = fmaf(x0, v0[k4].w, ta[4 * k4 + 3]);
+                    for (int i = 0; i < kTailBatch; ++i) {
+                        const float4* row = reinterpret_cast<const float4*>(lcb + (int64_t)(nn[i] & 0xFFFFu) * ws.kpad);
+#pragma unroll
+                        for (int k4 = 0; k4 < HALF / 4; ++k4) v[i][k4] = row[k4];
                     }
 #pragma unroll
-                    for (int k4 = 0; k4 < HALF / 4; ++k4) {
-                        ta[4 * k4 + 0] = fmaf(x1, v1[k4].x, ta[4 * k4 + 0]);
-                        ta[4 * k4 + 1] = fmaf(x1, v1[k4].y, ta[4 * k4 + 1]);
-                        ta[4 * k4 + 2] = fmaf(x1, v1[k4].z, ta[4 * k4 + 2]);
-                        ta[4 * k4 + 3] = fmaf(x1, v1[k4].w, ta[4 * k4 + 3]);
-                    }
-                }
-                if (e < te) {
-                    const uint32_t n0 = staged ? t_ent[e - tbase] : ws.lay_tail[e];
-                    const float4* r0 = reinterpret_cast<const float4*>(lcb + (int64_t)(n0 & 0xFFFFu) * ws.kpad);
-                    const float x0 = (float)(n0 >> 16);
+                    for (int i = 0; i < kTailBatch; ++i)
 #pragma unroll
-                    for (int k4 = 0; k4 < HALF / 4; ++k4) {
-                        const float4 v = r0[k4];
-                        ta[4 * k4 + 0] = fmaf(x0, v.x, ta[4 * k4 + 0]);
-                        ta[4 * k4 + 1] = fmaf(x0, v.y, ta[4 * k4 + 1]);
-                        ta[4 * k4 + 2] = fmaf(x0, v.z, ta[4 * k4 + 2]);
-                        ta[4 * k4 + 3] = fmaf(x0, v.w, ta[4 * k4 + 3]);
-                    }
+                        for (int k4 = 0; k4 < HALF / 4; ++k4) {
+                            ta[4 * k4 + 0] = fmaf(xs[i], v[i][k4].x, ta[4 * k4 + 0]);
+                            ta[4 * k4 + 1] = fmaf(xs[i], v[i][k4].y, ta[4 * k4 + 1]);
+                            ta[4 * k4 + 2] = fmaf(xs[i], v[i][k4].z, ta[4 * k4 + 2]);
+                            ta[4 * k4 + 3] = fmaf(xs[i], v[i][k4].w, ta[4 * k4 + 3]);
+                        }
                 }
 #pragma unroll
                 for (int k = 0; k < HALF; ++k) srow[k] = ta[k];
@@ -299,7 +291,7 @@ k_assign_bf16(Ws ws, AssignArgs a)
             for (int k = 0; k < HALF; ++k) {
                 const int kk = kh + k;
                 if (kk >= K) break;
-                dmax = fmaxf(dmax, srow[k] + (float)ws.logpi[kk]);
+                dmax = fmaxf(dmax, srow[k] + s_lp[kk]);
             }
             x_d[half][sl] = dmax;
         }
@@ -326,7 +318,7 @@ k_assign_bf16(Ws ws, AssignArgs a)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int kk = kh + k4 + q;
-                    if (kk < K && srow[k4 + q] + (float)ws.logpi[kk] >= cut) any = true;
+                    if (kk < K && srow[k4 + q] + s_lp[kk] >= cut) any = true;
                     if (a.dbg && kk < K && K + 2 <= a.dbg_stride)
                         put_dbg(a.dbg, a.dbg64, (int64_t)cell * a.dbg_stride + kk, (double)srow[k4 + q]);
                 }
@@ -337,7 +329,7 @@ k_assign_bf16(Ws ws, AssignArgs a)
                     const int kk = kh + k4 + q;
                     if (kk >= K) continue;
                     const float s = srow[k4 + q];
-                    const float lp = (float)ws.logpi[kk];
+                    const float lp = s_lp[kk];
                     if (s + lp < cut) continue;
                     top.add(lp + s + gumbel32(w.w[q]), s, lp, kk);
                 }

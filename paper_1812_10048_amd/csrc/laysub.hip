@@ -526,8 +526,12 @@ __global__ void __launch_bounds__(kPlaces) k_lay_span(Ws ws)
     const int64_t pw = ws.lay_pw;
     const uint32_t* in = ws.lay_part + (int64_t)b0 * pw + (int64_t)r * kPlaces + p;
     uint32_t acc = 0;                  // at most kRedSpan x 256 cells x 65535 < 2^32
-#pragma unroll 8
-    for (int i = 0; i < nb; ++i) acc += in[(int64_t)i * pw];
+    // all of the span's loads in flight at once (the last block's repeated)
+#pragma unroll
+    for (int i = 0; i < kRedSpan; ++i) {
+        const uint32_t v = in[(int64_t)min(i, nb - 1) * pw];
+        acc += i < nb ? v : 0u;
+    }
     if (!acc) return;
     const int G = ws.G;
     const int u = ws.lay_gene[(int64_t)L * kPlaces + p];

@@ -44,7 +44,7 @@ typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float floatx4_t;
 
 constexpr int kMfmaThreads = 2 * kBlkCells;   // 512: two threads per block slot
-constexpr int kStageChunks = 2;               // dense chunks whose B rows are staged in LDS at a time
+constexpr int kStageChunks = 3;               // dense chunks whose B rows are staged in LDS at a time
 constexpr int kTailStage = 2048;              // tail entries of a block staged in LDS (more: read from memory)
 constexpr int kTailBatch = 2;                 // tail entries whose table rows a thread has in flight together
 constexpr int kRowB = kBlkGenes + 8;          // BF16 elements per staged B row (padded against bank conflicts)

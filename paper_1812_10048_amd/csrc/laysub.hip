@@ -169,11 +169,16 @@ k_lay_sub(Ws ws, SubArgs a)
         cell[m] = ws.lay_cell[slot];
         tb[m] = ws.lay_toff[slot];
         te[m] = ws.lay_toff[slot + 1];
-        stay[m] = cell[m] >= 0 && L < K && a.c_new[cell[m]] == L;
-        ocode[m] = stay[m] && a.c_old[cell[m]] == L ? 1 + (a.cs_old[cell[m]] & 1) : 0;
-        en0[m] = stay[m] && tb[m] + g < te[m] ? ws.lay_tail[tb[m] + g] : 0u;   // (an entry's count is >= 1)
-        dt0[m] = !DUMP && !reset && en0[m] ? dfull[en0[m] & 0xFFFFu] : 0.0;
-        rk0[m] = en0[m] ? ws.lay_rank[(int64_t)L * G + (en0[m] & 0xFFFFu)] : 0;
+        // (the loads below depend only on the slot, not on whether the cell
+        // stays, so that they are in flight together)
+        const int ci = cell[m] >= 0 ? cell[m] : 0;
+        const int cn = a.c_new[ci], co = a.c_old[ci], so = a.cs_old[ci];
+        const uint32_t en = cell[m] >= 0 && L < K && tb[m] + g < te[m] ? ws.lay_tail[tb[m] + g] : 0u;
+        stay[m] = cell[m] >= 0 && L < K && cn == L;
+        ocode[m] = stay[m] && co == L ? 1 + (so & 1) : 0;
+        en0[m] = stay[m] ? en : 0u;                      // (an entry's count is >= 1)
+        dt0[m] = !DUMP && !reset && en ? dfull[en & 0xFFFFu] : 0.0;
+        rk0[m] = en ? ws.lay_rank[(int64_t)L * G + (en & 0xFFFFu)] : 0;
         if (g == 0 && cell[m] >= 0 && !stay[m]) {
             const int q = atomicAdd(&ws.st->n_mov, 1);
             if (q < ws.N) ws.mov[q] = (uint32_t)cell[m];

@@ -51,7 +51,7 @@ struct Layout {
 int32_t num_blocks(int64_t N) { return (int32_t)((N + kBlkCells - 1) / kBlkCells); }
 // blocks of the cluster-sorted copy: each cluster's last block may be partial
 int32_t lay_blocks(int64_t N, int32_t k_max) { return num_blocks(N) + k_max; }
-int32_t lay_cols(int32_t k_max) { return (k_max + 15) / 16 * 16 + kTablePadRows; }
+int32_t lay_cols(int32_t k_max) { return (k_max + kSubDigits + 15) / 16 * 16 + kTablePadRows; }
 // words of a block's statistics histogram in the sub-cluster pass over the
 // copy: (sub-cluster 0, 1 [, coin 0, 1]) x the places of the dense chunks
 int32_t lay_hist_words(uint32_t flags)
@@ -250,8 +250,7 @@ int32_t k_hint(const dpmm_ctx* ctx)
 // flags; with split-BF16 the cluster-sorted copy is rebuilt from the labels
 dpmm_status recompute_stats(dpmm_ctx* ctx)
 {
-    // no sweep has drawn these labels: no proposal term yet
-    // all NaN (no proposal term yet)
+    // no sweep has drawn these labels: no proposal term yet (all NaN)
     if (ctx->ws.subdd) HIP_TRY(hipMemsetAsync(ctx->ws.subdd, 0xFF, 8 * (size_t)ctx->N, ctx->stream));
     launch_stats(ctx->ws, ctx->c[ctx->cur], ctx->cs[ctx->cur], ctx->stream);
     launch_compact(ctx->ws, 0, ctx->stream);
@@ -570,16 +569,6 @@ dpmm_status dpmm_sweep(dpmm_ctx* ctx, int32_t n_sweeps)
         a.refine = ctx->precision != DPMM_FP64;
         a.refine_tol = (float)ctx->refine_tol;
         a.k_hint = k_hint(ctx);
-        {
-            StageTimer st(ctx, DPMM_STAGE_ASSIGN);
-            if (ctx->precision == DPMM_FP64) launch_assign_fp64(ws, a, ctx->stream);
-            else if (ctx->precision == DPMM_FP32) launch_assign_fp32(ws, a, ctx->stream);
-            else launch_assign_bf16(ws, a, ctx->stream);
-        }
-        if (a.refine) {
-            StageTimer st(ctx, DPMM_STAGE_REFINE);
-            launch_refine(ws, a, ctx->stream);
-        }
         SubArgs sa{};
         sa.c_old = ctx->c[ctx->cur];
         sa.cs_old = ctx->cs[ctx->cur];
@@ -595,9 +584,23 @@ dpmm_status dpmm_sweep(dpmm_ctx* ctx, int32_t n_sweeps)
             sa.rs_step = step + 1;
         }
         ctx->rs_ready_step = sa.rsplit ? (int64_t)ctx->step + 1 : -1;
+        // split-BF16 without a score dump: the sub-cluster pass of the cells
+        // that keep their block's cluster runs inside the cluster draw
+        const bool fused = ctx->precision == DPMM_SPLIT_BF16 && !ctx->dbg;
+        {
+            StageTimer st(ctx, DPMM_STAGE_ASSIGN);
+            if (ctx->precision == DPMM_FP64) launch_assign_fp64(ws, a, ctx->stream);
+            else if (ctx->precision == DPMM_FP32) launch_assign_fp32(ws, a, ctx->stream);
+            else launch_assign_bf16(ws, a, fused ? &sa : nullptr, ctx->stream);
+        }
+        if (a.refine) {
+            StageTimer st(ctx, DPMM_STAGE_REFINE);
+            launch_refine(ws, a, ctx->stream);
+        }
         {
             StageTimer st(ctx, DPMM_STAGE_SUBCLUSTER);
-            if (ctx->precision == DPMM_SPLIT_BF16) launch_lay_sub(ws, sa, ctx->stream);
+            if (fused) launch_lay_sub_rest(ws, sa, ctx->stream);
+            else if (ctx->precision == DPMM_SPLIT_BF16) launch_lay_sub(ws, sa, ctx->stream);
             else launch_sub_stats(ws, sa, ctx->stream);
         }
         {

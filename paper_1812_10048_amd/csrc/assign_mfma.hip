@@ -37,6 +37,7 @@
 // bound = (2^-17 + (2n + 8) 2^-23) 1.01 (|S| + |log pi| + 20) + 1e-5.
 #include "dpmm_common.hpp"
 #include "kernels.hpp"
+#include "laystats.hpp"
 
 namespace dpmm {
 
@@ -114,9 +115,9 @@ struct Top2 {
 };
 
 // (4 wavefronts per SIMD hold NT <= 3 without spilling; NT = 4 takes the registers of 2)
-template <int NT>
+template <int NT, bool SUB>
 __global__ void __launch_bounds__(kMfmaThreads) __attribute__((amdgpu_waves_per_eu(NT >= 4 ? 2 : 4)))
-k_assign_bf16(Ws ws, AssignArgs a)
+k_assign_bf16(Ws ws, AssignArgs a, SubArgs sa)
 {
     extern __shared__ __attribute__((aligned(16))) char lds[];
     uint16_t* bst = reinterpret_cast<uint16_t*>(lds);                 // [chunk][hi, lo][16 NT][kRowB]
@@ -127,13 +128,20 @@ k_assign_bf16(Ws ws, AssignArgs a)
     __shared__ float x_d[2][kBlkCells];        // each half's best score + log pi
     __shared__ uint32_t t_ent[kTailStage];     // the block's tail entries
     __shared__ float s_lp[kMaxClusters];       // log pi in FP32
+    __shared__ int8_t s_sub[SUB ? kBlkCells : 1];             // fused sub-cluster pass: each slot's sub-label
+    __shared__ uint8_t s_coin[SUB ? kBlkCells : 1];           // (-1: not drawn here) and coin
+    __shared__ uint32_t s_ncnt[4];
     constexpr int SS = 16 * NT + 1;
     constexpr int NCOL = 16 * NT;
     constexpr int HALF = NCOL / 2;             // clusters per thread of a slot's pair (multiple of 8)
 
     const int b = blockIdx.x;
+    if (SUB && b == 0 && threadIdx.x == 0) ws.st->rs_live = sa.rsplit ? 1 : 0;
     if (b >= ws.st->lay_nblk) return;
     const int K = ws.st->K;
+    // with the fused sub-cluster pass the digit columns K .. K + kSubDigits - 1
+    // of the hi/lo tables are scored too
+    const int KC = SUB ? K + kSubDigits : K;
     const int t = threadIdx.x;
     const int lane = t & 63;
     const int wave = t >> 6;                   // 8 wavefronts, 32 slots (two row tiles) each
@@ -161,8 +169,11 @@ k_assign_bf16(Ws ws, AssignArgs a)
 
     Top2 top;
     top.init();
+    double dfd = 0.0;                          // fused pass: the cell's digit sums combined in FP64
+    const int dE = SUB && L < K ? ws.lay_dE[L] : 0;
+    if (SUB && t < 4) s_ncnt[t] = 0;
 
-    for (int kb = 0; kb < K; kb += NCOL) {
+    for (int kb = 0; kb < KC; kb += NCOL) {
         floatx4_t acc[2][NT];
 #pragma unroll
         for (int m = 0; m < 2; ++m)
@@ -235,6 +246,15 @@ k_assign_bf16(Ws ws, AssignArgs a)
                 for (int q = 0; q < 4; ++q)
                     sc[(32 * wave + 16 * m + 4 * (lane >> 4) + q) * SS + 16 * n + (lane & 15)] = acc[m][n][q];
         __syncthreads();
+        if (SUB && half == 0) {
+            // the digit sums of this group's columns (exact integers in FP32;
+            // read before the tail adds to them)
+#pragma unroll
+            for (int k = 0; k < kSubDigits; ++k) {
+                const int col = K + k - kb;
+                if (col >= 0 && col < NCOL) dfd += ldexp((double)sc[sl * SS + col], 8 * k - dE);
+            }
+        }
         if (cell >= 0) {
             // this thread's half of the column group: HALF clusters from kh
             const int kh = kb + half * HALF;
@@ -344,78 +364,223 @@ k_assign_bf16(Ws ws, AssignArgs a)
         x_p1[sl] = top.p1; x_p2[sl] = top.p2; x_k1[sl] = top.k1;
     }
     __syncthreads();
-    if (half == 1 || cell < 0) return;
-    // column groups alternate halves, so the merged order differs from a scan
-    // only among exactly equal values: ties keep the lower cluster index, as
-    // here the strict comparisons keep the earlier value and the lower half's
-    // clusters of a group precede the upper half's.  With several groups
-    // (K > 16 NT) an upper-half cluster can precede a lower-half one of the
-    // next group; a tie between them resolves to the lower index explicitly.
-    {
-        const float u1 = x_t1[sl], u2 = x_t2[sl];
-        const int uk = x_k1[sl];
-        if (u1 > top.t1 || (u1 == top.t1 && uk < top.k1)) {
-            // the upper half's best wins; the runner-up is the better of the
-            // lower half's best and the upper half's second
-            const float o1 = top.t1, oa = top.a1, op = top.p1;
-            top.t2 = o1 > u2 ? o1 : u2;
-            top.a2 = o1 > u2 ? oa : x_a2[sl];
-            top.p2 = o1 > u2 ? op : x_p2[sl];
-            top.t1 = u1; top.a1 = x_a1[sl]; top.p1 = x_p1[sl]; top.k1 = uk;
-        } else if (u1 > top.t2) {
-            top.t2 = u1; top.a2 = x_a1[sl]; top.p2 = x_p1[sl];
+    if (!SUB && (half == 1 || cell < 0)) return;
+    int sv = -1, cv = 0;
+    if (half == 0 && cell >= 0) {
+        // column groups alternate halves, so the merged order differs from a scan
+        // only among exactly equal values: ties keep the lower cluster index, as
+        // here the strict comparisons keep the earlier value and the lower half's
+        // clusters of a group precede the upper half's.  With several groups
+        // (K > 16 NT) an upper-half cluster can precede a lower-half one of the
+        // next group; a tie between them resolves to the lower index explicitly.
+        {
+            const float u1 = x_t1[sl], u2 = x_t2[sl];
+            const int uk = x_k1[sl];
+            if (u1 > top.t1 || (u1 == top.t1 && uk < top.k1)) {
+                // the upper half's best wins; the runner-up is the better of the
+                // lower half's best and the upper half's second
+                const float o1 = top.t1, oa = top.a1, op = top.p1;
+                top.t2 = o1 > u2 ? o1 : u2;
+                top.a2 = o1 > u2 ? oa : x_a2[sl];
+                top.p2 = o1 > u2 ? op : x_p2[sl];
+                top.t1 = u1; top.a1 = x_a1[sl]; top.p1 = x_p1[sl]; top.k1 = uk;
+            } else if (u1 > top.t2) {
+                top.t2 = u1; top.a2 = x_a1[sl]; top.p2 = x_p1[sl];
+            }
+        }
+        bool uncertain = false;
+        if (K >= 2) {
+            const int nnz = ws.lay_nnz[slot];
+            const float bnd = bf16_bound(top.a1, top.p1, nnz) + bf16_bound(top.a2, top.p2, nnz);
+            const float near = (float)kNearTie * fmaxf(1.0f, fabsf(top.t1));
+            if (top.t1 - top.t2 <= bnd + near || (top.t1 - top.t2) / fmaxf(1.0f, fabsf(top.t1)) < a.refine_tol)
+                uncertain = true;
+        }
+        a.c_new[cell] = top.k1;
+        if (uncertain) {
+            const int q = atomicAdd(&ws.st->n_refine, 1);
+            if (q < ws.N) ws.refine[q] = (uint32_t)cell | kRefineCluster;
+        }
+
+        if (SUB) {
+            // the fused sub-cluster pass: a cell whose certified new label is
+            // the block's cluster draws its sub-label here; any other goes to
+            // the queue that k_mov_sub serves after the FP64 re-score
+            const uint32_t i = (uint32_t)cell;
+            if (!uncertain && top.k1 == L && L < K) {
+                const bool reset = ws.reset[L] != 0;
+                double dd = 0.0;
+                if (reset) {
+                    sv = (int)(philox(ws.seed, i, 0u, sa.step, kResub, 0u).w[0] >> 31);
+                } else {
+                    // the tail's part of the difference, in entry order, eight
+                    // entries' loads in flight at a time
+                    const double* dfull = ws.lay_dfull + (int64_t)L * ws.G;
+                    double df = dfd;
+                    for (int64_t e0 = tb; e0 < te; e0 += 8) {
+                        uint32_t en[8];
+                        double dv[8];
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) {
+                            const int64_t e = e0 + q < te ? e0 + q : te - 1;
+                            en[q] = staged ? t_ent[e - tbase] : ws.lay_tail[e];
+                        }
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) dv[q] = dfull[en[q] & 0xFFFFu];
+#pragma unroll
+                        for (int q = 0; q < 8; ++q)
+                            if (e0 + q < te) df = fma((double)(en[q] >> 16), dv[q], df);
+                    }
+                    const double* lw = ws.lay_sw + 4 * (int64_t)L;
+                    const SubWeights w{lw[0], lw[1], lw[2], lw[3]};
+                    const int code = sa.c_old[i] == L ? 1 + (sa.cs_old[i] & 1) : 0;
+                    sv = sub_draw(ws.seed, i, sa.step, kGumbelS, w, code, sub_noise(ws.seed, i, sa.step, kGumbelS), df, &dd);
+                }
+                sa.cs_new[i] = (uint8_t)sv;
+                atomicAdd(&s_ncnt[sv], 1u);
+                if (sa.rsplit) {
+                    cv = (int)(philox(ws.seed, i, 0u, sa.rs_step, kRSplit, 0u).w[0] >> 31);
+                    ws.rbits[i] = (uint8_t)cv;
+                    atomicAdd(&s_ncnt[2 + cv], 1u);
+                }
+                if (ws.subdd) ws.subdd[i] = reset ? __builtin_nan("") : dd;
+            } else {
+                const int q = atomicAdd(&ws.st->n_mov, 1);
+                if (q < ws.N) ws.mov[q] = i;
+            }
         }
     }
-    bool uncertain = false;
-    if (K >= 2) {
-        const int nnz = ws.lay_nnz[slot];
-        const float bnd = bf16_bound(top.a1, top.p1, nnz) + bf16_bound(top.a2, top.p2, nnz);
-        const float near = (float)kNearTie * fmaxf(1.0f, fabsf(top.t1));
-        if (top.t1 - top.t2 <= bnd + near || (top.t1 - top.t2) / fmaxf(1.0f, fabsf(top.t1)) < a.refine_tol)
-            uncertain = true;
-    }
-    a.c_new[cell] = top.k1;
-    if (uncertain) {
-        const int q = atomicAdd(&ws.st->n_refine, 1);
-        if (q < ws.N) ws.refine[q] = (uint32_t)cell | kRefineCluster;
+    if constexpr (SUB) {
+        if (half == 0) {
+            s_sub[sl] = (int8_t)sv;
+            s_coin[sl] = (uint8_t)cv;
+        }
+        __syncthreads();                       // the labels are in; the score tile is free
+        const bool rs = sa.rsplit != 0;
+        const int rows = rs ? 4 : 2;
+        uint32_t(*phist)[kPlaces] = reinterpret_cast<uint32_t(*)[kPlaces]>(lds);
+        for (int q = t; q < rows * kPlaces; q += kMfmaThreads) phist[q / kPlaces][q % kPlaces] = 0;
+        __syncthreads();
+        // the statistics of wavefront w's row tiles 2w, 2w + 1, as in the
+        // pass of laysub.hip: operand byte e of lane group g stands for cell
+        // 32 w + 16 (e >> 2) + 4 g + (e & 3); mask row r of that cell
+        const int r = lane & 15, g = lane >> 4;
+        long amask;
+        {
+            uint64_t mk = 0;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int c = 32 * wave + 16 * (e >> 2) + 4 * g + (e & 3);
+                const int svc = s_sub[c], cvc = s_coin[c];
+                const bool on = r < 2 ? svc == r : r < 4 && rs && svc >= 0 && cvc == r - 2;
+                if (on) mk |= (uint64_t)1 << (8 * e);
+            }
+            amask = (long)mk;
+        }
+        int rc128[4];
+        {
+            const int svc = lane < 32 ? s_sub[32 * wave + lane] : -1;
+            const int cvc = lane < 32 ? s_coin[32 * wave + lane] : 0;
+#pragma unroll
+            for (int row = 0; row < 4; ++row) {
+                const bool on = row < 2 ? svc == row : rs && svc >= 0 && cvc == row - 2;
+                rc128[row] = 128 * __popcll(__ballot(on));
+            }
+        }
+        long sel[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int q = 16 * h + r;
+            sel[h] = g == (q >> 3) ? (long)((uint64_t)1 << (8 * (q & 7))) : 0;
+        }
+        if (rs) chunk_stats<4>(dense, doff, D, amask, sel, rc128, phist, g, r);
+        else chunk_stats<2>(dense, doff, D, amask, sel, rc128, phist, g, r);
+        // the tail entries of the drawn cells, every other one per half: a
+        // gene among L's first kPlaces places goes to the histogram, any
+        // other straight to the statistics
+        {
+            const int svc = s_sub[sl], cvc = s_coin[sl];
+            if (cell >= 0 && svc >= 0) {
+                const uint16_t* rank = ws.lay_rank + (int64_t)L * ws.G;
+                unsigned long long* srow = ws.ssub + (int64_t)(2 * L + svc) * ws.G;
+                unsigned long long* crow = rs ? ws.rssub + (int64_t)(2 * L + cvc) * ws.G : nullptr;
+                for (int64_t e = tb + half; e < te; e += 2) {
+                    const uint32_t en = staged ? t_ent[e - tbase] : ws.lay_tail[e];
+                    const int p = rank[en & 0xFFFFu];
+                    const uint32_t x = en >> 16;
+                    if (p < kPlaces) {
+                        atomicAdd(&phist[svc][p], x);
+                        if (rs) atomicAdd(&phist[2 + cvc][p], x);
+                    } else {
+                        atomicAdd(&srow[en & 0xFFFFu], (unsigned long long)x);
+                        if (rs) atomicAdd(&crow[en & 0xFFFFu], (unsigned long long)x);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        uint32_t* part = ws.lay_part + (int64_t)b * ws.lay_pw;
+        for (int q = t; q < rows * kPlaces; q += kMfmaThreads) part[q] = phist[q / kPlaces][q % kPlaces];
+        if (t < 2 && s_ncnt[t]) atomicAdd(&ws.nsub[2 * L + t], (unsigned long long)s_ncnt[t]);
+        if (rs && t < 2 && s_ncnt[2 + t]) atomicAdd(&ws.rnsub[2 * L + t], (unsigned long long)s_ncnt[2 + t]);
     }
 }
 
-template <int NT>
-static void launch_nt(const Ws& ws, const AssignArgs& a, hipStream_t s)
+template <int NT, bool SUB>
+static void launch_nt(const Ws& ws, const AssignArgs& a, const SubArgs& sa, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_assign_bf16<NT>, dim3((unsigned)ws.nblk_cap), dim3(kMfmaThreads), mfma_lds_bytes(NT), s, ws, a);
+    hipLaunchKernelGGL((k_assign_bf16<NT, SUB>), dim3((unsigned)ws.nblk_cap), dim3(kMfmaThreads), mfma_lds_bytes(NT), s,
+                       ws, a, sa);
+}
+
+template <int NT>
+static hipError_t configure_nt()
+{
+    hipError_t e = hipFuncSetAttribute((const void*)k_assign_bf16<NT, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)mfma_lds_bytes(NT));
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)k_assign_bf16<NT, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)mfma_lds_bytes(NT));
+    return e;
 }
 
 // Allow the dynamic LDS size of every variant on the current device.
 hipError_t configure_assign_bf16()
 {
-    hipError_t e = hipFuncSetAttribute((const void*)k_assign_bf16<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)mfma_lds_bytes(1));
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void*)k_assign_bf16<2>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)mfma_lds_bytes(2));
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void*)k_assign_bf16<3>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)mfma_lds_bytes(3));
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void*)k_assign_bf16<4>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)mfma_lds_bytes(4));
+    hipError_t e = configure_nt<1>();
+    if (e == hipSuccess) e = configure_nt<2>();
+    if (e == hipSuccess) e = configure_nt<3>();
+    if (e == hipSuccess) e = configure_nt<4>();
     return e;
 }
 
 // The column-tile count is fixed at launch while K lives on the device: the
 // host passes the last K it has seen (k_hint); if K has grown beyond it the
-// kernel loops over column groups.
-void launch_assign_bf16(const Ws& ws, const AssignArgs& a, hipStream_t s)
+// kernel loops over column groups.  With the fused sub-cluster pass (sub not
+// null) the digit columns count too.
+void launch_assign_bf16(const Ws& ws, const AssignArgs& a, const SubArgs* sub, hipStream_t s)
 {
-    const int k_hint = a.k_hint > 0 ? a.k_hint : ws.k_max;
+    const int k_hint = (a.k_hint > 0 ? a.k_hint : ws.k_max) + (sub ? kSubDigits : 0);
     const int nt = k_hint <= 16 ? 1 : k_hint <= 32 ? 2 : k_hint <= 48 ? 3 : 4;
+    const SubArgs none{};
+    if (sub) {
+        if (sub->rsplit) {
+            launch_zero(ws.rssub, sizeof(unsigned long long) * 2 * (size_t)ws.k_max * (size_t)ws.G, s);
+            launch_zero(ws.rnsub, sizeof(unsigned long long) * 2 * (size_t)ws.k_max, s);
+        }
+        switch (nt) {
+        case 1: launch_nt<1, true>(ws, a, *sub, s); break;
+        case 2: launch_nt<2, true>(ws, a, *sub, s); break;
+        case 3: launch_nt<3, true>(ws, a, *sub, s); break;
+        default: launch_nt<4, true>(ws, a, *sub, s); break;
+        }
+        return;
+    }
     switch (nt) {
-    case 1: launch_nt<1>(ws, a, s); break;
-    case 2: launch_nt<2>(ws, a, s); break;
-    case 3: launch_nt<3>(ws, a, s); break;
-    default: launch_nt<4>(ws, a, s); break;
+    case 1: launch_nt<1, false>(ws, a, none, s); break;
+    case 2: launch_nt<2, false>(ws, a, none, s); break;
+    case 3: launch_nt<3, false>(ws, a, none, s); break;
+    default: launch_nt<4, false>(ws, a, none, s); break;
     }
 }
 

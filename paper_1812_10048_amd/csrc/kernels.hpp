@@ -53,6 +53,9 @@ struct SubArgs {
 void launch_sub_stats(const Ws& ws, const SubArgs& a, hipStream_t s);
 // laysub.hip (split-BF16 sweeps, over the cluster-sorted copy)
 void launch_lay_sub(const Ws& ws, const SubArgs& a, hipStream_t s);
+// the rest of that pass after its fused form in launch_assign_bf16: the queued
+// cells (after the FP64 re-score) and the sums of the block histograms
+void launch_lay_sub_rest(const Ws& ws, const SubArgs& a, hipStream_t s);
 hipError_t sub_stats_cells(int64_t N, int G, int32_t* cells);
 void launch_compact(const Ws& ws, int after_sweep, hipStream_t s);
 void launch_relabel(const Ws& ws, int32_t* c, uint8_t* cs, hipStream_t s);
@@ -77,7 +80,9 @@ struct AssignArgs {
 };
 void launch_assign_fp32(const Ws& ws, const AssignArgs& a, hipStream_t s);
 void launch_assign_fp64(const Ws& ws, const AssignArgs& a, hipStream_t s);
-void launch_assign_bf16(const Ws& ws, const AssignArgs& a, hipStream_t s);
+struct SubArgs;
+// (sub: the sweep's sub-cluster pass fused into the cluster draw, or null)
+void launch_assign_bf16(const Ws& ws, const AssignArgs& a, const SubArgs* sub, hipStream_t s);
 hipError_t configure_assign_bf16();
 void launch_refine(const Ws& ws, const AssignArgs& a, hipStream_t s);
 // FP64 scores of listed cells against the last redraw's parameters: K cluster

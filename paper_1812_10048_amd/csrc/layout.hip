@@ -293,9 +293,16 @@ void launch_relayout(const Ws& ws, const int32_t* c, int64_t* tile_sums, int for
 // the digits as the A operand of v_mfma_i32_16x16x32_i8 (row k, k-group g,
 // 8 consecutive places), lay_dS[L][D][k] the digit sums over the first D
 // chunks and lay_dE[L] = E; lay_dfull[L] holds delta_u gene-major (for the
-// tail entries) and lay_sw[L] the weights of the draw (sub_weights).  Block L
-// of k_lay_btab (256 threads), for every L of the copy that is a live,
-// non-reset cluster.
+// tail entries) and lay_sw[L] the weights of the draw (sub_weights).  The
+// digits also go to columns K .. K + kSubDigits - 1 of L's hi table in BF16
+// (exact: integers of at most 8 bits; the lo table is 0 there), so that the
+// matrix-core cluster draw forms the digit sums sum_p x_p d_{p,k} as extra
+// score columns, exactly in FP32 (every partial sum is an integer below
+// 512 x 255 x 128 < 2^24).  Block L of k_lay_btab (256 threads), for every L
+// of the copy that is a live, non-reset cluster.
+// BF16 bits of a small integer (|v| <= 128: exact)
+__device__ inline uint16_t bf16_of_int(int v) { return (uint16_t)(__float_as_uint((float)v) >> 16); }
+
 __device__ inline void lay_dtab(const Ws& ws, int L, int K, int KL)
 {
     constexpr int R = kLayDmax * kBlkGenes;
@@ -345,6 +352,13 @@ __device__ inline void lay_dtab(const Ws& ws, int L, int K, int KL)
         dig[t + 256 * h][7] = 0;
     }
     __syncthreads();
+    // the digit columns of L's hi / lo tables
+    for (int q = t; q < kSubDigits * R; q += 256) {
+        const int k = q / R, p = q - k * R;
+        const int64_t at = ((int64_t)L * ws.lay_cols + K + k) * R + p;
+        ws.lay_bhi[at] = bf16_of_int(dig[p][k]);
+        ws.lay_blo[at] = 0;
+    }
     // word (j, s, k, g): digit k of places 64 j + 32 s + 8 g .. + 7
     for (int w = t; w < kLayDmax * 2 * 8 * 4; w += 256) {
         const int g = w & 3, k = (w >> 2) & 7, s = (w >> 5) & 1, j = w >> 6;
@@ -391,11 +405,13 @@ __global__ void __launch_bounds__(256) k_lay_btab(Ws ws)
     }
     const int64_t n = (int64_t)KL * ws.lay_cols * R;
     const int64_t stride = (int64_t)(gridDim.x - ws.k_max) * blockDim.x;
+    // (the digit columns of live, non-reset clusters are lay_dtab's)
     for (int64_t q = (int64_t)(blockIdx.x - ws.k_max) * blockDim.x + threadIdx.x; q < n; q += stride) {
         const int j = (int)(q % R);
         const int64_t lc = q / R;
         const int col = (int)(lc % ws.lay_cols);
         const int L = (int)(lc / ws.lay_cols);
+        if (col >= K && col < K + kSubDigits && L < K && !ws.reset[L]) continue;
         uint16_t hi = 0, lo = 0;
         if (col < K) {
             const int64_t at = (int64_t)col * ws.Gpad + ws.lay_gene[(int64_t)L * R + j];

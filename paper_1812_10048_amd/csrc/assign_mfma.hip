@@ -131,6 +131,7 @@ k_assign_bf16(Ws ws, AssignArgs a, SubArgs sa)
     __shared__ int8_t s_sub[SUB ? kBlkCells : 1];             // fused sub-cluster pass: each slot's sub-label
     __shared__ uint8_t s_coin[SUB ? kBlkCells : 1];           // (-1: not drawn here) and coin
     __shared__ uint32_t s_ncnt[4];
+    __shared__ int s_old[SUB ? kBlkCells : 1];               // (old cluster << 1) | old sub-label
     constexpr int SS = 16 * NT + 1;
     constexpr int NCOL = 16 * NT;
     constexpr int HALF = NCOL / 2;             // clusters per thread of a slot's pair (multiple of 8)
@@ -149,6 +150,8 @@ k_assign_bf16(Ws ws, AssignArgs a, SubArgs sa)
     const int half = t >> 8;                   // which half of a column group it takes
     const int64_t slot = (int64_t)b * kBlkCells + sl;
     const int cell = ws.lay_cell[slot];
+    // (fused pass) the cell's old labels, needed by its draw at the end, kept in LDS
+    if (SUB && half == 0) s_old[sl] = cell >= 0 ? (sa.c_old[cell] << 1) | (sa.cs_old[cell] & 1) : 0;
     const int L = ws.lay_kc[b];
     const int64_t d0 = ws.lay_doff[b];
     const int D = (int)(ws.lay_doff[b + 1] - d0);
@@ -365,6 +368,13 @@ k_assign_bf16(Ws ws, AssignArgs a, SubArgs sa)
     }
     __syncthreads();
     if (!SUB && (half == 1 || cell < 0)) return;
+    if (SUB) {
+        // the score tile is free: the block's (row, place) histogram of the
+        // fused pass takes its place (visible after the next barrier)
+        uint32_t(*ph)[kPlaces] = reinterpret_cast<uint32_t(*)[kPlaces]>(lds);
+        const int rows = sa.rsplit ? 4 : 2;
+        for (int q = t; q < rows * kPlaces; q += kMfmaThreads) ph[q / kPlaces][q % kPlaces] = 0;
+    }
     int sv = -1, cv = 0;
     if (half == 0 && cell >= 0) {
         // column groups alternate halves, so the merged order differs from a scan
@@ -433,7 +443,8 @@ k_assign_bf16(Ws ws, AssignArgs a, SubArgs sa)
                     }
                     const double* lw = ws.lay_sw + 4 * (int64_t)L;
                     const SubWeights w{lw[0], lw[1], lw[2], lw[3]};
-                    const int code = sa.c_old[i] == L ? 1 + (sa.cs_old[i] & 1) : 0;
+                    const int old_code = s_old[sl];
+                    const int code = (old_code >> 1) == L ? 1 + (old_code & 1) : 0;
                     sv = sub_draw(ws.seed, i, sa.step, kGumbelS, w, code, sub_noise(ws.seed, i, sa.step, kGumbelS), df, &dd);
                 }
                 sa.cs_new[i] = (uint8_t)sv;
@@ -458,9 +469,7 @@ k_assign_bf16(Ws ws, AssignArgs a, SubArgs sa)
         __syncthreads();                       // the labels are in; the score tile is free
         const bool rs = sa.rsplit != 0;
         const int rows = rs ? 4 : 2;
-        uint32_t(*phist)[kPlaces] = reinterpret_cast<uint32_t(*)[kPlaces]>(lds);
-        for (int q = t; q < rows * kPlaces; q += kMfmaThreads) phist[q / kPlaces][q % kPlaces] = 0;
-        __syncthreads();
+        uint32_t(*phist)[kPlaces] = reinterpret_cast<uint32_t(*)[kPlaces]>(lds);   // (cleared above)
         // the statistics of wavefront w's row tiles 2w, 2w + 1, as in the
         // pass of laysub.hip: operand byte e of lane group g stands for cell
         // 32 w + 16 (e >> 2) + 4 g + (e & 3); mask row r of that cell
@@ -504,16 +513,28 @@ k_assign_bf16(Ws ws, AssignArgs a, SubArgs sa)
                 const uint16_t* rank = ws.lay_rank + (int64_t)L * ws.G;
                 unsigned long long* srow = ws.ssub + (int64_t)(2 * L + svc) * ws.G;
                 unsigned long long* crow = rs ? ws.rssub + (int64_t)(2 * L + cvc) * ws.G : nullptr;
-                for (int64_t e = tb + half; e < te; e += 2) {
-                    const uint32_t en = staged ? t_ent[e - tbase] : ws.lay_tail[e];
-                    const int p = rank[en & 0xFFFFu];
-                    const uint32_t x = en >> 16;
-                    if (p < kPlaces) {
-                        atomicAdd(&phist[svc][p], x);
-                        if (rs) atomicAdd(&phist[2 + cvc][p], x);
-                    } else {
-                        atomicAdd(&srow[en & 0xFFFFu], (unsigned long long)x);
-                        if (rs) atomicAdd(&crow[en & 0xFFFFu], (unsigned long long)x);
+                // eight entries' ranks in flight at a time
+                for (int64_t e0 = tb + half; e0 < te; e0 += 16) {
+                    uint32_t en[8];
+                    int p[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        const int64_t e = e0 + 2 * q < te ? e0 + 2 * q : e0;
+                        en[q] = staged ? t_ent[e - tbase] : ws.lay_tail[e];
+                    }
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) p[q] = rank[en[q] & 0xFFFFu];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        if (e0 + 2 * q >= te) break;
+                        const uint32_t x = en[q] >> 16;
+                        if (p[q] < kPlaces) {
+                            atomicAdd(&phist[svc][p[q]], x);
+                            if (rs) atomicAdd(&phist[2 + cvc][p[q]], x);
+                        } else {
+                            atomicAdd(&srow[en[q] & 0xFFFFu], (unsigned long long)x);
+                            if (rs) atomicAdd(&crow[en[q] & 0xFFFFu], (unsigned long long)x);
+                        }
                     }
                 }
             }

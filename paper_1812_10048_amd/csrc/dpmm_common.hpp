@@ -124,7 +124,7 @@ constexpr uint32_t kFlagRandomSplit = 4u;     // ... and of the random-split pas
 constexpr int kBlkGenes = 64;
 constexpr int kMaxClusters = 1024;                 // largest k_max dpmm_init accepts
 constexpr int kSubDigits = 7;                      // digit columns after the K clusters in lay_bhi (layout.hip)
-constexpr int kSpanBlocks = 32;                    // blocks per span of the statistics reduction (laysub.hip)
+constexpr int kSpanBlocks = 128;                   // blocks per span of the statistics reduction (laysub.hip)
 // spans of the reduction: each cluster's blocks are cut separately
 __host__ __device__ inline int32_t lay_spans(int32_t nblk_cap, int32_t k_max) { return nblk_cap / kSpanBlocks + k_max; }
 

@@ -464,11 +464,15 @@ __global__ void __launch_bounds__(kPlaces) k_lay_span(Ws ws)
     const int64_t pw = ws.lay_pw;
     const uint32_t* in = ws.lay_part + (int64_t)b0 * pw + (int64_t)r * kPlaces + p;
     uint32_t acc = 0;                  // at most kRedSpan x 256 cells x 65535 < 2^32
-    // all of the span's loads in flight at once (the last block's repeated)
+    // 32 of the span's loads in flight at a time (past its end the last
+    // block is read again and not added)
+#pragma unroll 1
+    for (int i0 = 0; i0 < nb; i0 += 32) {
 #pragma unroll
-    for (int i = 0; i < kRedSpan; ++i) {
-        const uint32_t v = in[(int64_t)min(i, nb - 1) * pw];
-        acc += i < nb ? v : 0u;
+        for (int i = 0; i < 32; ++i) {
+            const uint32_t v = in[(int64_t)min(i0 + i, nb - 1) * pw];
+            acc += i0 + i < nb ? v : 0u;
+        }
     }
     if (!acc) return;
     const int G = ws.G;

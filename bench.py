@@ -42,10 +42,12 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def alg_bytes(n_cells: int, nnz: int) -> int:
+def alg_bytes(n_cells: int, nnz: int, sub_dd: bool = False) -> int:
     # packed (gene | count) entries 4 B each, padded row offsets 8 B, labels
-    # read and written (int32 cluster + uint8 sub-cluster each way)
-    return 4 * nnz + 8 * (n_cells + 1) + 10 * n_cells
+    # read and written (int32 cluster + uint8 sub-cluster each way); with the
+    # sub-cluster draw in the same kernel and the split proposal term, the FP64
+    # score difference of each cell's draw written too
+    return 4 * nnz + 8 * (n_cells + 1) + 10 * n_cells + (8 * n_cells if sub_dd else 0)
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_assign_bf16_c5_hbm_traffic.txt")
@@ -61,7 +63,7 @@ def measured_traffic():
     text = open(TRAFFIC_FILE).read()
     digests = set(re.findall(r"^source digest: (\w+)", text, re.M))
     got = {}
-    for c, v in re.findall(r"^traffic (FETCH_SIZE|WRITE_SIZE) dpmm::k_assign_bf16\S*: ([0-9.eE+-]+) bytes per dispatch",
+    for c, v in re.findall(r"^traffic (FETCH_SIZE|WRITE_SIZE) dpmm::k_assign_bf16[^:]*: ([0-9.eE+-]+) bytes per dispatch",
                            text, re.M):
         got[c] = float(v)
     if digests != {source_digest()} or set(got) != {"FETCH_SIZE", "WRITE_SIZE"}:
@@ -245,9 +247,11 @@ def main() -> int:
     st1 = {"K": main_run["K1"]}
 
     kernel_s = kms / 1e3 / max(1, launches)
-    nbytes = alg_bytes(d.n_cells, d.nnz)
+    fused = args.precision == "split_bf16"
+    nbytes = alg_bytes(d.n_cells, d.nnz, sub_dd=fused)   # (paper-literal moves: the split proposal term is on)
     achieved = nbytes / kernel_s / 1e9
-    kname = {"split_bf16": "k_assign_bf16", "fp32": "k_assign_valu<float>", "fp64": "k_assign_valu<double>"}
+    kname = {"split_bf16": "k_assign_bf16 (cluster draw with the sub-cluster draw and statistics fused)",
+             "fp32": "k_assign_valu<float>", "fp64": "k_assign_valu<double>"}
     traffic = measured_traffic() if args.precision == "split_bf16" and args.workload == "c5" else None
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

@@ -28,7 +28,7 @@ RESOURCES = os.path.join(BUILD_DIR, "kernel_resources.txt")
 # dpmm_stats) or debug variants (the per-cell score dump, first template flag
 # DUMP of the sub-cluster passes)
 SCRATCH_OK = (re.compile(r"k_log_joint"), re.compile(r"k_sub_stats<\w+, \w+, true,"),
-              re.compile(r"k_lay_sub<true,"), re.compile(r"k_mov_sub<true,"))
+              re.compile(r"k_lay_sub<true,"), re.compile(r"k_mov_span<true,"))
 
 
 def _resources(text: str) -> list[dict]:

@@ -250,8 +250,11 @@ int32_t k_hint(const dpmm_ctx* ctx)
 // flags; with split-BF16 the cluster-sorted copy is rebuilt from the labels
 dpmm_status recompute_stats(dpmm_ctx* ctx)
 {
-    // no sweep has drawn these labels: no proposal term yet (all NaN)
+    // no sweep has drawn these labels: no proposal term yet (all NaN); the
+    // per-cluster sums of the term start at zero (each split pass clears
+    // them again after use)
     if (ctx->ws.subdd) HIP_TRY(hipMemsetAsync(ctx->ws.subdd, 0xFF, 8 * (size_t)ctx->N, ctx->stream));
+    HIP_TRY(hipMemsetAsync(ctx->ws.qsub, 0, sizeof(double) * (size_t)ctx->k_max, ctx->stream));
     launch_stats(ctx->ws, ctx->c[ctx->cur], ctx->cs[ctx->cur], ctx->stream);
     launch_compact(ctx->ws, 0, ctx->stream);
     launch_relabel(ctx->ws, ctx->c[ctx->cur], ctx->cs[ctx->cur], ctx->stream);
@@ -551,10 +554,13 @@ dpmm_status dpmm_sweep(dpmm_ctx* ctx, int32_t n_sweeps)
             launch_relayout(ws, ctx->c[ctx->cur], ctx->tiles, 0, ctx->stream);
             ctx->since_layout = 0;
         }
+        // a random split next: its coins and coin halves come with this pass
+        const bool rsplit = n + 1 == n_sweeps && ws.rssub && chain_pass(ctx, step + 1) == 2;
         {
             StageTimer st(ctx, DPMM_STAGE_REDRAW);
             if (ws.flags & kFlagNewCluster) launch_extend(ws, ctx->stream);
-            launch_redraw(ws, step, ctx->precision == DPMM_SPLIT_BF16, ctx->stream);   // also empties the re-score queue
+            // (also empties the re-score queue, and clears the coin halves for rsplit)
+            launch_redraw(ws, step, ctx->precision == DPMM_SPLIT_BF16, rsplit, ctx->stream);
             if (ctx->precision == DPMM_SPLIT_BF16) launch_lay_btab(ws, ctx->stream);
         }
         AssignArgs a{};
@@ -578,8 +584,7 @@ dpmm_status dpmm_sweep(dpmm_ctx* ctx, int32_t n_sweeps)
         sa.dbg = ctx->dbg;
         sa.dbg_stride = ctx->dbg_cap + 2;
         sa.dbg64 = ctx->dbg64;
-        // a random split next: its coins and coin halves come with this pass
-        if (n + 1 == n_sweeps && ws.rssub && chain_pass(ctx, step + 1) == 2) {
+        if (rsplit) {
             sa.rsplit = 1;
             sa.rs_step = step + 1;
         }
@@ -593,7 +598,7 @@ dpmm_status dpmm_sweep(dpmm_ctx* ctx, int32_t n_sweeps)
             else if (ctx->precision == DPMM_FP32) launch_assign_fp32(ws, a, ctx->stream);
             else launch_assign_bf16(ws, a, fused ? &sa : nullptr, ctx->stream);
         }
-        if (a.refine) {
+        if (a.refine && !fused) {      // (the fused pass re-scores in its queue kernel)
             StageTimer st(ctx, DPMM_STAGE_REFINE);
             launch_refine(ws, a, ctx->stream);
         }

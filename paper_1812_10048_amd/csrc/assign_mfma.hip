@@ -407,7 +407,10 @@ k_assign_bf16(Ws ws, AssignArgs a, SubArgs sa)
                 uncertain = true;
         }
         a.c_new[cell] = top.k1;
-        if (uncertain) {
+        // an uncertain decision is re-scored in FP64: by k_refine, or with the
+        // fused sub-cluster pass by k_mov_span, which serves that cell's queue
+        // entry (flagged) before its sub-cluster draw
+        if (!SUB && uncertain) {
             const int q = atomicAdd(&ws.st->n_refine, 1);
             if (q < ws.N) ws.refine[q] = (uint32_t)cell | kRefineCluster;
         }
@@ -415,7 +418,7 @@ k_assign_bf16(Ws ws, AssignArgs a, SubArgs sa)
         if (SUB) {
             // the fused sub-cluster pass: a cell whose certified new label is
             // the block's cluster draws its sub-label here; any other goes to
-            // the queue that k_mov_sub serves after the FP64 re-score
+            // the queue that k_mov_span serves
             const uint32_t i = (uint32_t)cell;
             if (!uncertain && top.k1 == L && L < K) {
                 const bool reset = ws.reset[L] != 0;
@@ -457,7 +460,7 @@ k_assign_bf16(Ws ws, AssignArgs a, SubArgs sa)
                 if (ws.subdd) ws.subdd[i] = reset ? __builtin_nan("") : dd;
             } else {
                 const int q = atomicAdd(&ws.st->n_mov, 1);
-                if (q < ws.N) ws.mov[q] = i;
+                if (q < ws.N) ws.mov[q] = i | (uncertain ? kRefineCluster : 0u);
             }
         }
     }
@@ -585,10 +588,7 @@ void launch_assign_bf16(const Ws& ws, const AssignArgs& a, const SubArgs* sub, h
     const int nt = k_hint <= 16 ? 1 : k_hint <= 32 ? 2 : k_hint <= 48 ? 3 : 4;
     const SubArgs none{};
     if (sub) {
-        if (sub->rsplit) {
-            launch_zero(ws.rssub, sizeof(unsigned long long) * 2 * (size_t)ws.k_max * (size_t)ws.G, s);
-            launch_zero(ws.rnsub, sizeof(unsigned long long) * 2 * (size_t)ws.k_max, s);
-        }
+        // (with rsplit, the redraw of the same sweep has cleared rssub / rnsub)
         switch (nt) {
         case 1: launch_nt<1, true>(ws, a, *sub, s); break;
         case 2: launch_nt<2, true>(ws, a, *sub, s); break;

@@ -461,18 +461,19 @@ __global__ void __launch_bounds__(1024) k_compact(Ws ws, int after_sweep)
     // the coin-half statistics of a coming random split move with the rest
     const bool rs = ws.rssub && ws.st->rs_live;
     if (s_changed || nk < K) {
+        // (lds_map is uniform over the workgroup: only a row that moves costs
+        // a barrier, which orders it before a later move into its place)
         for (int k = 0; k < K; ++k) {
             const int j = lds_map[k];
-            if (j >= 0 && j != k) {
+            if (j < 0 || j == k) continue;
+            for (int u = t; u < 2 * G; u += blockDim.x)
+                ws.ssub[(int64_t)2 * j * G + u] = ws.ssub[(int64_t)2 * k * G + u];
+            if (rs)
                 for (int u = t; u < 2 * G; u += blockDim.x)
-                    ws.ssub[(int64_t)2 * j * G + u] = ws.ssub[(int64_t)2 * k * G + u];
-                if (rs)
-                    for (int u = t; u < 2 * G; u += blockDim.x)
-                        ws.rssub[(int64_t)2 * j * G + u] = ws.rssub[(int64_t)2 * k * G + u];
-                if (t < 2) ws.nsub[2 * j + t] = ws.nsub[2 * k + t];
-                if (rs && t < 2) ws.rnsub[2 * j + t] = ws.rnsub[2 * k + t];
-                if (t == 0) ws.reset[j] = ws.reset[k];
-            }
+                    ws.rssub[(int64_t)2 * j * G + u] = ws.rssub[(int64_t)2 * k * G + u];
+            if (t < 2) ws.nsub[2 * j + t] = ws.nsub[2 * k + t];
+            if (rs && t < 2) ws.rnsub[2 * j + t] = ws.rnsub[2 * k + t];
+            if (t == 0) ws.reset[j] = ws.reset[k];
             __syncthreads();
         }
         for (int k = nk; k < K; ++k) {

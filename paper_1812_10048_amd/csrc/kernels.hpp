@@ -41,7 +41,7 @@ void launch_filter_fill(const int64_t* row_ptr, const int32_t* col, const int32_
 struct SubArgs {
     const int32_t* c_old;
     const uint8_t* cs_old;
-    const int32_t* c_new;
+    int32_t* c_new;       // (written by the queue kernel for a re-scored cell)
     uint8_t* cs_new;
     uint32_t step;
     void* dbg;            // optional score dump (FP32, or FP64 when dbg64), row stride dbg_stride
@@ -53,8 +53,9 @@ struct SubArgs {
 void launch_sub_stats(const Ws& ws, const SubArgs& a, hipStream_t s);
 // laysub.hip (split-BF16 sweeps, over the cluster-sorted copy)
 void launch_lay_sub(const Ws& ws, const SubArgs& a, hipStream_t s);
-// the rest of that pass after its fused form in launch_assign_bf16: the queued
-// cells (after the FP64 re-score) and the sums of the block histograms
+// the rest of that pass (also after its fused form in launch_assign_bf16):
+// the queued cells (those flagged kRefineCluster re-scored in FP64 first) and
+// the sums of the block histograms, in one launch
 void launch_lay_sub_rest(const Ws& ws, const SubArgs& a, hipStream_t s);
 hipError_t sub_stats_cells(int64_t N, int G, int32_t* cells);
 void launch_compact(const Ws& ws, int after_sweep, hipStream_t s);
@@ -62,7 +63,8 @@ void launch_relabel(const Ws& ws, int32_t* c, uint8_t* cs, hipStream_t s);
 void launch_check_labels(const Ws& ws, const int32_t* c, const uint8_t* cs, int32_t K, hipStream_t s);
 
 // redraw.hip
-void launch_redraw(const Ws& ws, uint32_t step, int write_split, hipStream_t s);
+// zero_rs: also clear rssub / rnsub (a random split follows the sweep)
+void launch_redraw(const Ws& ws, uint32_t step, int write_split, int zero_rs, hipStream_t s);
 
 // assign.hip
 struct AssignArgs {

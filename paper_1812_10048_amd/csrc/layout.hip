@@ -392,8 +392,11 @@ __device__ inline void lay_dtab(const Ws& ws, int L, int K, int KL)
 // After every redraw: the hi/lo tables of log theta (split-BF16, cluster-major
 // [k][Gpad]) with the genes in each layout cluster's order, for the first
 // kLayDmax chunks: tab[L][col][j] = table[col][gene_L[j]], zero for the
-// columns past K that the kernel's last column tile reads.  The first k_max
-// blocks write the fixed-point difference tables above instead.
+// columns past K that the kernel's last column tile reads.  That kernel reads
+// columns below K + kSubDigits rounded up to its column group (at most 64
+// columns), so the columns from K + kSubDigits + 63 on are left as they are.
+// The first k_max blocks write the fixed-point difference tables above
+// instead.
 __global__ void __launch_bounds__(256) k_lay_btab(Ws ws)
 {
     const int K = ws.st->K;
@@ -403,14 +406,15 @@ __global__ void __launch_bounds__(256) k_lay_btab(Ws ws)
         lay_dtab(ws, (int)blockIdx.x, K, KL);
         return;
     }
-    const int64_t n = (int64_t)KL * ws.lay_cols * R;
+    const int ncol = min(ws.lay_cols, K + kSubDigits + 63);
+    const int64_t n = (int64_t)KL * ncol * R;
     const int64_t stride = (int64_t)(gridDim.x - ws.k_max) * blockDim.x;
     // (the digit columns of live, non-reset clusters are lay_dtab's)
     for (int64_t q = (int64_t)(blockIdx.x - ws.k_max) * blockDim.x + threadIdx.x; q < n; q += stride) {
         const int j = (int)(q % R);
         const int64_t lc = q / R;
-        const int col = (int)(lc % ws.lay_cols);
-        const int L = (int)(lc / ws.lay_cols);
+        const int col = (int)(lc % ncol);
+        const int L = (int)(lc / ncol);
         if (col >= K && col < K + kSubDigits && L < K && !ws.reset[L]) continue;
         uint16_t hi = 0, lo = 0;
         if (col < K) {
@@ -418,8 +422,9 @@ __global__ void __launch_bounds__(256) k_lay_btab(Ws ws)
             hi = ws.lhi[at];
             lo = ws.llo[at];
         }
-        ws.lay_bhi[q] = hi;
-        ws.lay_blo[q] = lo;
+        const int64_t o = ((int64_t)L * ws.lay_cols + col) * R + j;
+        ws.lay_bhi[o] = hi;
+        ws.lay_blo[o] = lo;
     }
 }
 

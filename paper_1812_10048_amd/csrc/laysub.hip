@@ -8,7 +8,7 @@
 // (lane l: cell l % 16 of the tile, places 8 (l / 16) .. + 7 and
 // 32 + 8 (l / 16) .. + 7 of each chunk of 64 places).  The block's cells whose
 // new label is L (nearly all of them once the chain has settled) are drawn
-// here; any other cell of the block goes to a queue that k_mov_sub serves
+// here; any other cell of the block goes to a queue that k_mov_span serves
 // from the packed matrix, exactly as the packed-matrix pass would.  After the
 // workgroup has staged what depends on L, each wavefront works on its own,
 // with no further barrier until the block's histogram is written:
@@ -32,7 +32,7 @@
 //      per-block LDS histogram over (row, gene), together with the tail
 //      entries (a count above 255 is a tail entry too, and those crowd on a
 //      cluster's top genes).  Each block writes its whole histogram to
-//      lay_part; k_lay_span adds them over spans of consecutive blocks of a
+//      lay_part; k_mov_span adds them over spans of consecutive blocks of a
 //      cluster and adds the span sums to the statistics: device-scope 64-bit
 //      atomics from every cell (or every block) on a cluster's few hot
 //      addresses would serialise.  (Past kLsHistWords histogram words, the
@@ -44,7 +44,7 @@
 namespace dpmm {
 
 constexpr int kLsThreads = 2 * kBlkCells;     // 8 wavefronts of 32 cells
-constexpr int kMovGroups = 32;                 // cells per workgroup pass of k_mov_sub (8 lanes each)
+constexpr int kMovGroups = kPlaces / 8;        // cells per workgroup pass of the queue (8 lanes each)
 constexpr int kMovLanes = 8;
 constexpr int kRedSpan = kSpanBlocks;
 
@@ -355,25 +355,74 @@ k_lay_sub(Ws ws, SubArgs a)
     if (rs && t < 2 && ncnt2[t]) atomicAdd(&ws.rnsub[2 * L + t], (unsigned long long)ncnt2[t]);
 }
 
+// FP64 re-score of a queued cluster decision (eq. 4, third line, with the
+// FP64 tables) by the cell's kMovLanes lanes: every lane sums its share of the
+// packed row against log theta_k, the shares are combined in a fixed pattern
+// that gives all lanes the same value, and the Gumbel-max runs over the K
+// clusters in order with FP64 noise.  *near: the relative margin is below
+// kNearTie.
+__device__ inline int rescore_lanes(const Ws& ws, uint32_t step, uint32_t i, int64_t rb, int64_t re, int lg, int K,
+                                    bool* near)
+{
+    double best = -INFINITY, second = -INFINITY;
+    int bk = 0;
+    Words w{};
+    for (int kk = 0; kk < K; ++kk) {
+        const double* lrow = ws.lt64 + (int64_t)kk * ws.G;
+        double sk = 0.0;
+        for (int64_t p = rb + 4 * lg; p < re; p += 4 * kMovLanes) {
+            const uint4 v = *reinterpret_cast<const uint4*>(ws.ent + p);
+            const uint32_t en[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t x = en[j] >> 16;
+                if (x) sk = fma((double)x, lrow[en[j] & 0xFFFFu], sk);
+            }
+        }
+        for (int o = kMovLanes / 2; o > 0; o >>= 1) sk += __shfl_xor(sk, o, kMovLanes);
+        if ((kk & 3) == 0) w = philox(ws.seed, i, (uint32_t)(kk >> 2), step, kGumbelC, 0u);
+        const double v = ws.logpi[kk] + sk + (-log(-log(unit23d(w.w[kk & 3]))));
+        if (v > best) { second = best; best = v; bk = kk; }
+        else if (v > second) second = v;
+    }
+    *near = K >= 2 && (best - second) / fmax(1.0, fabs(best)) < kNearTie;
+    return bk;
+}
+
 // The queued cells, each by 8 lanes from the packed matrix: the same FP64 sum
 // and draw as the packed-matrix pass, and the statistics with 64-bit atomics.
+// An entry flagged kRefineCluster (an uncertain cluster decision of the fused
+// pass) is re-scored first.  mb / nmb: this workgroup's index among the nmb
+// workgroups that take the queue.
 template <bool DUMP, bool SPLITQ>
-__global__ void __launch_bounds__(256) k_mov_sub(Ws ws, SubArgs a)
+__device__ void mov_sub(const Ws& ws, const SubArgs& a, int mb, int nmb)
 {
     const int n = (int)min((int64_t)ws.st->n_mov, ws.N);
     const int K = ws.st->K;
     const int G = ws.G;
     const bool rs = a.rsplit != 0;
     const int lg = threadIdx.x % kMovLanes;
-    const int64_t first = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kMovLanes;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x / kMovLanes;
+    const int64_t first = ((int64_t)mb * blockDim.x + threadIdx.x) / kMovLanes;
+    const int64_t stride = (int64_t)nmb * blockDim.x / kMovLanes;
     for (int64_t q = first; q < n; q += stride) {
-        const uint32_t i = ws.mov[q];
-        const int k = a.c_new[i];
+        const uint32_t item = ws.mov[q];
+        const uint32_t i = item & ~kRefineCluster;
+        const int64_t rb = ws.roff[i], re = ws.roff[i + 1];
+        int k;
+        if (item & kRefineCluster) {
+            bool near;
+            k = rescore_lanes(ws, a.step, i, rb, re, lg, K, &near);
+            if (lg == 0) {
+                a.c_new[i] = k;
+                atomicAdd(&ws.st->counters[kCntRefined], 1ull);
+                if (near) atomicAdd(&ws.st->counters[kCntNearTie], 1ull);
+            }
+        } else {
+            k = a.c_new[i];
+        }
         const bool reset = ws.reset[k] != 0;
         const double* g0 = ws.lt64 + (int64_t)(ws.k_max + 2 * k) * G;
         const double* g1 = g0 + G;
-        const int64_t rb = ws.roff[i], re = ws.roff[i + 1];
         double df = 0.0, s0 = 0.0, s1 = 0.0;
         if (!reset) {
             for (int64_t p = rb + 4 * lg; p < re; p += 4 * kMovLanes) {
@@ -441,14 +490,13 @@ __global__ void __launch_bounds__(256) k_mov_sub(Ws ws, SubArgs a)
 
 // The blocks' histograms into the statistics.  The blocks of each layout
 // cluster L are consecutive, from lay_bbeg[L]; they are cut into spans of
-// kRedSpan blocks, lay_sbeg[L] spans before L's first.  Workgroup (x, r) sums
-// row r of span x's histograms, place by place, and adds each non-zero sum to
-// the statistics of the place's gene with one 64-bit atomic: a few per
-// address and span instead of one per count.
-__global__ void __launch_bounds__(kPlaces) k_lay_span(Ws ws)
+// kRedSpan blocks, lay_sbeg[L] spans before L's first.  A workgroup of kPlaces
+// threads sums row r of span x's histograms, place by place, and adds each
+// non-zero sum to the statistics of the place's gene with one 64-bit atomic:
+// a few per address and span instead of one per count.
+__device__ void lay_span(const Ws& ws, int x, int r)
 {
     const int KL = ws.st->lay_K;
-    const int x = blockIdx.x;
     if (x >= ws.lay_sbeg[KL]) return;
     int lo = 0, hi = KL;               // lay_sbeg[lo] <= x < lay_sbeg[hi]
     while (hi - lo > 1) {
@@ -458,7 +506,7 @@ __global__ void __launch_bounds__(kPlaces) k_lay_span(Ws ws)
     }
     const int L = lo;
     if (L >= ws.st->K) return;
-    const int r = blockIdx.y, p = threadIdx.x;
+    const int p = threadIdx.x;
     const int b0 = ws.lay_bbeg[L] + (x - ws.lay_sbeg[L]) * kRedSpan;
     const int nb = min(ws.lay_bbeg[L + 1] - b0, kRedSpan);
     const int64_t pw = ws.lay_pw;
@@ -481,6 +529,17 @@ __global__ void __launch_bounds__(kPlaces) k_lay_span(Ws ws)
     atomicAdd(dst, (unsigned long long)acc);
 }
 
+// Both remainders of the pass in one launch (they are independent: both only
+// add to the statistics): the first nspan x rows workgroups sum the block
+// histograms (span x, row r), the others serve the queue.
+template <bool DUMP, bool SPLITQ>
+__global__ void __launch_bounds__(kPlaces) k_mov_span(Ws ws, SubArgs a, int nspan, int rows)
+{
+    const int b = (int)blockIdx.x, ns = nspan * rows;
+    if (b < ns) lay_span(ws, b % nspan, b / nspan);
+    else mov_sub<DUMP, SPLITQ>(ws, a, b - ns, (int)gridDim.x - ns);
+}
+
 using LaySubKernel = void (*)(Ws, SubArgs);
 
 static LaySubKernel lay_sub_kernel(bool dump, bool split_q)
@@ -489,21 +548,19 @@ static LaySubKernel lay_sub_kernel(bool dump, bool split_q)
                 : (split_q ? k_lay_sub<false, true> : k_lay_sub<false, false>);
 }
 
-static LaySubKernel mov_sub_kernel(bool dump, bool split_q)
+using MovSpanKernel = void (*)(Ws, SubArgs, int, int);
+
+static MovSpanKernel mov_span_kernel(bool dump, bool split_q)
 {
-    return dump ? (split_q ? k_mov_sub<true, true> : k_mov_sub<true, false>)
-                : (split_q ? k_mov_sub<false, true> : k_mov_sub<false, false>);
+    return dump ? (split_q ? k_mov_span<true, true> : k_mov_span<true, false>)
+                : (split_q ? k_mov_span<false, true> : k_mov_span<false, false>);
 }
 
-// The sub-cluster pass of a split-BF16 sweep: the statistics and counts were
-// cleared by the redraw of the same sweep (k_redraw_norm), which also emptied
-// the queue of k_mov_sub.
+// The sub-cluster pass of a split-BF16 sweep: the statistics and counts (and,
+// with rsplit, the coin halves') were cleared by the redraw of the same sweep
+// (k_redraw_norm), which also emptied the queue of k_mov_span.
 void launch_lay_sub(const Ws& ws, const SubArgs& a, hipStream_t s)
 {
-    if (a.rsplit) {
-        launch_zero(ws.rssub, sizeof(unsigned long long) * 2 * (size_t)ws.k_max * (size_t)ws.G, s);
-        launch_zero(ws.rnsub, sizeof(unsigned long long) * 2 * (size_t)ws.k_max, s);
-    }
     const bool dump = a.dbg != nullptr, split_q = ws.subdd != nullptr;
     hipLaunchKernelGGL(lay_sub_kernel(dump, split_q), dim3((unsigned)ws.nblk_cap), dim3(kLsThreads), 0, s, ws, a);
     launch_lay_sub_rest(ws, a, s);
@@ -513,11 +570,11 @@ void launch_lay_sub_rest(const Ws& ws, const SubArgs& a, hipStream_t s)
 {
     const bool dump = a.dbg != nullptr, split_q = ws.subdd != nullptr;
     int64_t mb = (ws.N + kMovGroups - 1) / kMovGroups;
-    if (mb > 1024) mb = 1024;
-    hipLaunchKernelGGL(mov_sub_kernel(dump, split_q), dim3((unsigned)mb), dim3(kMovGroups * kMovLanes), 0, s, ws, a);
+    if (mb > 512) mb = 512;
     const int rows = a.rsplit ? 4 : 2;
-    hipLaunchKernelGGL(k_lay_span, dim3((unsigned)lay_spans(ws.nblk_cap, ws.k_max), (unsigned)rows), dim3(kPlaces), 0, s,
-                       ws);
+    const int nspan = lay_spans(ws.nblk_cap, ws.k_max);
+    hipLaunchKernelGGL(mov_span_kernel(dump, split_q), dim3((unsigned)(nspan * rows + mb)), dim3(kPlaces), 0, s, ws, a,
+                       nspan, rows);
 }
 
 }  // namespace dpmm

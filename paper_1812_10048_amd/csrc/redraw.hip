@@ -175,7 +175,10 @@ __global__ void __launch_bounds__(kRedrawThreads) k_redraw_draw(Ws ws, uint32_t 
 // counts at the start of the sweep, which feed eq. 8, move to nsub_prev, and
 // the new counts, statistics and sort counters start from zero.  Pass 1 has
 // read them; nothing else reads them before the sub-cluster pass rebuilds them.
-__global__ void __launch_bounds__(kRedrawThreads) k_redraw_norm(Ws ws, int write_split)
+// With zero_rs the coin-half statistics (rssub / rnsub) start from zero too:
+// the sub-cluster pass of this sweep gathers them for the random split that
+// follows it.
+__global__ void __launch_bounds__(kRedrawThreads) k_redraw_norm(Ws ws, int write_split, int zero_rs)
 {
     const int K = ws.st->K;
     // the re-score queue of the sweep that follows starts empty
@@ -190,6 +193,11 @@ __global__ void __launch_bounds__(kRedrawThreads) k_redraw_norm(Ws ws, int write
         for (int64_t q = t0; q < ws.k_max; q += nt) ws.grp_cnt[q] = 0;
         ulonglong2* sv = reinterpret_cast<ulonglong2*>(ws.ssub);      // 2 k_max G is even
         for (int64_t q = t0; q < (int64_t)ws.k_max * ws.G; q += nt) sv[q] = make_ulonglong2(0ull, 0ull);
+        if (zero_rs) {
+            ulonglong2* rv = reinterpret_cast<ulonglong2*>(ws.rssub);
+            for (int64_t q = t0; q < (int64_t)ws.k_max * ws.G; q += nt) rv[q] = make_ulonglong2(0ull, 0ull);
+            for (int64_t q = t0; q < 2 * (int64_t)ws.k_max; q += nt) ws.rnsub[q] = 0;
+        }
     }
     const int row = blockIdx.x;
     const int tile = blockIdx.y;
@@ -223,11 +231,12 @@ __global__ void __launch_bounds__(kRedrawThreads) k_redraw_norm(Ws ws, int write
     }
 }
 
-void launch_redraw(const Ws& ws, uint32_t step, int write_split, hipStream_t s)
+void launch_redraw(const Ws& ws, uint32_t step, int write_split, int zero_rs, hipStream_t s)
 {
     const dim3 grid((unsigned)(3 * ws.k_max + 1), (unsigned)redraw_tiles(ws.G));
     hipLaunchKernelGGL(k_redraw_draw, grid, dim3(kRedrawThreads), 0, s, ws, step);
-    hipLaunchKernelGGL(k_redraw_norm, grid, dim3(kRedrawThreads), 0, s, ws, write_split);
+    hipLaunchKernelGGL(k_redraw_norm, grid, dim3(kRedrawThreads), 0, s, ws, write_split,
+                       zero_rs && ws.rssub != nullptr ? 1 : 0);
 }
 
 }  // namespace dpmm

@@ -187,7 +187,10 @@ __global__ void __launch_bounds__(64) k_sm_finish(Ws ws, int mode, int T)
     const int lane = threadIdx.x;
     for (int k = blockIdx.x; k < K; k += gridDim.x) {
         if (mode != 2 && !split_eligible(ws, k, mode)) {
-            if (lane == 0) ws.sm_logr[k] = __builtin_nan("");
+            if (lane == 0) {
+                ws.sm_logr[k] = __builtin_nan("");
+                if (mode == 0) ws.qsub[k] = 0.0;        // ready for the next split pass
+            }
             continue;
         }
         const SmPart* part = ws.sm_part + (int64_t)k * T;
@@ -234,6 +237,7 @@ __global__ void __launch_bounds__(64) k_sm_finish(Ws ws, int mode, int T)
                 tot.add(lg[7] + lg[4] + lg[5] - lg[6]);
                 if (mode == 1) tot.add((double)(n0 + n1 - 2) * log(2.0));    // chain B, Section 2.4
                 else if (ws.flags & kFlagSplitQ) tot.add(-ws.qsub[k]);      // proposal term, Section 2.3
+                if (mode == 0) ws.qsub[k] = 0.0;        // ready for the next split pass
                 ws.sm_logr[k] = tot.value();
             }
         }
@@ -339,22 +343,37 @@ __global__ void __launch_bounds__(kMergeThreads) k_merge_ratios(Ws ws)
 // Q_k = sum over the cells now in cluster k of log p(cbar_i) from the last
 // sweep (the split proposal term of Section 2.3), formed here from the score
 // difference of each cell's draw and its sub-label (only split passes need
-// it): per-workgroup LDS sums, then one FP64 atomic per cluster.
-constexpr int kQThreads = 256;
+// it): per-workgroup LDS sums, then one FP64 atomic per cluster into qsub,
+// which is zero on entry (k_sm_finish clears it after use).  Each thread takes
+// kQCells cells a workgroup-width apart, all loads issued before the sums.
+constexpr int kQThreads = 1024;
+constexpr int kQCells = 4;
 __global__ void __launch_bounds__(kQThreads) k_split_q(Ws ws, const int32_t* __restrict__ c,
                                                        const uint8_t* __restrict__ cs)
 {
     extern __shared__ double qacc[];     // [K]
     const int K = ws.st->K;
     for (int k = threadIdx.x; k < K; k += kQThreads) qacc[k] = 0.0;
-    __syncthreads();
-    for (int64_t i = (int64_t)blockIdx.x * kQThreads + threadIdx.x; i < ws.N; i += (int64_t)gridDim.x * kQThreads) {
-        const int k = c[i];
-        if (k >= 0 && k < K) {
-            const double dd = ws.subdd[i];
-            if (!isnan(dd)) atomicAdd(&qacc[k], sub_logp(dd, cs[i] & 1));
-        }
+    const int64_t i0 = (int64_t)blockIdx.x * (kQThreads * kQCells) + threadIdx.x;
+    int kk[kQCells];
+#pragma unroll
+    for (int j = 0; j < kQCells; ++j) {
+        const int64_t i = i0 + (int64_t)j * kQThreads;
+        kk[j] = i < ws.N ? c[i] : -1;
     }
+    double dd[kQCells];
+    int sb[kQCells];
+#pragma unroll
+    for (int j = 0; j < kQCells; ++j) {
+        const int64_t i = i0 + (int64_t)j * kQThreads;
+        const bool live = kk[j] >= 0 && kk[j] < K;
+        dd[j] = live ? ws.subdd[i] : __builtin_nan("");
+        sb[j] = live ? (cs[i] & 1) : 0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kQCells; ++j)
+        if (!isnan(dd[j])) atomicAdd(&qacc[kk[j]], sub_logp(dd[j], sb[j]));
     __syncthreads();
     for (int k = threadIdx.x; k < K; k += kQThreads)
         if (qacc[k] != 0.0) atomicAdd(&ws.qsub[k], qacc[k]);
@@ -363,8 +382,10 @@ __global__ void __launch_bounds__(kQThreads) k_split_q(Ws ws, const int32_t* __r
 void launch_split_ratios(const Ws& ws, const int32_t* c, const uint8_t* cs, hipStream_t s)
 {
     if (ws.flags & kFlagSplitQ) {
-        launch_zero(ws.qsub, sizeof(double) * (size_t)ws.k_max, s);
-        hipLaunchKernelGGL(k_split_q, dim3(256), dim3(kQThreads), sizeof(double) * (size_t)ws.k_max, s, ws, c, cs);
+        const int64_t per = (int64_t)kQThreads * kQCells;
+        const int64_t blocks = ws.N > 0 ? (ws.N + per - 1) / per : 1;
+        hipLaunchKernelGGL(k_split_q, dim3((unsigned)blocks), dim3(kQThreads), sizeof(double) * (size_t)ws.k_max, s,
+                           ws, c, cs);
     }
     launch_sm_pair(ws, 0, s);
 }

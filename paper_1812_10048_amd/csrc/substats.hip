@@ -296,12 +296,9 @@ hipError_t sub_stats_cells(int64_t N, int G, int32_t* cells)
 
 void launch_sub_stats(const Ws& ws, const SubArgs& a, hipStream_t s)
 {
-    // the counts were cleared by the redraw of the same sweep (k_redraw_norm)
+    // the counts (and, with rsplit, the coin halves') were cleared by the
+    // redraw of the same sweep (k_redraw_norm)
     launch_sort(ws, a.c_new, a.cs_old, 1, s, true, a.c_old);
-    if (a.rsplit) {
-        launch_zero(ws.rssub, sizeof(unsigned long long) * 2 * (size_t)ws.k_max * (size_t)ws.G, s);
-        launch_zero(ws.rnsub, sizeof(unsigned long long) * 2 * (size_t)ws.k_max, s);
-    }
     hipLaunchKernelGGL(sub_stats_kernel(ws.G, a.dbg != nullptr, ws.subdd != nullptr), dim3((unsigned)((ws.N + ws.sub_cells - 1) / ws.sub_cells)), dim3(kSubThreads),
                        sub_stats_lds(ws.G, a.rsplit != 0), s, ws, a);
 }

@@ -363,6 +363,29 @@ def test_many_cluster_kernel_paths(precision, k_init):
     ls.finish()
 
 
+def test_every_decision_rescored_in_the_fused_pass():
+    """With refine_tol 1 every cluster decision of the split-BF16 sweep is
+    uncertain, so the queue kernel of the fused sub-cluster pass re-scores each
+    cell in FP64 (eq. 4) before its sub-cluster draw (eq. 8): the chain still
+    matches the oracle in lockstep, and every decision is counted."""
+    say("rescore all")
+    d = synth.generate("c1", seed=6, n_cells=3000)
+    kw = dict(alpha=1.0, beta=1.0, seed=21, k_max=32, k_init=6)
+    o = _oracle(d, **kw)
+    s = _sampler(d, "split_bf16", refine_tol=1.0, **kw)
+    r0 = s.stats()["refined"]
+    ls = Lockstep("rescore-all", o, s)
+    for _ in range(3):
+        K = s.K
+        r1 = s.stats()["refined"]
+        ls.sweep()
+        if K >= 2:
+            assert s.stats()["refined"] - r1 == d.n_cells
+        ls.split_merge()
+    ls.finish()
+    assert s.stats()["refined"] > r0
+
+
 def test_split_bf16_tables_are_hi_lo_of_log_theta():
     """Row a8: hi = bf16(fp32(log theta)), lo = bf16(fp32(log theta - hi)),
     round to nearest even, and |log theta - hi - lo| <= 2^-17 |log theta|."""

@@ -560,7 +560,8 @@ dpmm_status dpmm_sweep(dpmm_ctx* ctx, int32_t n_sweeps)
             StageTimer st(ctx, DPMM_STAGE_REDRAW);
             if (ws.flags & kFlagNewCluster) launch_extend(ws, ctx->stream);
             // (also empties the re-score queue, and clears the coin halves for rsplit)
-            launch_redraw(ws, step, ctx->precision == DPMM_SPLIT_BF16, rsplit, ctx->stream);
+            launch_redraw(ws, step, ctx->precision == DPMM_SPLIT_BF16, rsplit,
+                          k_hint(ctx) + ((ws.flags & kFlagNewCluster) ? 1 : 0), ctx->stream);
             if (ctx->precision == DPMM_SPLIT_BF16) launch_lay_btab(ws, ctx->stream);
         }
         AssignArgs a{};

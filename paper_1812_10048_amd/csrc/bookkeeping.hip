@@ -435,14 +435,21 @@ void launch_stats(const Ws& ws, const int32_t* c, const uint8_t* cs, hipStream_t
 // the consumed reset flags are cleared and a cluster of >= 2 cells with an
 // empty sub-cluster is flagged; after a split/merge the flags move along.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(1024) k_compact(Ws ws, int after_sweep)
+__global__ void __launch_bounds__(kMaxClusters) k_compact(Ws ws, int after_sweep)
 {
     extern __shared__ int32_t lds_map[];      // [k_max]
     __shared__ int32_t s_nk, s_changed;
-    const int K = ws.st->K;
     const int t = threadIdx.x;
-    // which clusters have cells, read by all threads; then the map in order
-    for (int k = t; k < K; k += blockDim.x) lds_map[k] = (ws.nsub[2 * k] + ws.nsub[2 * k + 1]) > 0 ? 1 : 0;
+    // thread t holds cluster t's counts (k_max <= kMaxClusters = blockDim.x),
+    // loaded before K is known
+    unsigned long long n0 = 0, n1 = 0;
+    if (t < ws.k_max) {
+        n0 = ws.nsub[2 * t];
+        n1 = ws.nsub[2 * t + 1];
+    }
+    const int K = ws.st->K;
+    // which clusters have cells; then the map in order
+    if (t < K) lds_map[t] = (n0 + n1) > 0 ? 1 : 0;
     __syncthreads();
     if (t == 0) {
         // changed: a cluster with cells takes a new index, so labels must be
@@ -493,14 +500,11 @@ __global__ void __launch_bounds__(1024) k_compact(Ws ws, int after_sweep)
         ws.relab_s[2 * k + 1] = 0xFF;
     }
     if (after_sweep) {
-        for (int k = t; k < ws.k_max; k += blockDim.x) {
-            uint8_t flag = 0;
-            if (k < nk) {
-                const unsigned long long n0 = ws.nsub[2 * k], n1 = ws.nsub[2 * k + 1];
-                flag = (n0 + n1 >= 2 && (n0 == 0 || n1 == 0)) ? 1 : 0;
-            }
-            ws.reset[k] = flag;
-        }
+        // cluster t (if it has cells) is now cluster lds_map[t] < nk, with the
+        // counts this thread holds; the flags from nk on are 0 (two disjoint
+        // sets of indices)
+        if (t < ws.k_max && t >= nk) ws.reset[t] = 0;
+        if (t < K && lds_map[t] >= 0) ws.reset[lds_map[t]] = (n0 + n1 >= 2 && (n0 == 0 || n1 == 0)) ? 1 : 0;
     }
     if (t == 0) {
         ws.st->K = nk;
@@ -537,7 +541,7 @@ void launch_extend(const Ws& ws, hipStream_t s)
 
 void launch_compact(const Ws& ws, int after_sweep, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), sizeof(int32_t) * (size_t)ws.k_max, s, ws, after_sweep);
+    hipLaunchKernelGGL(k_compact, dim3(1), dim3(kMaxClusters), sizeof(int32_t) * (size_t)ws.k_max, s, ws, after_sweep);
 }
 
 // Apply relab_c / relab_s to every label when the relabel flag is set.

@@ -63,8 +63,9 @@ void launch_relabel(const Ws& ws, int32_t* c, uint8_t* cs, hipStream_t s);
 void launch_check_labels(const Ws& ws, const int32_t* c, const uint8_t* cs, int32_t K, hipStream_t s);
 
 // redraw.hip
-// zero_rs: also clear rssub / rnsub (a random split follows the sweep)
-void launch_redraw(const Ws& ws, uint32_t step, int write_split, int zero_rs, hipStream_t s);
+// zero_rs: also clear rssub / rnsub (a random split follows the sweep);
+// k_guess: a recent K of the sweep (sizes the grid; any K is covered)
+void launch_redraw(const Ws& ws, uint32_t step, int write_split, int zero_rs, int k_guess, hipStream_t s);
 
 // assign.hip
 struct AssignArgs {

@@ -309,11 +309,15 @@ __device__ inline void lay_dtab(const Ws& ws, int L, int K, int KL)
     constexpr int kNoExp = -(1 << 30);         // no non-zero difference
     __shared__ int8_t dig[R][8];
     __shared__ int red[4];
-    if (L >= KL || L >= K || ws.reset[L]) return;
     const int t = threadIdx.x;
     const int G = ws.G;
     const double* g0 = ws.lt64 + (int64_t)(ws.k_max + 2 * L) * G;
     const double* g1 = g0 + G;
+    // L's gene order is loaded before the checks (L < k_max: in the table)
+    int ug[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) ug[h] = ws.lay_gene[(int64_t)L * R + t + 256 * h];
+    if (L >= KL || L >= K || ws.reset[L]) return;
     for (int u = t; u < G; u += 256) ws.lay_dfull[(int64_t)L * G + u] = g1[u] - g0[u];
     if (t == 0) {
         const SubWeights w = sub_weights(ws.nsub_prev, L);
@@ -327,7 +331,7 @@ __device__ inline void lay_dtab(const Ws& ws, int L, int K, int KL)
     int e = kNoExp;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-        const int u = ws.lay_gene[(int64_t)L * R + t + 256 * h];
+        const int u = ug[h];
         d[h] = g1[u] - g0[u];
         if (d[h] != 0.0) {
             int ex;

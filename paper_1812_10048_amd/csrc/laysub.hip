@@ -496,19 +496,28 @@ __device__ void mov_sub(const Ws& ws, const SubArgs& a, int mb, int nmb)
 // a few per address and span instead of one per count.
 __device__ void lay_span(const Ws& ws, int x, int r)
 {
+    // the span and block offsets of the layout clusters into LDS, then the
+    // span's cluster by bisection there
+    __shared__ int32_t s_sbeg[kMaxClusters + 1], s_bbeg[kMaxClusters + 1];
     const int KL = ws.st->lay_K;
-    if (x >= ws.lay_sbeg[KL]) return;
-    int lo = 0, hi = KL;               // lay_sbeg[lo] <= x < lay_sbeg[hi]
+    const int K = ws.st->K;
+    for (int q = threadIdx.x; q <= KL; q += blockDim.x) {
+        s_sbeg[q] = ws.lay_sbeg[q];
+        s_bbeg[q] = ws.lay_bbeg[q];
+    }
+    __syncthreads();
+    if (x >= s_sbeg[KL]) return;
+    int lo = 0, hi = KL;               // s_sbeg[lo] <= x < s_sbeg[hi]
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
-        if (ws.lay_sbeg[mid] <= x) lo = mid;
+        if (s_sbeg[mid] <= x) lo = mid;
         else hi = mid;
     }
     const int L = lo;
-    if (L >= ws.st->K) return;
+    if (L >= K) return;
     const int p = threadIdx.x;
-    const int b0 = ws.lay_bbeg[L] + (x - ws.lay_sbeg[L]) * kRedSpan;
-    const int nb = min(ws.lay_bbeg[L + 1] - b0, kRedSpan);
+    const int b0 = s_bbeg[L] + (x - s_sbeg[L]) * kRedSpan;
+    const int nb = min(s_bbeg[L + 1] - b0, kRedSpan);
     const int64_t pw = ws.lay_pw;
     const uint32_t* in = ws.lay_part + (int64_t)b0 * pw + (int64_t)r * kPlaces + p;
     uint32_t acc = 0;                  // at most kRedSpan x 256 cells x 65535 < 2^32

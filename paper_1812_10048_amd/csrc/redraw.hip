@@ -104,20 +104,29 @@ __device__ inline bool redraw_row(const Ws& ws, int row, int K, RedrawRow& rr)
     return true;
 }
 
-// Pass 1, one workgroup per (row, tile of kRedrawGenes genes): the log Gamma
-// variates of the tile, and the tile's (max, sum exp(v - max)).  The last row
-// (3 k_max) is log pi, drawn and normalised by its first tile alone.
+// The rows a sweep redraws, as virtual rows v: the K cluster rows (v < K),
+// then the 2K sub-cluster rows (row k_max + v - K).  The grid is sized from
+// the host's recent K and loops when K has grown past it; its last column
+// draws log pi.
+__device__ inline int redraw_vrow(const Ws& ws, int v, int K)
+{
+    return v < K ? v : ws.k_max + (v - K);
+}
+
+// Pass 1, one workgroup per (virtual row, tile of kRedrawGenes genes): the log
+// Gamma variates of the tile, and the tile's (max, sum exp(v - max)).  Log pi
+// is drawn and normalised by tile 0 of the grid's last column.
 __global__ void __launch_bounds__(kRedrawThreads) k_redraw_draw(Ws ws, uint32_t step)
 {
     __shared__ double red[kRedrawThreads / 64];
     const int K = ws.st->K;
-    const int row = blockIdx.x;
     const int tile = blockIdx.y;
     const int G = ws.G;
     const int t = threadIdx.x;
+    const int nrow = (int)gridDim.x - 1;        // columns of the gene rows
     int capped = 0;
 
-    if (row == 3 * ws.k_max) {
+    if ((int)blockIdx.x == nrow) {
         if (tile != 0) return;
         if (t == 0) atomicAdd(&ws.st->counters[kCntEvals], (unsigned long long)ws.N * (unsigned long long)(K + 2));
         double* lp = ws.logpi;
@@ -146,25 +155,29 @@ __global__ void __launch_bounds__(kRedrawThreads) k_redraw_draw(Ws ws, uint32_t 
         const double lse = m + log(block_sum(s, red));
         __syncthreads();
         for (int k = t; k < K; k += kRedrawThreads) lp[k] -= lse;
-        if (capped) atomicAdd(&ws.st->counters[kCntGammaCaps], 1ull);
+        if (capped) atomicAdd(&ws.st->counters[kCntGammaCaps], (unsigned long long)capped);
         return;
     }
 
-    RedrawRow rr;
-    if (!redraw_row(ws, row, K, rr)) return;
-    const unsigned long long* s0 = ws.ssub + (int64_t)(2 * rr.k) * G;
-    const unsigned long long* s1 = s0 + G;
     const int u = tile * kRedrawGenes + t;
-    double v = -INFINITY;
-    if (u < G) {
-        const unsigned long long cnt = rr.r < 0 ? s0[u] + s1[u] : (rr.r == 0 ? s0[u] : s1[u]);
-        v = log_gamma_draw(ws.beta[u] + (double)cnt, ws.seed, (uint32_t)u, rr.philox_row, step, kGamma, &capped);
-        rr.out[u] = v;
+#pragma unroll 1
+    for (int vr = blockIdx.x; vr < 3 * K; vr += nrow) {
+        const int row = redraw_vrow(ws, vr, K);
+        RedrawRow rr;
+        redraw_row(ws, row, K, rr);
+        const unsigned long long* s0 = ws.ssub + (int64_t)(2 * rr.k) * G;
+        const unsigned long long* s1 = s0 + G;
+        double v = -INFINITY;
+        if (u < G) {
+            const unsigned long long cnt = rr.r < 0 ? s0[u] + s1[u] : (rr.r == 0 ? s0[u] : s1[u]);
+            v = log_gamma_draw(ws.beta[u] + (double)cnt, ws.seed, (uint32_t)u, rr.philox_row, step, kGamma, &capped);
+            rr.out[u] = v;
+        }
+        const double m = block_max(v, red);
+        const double s = block_sum(u < G ? exp(v - m) : 0.0, red);
+        if (t == 0) ws.rd_part[(int64_t)row * redraw_tiles(G) + tile] = make_double2(m, s);
     }
-    const double m = block_max(v, red);
-    const double s = block_sum(u < G ? exp(v - m) : 0.0, red);
-    if (t == 0) ws.rd_part[(int64_t)row * redraw_tiles(G) + tile] = make_double2(m, s);
-    if (capped) atomicAdd(&ws.st->counters[kCntGammaCaps], 1ull);
+    if (capped) atomicAdd(&ws.st->counters[kCntGammaCaps], (unsigned long long)capped);
 }
 
 // Pass 2, same grid: the row's log normaliser from its tiles' partials
@@ -199,41 +212,49 @@ __global__ void __launch_bounds__(kRedrawThreads) k_redraw_norm(Ws ws, int write
             for (int64_t q = t0; q < 2 * (int64_t)ws.k_max; q += nt) ws.rnsub[q] = 0;
         }
     }
-    const int row = blockIdx.x;
     const int tile = blockIdx.y;
     const int G = ws.G;
     const int t = threadIdx.x;
-    RedrawRow rr;
-    if (row == 3 * ws.k_max || !redraw_row(ws, row, K, rr)) return;
     const int nt = redraw_tiles(G);
-    const double2* part = ws.rd_part + (int64_t)row * nt;
-    double m = -INFINITY;
-    for (int q = 0; q < nt; ++q) m = fmax(m, part[q].x);
-    double s = 0.0;
-    for (int q = 0; q < nt; ++q) s += part[q].y * exp(part[q].x - m);
-    const double lse = m + log(s);
     const int u = tile * kRedrawGenes + t;
-    if (u >= G) return;
-    const double v = rr.out[u] - lse;
-    rr.out[u] = v;
-    const int k = rr.k;
-    if (rr.r < 0) {
-        ws.lc32[(int64_t)u * ws.kpad + k] = (float)v;
-        if (write_split) {
-            const float f = (float)v;
-            const uint16_t hi = bf16_bits(f);
-            const uint16_t lo = bf16_bits((float)(v - (double)bf16_value(hi)));
-            ws.lhi[(int64_t)k * ws.Gpad + u] = hi;
-            ws.llo[(int64_t)k * ws.Gpad + u] = lo;
+    // the virtual rows of pass 1, by the same columns (the last one, log pi's,
+    // has nothing to do here)
+    const int nrow = (int)gridDim.x - 1;
+    if ((int)blockIdx.x == nrow) return;
+    for (int vr = blockIdx.x; vr < 3 * K; vr += nrow) {
+        const int row = redraw_vrow(ws, vr, K);
+        RedrawRow rr;
+        redraw_row(ws, row, K, rr);
+        const double2* part = ws.rd_part + (int64_t)row * nt;
+        double m = -INFINITY;
+        for (int q = 0; q < nt; ++q) m = fmax(m, part[q].x);
+        double s = 0.0;
+        for (int q = 0; q < nt; ++q) s += part[q].y * exp(part[q].x - m);
+        const double lse = m + log(s);
+        if (u >= G) continue;
+        const double v = rr.out[u] - lse;
+        rr.out[u] = v;
+        const int k = rr.k;
+        if (rr.r < 0) {
+            ws.lc32[(int64_t)u * ws.kpad + k] = (float)v;
+            if (write_split) {
+                const float f = (float)v;
+                const uint16_t hi = bf16_bits(f);
+                const uint16_t lo = bf16_bits((float)(v - (double)bf16_value(hi)));
+                ws.lhi[(int64_t)k * ws.Gpad + u] = hi;
+                ws.llo[(int64_t)k * ws.Gpad + u] = lo;
+            }
+        } else {
+            reinterpret_cast<float*>(ws.ls32)[((int64_t)u * ws.k_max + k) * 2 + rr.r] = (float)v;
         }
-    } else {
-        reinterpret_cast<float*>(ws.ls32)[((int64_t)u * ws.k_max + k) * 2 + rr.r] = (float)v;
     }
 }
 
-void launch_redraw(const Ws& ws, uint32_t step, int write_split, int zero_rs, hipStream_t s)
+void launch_redraw(const Ws& ws, uint32_t step, int write_split, int zero_rs, int k_guess, hipStream_t s)
 {
-    const dim3 grid((unsigned)(3 * ws.k_max + 1), (unsigned)redraw_tiles(ws.G));
+    // rows for a sweep over k_guess clusters (the kernels loop past it)
+    const int kg = k_guess > 0 && k_guess < ws.k_max ? k_guess : ws.k_max;
+    const dim3 grid((unsigned)(3 * kg + 1), (unsigned)redraw_tiles(ws.G));
     hipLaunchKernelGGL(k_redraw_draw, grid, dim3(kRedrawThreads), 0, s, ws, step);
     hipLaunchKernelGGL(k_redraw_norm, grid, dim3(kRedrawThreads), 0, s, ws, write_split,
                        zero_rs && ws.rssub != nullptr ? 1 : 0);

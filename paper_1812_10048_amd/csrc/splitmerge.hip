@@ -129,52 +129,61 @@ void launch_lgamma_beta(const Ws& ws, hipStream_t s)
 // (n - 2) log 2 that reverses the eq. 23 merge; 2: logDM(s_{k,0} + s_{k,1}).
 static_assert(kSmGenes == kSmThreads, "one gene per thread of a tile");
 
-__device__ inline bool split_eligible(const Ws& ws, int k, int mode)
+__device__ inline bool split_eligible(unsigned long long n0, unsigned long long n1, uint8_t reset, int mode)
 {
-    const unsigned long long n0 = ws.nsub[2 * k], n1 = ws.nsub[2 * k + 1];
-    return !((mode == 0 && ws.reset[k]) || n0 < 1 || n1 < 1);
+    return !((mode == 0 && reset) || n0 < 1 || n1 < 1);
 }
 
+// Workgroup (k, tile): one cluster per workgroup column (the grid has k_max
+// columns; those past K leave at once), its counts, beta and log Gamma(beta)
+// loaded together with what decides the cluster's eligibility.
 __global__ void __launch_bounds__(kSmThreads) k_sm_tiles(Ws ws, int mode)
 {
-    const int K = ws.st->K;
+    const int k = blockIdx.x;
+    if (k >= ws.st->K) return;
     const int G = ws.G;
     const int T = gridDim.y;
     const int u = blockIdx.y * kSmThreads + threadIdx.x;
-    for (int k = blockIdx.x; k < K; k += gridDim.x) {
-        if (mode != 2 && !split_eligible(ws, k, mode)) continue;
-        const unsigned long long* s0 = ws.ssub + (int64_t)(2 * k) * G;
-        const unsigned long long* s1 = s0 + G;
-        SmRed r;
-        r.a = r.b = 0;
-        r.beta = 0.0;
-        if (u < G) {
-            const double bu = ws.beta[u], lgb = ws.lgbeta[u];
-            r.beta = bu;
-            if (mode == 2) {
-                const long long v = (long long)(s0[u] + s1[u]);
-                r.a = v;
-                r.cs.add(rising(ws, u, bu, lgb, v));
-            } else {
-                const long long x0 = (long long)s0[u], x1 = (long long)s1[u];
-                r.a = x0;
-                r.b = x1;
-                if (x0 + x1 != 0) {
-                    r.cs.add(rising(ws, u, bu, lgb, x0));
-                    r.cs.add(rising(ws, u, bu, lgb, x1));
-                    r.cs.add(-rising(ws, u, bu, lgb, x0 + x1));
-                }
+    const unsigned long long* s0 = ws.ssub + (int64_t)(2 * k) * G;
+    const unsigned long long* s1 = s0 + G;
+    long long x0 = 0, x1 = 0;
+    double bu = 0.0, lgb = 0.0;
+    if (u < G) {
+        x0 = (long long)s0[u];
+        x1 = (long long)s1[u];
+        bu = ws.beta[u];
+        lgb = ws.lgbeta[u];
+    }
+    const unsigned long long n0 = ws.nsub[2 * k], n1 = ws.nsub[2 * k + 1];
+    const uint8_t rst = ws.reset[k];
+    if (mode != 2 && !split_eligible(n0, n1, rst, mode)) return;
+    SmRed r;
+    r.a = r.b = 0;
+    r.beta = 0.0;
+    if (u < G) {
+        r.beta = bu;
+        if (mode == 2) {
+            const long long v = x0 + x1;
+            r.a = v;
+            r.cs.add(rising(ws, u, bu, lgb, v));
+        } else {
+            r.a = x0;
+            r.b = x1;
+            if (x0 + x1 != 0) {
+                r.cs.add(rising(ws, u, bu, lgb, x0));
+                r.cs.add(rising(ws, u, bu, lgb, x1));
+                r.cs.add(-rising(ws, u, bu, lgb, x0 + x1));
             }
         }
-        r = block_reduce<kSmThreads>(r);
-        if (threadIdx.x == 0) {
-            SmPart& o = ws.sm_part[(int64_t)k * T + blockIdx.y];
-            o.s = r.cs.s;
-            o.c = r.cs.c;
-            o.beta = r.beta;
-            o.a = r.a;
-            o.b = r.b;
-        }
+    }
+    r = block_reduce<kSmThreads>(r);
+    if (threadIdx.x == 0) {
+        SmPart& o = ws.sm_part[(int64_t)k * T + blockIdx.y];
+        o.s = r.cs.s;
+        o.c = r.cs.c;
+        o.beta = r.beta;
+        o.a = r.a;
+        o.b = r.b;
     }
 }
 
@@ -183,63 +192,67 @@ __global__ void __launch_bounds__(kSmThreads) k_sm_tiles(Ws ws, int mode)
 // tiles' compensated sums in a fixed order.
 __global__ void __launch_bounds__(64) k_sm_finish(Ws ws, int mode, int T)
 {
-    const int K = ws.st->K;
+    // one cluster per workgroup (the grid has k_max), its counts and the
+    // first tiles' partials loaded before K and the eligibility are known
+    const int k = blockIdx.x;
     const int lane = threadIdx.x;
-    for (int k = blockIdx.x; k < K; k += gridDim.x) {
-        if (mode != 2 && !split_eligible(ws, k, mode)) {
-            if (lane == 0) {
-                ws.sm_logr[k] = __builtin_nan("");
-                if (mode == 0) ws.qsub[k] = 0.0;        // ready for the next split pass
-            }
-            continue;
-        }
-        const SmPart* part = ws.sm_part + (int64_t)k * T;
-        double B = 0.0;
-        long long a = 0, b = 0;
-        for (int q = 0; q < T; ++q) {
-            B += part[q].beta;
-            a += part[q].a;
-            b += part[q].b;
-        }
-        const unsigned long long n0 = ws.nsub[2 * k], n1 = ws.nsub[2 * k + 1];
-        // the argument per lane, then one log-gamma call shared by all lanes
-        // (a different call per lane would run one after another)
-        double arg = 1.0;
-        switch (lane) {
-        case 0: arg = B; break;
-        case 1: arg = B + (double)a; break;
-        case 2: arg = B + (double)b; break;
-        case 3: arg = B + (double)(a + b); break;
-        case 4: arg = (double)n0; break;
-        case 5: arg = (double)n1; break;
-        case 6: arg = (double)(n0 + n1); break;
-        default: break;
-        }
-        double x = lgamma(arg);
-        if (lane == 7) x = log(ws.alpha);
-        double lg[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) lg[j] = __shfl(x, j);
+    const SmPart* part = ws.sm_part + (int64_t)k * T;
+    const unsigned long long n0 = ws.nsub[2 * k], n1 = ws.nsub[2 * k + 1];
+    const uint8_t rst = ws.reset[k];
+    double B = 0.0;
+    long long a = 0, b = 0;
+#pragma unroll 8
+    for (int q = 0; q < T; ++q) {
+        B += part[q].beta;
+        a += part[q].a;
+        b += part[q].b;
+    }
+    const int K = ws.st->K;
+    if (k >= K) return;
+    if (mode != 2 && !split_eligible(n0, n1, rst, mode)) {
         if (lane == 0) {
-            CSum tot;
-            for (int q = 0; q < T; ++q) {
-                CSum y;
-                y.s = part[q].s;
-                y.c = part[q].c;
-                tot.merge(y);
-            }
-            tot.add(lg[0] - lg[1]);
-            if (mode == 2) {
-                ws.dm_k[k] = tot.value();
-            } else {
-                tot.add(lg[0] - lg[2]);
-                tot.add(-(lg[0] - lg[3]));
-                tot.add(lg[7] + lg[4] + lg[5] - lg[6]);
-                if (mode == 1) tot.add((double)(n0 + n1 - 2) * log(2.0));    // chain B, Section 2.4
-                else if (ws.flags & kFlagSplitQ) tot.add(-ws.qsub[k]);      // proposal term, Section 2.3
-                if (mode == 0) ws.qsub[k] = 0.0;        // ready for the next split pass
-                ws.sm_logr[k] = tot.value();
-            }
+            ws.sm_logr[k] = __builtin_nan("");
+            if (mode == 0) ws.qsub[k] = 0.0;        // ready for the next split pass
+        }
+        return;
+    }
+    // the argument per lane, then one log-gamma call shared by all lanes
+    // (a different call per lane would run one after another)
+    double arg = 1.0;
+    switch (lane) {
+    case 0: arg = B; break;
+    case 1: arg = B + (double)a; break;
+    case 2: arg = B + (double)b; break;
+    case 3: arg = B + (double)(a + b); break;
+    case 4: arg = (double)n0; break;
+    case 5: arg = (double)n1; break;
+    case 6: arg = (double)(n0 + n1); break;
+    default: break;
+    }
+    double x = lgamma_pos(arg);
+    if (lane == 7) x = log(ws.alpha);
+    double lg[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) lg[j] = __shfl(x, j);
+    if (lane == 0) {
+        CSum tot;
+        for (int q = 0; q < T; ++q) {
+            CSum y;
+            y.s = part[q].s;
+            y.c = part[q].c;
+            tot.merge(y);
+        }
+        tot.add(lg[0] - lg[1]);
+        if (mode == 2) {
+            ws.dm_k[k] = tot.value();
+        } else {
+            tot.add(lg[0] - lg[2]);
+            tot.add(-(lg[0] - lg[3]));
+            tot.add(lg[7] + lg[4] + lg[5] - lg[6]);
+            if (mode == 1) tot.add((double)(n0 + n1 - 2) * log(2.0));    // chain B, Section 2.4
+            else if (ws.flags & kFlagSplitQ) tot.add(-ws.qsub[k]);      // proposal term, Section 2.3
+            if (mode == 0) ws.qsub[k] = 0.0;        // ready for the next split pass
+            ws.sm_logr[k] = tot.value();
         }
     }
 }
@@ -247,7 +260,7 @@ __global__ void __launch_bounds__(64) k_sm_finish(Ws ws, int mode, int T)
 static void launch_sm_pair(const Ws& ws, int mode, hipStream_t s)
 {
     const int T = sm_tiles(ws.G);
-    const int kb = ws.k_max < 1024 ? ws.k_max : 1024;
+    const int kb = ws.k_max;      // one workgroup (column) per cluster slot
     hipLaunchKernelGGL(k_sm_tiles, dim3((unsigned)kb, (unsigned)T), dim3(kSmThreads), 0, s, ws, mode);
     hipLaunchKernelGGL(k_sm_finish, dim3((unsigned)kb), dim3(64), 0, s, ws, mode, T);
 }
@@ -321,7 +334,7 @@ __global__ void __launch_bounds__(kMergeThreads) k_merge_ratios(Ws ws)
             case 4: arg = r.beta + (double)r.a; break;
             default: break;
             }
-            const double x = lgamma(arg);
+            const double x = lgamma_pos(arg);
             double lg[5];
 #pragma unroll
             for (int j = 0; j < 5; ++j) lg[j] = __shfl(x, j);
@@ -352,24 +365,23 @@ __global__ void __launch_bounds__(kQThreads) k_split_q(Ws ws, const int32_t* __r
                                                        const uint8_t* __restrict__ cs)
 {
     extern __shared__ double qacc[];     // [K]
-    const int K = ws.st->K;
-    for (int k = threadIdx.x; k < K; k += kQThreads) qacc[k] = 0.0;
     const int64_t i0 = (int64_t)blockIdx.x * (kQThreads * kQCells) + threadIdx.x;
     int kk[kQCells];
-#pragma unroll
-    for (int j = 0; j < kQCells; ++j) {
-        const int64_t i = i0 + (int64_t)j * kQThreads;
-        kk[j] = i < ws.N ? c[i] : -1;
-    }
     double dd[kQCells];
     int sb[kQCells];
 #pragma unroll
     for (int j = 0; j < kQCells; ++j) {
         const int64_t i = i0 + (int64_t)j * kQThreads;
-        const bool live = kk[j] >= 0 && kk[j] < K;
-        dd[j] = live ? ws.subdd[i] : __builtin_nan("");
-        sb[j] = live ? (cs[i] & 1) : 0;
+        const bool in = i < ws.N;
+        kk[j] = in ? c[i] : -1;
+        dd[j] = in ? ws.subdd[i] : __builtin_nan("");
+        sb[j] = in ? (cs[i] & 1) : 0;
     }
+    const int K = ws.st->K;
+    for (int k = threadIdx.x; k < K; k += kQThreads) qacc[k] = 0.0;
+#pragma unroll
+    for (int j = 0; j < kQCells; ++j)
+        if (kk[j] < 0 || kk[j] >= K) dd[j] = __builtin_nan("");
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < kQCells; ++j)
@@ -486,6 +498,13 @@ __global__ void __launch_bounds__(kDecideThreads) k_sm_decide(Ws ws, int merge_p
     __shared__ long long ridx[kDecideThreads];
     __shared__ int s_count, s_K, s_any;
     const int t = threadIdx.x;
+    // the first candidate of this thread (cluster or pair t) is read and its
+    // uniform drawn before K is known (sm_logr has k_max + k_max (k_max - 1) / 2
+    // entries)
+    const long long nslots = (long long)ws.k_max + (long long)ws.k_max * (ws.k_max - 1) / 2;
+    const double lr_t = t < nslots ? ws.sm_logr[t] : __builtin_nan("");
+    const Words w_t = philox(ws.seed, (uint32_t)t, 0u, step, merge_pass ? kMerge : kSplit, 0u);
+    const double lu_t = log(unit52(w_t.w[0], w_t.w[1]));
     const int K = ws.st->K;
     const int G = ws.G;
     for (int k = t; k < ws.k_max; k += kDecideThreads) {
@@ -496,14 +515,11 @@ __global__ void __launch_bounds__(kDecideThreads) k_sm_decide(Ws ws, int merge_p
     __syncthreads();
 
     if (!merge_pass) {
-        // acceptance tests in parallel, new labels in cluster order
-        for (int k = t; k < K; k += kDecideThreads) {
-            ws.sm_acc[k] = 0;
-            const double lr = ws.sm_logr[k];
-            used[k] = 0;
-            if (isnan(lr)) continue;
-            const Words w = philox(ws.seed, (uint32_t)k, 0u, step, kSplit, 0u);
-            used[k] = log(unit52(w.w[0], w.w[1])) < lr ? 2 : 1;   // 1 proposed, 2 accepted
+        // acceptance tests in parallel (cluster t is this thread's, K <= k_max
+        // <= kDecideThreads), new labels in cluster order
+        if (t < K) {
+            ws.sm_acc[t] = 0;
+            used[t] = isnan(lr_t) ? 0 : (lu_t < lr_t ? 2 : 1);   // 1 proposed, 2 accepted
         }
         __syncthreads();
         if (t == 0) {
@@ -569,8 +585,10 @@ __global__ void __launch_bounds__(kDecideThreads) k_sm_decide(Ws ws, int merge_p
     const long long npairs = (long long)K * (K - 1) / 2;
     for (long long p = t; p < npairs; p += kDecideThreads) {
         ws.sm_acc[p] = 0;
-        const Words w = philox(ws.seed, (uint32_t)p, 0u, step, kMerge, 0u);
-        if (log(unit52(w.w[0], w.w[1])) < ws.sm_logr[p]) {
+        const bool first = p == t;
+        const Words w = first ? w_t : philox(ws.seed, (uint32_t)p, 0u, step, kMerge, 0u);
+        const double lu = first ? lu_t : log(unit52(w.w[0], w.w[1]));
+        if (lu < (first ? lr_t : ws.sm_logr[p])) {
             const int q = atomicAdd(&s_count, 1);
             ws.mkey[q] = ((unsigned long long)w.w[2] << 32) | w.w[3];
             ws.mlist[q] = (int32_t)p;

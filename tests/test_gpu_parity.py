@@ -348,6 +348,40 @@ def test_resume_reproduces_the_chain():
         assert torch.equal(cx, ca) and torch.equal(csx, csa)
 
 
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
+def test_chain_does_not_depend_on_host_timing(precision):
+    """Launch sizes follow the K the host last saw (a mapped word the device
+    updates), which lags behind K when the host queues steps ahead of the GPU:
+    a chain queued in one go (from one cluster, so that splits raise K while
+    later steps are already queued) must equal the same chain run with a
+    synchronisation after every call."""
+    say("host timing", precision)
+    d = synth.generate("c1", seed=2)
+    kw = dict(alpha=1.0, beta=1.0, seed=41, k_max=64, k_init=1)
+    a = _sampler(d, precision, **kw)
+    a.iterate(20, eb_every=7)
+    b = _sampler(d, precision, **kw)
+    for it in range(20):
+        b.sweep(1)
+        torch.cuda.synchronize()
+        b.stats()
+        b.split_merge()
+        torch.cuda.synchronize()
+        b.stats()
+        if (it + 1) % 7 == 0:
+            b.eb_update()
+    sa, sb = a.stats(with_tables=True), b.stats(with_tables=True)
+    assert sa["K"] == sb["K"] and sa["K"] >= 3
+    assert np.array_equal(sa["nsub"], sb["nsub"])
+    ca, csa = a.labels()
+    cb, csb = b.labels()
+    assert torch.equal(ca, cb) and torch.equal(csa, csb)
+    K, km = sa["K"], kw["k_max"]
+    _, lta = a.params()
+    _, ltb = b.params()
+    assert torch.equal(lta[:K], ltb[:K]) and torch.equal(lta[km:km + 2 * K], ltb[km:km + 2 * K])
+
+
 @pytest.mark.parametrize("precision", ["fp32", "fp64", "split_bf16"])
 @pytest.mark.parametrize("k_init", [12, 24, 40, 56, 70])
 def test_many_cluster_kernel_paths(precision, k_init):

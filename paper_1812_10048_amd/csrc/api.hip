@@ -560,9 +560,9 @@ dpmm_status dpmm_sweep(dpmm_ctx* ctx, int32_t n_sweeps)
             StageTimer st(ctx, DPMM_STAGE_REDRAW);
             if (ws.flags & kFlagNewCluster) launch_extend(ws, ctx->stream);
             // (also empties the re-score queue, and clears the coin halves for rsplit)
-            launch_redraw(ws, step, ctx->precision == DPMM_SPLIT_BF16, rsplit,
-                          k_hint(ctx) + ((ws.flags & kFlagNewCluster) ? 1 : 0), ctx->stream);
-            if (ctx->precision == DPMM_SPLIT_BF16) launch_lay_btab(ws, ctx->stream);
+            const int kg = k_hint(ctx) + ((ws.flags & kFlagNewCluster) ? 1 : 0);   // sizes grids
+            launch_redraw(ws, step, ctx->precision == DPMM_SPLIT_BF16, rsplit, kg, ctx->stream);
+            if (ctx->precision == DPMM_SPLIT_BF16) launch_lay_btab(ws, kg, ctx->stream);
         }
         AssignArgs a{};
         a.c_old = ctx->c[ctx->cur];
@@ -633,14 +633,15 @@ dpmm_status dpmm_split_merge(dpmm_ctx* ctx)
     const bool ready = ctx->rs_ready_step == ctx->step;
     ctx->rs_ready_step = -1;
     StageTimer st(ctx, DPMM_STAGE_SPLIT_MERGE);
+    const int kg = k_hint(ctx);     // sizes the grids (any K is covered)
     if (pass == 1) {
-        launch_merge_ratios(ctx->ws, ctx->stream);
+        launch_merge_ratios(ctx->ws, kg, ctx->stream);
         launch_sm_decide(ctx->ws, 1, step, ctx->stream);
     } else if (pass == 0) {
-        launch_split_ratios(ctx->ws, ctx->c[ctx->cur], ctx->cs[ctx->cur], ctx->stream);
+        launch_split_ratios(ctx->ws, ctx->c[ctx->cur], ctx->cs[ctx->cur], kg, ctx->stream);
         launch_sm_decide(ctx->ws, 0, step, ctx->stream);
     } else {
-        launch_random_split(ctx->ws, ctx->c[ctx->cur], ctx->cs[ctx->cur], step, ready, ctx->stream);
+        launch_random_split(ctx->ws, ctx->c[ctx->cur], ctx->cs[ctx->cur], step, ready, kg, ctx->stream);
     }
     launch_relabel(ctx->ws, ctx->c[ctx->cur], ctx->cs[ctx->cur], ctx->stream);
     HIP_TRY(hipGetLastError());     // (k_sm_decide has written the K hint)

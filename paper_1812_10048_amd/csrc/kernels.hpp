@@ -23,7 +23,7 @@ void launch_sort(const Ws& ws, const int32_t* c, const uint8_t* cs, int by_clust
 // rebuild the cluster-sorted copy from labels c (force: unconditionally; else
 // only when the partition changed structurally since the last build)
 void launch_relayout(const Ws& ws, const int32_t* c, int64_t* tile_sums, int force, hipStream_t s);
-void launch_lay_btab(const Ws& ws, hipStream_t s);    // permuted hi/lo tables, after each redraw
+void launch_lay_btab(const Ws& ws, int k_guess, hipStream_t s);   // k_guess: a recent K (sizes the grid)    // permuted hi/lo tables, after each redraw
 hipError_t configure_layout();
 
 // bookkeeping.hip
@@ -94,9 +94,11 @@ void launch_dump_scores(const Ws& ws, const int32_t* c, const int32_t* cells, in
 
 // splitmerge.hip
 void launch_lgamma_beta(const Ws& ws, hipStream_t s);   // lgbeta = lgamma(beta), wherever beta changes
-void launch_split_ratios(const Ws& ws, const int32_t* c, const uint8_t* cs, hipStream_t s);
-void launch_random_split(const Ws& ws, const int32_t* c, uint8_t* cs, uint32_t step, bool ready, hipStream_t s);
-void launch_merge_ratios(const Ws& ws, hipStream_t s);
+// (k_guess below: a recent K, which sizes the grids; any K is covered)
+void launch_split_ratios(const Ws& ws, const int32_t* c, const uint8_t* cs, int k_guess, hipStream_t s);
+void launch_random_split(const Ws& ws, const int32_t* c, uint8_t* cs, uint32_t step, bool ready, int k_guess,
+                         hipStream_t s);
+void launch_merge_ratios(const Ws& ws, int k_guess, hipStream_t s);
 void launch_sm_decide(const Ws& ws, int merge_pass, uint32_t step, hipStream_t s);
 // collapsed log joint log p(c) + sum_k logDM(s_k) (eq. 10 with Gamma(alpha), eq. 12
 // integrated against eq. 28) into ws.st->log_joint

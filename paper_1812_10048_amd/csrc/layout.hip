@@ -401,20 +401,24 @@ __device__ inline void lay_dtab(const Ws& ws, int L, int K, int KL)
 // columns), so the columns from K + kSubDigits + 63 on are left as they are.
 // The first k_max blocks write the fixed-point difference tables above
 // instead.
-__global__ void __launch_bounds__(256) k_lay_btab(Ws ws)
+__global__ void __launch_bounds__(256) k_lay_btab(Ws ws, int kd)
 {
     const int K = ws.st->K;
     const int KL = ws.st->lay_K;
     const int R = kLayDmax * kBlkGenes;
-    if ((int)blockIdx.x < ws.k_max) {
-        lay_dtab(ws, (int)blockIdx.x, K, KL);
+    if ((int)blockIdx.x < kd) {
+        // the first kd workgroups: clusters x, x + kd, ... (kd from a recent K)
+        for (int L = blockIdx.x; L < KL && L < K; L += kd) {
+            __syncthreads();               // (the LDS tables of the last cluster are read)
+            lay_dtab(ws, L, K, KL);
+        }
         return;
     }
     const int ncol = min(ws.lay_cols, K + kSubDigits + 63);
     const int64_t n = (int64_t)KL * ncol * R;
-    const int64_t stride = (int64_t)(gridDim.x - ws.k_max) * blockDim.x;
+    const int64_t stride = (int64_t)(gridDim.x - kd) * blockDim.x;
     // (the digit columns of live, non-reset clusters are lay_dtab's)
-    for (int64_t q = (int64_t)(blockIdx.x - ws.k_max) * blockDim.x + threadIdx.x; q < n; q += stride) {
+    for (int64_t q = (int64_t)(blockIdx.x - kd) * blockDim.x + threadIdx.x; q < n; q += stride) {
         const int j = (int)(q % R);
         const int64_t lc = q / R;
         const int col = (int)(lc % ncol);
@@ -432,12 +436,13 @@ __global__ void __launch_bounds__(256) k_lay_btab(Ws ws)
     }
 }
 
-void launch_lay_btab(const Ws& ws, hipStream_t s)
+void launch_lay_btab(const Ws& ws, int k_guess, hipStream_t s)
 {
-    const int64_t n = (int64_t)ws.k_max * ws.lay_cols * kLayDmax * kBlkGenes;
+    const int kd = k_guess > 0 && k_guess < ws.k_max ? k_guess : ws.k_max;
+    const int64_t n = (int64_t)kd * (kd + kSubDigits + 63) * kLayDmax * kBlkGenes;
     int64_t blocks = (n + 255) / 256;
     if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(k_lay_btab, dim3((unsigned)(blocks + ws.k_max)), dim3(256), 0, s, ws);
+    hipLaunchKernelGGL(k_lay_btab, dim3((unsigned)(blocks + kd)), dim3(256), 0, s, ws, kd);
 }
 
 }  // namespace dpmm

@@ -134,56 +134,57 @@ __device__ inline bool split_eligible(unsigned long long n0, unsigned long long 
     return !((mode == 0 && reset) || n0 < 1 || n1 < 1);
 }
 
-// Workgroup (k, tile): one cluster per workgroup column (the grid has k_max
-// columns; those past K leave at once), its counts, beta and log Gamma(beta)
-// loaded together with what decides the cluster's eligibility.
+// Workgroup (x, tile) takes clusters x, x + gridDim.x, ... below K (the grid
+// is sized from a recent K): their counts, beta and log Gamma(beta) loaded
+// together with what decides the cluster's eligibility.
 __global__ void __launch_bounds__(kSmThreads) k_sm_tiles(Ws ws, int mode)
 {
-    const int k = blockIdx.x;
-    if (k >= ws.st->K) return;
+    const int K = ws.st->K;
     const int G = ws.G;
     const int T = gridDim.y;
     const int u = blockIdx.y * kSmThreads + threadIdx.x;
-    const unsigned long long* s0 = ws.ssub + (int64_t)(2 * k) * G;
-    const unsigned long long* s1 = s0 + G;
-    long long x0 = 0, x1 = 0;
-    double bu = 0.0, lgb = 0.0;
-    if (u < G) {
-        x0 = (long long)s0[u];
-        x1 = (long long)s1[u];
-        bu = ws.beta[u];
-        lgb = ws.lgbeta[u];
-    }
-    const unsigned long long n0 = ws.nsub[2 * k], n1 = ws.nsub[2 * k + 1];
-    const uint8_t rst = ws.reset[k];
-    if (mode != 2 && !split_eligible(n0, n1, rst, mode)) return;
-    SmRed r;
-    r.a = r.b = 0;
-    r.beta = 0.0;
-    if (u < G) {
-        r.beta = bu;
-        if (mode == 2) {
-            const long long v = x0 + x1;
-            r.a = v;
-            r.cs.add(rising(ws, u, bu, lgb, v));
-        } else {
-            r.a = x0;
-            r.b = x1;
-            if (x0 + x1 != 0) {
-                r.cs.add(rising(ws, u, bu, lgb, x0));
-                r.cs.add(rising(ws, u, bu, lgb, x1));
-                r.cs.add(-rising(ws, u, bu, lgb, x0 + x1));
+    for (int k = blockIdx.x; k < K; k += gridDim.x) {
+        const unsigned long long* s0 = ws.ssub + (int64_t)(2 * k) * G;
+        const unsigned long long* s1 = s0 + G;
+        long long x0 = 0, x1 = 0;
+        double bu = 0.0, lgb = 0.0;
+        if (u < G) {
+            x0 = (long long)s0[u];
+            x1 = (long long)s1[u];
+            bu = ws.beta[u];
+            lgb = ws.lgbeta[u];
+        }
+        const unsigned long long n0 = ws.nsub[2 * k], n1 = ws.nsub[2 * k + 1];
+        const uint8_t rst = ws.reset[k];
+        if (mode != 2 && !split_eligible(n0, n1, rst, mode)) continue;
+        SmRed r;
+        r.a = r.b = 0;
+        r.beta = 0.0;
+        if (u < G) {
+            r.beta = bu;
+            if (mode == 2) {
+                const long long v = x0 + x1;
+                r.a = v;
+                r.cs.add(rising(ws, u, bu, lgb, v));
+            } else {
+                r.a = x0;
+                r.b = x1;
+                if (x0 + x1 != 0) {
+                    r.cs.add(rising(ws, u, bu, lgb, x0));
+                    r.cs.add(rising(ws, u, bu, lgb, x1));
+                    r.cs.add(-rising(ws, u, bu, lgb, x0 + x1));
+                }
             }
         }
-    }
-    r = block_reduce<kSmThreads>(r);
-    if (threadIdx.x == 0) {
-        SmPart& o = ws.sm_part[(int64_t)k * T + blockIdx.y];
-        o.s = r.cs.s;
-        o.c = r.cs.c;
-        o.beta = r.beta;
-        o.a = r.a;
-        o.b = r.b;
+        r = block_reduce<kSmThreads>(r);
+        if (threadIdx.x == 0) {
+            SmPart& o = ws.sm_part[(int64_t)k * T + blockIdx.y];
+            o.s = r.cs.s;
+            o.c = r.cs.c;
+            o.beta = r.beta;
+            o.a = r.a;
+            o.b = r.b;
+        }
     }
 }
 
@@ -192,75 +193,78 @@ __global__ void __launch_bounds__(kSmThreads) k_sm_tiles(Ws ws, int mode)
 // tiles' compensated sums in a fixed order.
 __global__ void __launch_bounds__(64) k_sm_finish(Ws ws, int mode, int T)
 {
-    // one cluster per workgroup (the grid has k_max), its counts and the
-    // first tiles' partials loaded before K and the eligibility are known
-    const int k = blockIdx.x;
-    const int lane = threadIdx.x;
-    const SmPart* part = ws.sm_part + (int64_t)k * T;
-    const unsigned long long n0 = ws.nsub[2 * k], n1 = ws.nsub[2 * k + 1];
-    const uint8_t rst = ws.reset[k];
-    double B = 0.0;
-    long long a = 0, b = 0;
-#pragma unroll 8
-    for (int q = 0; q < T; ++q) {
-        B += part[q].beta;
-        a += part[q].a;
-        b += part[q].b;
-    }
     const int K = ws.st->K;
-    if (k >= K) return;
-    if (mode != 2 && !split_eligible(n0, n1, rst, mode)) {
-        if (lane == 0) {
-            ws.sm_logr[k] = __builtin_nan("");
-            if (mode == 0) ws.qsub[k] = 0.0;        // ready for the next split pass
+    const int lane = threadIdx.x;
+    for (int k = blockIdx.x; k < K; k += gridDim.x) {
+        const SmPart* part = ws.sm_part + (int64_t)k * T;
+        const unsigned long long n0 = ws.nsub[2 * k], n1 = ws.nsub[2 * k + 1];
+        if (mode != 2 && !split_eligible(n0, n1, ws.reset[k], mode)) {
+            if (lane == 0) {
+                ws.sm_logr[k] = __builtin_nan("");
+                if (mode == 0) ws.qsub[k] = 0.0;        // ready for the next split pass
+            }
+            continue;
         }
-        return;
-    }
-    // the argument per lane, then one log-gamma call shared by all lanes
-    // (a different call per lane would run one after another)
-    double arg = 1.0;
-    switch (lane) {
-    case 0: arg = B; break;
-    case 1: arg = B + (double)a; break;
-    case 2: arg = B + (double)b; break;
-    case 3: arg = B + (double)(a + b); break;
-    case 4: arg = (double)n0; break;
-    case 5: arg = (double)n1; break;
-    case 6: arg = (double)(n0 + n1); break;
-    default: break;
-    }
-    double x = lgamma_pos(arg);
-    if (lane == 7) x = log(ws.alpha);
-    double lg[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) lg[j] = __shfl(x, j);
-    if (lane == 0) {
-        CSum tot;
+        double B = 0.0;
+        long long a = 0, b = 0;
+#pragma unroll 8
         for (int q = 0; q < T; ++q) {
-            CSum y;
-            y.s = part[q].s;
-            y.c = part[q].c;
-            tot.merge(y);
+            B += part[q].beta;
+            a += part[q].a;
+            b += part[q].b;
         }
-        tot.add(lg[0] - lg[1]);
-        if (mode == 2) {
-            ws.dm_k[k] = tot.value();
-        } else {
-            tot.add(lg[0] - lg[2]);
-            tot.add(-(lg[0] - lg[3]));
-            tot.add(lg[7] + lg[4] + lg[5] - lg[6]);
-            if (mode == 1) tot.add((double)(n0 + n1 - 2) * log(2.0));    // chain B, Section 2.4
-            else if (ws.flags & kFlagSplitQ) tot.add(-ws.qsub[k]);      // proposal term, Section 2.3
-            if (mode == 0) ws.qsub[k] = 0.0;        // ready for the next split pass
-            ws.sm_logr[k] = tot.value();
+        // the argument per lane, then one log-gamma call shared by all lanes
+        // (a different call per lane would run one after another)
+        double arg = 1.0;
+        switch (lane) {
+        case 0: arg = B; break;
+        case 1: arg = B + (double)a; break;
+        case 2: arg = B + (double)b; break;
+        case 3: arg = B + (double)(a + b); break;
+        case 4: arg = (double)n0; break;
+        case 5: arg = (double)n1; break;
+        case 6: arg = (double)(n0 + n1); break;
+        default: break;
+        }
+        double x = lgamma_pos(arg);
+        if (lane == 7) x = log(ws.alpha);
+        double lg[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) lg[j] = __shfl(x, j);
+        if (lane == 0) {
+            CSum tot;
+            for (int q = 0; q < T; ++q) {
+                CSum y;
+                y.s = part[q].s;
+                y.c = part[q].c;
+                tot.merge(y);
+            }
+            tot.add(lg[0] - lg[1]);
+            if (mode == 2) {
+                ws.dm_k[k] = tot.value();
+            } else {
+                tot.add(lg[0] - lg[2]);
+                tot.add(-(lg[0] - lg[3]));
+                tot.add(lg[7] + lg[4] + lg[5] - lg[6]);
+                if (mode == 1) tot.add((double)(n0 + n1 - 2) * log(2.0));    // chain B, Section 2.4
+                else if (ws.flags & kFlagSplitQ) tot.add(-ws.qsub[k]);      // proposal term, Section 2.3
+                if (mode == 0) ws.qsub[k] = 0.0;        // ready for the next split pass
+                ws.sm_logr[k] = tot.value();
+            }
         }
     }
 }
 
-static void launch_sm_pair(const Ws& ws, int mode, hipStream_t s)
+// k_guess: a recent K (sizes the grids; the kernels loop over any K)
+static int k_grid(const Ws& ws, int k_guess)
+{
+    return k_guess > 0 && k_guess < ws.k_max ? k_guess : ws.k_max;
+}
+
+static void launch_sm_pair(const Ws& ws, int mode, int k_guess, hipStream_t s)
 {
     const int T = sm_tiles(ws.G);
-    const int kb = ws.k_max;      // one workgroup (column) per cluster slot
+    const int kb = k_grid(ws, k_guess);
     hipLaunchKernelGGL(k_sm_tiles, dim3((unsigned)kb, (unsigned)T), dim3(kSmThreads), 0, s, ws, mode);
     hipLaunchKernelGGL(k_sm_finish, dim3((unsigned)kb), dim3(64), 0, s, ws, mode, T);
 }
@@ -287,7 +291,7 @@ __global__ void k_log_joint(Ws ws)
 
 void launch_log_joint(const Ws& ws, hipStream_t s)
 {
-    launch_sm_pair(ws, 2, s);
+    launch_sm_pair(ws, 2, ws.k_max, s);
     hipLaunchKernelGGL(k_log_joint, dim3(1), dim3(64), 0, s, ws);
 }
 
@@ -391,7 +395,7 @@ __global__ void __launch_bounds__(kQThreads) k_split_q(Ws ws, const int32_t* __r
         if (qacc[k] != 0.0) atomicAdd(&ws.qsub[k], qacc[k]);
 }
 
-void launch_split_ratios(const Ws& ws, const int32_t* c, const uint8_t* cs, hipStream_t s)
+void launch_split_ratios(const Ws& ws, const int32_t* c, const uint8_t* cs, int k_guess, hipStream_t s)
 {
     if (ws.flags & kFlagSplitQ) {
         const int64_t per = (int64_t)kQThreads * kQCells;
@@ -399,7 +403,7 @@ void launch_split_ratios(const Ws& ws, const int32_t* c, const uint8_t* cs, hipS
         hipLaunchKernelGGL(k_split_q, dim3((unsigned)blocks), dim3(kQThreads), sizeof(double) * (size_t)ws.k_max, s,
                            ws, c, cs);
     }
-    launch_sm_pair(ws, 0, s);
+    launch_sm_pair(ws, 0, k_guess, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -449,7 +453,8 @@ __global__ void k_rsplit_apply(Ws ws, const int32_t* __restrict__ c, uint8_t* __
 
 // With `ready` the coins and the statistics of the halves were built by the
 // sub-cluster pass of the sweep before (k_sub_stats) for this step.
-void launch_random_split(const Ws& ws, const int32_t* c, uint8_t* cs, uint32_t step, bool ready, hipStream_t s)
+void launch_random_split(const Ws& ws, const int32_t* c, uint8_t* cs, uint32_t step, bool ready, int k_guess,
+                         hipStream_t s)
 {
     int64_t cb = (ws.N + 255) / 256;
     if (cb > 4096) cb = 4096;
@@ -460,15 +465,16 @@ void launch_random_split(const Ws& ws, const int32_t* c, uint8_t* cs, uint32_t s
         hipLaunchKernelGGL(k_rsplit_coins, dim3((unsigned)cb), dim3(256), 0, s, ws, step);
         launch_stats(halves, c, ws.rbits, s);
     }
-    launch_sm_pair(halves, 1, s);
+    launch_sm_pair(halves, 1, k_guess, s);
     launch_sm_decide(halves, 0, step, s);
     hipLaunchKernelGGL(k_rsplit_apply, dim3((unsigned)cb), dim3(256), 0, s, ws, c, cs);
 }
 
-void launch_merge_ratios(const Ws& ws, hipStream_t s)
+void launch_merge_ratios(const Ws& ws, int k_guess, hipStream_t s)
 {
-    launch_sm_pair(ws, 2, s);
-    const long long np = (long long)ws.k_max * (ws.k_max - 1) / 2;
+    launch_sm_pair(ws, 2, k_guess, s);
+    const long long kg = k_grid(ws, k_guess);
+    const long long np = kg * (kg - 1) / 2;
     const int mb = np < 4096 ? (int)(np > 0 ? np : 1) : 4096;
     hipLaunchKernelGGL(k_merge_ratios, dim3(mb), dim3(kMergeThreads), 0, s, ws);
 }

@@ -359,6 +359,13 @@ def test_chain_does_not_depend_on_host_timing(precision):
     d = synth.generate("c1", seed=2)
     kw = dict(alpha=1.0, beta=1.0, seed=41, k_max=64, k_init=1)
     a = _sampler(d, precision, **kw)
+    torch.cuda.synchronize()
+    # keep the stream busy (about 0.1 s of products) while the whole chain is
+    # queued, so that every launch of it sees the K of the start
+    m = torch.randn(8192, 8192, device="cuda")
+    sink = torch.empty_like(m)
+    for _ in range(10):
+        torch.mm(m, m, out=sink)
     a.iterate(20, eb_every=7)
     b = _sampler(d, precision, **kw)
     for it in range(20):

@@ -227,8 +227,10 @@ __global__ void __launch_bounds__(kRedrawThreads) k_redraw_norm(Ws ws, int write
         redraw_row(ws, row, K, rr);
         const double2* part = ws.rd_part + (int64_t)row * nt;
         double m = -INFINITY;
+#pragma unroll 8
         for (int q = 0; q < nt; ++q) m = fmax(m, part[q].x);
         double s = 0.0;
+#pragma unroll 8
         for (int q = 0; q < nt; ++q) s += part[q].y * exp(part[q].x - m);
         const double lse = m + log(s);
         if (u >= G) continue;

@@ -438,7 +438,7 @@ void launch_stats(const Ws& ws, const int32_t* c, const uint8_t* cs, hipStream_t
 __global__ void __launch_bounds__(kMaxClusters) k_compact(Ws ws, int after_sweep)
 {
     extern __shared__ int32_t lds_map[];      // [k_max]
-    __shared__ int32_t s_nk, s_changed;
+    __shared__ int32_t s_wave[kMaxClusters / 64];
     const int t = threadIdx.x;
     // thread t holds cluster t's counts (k_max <= kMaxClusters = blockDim.x),
     // loaded before K is known
@@ -448,26 +448,20 @@ __global__ void __launch_bounds__(kMaxClusters) k_compact(Ws ws, int after_sweep
         n1 = ws.nsub[2 * t + 1];
     }
     const int K = ws.st->K;
-    // which clusters have cells; then the map in order
-    if (t < K) lds_map[t] = (n0 + n1) > 0 ? 1 : 0;
-    __syncthreads();
-    if (t == 0) {
-        // changed: a cluster with cells takes a new index, so labels must be
-        // rewritten; dropping empty clusters at the end renumbers nobody
-        int nk = 0, changed = 0;
-        for (int k = 0; k < K; ++k) {
-            lds_map[k] = lds_map[k] ? nk++ : -1;
-            if (lds_map[k] >= 0 && lds_map[k] != k) changed = 1;
-        }
-        s_nk = nk;
-        s_changed = changed;
-    }
-    __syncthreads();
-    const int nk = s_nk;
+    // the map in order: a cluster with cells takes the number of clusters
+    // with cells below it (a workgroup-wide exclusive count)
+    const bool live = t < K && (n0 + n1) > 0;
+    int nk;
+    const int pos = block_exclusive_count(live, s_wave, &nk);
+    if (t < K) lds_map[t] = live ? pos : -1;
+    // changed: a cluster with cells takes a new index, so labels must be
+    // rewritten; dropping empty clusters at the end renumbers nobody (the
+    // barrier also publishes the map)
+    const int changed = __syncthreads_or(live && pos != t);
     const int G = ws.G;
     // the coin-half statistics of a coming random split move with the rest
     const bool rs = ws.rssub && ws.st->rs_live;
-    if (s_changed || nk < K) {
+    if (changed || nk < K) {
         // (lds_map is uniform over the workgroup: only a row that moves costs
         // a barrier, which orders it before a later move into its place)
         for (int k = 0; k < K; ++k) {
@@ -509,8 +503,8 @@ __global__ void __launch_bounds__(kMaxClusters) k_compact(Ws ws, int after_sweep
     if (t == 0) {
         ws.st->K = nk;
         ws.st->has_new = 0;
-        ws.st->relabel = s_changed;
-        if (s_changed) ws.st->relabels += 1;
+        ws.st->relabel = changed;
+        if (changed) ws.st->relabels += 1;
         if (ws.k_hint) __hip_atomic_store(ws.k_hint, nk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }

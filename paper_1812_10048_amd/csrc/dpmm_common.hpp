@@ -133,6 +133,31 @@ constexpr uint32_t kRefineCluster = 1u << 31;
 constexpr uint32_t kRefineSub = 1u << 30;
 constexpr uint32_t kRefineMask = (1u << 30) - 1;
 
+#if defined(__HIPCC__)
+// Exclusive count of `on` over the threads below this one, and the total, for
+// a workgroup of whole wavefronts (one flag per thread): ballots per
+// wavefront, then the wavefront totals through LDS (s_wave: blockDim.x / 64
+// words).  Every thread of the workgroup must call it.
+__device__ inline int block_exclusive_count(bool on, int32_t* s_wave, int* total)
+{
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const unsigned long long m = __ballot(on);
+    const int below = __popcll(m & ((1ull << lane) - 1ull));
+    if (lane == 0) s_wave[w] = __popcll(m);
+    __syncthreads();
+    int base = 0, tot = 0;
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) {
+        const int c = s_wave[q];
+        if (q < w) base += c;
+        tot += c;
+    }
+    __syncthreads();                   // (s_wave may be reused)
+    *total = tot;
+    return base + below;
+}
+
+#endif
+
 // Row walker: entries are read 16 bytes at a time (rows start and end on
 // 16-byte boundaries) with the next block already in flight.
 #if defined(__HIPCC__)

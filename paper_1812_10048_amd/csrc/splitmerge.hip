@@ -503,6 +503,7 @@ __global__ void __launch_bounds__(kDecideThreads) k_sm_decide(Ws ws, int merge_p
     __shared__ unsigned long long rkey[kDecideThreads];
     __shared__ long long ridx[kDecideThreads];
     __shared__ int s_count, s_K, s_any;
+    __shared__ int32_t s_wave[kDecideThreads / 64];
     const int t = threadIdx.x;
     // the first candidate of this thread (cluster or pair t) is read and its
     // uniform drawn before K is known (sm_logr has k_max + k_max (k_max - 1) / 2
@@ -528,28 +529,26 @@ __global__ void __launch_bounds__(kDecideThreads) k_sm_decide(Ws ws, int merge_p
             used[t] = isnan(lr_t) ? 0 : (lu_t < lr_t ? 2 : 1);   // 1 proposed, 2 accepted
         }
         __syncthreads();
-        if (t == 0) {
-            int knew = K;
-            unsigned long long prop = 0, acc = 0, skip = 0;
-            for (int k = 0; k < K; ++k) {
-                if (used[k] == 0) continue;
-                ++prop;
-                if (used[k] == 2) {
-                    if (knew < ws.k_max) {
-                        newlab[k] = knew++;
-                        ws.sm_acc[k] = 1;
-                        ++acc;
-                    } else {
-                        ++skip;
-                    }
-                }
+        // accepted splits take new labels K, K + 1, ... in cluster order while
+        // they fit below k_max (workgroup-wide exclusive counts)
+        {
+            const int ut = t < K ? used[t] : 0;
+            int nprop, nacc;
+            block_exclusive_count(ut != 0, s_wave, &nprop);
+            const int pos = block_exclusive_count(ut == 2, s_wave, &nacc);
+            if (ut == 2 && K + pos < ws.k_max) {
+                newlab[t] = K + pos;
+                ws.sm_acc[t] = 1;
             }
-            // counters by atomics that return nothing: no round trip before the barrier
-            atomicAdd(&ws.st->counters[kCntSplitsProposed], prop);
-            atomicAdd(&ws.st->counters[kCntSplitsAccepted], acc);
-            atomicAdd(&ws.st->counters[kCntKmaxSkips], skip);
-            s_K = knew;
-            s_any = acc > 0;
+            if (t == 0) {
+                const int fit = min(nacc, ws.k_max - K);
+                // counters by atomics that return nothing: no round trip before the barrier
+                atomicAdd(&ws.st->counters[kCntSplitsProposed], (unsigned long long)nprop);
+                atomicAdd(&ws.st->counters[kCntSplitsAccepted], (unsigned long long)fit);
+                atomicAdd(&ws.st->counters[kCntKmaxSkips], (unsigned long long)(nacc - fit));
+                s_K = K + fit;
+                s_any = fit > 0;
+            }
         }
         __syncthreads();
         for (int k = 0; k < K; ++k) {
@@ -667,19 +666,19 @@ __global__ void __launch_bounds__(kDecideThreads) k_sm_decide(Ws ws, int merge_p
         }
         __syncthreads();
     }
-    // compaction of the emptied clusters
+    // compaction of the emptied clusters: the others keep their order
+    // (a workgroup-wide exclusive count)
+    int nk;
+    {
+        const bool keep = t < K && !(newlab[t] >= 0 && newlab[t] != t);
+        const int pos = block_exclusive_count(keep, s_wave, &nk);
+        if (t < K) cmap[t] = keep ? pos : -1;
+    }
     if (t == 0) {
-        int nk = 0;
-        for (int k = 0; k < K; ++k) {
-            const bool gone = newlab[k] >= 0 && newlab[k] != k;
-            cmap[k] = gone ? -1 : nk++;
-        }
-        s_K = nk;
         atomicAdd(&ws.st->counters[kCntMergesProposed], (unsigned long long)npairs);
         atomicAdd(&ws.st->counters[kCntMergesAccepted], merges);
     }
     __syncthreads();
-    const int nk = s_K;
     if (merges) {
         for (int k = 0; k < K; ++k) {
             const int j = cmap[k];

@@ -14,7 +14,8 @@ namespace dpmm {
 // normals; a < 1 uses Gamma(a) = Gamma(a + 1) U^(1/a), added in log space.
 // Attempt j reads counter calls 2j (normal) and 2j + 1 (acceptance uniform,
 // boost uniform).  The log-acceptance 0.5 z^2 + d - d v + d log v is written
-// through t = c z, v = (1 + t)^3, so large shapes do not cancel.
+// through t = c z, v = (1 + t)^3, so large shapes do not cancel.  A draw
+// that exhausts kGammaTries attempts adds one to *capped.
 __device__ double log_gamma_draw(double a, uint64_t seed, uint32_t element, uint32_t row, uint32_t step,
                                  uint32_t stream, int* capped)
 {
@@ -38,7 +39,7 @@ __device__ double log_gamma_draw(double a, uint64_t seed, uint32_t element, uint
             return out;
         }
     }
-    *capped = 1;
+    *capped += 1;
     return log(d);
 }
 

@@ -15,7 +15,11 @@ dumps the scores its matrix-core kernel computed.  Recorded per sweep:
     into those whose oracle Gumbel-max margin is below 1e-6 (near ties) and
     the others (which must not occur).
 
-usage: python tests/precision_report.py [--recipe c2] [--sweeps 200] [--seed 0]
+With --fused the GPU sweeps run without the dump, i.e. with the sub-cluster
+pass fused into the cluster draw (the benchmarked form); then only the labels,
+re-scores and near ties are recorded.
+
+usage: python tests/precision_report.py [--recipe c2] [--sweeps 200] [--seed 0] [--fused]
            [--out gpurun_out/precision_c2_split_bf16.jsonl]
            [--summary gpurun_out/split_bf16_c2_precision.txt]
 """
@@ -46,6 +50,7 @@ def main(argv=None) -> int:
     ap.add_argument("--sweeps", type=int, default=200)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--k-max", type=int, default=128)
+    ap.add_argument("--fused", action="store_true", help="no score dump: the fused sweep, labels only")
     ap.add_argument("--out", default=os.path.join(ROOT, "gpurun_out", "precision_c2_split_bf16.jsonl"))
     ap.add_argument("--summary", default=os.path.join(ROOT, "gpurun_out", "split_bf16_c2_precision.txt"))
     args = ap.parse_args(argv)
@@ -72,16 +77,20 @@ def main(argv=None) -> int:
                 o.extend()
             o.redraw()
             Ks = o.K
-            ref = o.cell_logliks(all_cells)[:, :Ks]
-            # the GPU sweep with its matrix-core scores dumped
             st0 = s.stats()
-            dbg = s.debug_scores(Ks, fp64=False)
-            s.sweep(1)
-            s.debug_scores(None)
-            got = dbg[:, :Ks].double().cpu().numpy()
-            del dbg
+            if args.fused:
+                s.sweep(1)
+                rel = np.full(1, np.nan)
+            else:
+                # the GPU sweep with its matrix-core scores dumped
+                ref = o.cell_logliks(all_cells)[:, :Ks]
+                dbg = s.debug_scores(Ks, fp64=False)
+                s.sweep(1)
+                s.debug_scores(None)
+                got = dbg[:, :Ks].double().cpu().numpy()
+                del dbg
+                rel = np.abs(got - ref) / np.maximum(1.0, np.abs(ref))
             st1 = s.stats()
-            rel = np.abs(got - ref) / np.maximum(1.0, np.abs(ref))
             # the oracle's own sweep from the same state: labels and margins
             o.set_state(snap["step"], snap["K"], c0, cs0, reset)
             o.sweep()
@@ -105,14 +114,22 @@ def main(argv=None) -> int:
     dt = time.time() - t0
     mx = np.array([r["max_rel_err"] for r in recs])
     md = np.array([r["median_rel_err"] for r in recs])
+    form = ("the fused sweep (no score dump; labels only)" if args.fused
+            else "the sweep with its matrix-core scores dumped")
     lines = [
         f"split-BF16 sweep against the FP64 oracle, per sweep: recipe {args.recipe} "
         f"({d.n_cells} cells x {d.n_genes} genes, nnz {d.nnz}), {len(recs)} sweeps from one cluster, seed {args.seed}, "
-        f"paper-literal moves, k_max {args.k_max}",
-        f"command: python tests/precision_report.py --recipe {args.recipe} --sweeps {args.sweeps} --seed {args.seed}",
+        f"paper-literal moves, k_max {args.k_max}; {form}",
+        f"command: python tests/precision_report.py --recipe {args.recipe} --sweeps {args.sweeps} --seed {args.seed}"
+        + (" --fused" if args.fused else ""),
         f"run time {dt:.1f} s; K after the last sweep {recs[-1]['K'] if recs else 0}",
-        f"max relative log-likelihood error: worst sweep {mx.max():.3e}, median over sweeps {np.median(mx):.3e}",
-        f"median relative error: worst sweep {md.max():.3e}, median over sweeps {np.median(md):.3e}",
+    ]
+    if not args.fused:
+        lines += [
+            f"max relative log-likelihood error: worst sweep {mx.max():.3e}, median over sweeps {np.median(mx):.3e}",
+            f"median relative error: worst sweep {md.max():.3e}, median over sweeps {np.median(md):.3e}",
+        ]
+    lines += [
         f"cells re-scored in FP64: {sum(r['refined'] for r in recs)} in all; GPU near-tie decisions "
         f"{sum(r['gpu_near_tie'] for r in recs)}, oracle near-tie decisions {sum(r['oracle_near_tie'] for r in recs)}",
         f"label differences from the oracle: {sum(r['label_mismatch'] for r in recs)} "
@@ -127,7 +144,7 @@ def main(argv=None) -> int:
                      f"{r['near_tie_mismatch']}/{r['other_mismatch']}")
     with open(args.summary, "w") as f:
         f.write("\n".join(lines) + "\n")
-    print("\n".join(lines[:7]), flush=True)
+    print("\n".join(lines[:8]), flush=True)
     return 0 if all(r["other_mismatch"] == 0 for r in recs) else 1
 
 

@@ -44,7 +44,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 struct Layout {
     size_t ent, roff, tiles, c0, c1, cs0, cs1, st, reset, nsub, ssub, beta, lgbeta, logpi, lt64, lc32, ls32, lhi, llo,
         lgrise, subdd, qsub, rbits, rssub, rnsub, refine, perm, srow, grp_cnt, grp_off, grp_cur, nsub_prev, lay_kc,
-        lay_pbeg, lay_pcnt, lay_cell, lay_doff, lay_toff, lay_dense, lay_tail, lay_nnz, lay_rank, lay_gene, lay_bhi,
+        lay_pbeg, lay_pcnt, lay_cell, lay_doff, lay_toff, lay_dense, lay_tail, lay_nnz, lay_hcnt, lay_bh, lay_rank, lay_gene, lay_bhi,
         lay_blo, lay_lim, lay_dE, lay_dS, lay_dfull, lay_sw, lay_part, lay_bbeg, lay_sbeg, mov, relab_c, relab_s, sm_logr, sm_acc, mkey, mlist, dm_k, eb_tmp, rd_part, sm_part, total;
 };
 
@@ -121,9 +121,12 @@ Layout plan(int64_t N, int32_t G, int64_t nnz, int32_t k_max, int32_t precision,
     L.lay_toff = take(blocked ? 8 * (size_t)(nslots + 1) : 0);
     // a block's dense chunks cost less than the tail entries they take (36
     // each), so they hold at most 36 bytes per entry
-    L.lay_dense = take(blocked ? (size_t)kDenseChunkBytes * (size_t)((nnz * 36 + kDenseChunkBytes - 1) / kDenseChunkBytes + 1) : 0);
+    // (plus one high-plane chunk per block)
+    L.lay_dense = take(blocked ? (size_t)kDenseChunkBytes * (size_t)((nnz * 36 + kDenseChunkBytes - 1) / kDenseChunkBytes + 1 + nbc) : 0);
     L.lay_tail = take(blocked ? 4 * (size_t)(nnz > 0 ? nnz : 1) : 0);   // at most every entry
     L.lay_nnz = take(blocked ? 2 * (size_t)nslots : 0);
+    L.lay_hcnt = take(blocked ? (size_t)nslots : 0);
+    L.lay_bh = take(blocked ? (size_t)nbc : 0);
     L.lay_rank = take(blocked ? 2 * (size_t)k_max * (size_t)G : 0);
     L.lay_gene = take(blocked ? 2 * (size_t)k_max * kLayDmax * kBlkGenes : 0);
     L.lay_bhi = take(blocked ? 2 * (size_t)k_max * (size_t)lay_cols(k_max) * kLayDmax * kBlkGenes : 0);
@@ -364,6 +367,8 @@ dpmm_status init_impl(const dpmm_csr* csr, const dpmm_params* params, void* work
     ws.lay_dense = (uint8_t*)(base + L.lay_dense);
     ws.lay_tail = (uint32_t*)(base + L.lay_tail);
     ws.lay_nnz = (uint16_t*)(base + L.lay_nnz);
+    ws.lay_hcnt = (uint8_t*)(base + L.lay_hcnt);
+    ws.lay_bh = (uint8_t*)(base + L.lay_bh);
     ws.lay_rank = (uint16_t*)(base + L.lay_rank);
     ws.lay_gene = (uint16_t*)(base + L.lay_gene);
     ws.lay_bhi = (uint16_t*)(base + L.lay_bhi);

@@ -93,6 +93,25 @@ __device__ inline bf16x8_t widen8(uint32_t w0, uint32_t w1)
     return r;
 }
 
+// the same for high-plane bytes, times 256 (exact: 8 significant bits)
+__device__ inline bf16x8_t widen8_x256(uint32_t w0, uint32_t w1)
+{
+    uint32_t p[4];
+    const uint32_t w[2] = {w0, w1};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const uint32_t f0 = __float_as_uint((float)(w[h] & 0xFFu) * 256.0f);
+        const uint32_t f1 = __float_as_uint((float)((w[h] >> 8) & 0xFFu) * 256.0f);
+        const uint32_t f2 = __float_as_uint((float)((w[h] >> 16) & 0xFFu) * 256.0f);
+        const uint32_t f3 = __float_as_uint((float)(w[h] >> 24) * 256.0f);
+        p[2 * h] = __builtin_amdgcn_perm(f1, f0, 0x07060302u);
+        p[2 * h + 1] = __builtin_amdgcn_perm(f3, f2, 0x07060302u);
+    }
+    bf16x8_t r;
+    __builtin_memcpy(&r, p, sizeof(r));
+    return r;
+}
+
 // The best two Gumbel-perturbed scores seen: value, score and log pi of each.
 struct Top2 {
     float t1, t2, a1, a2, p1, p2;
@@ -131,6 +150,9 @@ k_assign_bf16(Ws ws, AssignArgs a, SubArgs sa)
     __shared__ int8_t s_sub[SUB ? kBlkCells : 1];             // fused sub-cluster pass: each slot's sub-label
     __shared__ uint8_t s_coin[SUB ? kBlkCells : 1];           // (-1: not drawn here) and coin
     __shared__ uint32_t s_ncnt[4];
+    __shared__ uint8_t s_hcnt[kBlkCells];      // each slot's high-plane tail entries
+    __shared__ uint32_t s_tbo[kBlkCells], s_teo[kBlkCells];   // each slot's tail, from the block's first
+    __shared__ double s_dfd[SUB ? kBlkCells : 1];
     __shared__ int s_old[SUB ? kBlkCells : 1];               // (old cluster << 1) | old sub-label
     constexpr int SS = 16 * NT + 1;
     constexpr int NCOL = 16 * NT;
@@ -154,14 +176,24 @@ k_assign_bf16(Ws ws, AssignArgs a, SubArgs sa)
     if (SUB && half == 0) s_old[sl] = cell >= 0 ? (sa.c_old[cell] << 1) | (sa.cs_old[cell] & 1) : 0;
     const int L = ws.lay_kc[b];
     const int64_t d0 = ws.lay_doff[b];
-    const int D = (int)(ws.lay_doff[b + 1] - d0);
+    const int HP = ws.lay_bh[b];               // a high plane after the D dense chunks
+    const int D = (int)(ws.lay_doff[b + 1] - d0) - HP;
     // this lane's 16 bytes of row tile 2w + m of chunk j: + j chunk + m 1 KiB
     const uint8_t* dense = ws.lay_dense + d0 * kDenseChunkBytes;   // uniform base
     const uint32_t doff = (uint32_t)((wave * 2) * 64 + lane) * 16;
-    const int64_t tb = ws.lay_toff[slot], te = ws.lay_toff[slot + 1];
+    // the slot's tail [tb, te) is kept in LDS as offsets from the block's
+    // (registers are short across the chunk loop)
+    const int64_t tbase = ws.lay_toff[(int64_t)b * kBlkCells];
+    if (half == 0) {
+        s_tbo[sl] = (uint32_t)(ws.lay_toff[slot] - tbase);
+        s_teo[sl] = (uint32_t)(ws.lay_toff[slot + 1] - tbase);
+    }
+    // the cluster scores take the tail up to the high-plane entries (the
+    // plane's MFMA covers those; their count kept in LDS until the tail walk);
+    // the draw and the statistics take all of it
+    if (half == 0) s_hcnt[sl] = ws.lay_hcnt[slot];
     // the block's tail entries are contiguous: one coalesced copy into LDS,
     // read after the first barrier below
-    const int64_t tbase = ws.lay_toff[(int64_t)b * kBlkCells];
     const int64_t tcount = ws.lay_toff[(int64_t)(b + 1) * kBlkCells] - tbase;
     const bool staged = tcount <= kTailStage;
     if (staged)
@@ -172,7 +204,9 @@ k_assign_bf16(Ws ws, AssignArgs a, SubArgs sa)
 
     Top2 top;
     top.init();
-    double dfd = 0.0;                          // fused pass: the cell's digit sums combined in FP64
+    // (fused pass: the cell's digit sums combined in FP64, s_dfd[sl], kept in
+    // LDS across the column groups)
+    if (SUB && half == 0) s_dfd[sl] = 0.0;
     const int dE = SUB && L < K ? ws.lay_dE[L] : 0;
     if (SUB && t < 4) s_ncnt[t] = 0;
 
@@ -237,6 +271,34 @@ k_assign_bf16(Ws ws, AssignArgs a, SubArgs sa)
                     }
                 }
             }
+            if (g0 == 0 && HP) {
+                // the high plane (256 x the high bytes of chunk 0's counts
+                // above 255) against chunk 0's B rows, still staged; the digit
+                // columns see zeros (their sums stay exact integers of the low
+                // bytes; the high part of the score difference comes with the
+                // cell's tail entries).  One row tile at a time.
+                const uint16_t* bh = bst;
+                const uint16_t* bl = bst + NCOL * kRowB;
+                const bf16x8_t zero8 = {};
+#pragma unroll
+                for (int m = 0; m < 2; ++m) {
+                    const uint4 hv = *reinterpret_cast<const uint4*>(dense + (doff + (uint32_t)(D * kDenseChunkBytes + m * 1024)));
+                    const bf16x8_t hf[2] = {widen8_x256(hv.x, hv.y), widen8_x256(hv.z, hv.w)};
+#pragma unroll
+                    for (int s = 0; s < 2; ++s) {
+                        const int col = 32 * s + 8 * (lane >> 4);
+#pragma unroll
+                        for (int n = 0; n < NT; ++n) {
+                            const int c = kb + 16 * n + (lane & 15);
+                            const bool digit = c >= K && c < K + kSubDigits;
+                            const bf16x8_t vh = digit ? zero8 : *reinterpret_cast<const bf16x8_t*>(bh + (16 * n + (lane & 15)) * kRowB + col);
+                            const bf16x8_t vl = digit ? zero8 : *reinterpret_cast<const bf16x8_t*>(bl + (16 * n + (lane & 15)) * kRowB + col);
+                            acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hf[s], vh, acc[m][n], 0, 0, 0);
+                            acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hf[s], vl, acc[m][n], 0, 0, 0);
+                        }
+                    }
+                }
+            }
         }
         __syncthreads();
         // scores through LDS: lane l holds, for row tile m and column tile n,
@@ -255,7 +317,7 @@ k_assign_bf16(Ws ws, AssignArgs a, SubArgs sa)
 #pragma unroll
             for (int k = 0; k < kSubDigits; ++k) {
                 const int col = K + k - kb;
-                if (col >= 0 && col < NCOL) dfd += ldexp((double)sc[sl * SS + col], 8 * k - dE);
+                if (col >= 0 && col < NCOL) s_dfd[sl] += ldexp((double)sc[sl * SS + col], 8 * k - dE);
             }
         }
         if (cell >= 0) {
@@ -265,6 +327,8 @@ k_assign_bf16(Ws ws, AssignArgs a, SubArgs sa)
             // added in entry order to this thread's own columns of the score
             // row, two entries' table rows in flight at a time
             float* srow = sc + sl * SS + half * HALF;
+            const int64_t tb = tbase + s_tbo[sl];
+            const int64_t te = tbase + s_teo[sl] - s_hcnt[sl];     // (without the high-plane entries)
             if (te > tb) {
                 float ta[HALF];
 #pragma unroll
@@ -429,7 +493,8 @@ k_assign_bf16(Ws ws, AssignArgs a, SubArgs sa)
                     // the tail's part of the difference, in entry order, eight
                     // entries' loads in flight at a time
                     const double* dfull = ws.lay_dfull + (int64_t)L * ws.G;
-                    double df = dfd;
+                    double df = s_dfd[sl];
+                    const int64_t tb = tbase + s_tbo[sl], te = tbase + s_teo[sl];
                     for (int64_t e0 = tb; e0 < te; e0 += 8) {
                         uint32_t en[8];
                         double dv[8];
@@ -505,8 +570,14 @@ k_assign_bf16(Ws ws, AssignArgs a, SubArgs sa)
             const int q = 16 * h + r;
             sel[h] = g == (q >> 3) ? (long)((uint64_t)1 << (8 * (q & 7))) : 0;
         }
-        if (rs) chunk_stats<4>(dense, doff, D, amask, sel, rc128, phist, g, r);
-        else chunk_stats<2>(dense, doff, D, amask, sel, rc128, phist, g, r);
+        // (the lane's chunk offset formed again from the thread index, which an
+        // empty asm hides from the compiler: otherwise the value from the
+        // prologue is kept, or spilled, across the whole kernel)
+        uint32_t tx = threadIdx.x;
+        asm volatile("" : "+v"(tx));
+        const uint32_t doff2 = (uint32_t)(((tx >> 6) * 2) * 64 + (tx & 63)) * 16;
+        if (rs) chunk_stats<4>(dense, doff2, D, amask, sel, rc128, phist, g, r);
+        else chunk_stats<2>(dense, doff2, D, amask, sel, rc128, phist, g, r);
         // the tail entries of the drawn cells, every other one per half: a
         // gene among L's first kPlaces places goes to the histogram, any
         // other straight to the statistics
@@ -517,6 +588,7 @@ k_assign_bf16(Ws ws, AssignArgs a, SubArgs sa)
                 unsigned long long* srow = ws.ssub + (int64_t)(2 * L + svc) * ws.G;
                 unsigned long long* crow = rs ? ws.rssub + (int64_t)(2 * L + cvc) * ws.G : nullptr;
                 // eight entries' ranks in flight at a time
+                const int64_t tb = tbase + s_tbo[sl], te = tbase + s_teo[sl];
                 for (int64_t e0 = tb + half; e0 < te; e0 += 16) {
                     uint32_t en[8];
                     int p[8];

@@ -318,7 +318,10 @@ struct Ws {
     int64_t* lay_toff;     // [nblk_cap kBlkCells + 1] tail entries before each slot
     uint8_t* lay_dense;    // dense chunks, kDenseChunkBytes each
     uint32_t* lay_tail;    // tail entries (gene | count << 16), each slot's in row order
-    uint16_t* lay_nnz;     // [nblk_cap kBlkCells] non-zero counts of each slot's cell
+    uint16_t* lay_nnz;     // [nblk_cap kBlkCells] the products of each slot's cell that its scores sum
+                           // (its non-zero counts, plus one for each count split by the high plane)
+    uint8_t* lay_hcnt;     // [nblk_cap kBlkCells] the slot's high-plane entries, last in its tail
+    uint8_t* lay_bh;       // [nblk_cap] 1 when the block has a high plane (one more chunk after its D)
     uint16_t* lay_rank;    // [k_max G] place of gene u in cluster L's order
     uint16_t* lay_gene;    // [k_max kLayDmax kBlkGenes] gene at place j
     uint16_t* lay_bhi;     // [k_max][lay_cols][kLayDmax kBlkGenes] hi of log theta in L's gene order

@@ -13,7 +13,13 @@
 // of the matrix-core fragments; every other entry (a gene past those chunks,
 // or a count above 255) is a tail entry of its cell, (gene | count << 16).
 // D_b (at most kLayDmax) minimises the block's cost, 16 KiB per dense chunk
-// against kTailCost per tail entry.
+// against kTailCost per tail entry.  A count above 255 on one of the first
+// kBlkGenes places (the cluster's top genes, where such counts crowd) is split
+// when D_b >= 1: its low byte goes to chunk 0, its high byte to a high plane
+// (one more chunk after the D_b, in the same byte order, scored with weight
+// 256), and 256 x the high byte stays in the cell's tail, last, for the
+// sub-cluster pass and the statistics (lay_hcnt of them per slot; lay_bh[b]
+// = 1 when the block has the plane).
 //
 // The copy only decides how each cell's log-likelihoods are summed; any cell
 // in any block is scored exactly the same way, so the copy may lag behind the
@@ -138,10 +144,14 @@ __global__ void __launch_bounds__(kLayThreads) k_lay_count(Ws ws, int gated)
     const int t = threadIdx.x;
     const int64_t slot = (int64_t)b * kBlkCells + t;
     if (b >= ws.st->lay_nblk) {
-        if (t == 0) ws.lay_doff[b] = 0;
+        if (t == 0) {
+            ws.lay_doff[b] = 0;
+            ws.lay_bh[b] = 0;
+        }
         ws.lay_toff[slot] = 0;
         ws.lay_cell[slot] = -1;
         ws.lay_nnz[slot] = 0;
+        ws.lay_hcnt[slot] = 0;
         return;
     }
     if (t < kLayDmax) hist[t] = 0;
@@ -181,12 +191,12 @@ __global__ void __launch_bounds__(kLayThreads) k_lay_count(Ws ws, int gated)
             }
         }
         s_D = D;
-        ws.lay_doff[b] = D;
     }
     __syncthreads();
-    // pass 2: the slot's entries that stay out of the dense chunks
+    // pass 2: the slot's entries that stay out of the dense chunks, and its
+    // counts above 255 on chunk 0's places (split by the high plane)
     const uint32_t lim = s_D * kBlkGenes;
-    uint32_t dense = 0;
+    uint32_t dense = 0, big = 0;
     for (int64_t p = rb; p < re; p += 4) {
         const uint4 v = *reinterpret_cast<const uint4*>(ws.ent + p);
         const uint32_t en[4] = {v.x, v.y, v.z, v.w};
@@ -194,11 +204,22 @@ __global__ void __launch_bounds__(kLayThreads) k_lay_count(Ws ws, int gated)
         for (int q = 0; q < 4; ++q) {
             const uint32_t x = en[q] >> 16;
             const uint32_t g = en[q] & 0xFFFFu;
-            if (x && x < 256u && g < (uint32_t)ws.G && rank[g] < lim) ++dense;
+            if (!x || g >= (uint32_t)ws.G) continue;
+            const uint32_t rk = rank[g];
+            if (x < 256u && rk < lim) ++dense;
+            else if (x >= 256u && rk < (uint32_t)kBlkGenes && lim > 0) ++big;
         }
     }
+    // the plane when any slot of the block has such a count
+    const int H = __syncthreads_or(big > 0);
+    if (t == 0) {
+        ws.lay_doff[b] = s_D + (uint32_t)H;
+        ws.lay_bh[b] = (uint8_t)H;
+    }
     ws.lay_cell[slot] = cell;
-    ws.lay_nnz[slot] = (uint16_t)min(nnz, 65535u);
+    // (a split count is two products, of its low and its high byte)
+    ws.lay_nnz[slot] = (uint16_t)min(nnz + big, 65535u);
+    ws.lay_hcnt[slot] = (uint8_t)big;              // at most kBlkGenes
     ws.lay_toff[slot] = (int64_t)(nnz - dense);
 }
 
@@ -217,21 +238,25 @@ __device__ inline uint32_t dense_byte(int slot, int j, int jj)
 // with 16-byte stores; the tail entries of each slot in row order.
 __global__ void __launch_bounds__(kLayThreads) k_lay_fill(Ws ws, int gated)
 {
-    extern __shared__ __attribute__((aligned(16))) uint8_t tile[];     // [kLayDmax][16 KiB]
+    extern __shared__ __attribute__((aligned(16))) uint8_t tile[];     // [kLayDmax + 1][16 KiB]
     if (!lay_gate(ws, gated)) return;
     const int b = blockIdx.x;
     if (b >= ws.st->lay_nblk) return;
     const int t = threadIdx.x;
-    const int D = (int)(ws.lay_doff[b + 1] - ws.lay_doff[b]);
+    const int H = ws.lay_bh[b];
+    const int DT = (int)(ws.lay_doff[b + 1] - ws.lay_doff[b]);     // dense chunks and the plane
+    const int D = DT - H;
     uint4* t4 = reinterpret_cast<uint4*>(tile);
-    for (int q = t; q < D * kDenseChunkBytes / 16; q += kLayThreads) t4[q] = make_uint4(0, 0, 0, 0);
+    for (int q = t; q < DT * kDenseChunkBytes / 16; q += kLayThreads) t4[q] = make_uint4(0, 0, 0, 0);
     __syncthreads();
     const int64_t slot = (int64_t)b * kBlkCells + t;
     const int cell = ws.lay_cell[slot];
     const int kc = ws.lay_kc[b];
     const uint16_t* rank = ws.lay_rank + (int64_t)kc * ws.G;
     if (cell >= 0) {
+        // the tail entries in row order, then the high bytes' (256 x hi) last
         int64_t w = ws.lay_toff[slot];
+        int64_t wh = ws.lay_toff[slot + 1] - ws.lay_hcnt[slot];
         const uint32_t lim = (uint32_t)D * kBlkGenes;
         for (int64_t p = ws.roff[cell]; p < ws.roff[cell + 1]; p += 4) {
             const uint4 v = *reinterpret_cast<const uint4*>(ws.ent + p);
@@ -243,20 +268,27 @@ __global__ void __launch_bounds__(kLayThreads) k_lay_fill(Ws ws, int gated)
                 const uint32_t g = en & 0xFFFFu;
                 if (!x || g >= (uint32_t)ws.G) continue;
                 const uint32_t rk = rank[g];
-                if (x < 256u && rk < lim) tile[dense_byte(t, rk / kBlkGenes, rk % kBlkGenes)] = (uint8_t)x;
-                else ws.lay_tail[w++] = en;
+                if (x < 256u && rk < lim) {
+                    tile[dense_byte(t, rk / kBlkGenes, rk % kBlkGenes)] = (uint8_t)x;
+                } else if (H && x >= 256u && rk < (uint32_t)kBlkGenes) {
+                    tile[dense_byte(t, 0, rk)] = (uint8_t)(x & 0xFFu);
+                    tile[dense_byte(t, D, rk)] = (uint8_t)(x >> 8);
+                    ws.lay_tail[wh++] = g | ((x & 0xFF00u) << 16);
+                } else {
+                    ws.lay_tail[w++] = en;
+                }
             }
         }
     }
     __syncthreads();
     uint4* out = reinterpret_cast<uint4*>(ws.lay_dense + ws.lay_doff[b] * kDenseChunkBytes);
-    for (int q = t; q < D * kDenseChunkBytes / 16; q += kLayThreads) out[q] = t4[q];
+    for (int q = t; q < DT * kDenseChunkBytes / 16; q += kLayThreads) out[q] = t4[q];
 }
 
 hipError_t configure_layout()
 {
     hipError_t e = hipFuncSetAttribute((const void*)k_lay_fill, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)(kLayDmax * kDenseChunkBytes));
+                                       (int)((kLayDmax + 1) * kDenseChunkBytes));
     if (e == hipSuccess)
         e = hipFuncSetAttribute((const void*)k_lay_ranks, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)(sizeof(unsigned long long) * kRankMaxGenes));
@@ -280,7 +312,7 @@ void launch_relayout(const Ws& ws, const int32_t* c, int64_t* tile_sums, int for
     launch_exclusive_scan(ws.lay_doff, ws.nblk_cap, tile_sums, s, gated ? &ws.st->lay_go : nullptr);
     launch_exclusive_scan(ws.lay_toff, (int64_t)ws.nblk_cap * kBlkCells, tile_sums, s,
                           gated ? &ws.st->lay_go : nullptr);
-    hipLaunchKernelGGL(k_lay_fill, dim3((unsigned)ws.nblk_cap), dim3(kLayThreads), kLayDmax * kDenseChunkBytes, s, ws,
+    hipLaunchKernelGGL(k_lay_fill, dim3((unsigned)ws.nblk_cap), dim3(kLayThreads), (kLayDmax + 1) * kDenseChunkBytes, s, ws,
                        gated);
 }
 

@@ -71,7 +71,9 @@ k_lay_sub(Ws ws, SubArgs a)
     const int K = ws.st->K;
     const int G = ws.G;
     const int64_t d0 = ws.lay_doff[b];
-    const int D = (int)(ws.lay_doff[b + 1] - d0);
+    // (the high plane after the D dense chunks is for the cluster scores; the
+    // high parts of those counts are in the tail entries here)
+    const int D = (int)(ws.lay_doff[b + 1] - d0) - ws.lay_bh[b];
     const bool reset = L < K ? ws.reset[L] != 0 : true;
     const double* g0 = ws.lt64 + (int64_t)(ws.k_max + 2 * (L < K ? L : 0)) * G;
     const double* g1 = g0 + G;

@@ -272,30 +272,28 @@ k_assign_bf16(Ws ws, AssignArgs a, SubArgs sa)
                 }
             }
             if (g0 == 0 && HP) {
-                // the high plane (256 x the high bytes of chunk 0's counts
-                // above 255) against chunk 0's B rows, still staged; the digit
+                // the high plane (256 x the high bytes of the counts above 255
+                // on chunk 0's first kPlaneGenes places, one k-step, 8 bytes
+                // per lane) against chunk 0's B rows, still staged; the digit
                 // columns see zeros (their sums stay exact integers of the low
                 // bytes; the high part of the score difference comes with the
                 // cell's tail entries).  One row tile at a time.
                 const uint16_t* bh = bst;
                 const uint16_t* bl = bst + NCOL * kRowB;
                 const bf16x8_t zero8 = {};
+                const int col = 8 * (lane >> 4);
 #pragma unroll
                 for (int m = 0; m < 2; ++m) {
-                    const uint4 hv = *reinterpret_cast<const uint4*>(dense + (doff + (uint32_t)(D * kDenseChunkBytes + m * 1024)));
-                    const bf16x8_t hf[2] = {widen8_x256(hv.x, hv.y), widen8_x256(hv.z, hv.w)};
+                    const uint2 hv = *reinterpret_cast<const uint2*>(dense + ((doff >> 1) + (uint32_t)(D * kDenseChunkBytes + m * 512)));
+                    const bf16x8_t hf = widen8_x256(hv.x, hv.y);
 #pragma unroll
-                    for (int s = 0; s < 2; ++s) {
-                        const int col = 32 * s + 8 * (lane >> 4);
-#pragma unroll
-                        for (int n = 0; n < NT; ++n) {
-                            const int c = kb + 16 * n + (lane & 15);
-                            const bool digit = c >= K && c < K + kSubDigits;
-                            const bf16x8_t vh = digit ? zero8 : *reinterpret_cast<const bf16x8_t*>(bh + (16 * n + (lane & 15)) * kRowB + col);
-                            const bf16x8_t vl = digit ? zero8 : *reinterpret_cast<const bf16x8_t*>(bl + (16 * n + (lane & 15)) * kRowB + col);
-                            acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hf[s], vh, acc[m][n], 0, 0, 0);
-                            acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hf[s], vl, acc[m][n], 0, 0, 0);
-                        }
+                    for (int n = 0; n < NT; ++n) {
+                        const int c = kb + 16 * n + (lane & 15);
+                        const bool digit = c >= K && c < K + kSubDigits;
+                        const bf16x8_t vh = digit ? zero8 : *reinterpret_cast<const bf16x8_t*>(bh + (16 * n + (lane & 15)) * kRowB + col);
+                        const bf16x8_t vl = digit ? zero8 : *reinterpret_cast<const bf16x8_t*>(bl + (16 * n + (lane & 15)) * kRowB + col);
+                        acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hf, vh, acc[m][n], 0, 0, 0);
+                        acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hf, vl, acc[m][n], 0, 0, 0);
                     }
                 }
             }

@@ -122,6 +122,7 @@ constexpr uint32_t kFlagSplitQ = 1u;          // dpmm_params.flags bit of the sp
 constexpr uint32_t kFlagNewCluster = 2u;      // ... and of the Gibbs step over K + 1 clusters
 constexpr uint32_t kFlagRandomSplit = 4u;     // ... and of the random-split pass
 constexpr int kBlkGenes = 64;
+constexpr int kPlaneGenes = 32;                    // places of chunk 0 that the high plane covers (one k-step)
 constexpr int kMaxClusters = 1024;                 // largest k_max dpmm_init accepts
 constexpr int kSubDigits = 7;                      // digit columns after the K clusters in lay_bhi (layout.hip)
 constexpr int kSpanBlocks = 128;                   // blocks per span of the statistics reduction (laysub.hip)

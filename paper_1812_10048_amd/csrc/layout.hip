@@ -14,12 +14,13 @@
 // or a count above 255) is a tail entry of its cell, (gene | count << 16).
 // D_b (at most kLayDmax) minimises the block's cost, 16 KiB per dense chunk
 // against kTailCost per tail entry.  A count above 255 on one of the first
-// kBlkGenes places (the cluster's top genes, where such counts crowd) is split
-// when D_b >= 1: its low byte goes to chunk 0, its high byte to a high plane
-// (one more chunk after the D_b, in the same byte order, scored with weight
-// 256), and 256 x the high byte stays in the cell's tail, last, for the
-// sub-cluster pass and the statistics (lay_hcnt of them per slot; lay_bh[b]
-// = 1 when the block has the plane).
+// kPlaneGenes places (the cluster's top genes, where such counts crowd) is
+// split when D_b >= 1: its low byte goes to chunk 0, its high byte to a high
+// plane (one more chunk slot after the D_b, of which it fills the first half:
+// the A fragments of one k-step, 8 bytes per lane; scored with weight 256),
+// and 256 x the high byte stays in the cell's tail, last, for the sub-cluster
+// pass and the statistics (lay_hcnt of them per slot; lay_bh[b] = 1 when the
+// block has the plane).
 //
 // The copy only decides how each cell's log-likelihoods are summed; any cell
 // in any block is scored exactly the same way, so the copy may lag behind the
@@ -207,7 +208,7 @@ __global__ void __launch_bounds__(kLayThreads) k_lay_count(Ws ws, int gated)
             if (!x || g >= (uint32_t)ws.G) continue;
             const uint32_t rk = rank[g];
             if (x < 256u && rk < lim) ++dense;
-            else if (x >= 256u && rk < (uint32_t)kBlkGenes && lim > 0) ++big;
+            else if (x >= 256u && rk < (uint32_t)kPlaneGenes && lim > 0) ++big;
         }
     }
     // the plane when any slot of the block has such a count
@@ -219,7 +220,7 @@ __global__ void __launch_bounds__(kLayThreads) k_lay_count(Ws ws, int gated)
     ws.lay_cell[slot] = cell;
     // (a split count is two products, of its low and its high byte)
     ws.lay_nnz[slot] = (uint16_t)min(nnz + big, 65535u);
-    ws.lay_hcnt[slot] = (uint8_t)big;              // at most kBlkGenes
+    ws.lay_hcnt[slot] = (uint8_t)big;              // at most kPlaneGenes
     ws.lay_toff[slot] = (int64_t)(nnz - dense);
 }
 
@@ -232,6 +233,15 @@ __device__ inline uint32_t dense_byte(int slot, int j, int jj)
     const int s = (jj >> 5) & 1, q = (jj >> 3) & 3, e = jj & 7;
     const int lane = 16 * q + r;
     return (uint32_t)j * kDenseChunkBytes + (uint32_t)(((w * 4 + m) * 64 + lane) * 16 + s * 8 + e);
+}
+
+// Byte of (slot, place jj < kPlaneGenes) in the high plane at chunk slot j:
+// the same fragment order for the one k-step, 8 bytes per lane.
+__device__ inline uint32_t plane_byte(int slot, int j, int jj)
+{
+    const int rt = slot >> 4, r = slot & 15;
+    const int q = (jj >> 3) & 3, e = jj & 7;
+    return (uint32_t)j * kDenseChunkBytes + (uint32_t)((rt * 64 + 16 * q + r) * 8 + e);
 }
 
 // One workgroup per block: the dense chunks assembled in LDS and written out
@@ -270,9 +280,9 @@ __global__ void __launch_bounds__(kLayThreads) k_lay_fill(Ws ws, int gated)
                 const uint32_t rk = rank[g];
                 if (x < 256u && rk < lim) {
                     tile[dense_byte(t, rk / kBlkGenes, rk % kBlkGenes)] = (uint8_t)x;
-                } else if (H && x >= 256u && rk < (uint32_t)kBlkGenes) {
+                } else if (H && x >= 256u && rk < (uint32_t)kPlaneGenes) {
                     tile[dense_byte(t, 0, rk)] = (uint8_t)(x & 0xFFu);
-                    tile[dense_byte(t, D, rk)] = (uint8_t)(x >> 8);
+                    tile[plane_byte(t, D, rk)] = (uint8_t)(x >> 8);
                     ws.lay_tail[wh++] = g | ((x & 0xFF00u) << 16);
                 } else {
                     ws.lay_tail[w++] = en;

@@ -310,6 +310,45 @@ def test_edge_cases():
     assert e.value.status == C.DPMM_ERR_STATE
 
 
+def _big_counts(seed: int = 5) -> np.ndarray:
+    """Three groups of cells (ragged blocks of 256), each dense on its own 90
+    genes, with about 30 % of those counts at or above 256 (up to the largest
+    count a packed entry holds, 65,535) and some at exactly 255; a cell with no
+    counts and a cell whose one count is 65,535.  In any partition, a block's
+    cluster then has counts above 255 on its first 32 places (split into a low
+    byte and a high plane), on places 32-63 (tail entries beside the dense
+    chunk) and on genes past the dense chunks."""
+    rng = np.random.default_rng(seed)
+    sizes, G, width = (260, 300, 180), 300, 90
+    big = np.array([255, 256, 257, 300, 511, 512, 1000, 4095, 65535])
+    rows = []
+    for g, n in enumerate(sizes):
+        x = rng.poisson(0.2, size=(n, G))
+        x[:, g * width:(g + 1) * width] = rng.poisson(20.0, size=(n, width)) + 1
+        hit = rng.random((n, width)) < 0.3
+        blk = x[:, g * width:(g + 1) * width]
+        blk[hit] = rng.choice(big, size=int(hit.sum()))
+        rows.append(x)
+    x = np.concatenate(rows)
+    x[5] = 0
+    x[7] = 0
+    x[7, 3] = 65535
+    return x
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "split_bf16"])
+def test_counts_above_255_on_the_top_genes(precision):
+    """Large counts where the split-BF16 copy splits them (the high plane),
+    keeps them in the tail beside a dense chunk, or past the dense chunks:
+    labels, statistics and split/merge decisions in lockstep with the
+    oracle (eq. 26 for the scores, eq. 8 and the sufficient statistics)."""
+    say(f"bigcounts-{precision}")
+    d = synth.from_dense(_big_counts())
+    ls = Lockstep(f"bigcounts-{precision}", *_pair(d, precision, seed=3, k_max=16, k_init=2))
+    ls.iterate(8)
+    ls.finish()
+
+
 def test_capacity_limit_counts_skipped_splits():
     say("kmax")
     d = synth.generate("c1", seed=0, n_cells=600)

@@ -3,8 +3,11 @@ worst-case emulation on the CPU (no GPU needed).
 
 The matrix-core kernel (assign_mfma.hip) scores a cell with n non-zero counts
 as S = sum over its dense entries of x (hi + lo) (BF16 hi/lo of FP32 log theta,
-products exact) plus sum over its tail entries of fp32(x fp32(log theta)), all
-added in FP32, then adds log pi and the Gumbel noise.  The kernel trusts a
+products exact; a count above 255 on one of the first 32 places of the block's
+cluster is split into its low byte and 256 x its high byte, four exact
+products, and counted as two entries) plus sum over its tail entries of
+fp32(x fp32(log theta)), all added in FP32, then adds log pi and the Gumbel
+noise.  The kernel trusts a
 decision when the gap of its two best values exceeds the sum of their bounds
     b(S, lp, n) = (2^-17 + (2n + 8) 2^-23) 1.01 (|S| + |lp| + 20) + 1e-5,
 evaluated in FP32 on its own S.  The hardware assumption is that each FP32
@@ -43,15 +46,23 @@ def round_f32(v: float, mode: str) -> np.float32:
     return f
 
 
-def emulate(x: np.ndarray, lt: np.ndarray, dense: np.ndarray, lp: float, gumbel: float, mode: str = "down"):
+def emulate(x: np.ndarray, lt: np.ndarray, dense: np.ndarray, lp: float, gumbel: float, mode: str = "down",
+            split: np.ndarray = None):
     """Worst-case FP32 score of one cell: x counts, lt FP64 log theta of its
-    genes, dense[i] whether entry i is in the dense chunks (x <= 255)."""
+    genes, dense[i] whether entry i is in the dense chunks (x <= 255), split[i]
+    whether a count above 255 is split into its low byte (a dense chunk) and
+    256 x its high byte (the high plane): four products, each exact."""
     f = lt.astype(np.float32)
     hi = bf16_rne(f)
     lo = bf16_rne((lt - hi).astype(np.float32))
+    if split is None:
+        split = np.zeros(len(x), dtype=bool)
     terms = []
-    for xi, fi, hi_i, lo_i, d in zip(x, f, hi, lo, dense):
-        if d:
+    for xi, fi, hi_i, lo_i, d, s in zip(x, f, hi, lo, dense, split):
+        if s:
+            lb, hb = xi % 256.0, xi - xi % 256.0       # 256 x the high byte: 8 significant bits
+            terms += [lb * hi_i, lb * lo_i, hb * hi_i, hb * lo_i]
+        elif d:
             terms += [xi * hi_i, xi * lo_i]          # exact in FP32 (8-bit x 8-bit significands)
         else:
             terms.append(float(round_f32(float(xi) * float(fi), mode)))
@@ -105,6 +116,22 @@ def test_bound_dominates_worst_case_rounding():
             # noise's own FP32 error, which the 1e-5 covers)
             assert abs(S - exact) <= b, (mode, len(x), S, exact, b)
             assert abs(val - (exact + lp + g)) <= b, (mode, len(x), val, exact + lp + g, b)
+            worst = max(worst, abs(S - exact) / b)
+    assert worst > 0.1, worst
+
+
+def test_bound_covers_split_counts():
+    """Counts above 255 split between a dense chunk and the high plane: the
+    kernel counts each as two entries (lay_nnz), so a cell with n entries of
+    which s are split is bounded with n + s."""
+    worst = 0.0
+    for mode in ("down", "zero"):
+        for x, lt, dense, lp, g in cases():
+            split = (x >= 256) & (rng.random(len(x)) < 0.6)
+            S, val, exact = emulate(x, lt, dense, lp, g, mode, split)
+            b = bound(S, lp, len(x) + int(split.sum()))
+            assert abs(S - exact) <= b, (mode, len(x), S, exact, b)
+            assert abs(val - (exact + lp + g)) <= b
             worst = max(worst, abs(S - exact) / b)
     assert worst > 0.1, worst
 

@@ -195,7 +195,8 @@ __global__ void __launch_bounds__(kLayThreads) k_lay_count(Ws ws, int gated)
     }
     __syncthreads();
     // pass 2: the slot's entries that stay out of the dense chunks, and its
-    // counts above 255 on chunk 0's places (split by the high plane)
+    // counts above 255 on chunk 0's first kPlaneGenes places (split by the high
+    // plane)
     const uint32_t lim = s_D * kBlkGenes;
     uint32_t dense = 0, big = 0;
     for (int64_t p = rb; p < re; p += 4) {

@@ -25,6 +25,7 @@ import csv
 import glob
 import hashlib
 import os
+import re
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -33,12 +34,20 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 TRAFFIC_SOURCES = ("csrc/assign_mfma.hip", "csrc/layout.hip", "csrc/dpmm_common.hpp")
 
 
+def _code_only(text: str) -> str:
+    """The source without its comments and with whitespace runs collapsed,
+    so that an edit of a comment does not count as a change of the kernel."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def source_digest(files=TRAFFIC_SOURCES) -> str:
     h = hashlib.sha256()
     for f in files:
-        with open(os.path.join(HERE, f), "rb") as fh:
+        with open(os.path.join(HERE, f), encoding="utf-8") as fh:
             h.update(f.encode())
-            h.update(fh.read())
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

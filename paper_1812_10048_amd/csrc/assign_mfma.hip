@@ -158,9 +158,17 @@ k_assign_bf16(Ws ws, AssignArgs a, SubArgs sa)
     constexpr int NCOL = 16 * NT;
     constexpr int HALF = NCOL / 2;             // clusters per thread of a slot's pair (multiple of 8)
 
-    const int b = blockIdx.x;
-    if (SUB && b == 0 && threadIdx.x == 0) ws.st->rs_live = sa.rsplit ? 1 : 0;
-    if (b >= ws.st->lay_nblk) return;
+    if (SUB && blockIdx.x == 0 && threadIdx.x == 0) ws.st->rs_live = sa.rsplit ? 1 : 0;
+    // XCD-aware order: workgroups are dealt to the 8 XCDs in turn (workgroup i
+    // to XCD i % 8), and each XCD takes one contiguous range of the live
+    // blocks, so the blocks of a cluster, which share its tables, run on one
+    // XCD and its L2 (a bijection of [0, nb))
+    const int nb = ws.st->lay_nblk;
+    if ((int)blockIdx.x >= nb) return;
+    const int b = [&] {
+        const int x = blockIdx.x & 7, i = blockIdx.x >> 3, q = nb >> 3, r = nb & 7;
+        return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+    }();
     const int K = ws.st->K;
     // with the fused sub-cluster pass the digit columns K .. K + kSubDigits - 1
     // of the hi/lo tables are scored too

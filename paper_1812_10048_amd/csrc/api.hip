@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -119,10 +120,12 @@ Layout plan(int64_t N, int32_t G, int64_t nnz, int32_t k_max, int32_t precision,
     L.lay_cell = take(blocked ? 4 * (size_t)nslots : 0);
     L.lay_doff = take(blocked ? 8 * (size_t)(nbc + 1) : 0);
     L.lay_toff = take(blocked ? 8 * (size_t)(nslots + 1) : 0);
-    // a block's dense chunks cost less than the tail entries they take (36
-    // each), so they hold at most 36 bytes per entry
-    // (plus one high-plane chunk per block)
-    L.lay_dense = take(blocked ? (size_t)kDenseChunkBytes * (size_t)((nnz * 36 + kDenseChunkBytes - 1) / kDenseChunkBytes + 1 + nbc) : 0);
+    // a block's dense chunks cost less than the tail entries they take
+    // (kTailCost each), so they hold at most kTailCost bytes per entry, and a
+    // block has at most kLayDmax of them; plus one high-plane chunk per block
+    const int64_t dense_chunks = std::min<int64_t>((nnz * kTailCost + kDenseChunkBytes - 1) / kDenseChunkBytes + 1,
+                                                   nbc * (int64_t)kLayDmax);
+    L.lay_dense = take(blocked ? (size_t)kDenseChunkBytes * (size_t)(dense_chunks + nbc) : 0);
     L.lay_tail = take(blocked ? 4 * (size_t)(nnz > 0 ? nnz : 1) : 0);   // at most every entry
     L.lay_nnz = take(blocked ? 2 * (size_t)nslots : 0);
     L.lay_hcnt = take(blocked ? (size_t)nslots : 0);

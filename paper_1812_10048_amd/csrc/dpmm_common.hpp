@@ -122,6 +122,11 @@ constexpr uint32_t kFlagSplitQ = 1u;          // dpmm_params.flags bit of the sp
 constexpr uint32_t kFlagNewCluster = 2u;      // ... and of the Gibbs step over K + 1 clusters
 constexpr uint32_t kFlagRandomSplit = 4u;     // ... and of the random-split pass
 constexpr int kBlkGenes = 64;
+// cost of a tail entry against a dense byte in the choice of a block's dense
+// chunks (layout.hip): its 4 bytes, the gather of its gene's FP32 row of log
+// theta, and its place in the serial tail walk, where a wavefront waits for
+// its longest tail (measured: 72-192 equally fast at 1.3M x 2000, 36 slower)
+constexpr long long kTailCost = 96;
 constexpr int kPlaneGenes = 32;                    // places of chunk 0 that the high plane covers (one k-step)
 constexpr int kMaxClusters = 1024;                 // largest k_max dpmm_init accepts
 constexpr int kSubDigits = 7;                      // digit columns after the K clusters in lay_bhi (layout.hip)

@@ -35,7 +35,6 @@ namespace dpmm {
 constexpr int kLayThreads = kBlkCells;        // one thread per block slot
 constexpr int kRankThreads = 1024;
 constexpr int kRankMaxGenes = 8192;           // genes renumbered per cluster up to this G
-constexpr long long kTailCost = 36;           // a tail entry against a dense byte
 
 __device__ inline bool lay_gate(const Ws& ws, int gated) { return !gated || ws.st->lay_go; }
 
@@ -180,8 +179,7 @@ __global__ void __launch_bounds__(kLayThreads) k_lay_count(Ws ws, int gated)
     __syncthreads();
     if (t == 0) {
         // cost of D dense chunks: 16 KiB each, plus kTailCost per entry not
-        // in them (4 bytes of HBM, and a gather of the gene's FP32 row of
-        // log theta, about 160 bytes from L2, which moves about 5x faster)
+        // in them
         long long best = 0, cost = 0;
         uint32_t D = 0;
         for (int d = 1; d <= kLayDmax; ++d) {
